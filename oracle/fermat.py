@@ -1,0 +1,128 @@
+"""Two-layer refraction through the lens by Fermat's principle.
+
+Paper: Section II-B (Bent-Ray Model for Lens Compensation), Eqs. 7-8, and the
+Model Implementation subsection (refraction points from the global mean speed).
+
+Geometry: the centre of curvature is the origin; element a sits at radius R_a
+and polar angle theta_a; the lens outer surface is the concentric arc of radius
+R_L = R_a + d_lens.  For a point p at radius rho and polar angle theta_p the
+travel time through the lens and a homogeneous medium of speed c_med via the
+lens point L(phi) = R_L (sin phi, cos phi) is
+
+    T(phi) = |L(phi) - e_a| / c_lens + |p - L(phi)| / c_med .
+
+Reading: the paper searches a finite set of N_search candidate points; the
+oracle returns the continuous minimiser instead (the discrete search converges
+to it).  It scans phi over [min(theta_a, theta_p), max(theta_a, theta_p)] --
+outside that interval both legs get longer -- and then bisects the sign of
+dT/dphi inside the bracket around the best scanned point.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _legs(phi, ex, ez, px, pz, rl):
+    lx = rl * np.sin(phi)
+    lz = rl * np.cos(phi)
+    l1 = np.hypot(lx - ex, lz - ez)
+    l2 = np.hypot(px - lx, pz - lz)
+    return lx, lz, l1, l2
+
+
+def travel_time_via(phi, ex, ez, px, pz, rl, c_lens, c_med):
+    """T(phi) for every ray (arrays broadcast)."""
+    _, _, l1, l2 = _legs(phi, ex, ez, px, pz, rl)
+    return l1 / c_lens + l2 / c_med
+
+
+def _dT(phi, ex, ez, px, pz, rl, c_lens, c_med):
+    """dT/dphi: the tangential components of both legs at L(phi)."""
+    lx, lz, l1, l2 = _legs(phi, ex, ez, px, pz, rl)
+    tx = rl * np.cos(phi)
+    tz = -rl * np.sin(phi)
+    d1 = ((lx - ex) * tx + (lz - ez) * tz) / np.where(l1 > 0, l1, 1.0)
+    d2 = ((lx - px) * tx + (lz - pz) * tz) / np.where(l2 > 0, l2, 1.0)
+    return d1 / c_lens + d2 / c_med
+
+
+def refract(elem_xz: np.ndarray, d_lens: float, c_lens: float, c_med: float,
+            pts: np.ndarray, n_scan: int = 129, n_bisect: int = 64,
+            pairs: tuple[np.ndarray, np.ndarray] | None = None):
+    """Refraction point and legs for every (element, point) ray.
+
+    ``pts`` is [P][2].  Without ``pairs`` every element-point combination is
+    solved and the outputs are [N][P]; with ``pairs = (a_idx, p_idx)`` only
+    those rays are solved and the outputs are 1-D.
+
+    Returns dict(phi, l1, l2, t_hom, ref_x, ref_z): refraction angle on the
+    lens arc, lens leg, medium leg, homogeneous travel time l1/c_lens + l2/c_med
+    and the refraction point.
+    """
+    ex_all = np.asarray(elem_xz[:, 0], dtype=np.float64)
+    ez_all = np.asarray(elem_xz[:, 1], dtype=np.float64)
+    if pairs is None:
+        ex = ex_all[:, None] * np.ones((1, pts.shape[0]))
+        ez = ez_all[:, None] * np.ones((1, pts.shape[0]))
+        px = np.ones((elem_xz.shape[0], 1)) * pts[None, :, 0]
+        pz = np.ones((elem_xz.shape[0], 1)) * pts[None, :, 1]
+    else:
+        ai, pi = pairs
+        ex, ez = ex_all[ai], ez_all[ai]
+        px, pz = pts[pi, 0], pts[pi, 1]
+    shape = ex.shape
+    ex, ez, px, pz = (v.ravel().astype(np.float64) for v in (ex, ez, px, pz))
+    ra = np.hypot(ex, ez)
+    rl = ra + d_lens
+    th_a = np.arctan2(ex, ez)
+    th_p = np.arctan2(px, pz)
+    lo = np.minimum(th_a, th_p)
+    hi = np.maximum(th_a, th_p)
+
+    # scan
+    k = np.arange(n_scan) / (n_scan - 1)
+    phis = lo[:, None] + (hi - lo)[:, None] * k[None, :]
+    tt = travel_time_via(phis, ex[:, None], ez[:, None], px[:, None], pz[:, None],
+                         rl[:, None], c_lens, c_med)
+    best = np.argmin(tt, axis=1)
+    b_lo = phis[np.arange(phis.shape[0]), np.maximum(best - 1, 0)]
+    b_hi = phis[np.arange(phis.shape[0]), np.minimum(best + 1, n_scan - 1)]
+
+    # bisect the sign of dT/dphi (a minimum has dT < 0 to its left, > 0 to its right)
+    a_ = b_lo.copy()
+    b_ = b_hi.copy()
+    d_a = _dT(a_, ex, ez, px, pz, rl, c_lens, c_med)
+    d_b = _dT(b_, ex, ez, px, pz, rl, c_lens, c_med)
+    interior = (d_a < 0) & (d_b > 0)
+    for _ in range(n_bisect):
+        m = 0.5 * (a_ + b_)
+        dm = _dT(m, ex, ez, px, pz, rl, c_lens, c_med)
+        go_right = dm < 0
+        a_ = np.where(interior & go_right, m, a_)
+        b_ = np.where(interior & ~go_right, m, b_)
+    phi = np.where(interior, 0.5 * (a_ + b_), phis[np.arange(phis.shape[0]), best])
+    # end-point minima (degenerate or monotone brackets) keep the best scanned end
+    lx, lz, l1, l2 = _legs(phi, ex, ez, px, pz, rl)
+    out = dict(phi=phi, l1=l1, l2=l2, t_hom=l1 / c_lens + l2 / c_med, ref_x=lx, ref_z=lz)
+    return {k_: v.reshape(shape) for k_, v in out.items()}
+
+
+def brute_refract(elem_xz, d_lens, c_lens, c_med, pts, n_points=200001):
+    """Minimum of T over ``n_points`` evenly spaced lens points spanning the whole
+    element-to-point angular interval (pin for small cases only)."""
+    res = np.empty((elem_xz.shape[0], pts.shape[0]))
+    arg = np.empty_like(res)
+    for a in range(elem_xz.shape[0]):
+        ex, ez = elem_xz[a]
+        ra = np.hypot(ex, ez)
+        rl = ra + d_lens
+        th_a = np.arctan2(ex, ez)
+        for p in range(pts.shape[0]):
+            px, pz = pts[p]
+            th_p = np.arctan2(px, pz)
+            phis = np.linspace(min(th_a, th_p), max(th_a, th_p), n_points)
+            tt = travel_time_via(phis, ex, ez, px, pz, rl, c_lens, c_med)
+            i = int(np.argmin(tt))
+            res[a, p] = tt[i]
+            arg[a, p] = phis[i]
+    return res, arg

@@ -1,0 +1,77 @@
+"""Pins of the oracle's lens refraction (Eq. 8) against closed forms, Snell's law
+written with angles, and brute force over lens points."""
+import json
+import math
+import os
+
+import numpy as np
+
+import afsynth
+from oracle import fermat
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+
+
+def _setup(n=4, R=49.6, pitch=0.5083, d=0.90, n_pts=16, seed=0):
+    elem = afsynth.element_positions(afsynth.ArrayCfg(n, R, pitch, d, 1.0))
+    rng = np.random.default_rng(seed)
+    rl = R + d
+    rho = rl + rng.uniform(0.5, 60.0, n_pts)
+    th = rng.uniform(-0.4, 0.4, n_pts)
+    pts = np.stack([rho * np.sin(th), rho * np.cos(th)], axis=1)
+    return elem, pts
+
+
+def test_zero_thickness_is_straight_ray():
+    elem, pts = _setup()
+    r = fermat.refract(elem, 0.0, 0.9994, 1.54, pts)
+    d = np.hypot(pts[None, :, 0] - elem[:, None, 0], pts[None, :, 1] - elem[:, None, 1])
+    assert np.allclose(r["t_hom"], d / 1.54, rtol=1e-13, atol=0)
+
+
+def test_equal_speeds_is_straight_ray():
+    elem, pts = _setup()
+    r = fermat.refract(elem, 0.9, 1.54, 1.54, pts)
+    d = np.hypot(pts[None, :, 0] - elem[:, None, 0], pts[None, :, 1] - elem[:, None, 1])
+    assert np.allclose(r["t_hom"], d / 1.54, rtol=1e-12, atol=0)
+
+
+def test_radial_closed_form_table1_lens():
+    # Table I, C5-2v (Phantoms): c_lens 999.4 m/s, d_lens 0.90 mm
+    c_lens, d_lens = [GOLD["table1_lens_calibration"]["C5-2v (Phantoms)"][i] for i in (0, 1)]
+    c_lens /= 1000.0
+    elem, _ = _setup(n=5, d=d_lens)
+    R = float(np.hypot(*elem[0]))
+    th = np.arctan2(elem[:, 0], elem[:, 1])
+    depth = np.array([3.0, 40.0])
+    pts = np.concatenate([np.stack([(R + d_lens + dd) * np.sin(th), (R + d_lens + dd) * np.cos(th)], 1)
+                          for dd in depth])
+    r = fermat.refract(elem, d_lens, c_lens, 1.54, pts)
+    for k, dd in enumerate(depth):
+        for a in range(5):
+            p = k * 5 + a
+            assert abs(r["t_hom"][a, p] - (d_lens / c_lens + dd / 1.54)) < 1e-12
+            assert abs(r["phi"][a, p] - th[a]) < 1e-12
+
+
+def test_snell_law_at_refraction_point():
+    elem, pts = _setup(n=6, n_pts=40, seed=3)
+    c_lens, c_med = 0.9994, 1.52
+    r = fermat.refract(elem, 0.9, c_lens, c_med, pts)
+    for a in range(elem.shape[0]):
+        for p in range(pts.shape[0]):
+            lx, lz = r["ref_x"][a, p], r["ref_z"][a, p]
+            normal = math.atan2(lx, lz)
+            inc = math.atan2(lx - elem[a, 0], lz - elem[a, 1]) - normal
+            out = math.atan2(pts[p, 0] - lx, pts[p, 1] - lz) - normal
+            assert abs(math.sin(inc) / c_lens - math.sin(out) / c_med) < 1e-9
+
+
+def test_brute_force_tiny():
+    elem, pts = _setup(n=4, n_pts=16, seed=1)
+    r = fermat.refract(elem, 0.9, 0.9994, 1.48, pts)
+    tb, _ = fermat.brute_refract(elem, 0.9, 0.9994, 1.48, pts, n_points=400001)
+    # the continuous minimiser can only be lower than a discrete search, and only by
+    # the discretisation error (quadratic in the lens-point spacing)
+    assert np.all(r["t_hom"] <= tb + 1e-13)
+    assert np.max(tb - r["t_hom"]) < 1e-9
