@@ -1,0 +1,188 @@
+/*
+ * af.h -- C ABI of the MI355X (gfx950) lens-aware differentiable beamformer.
+ *
+ * The library evaluates, at every optimiser step, the hot path of lens-aware
+ * ultrasound autofocusing (Frey et al., "Lens-Aware Differentiable Beamforming
+ * for In Vivo Distributed Aberration Correction with Curvilinear Transducers"):
+ *   bent-ray travel times (Fermat refraction through the lens, Eqs. 7-8, then
+ *   the bicubic path integral of slowness, Eq. 1 and Section III-A), complex-IQ
+ *   delay-and-sum over transmit x receive x point with phase rotation (Eq. 5),
+ *   the common-midpoint phase-error loss with deadzone regularisers (Eqs. 10-12)
+ *   and, by hand-written adjoints, its gradient with respect to the slowness grid.
+ *
+ * Conventions
+ *   Units: mm, microseconds, MHz; speed in mm/us, slowness in us/mm.
+ *   Coordinates: origin at the array's centre of curvature, x lateral, z into
+ *   the body.  Host arrays are read during the call and never retained; device
+ *   pointers are caller-owned and must stay valid until the work enqueued on
+ *   the context's stream has finished.  Every call that takes device pointers
+ *   only enqueues work on that stream (no host synchronisation); results are
+ *   visible after the caller synchronises the stream.
+ *   Complex data are interleaved float pairs (re, im).
+ *   Errors: every call returns an af_status; nothing throws across the ABI.
+ *   af_last_error() gives a human-readable reason for the last failure.
+ *   A context is not thread-safe; use one per host thread / stream.
+ */
+#ifndef AF_H_
+#define AF_H_
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct af_ctx af_ctx;
+
+typedef enum {
+  AF_OK = 0,
+  AF_ERR_ARG = -1,      /* invalid argument (sizes, geometry, coverage) */
+  AF_ERR_STATE = -2,    /* call out of order (e.g. beamform before set_slowness) */
+  AF_ERR_HIP = -3,      /* HIP runtime error; see af_last_error */
+  AF_ERR_OOM = -4,      /* device allocation failed */
+  AF_ERR_NUMERIC = -5   /* non-finite input slowness */
+} af_status;
+
+typedef struct { float x, y; } af_complex;
+
+/* Objective weights (Eq. 12 plus an optional speckle-brightness term).
+ * total = L_CMPE + w1 R_TV + w2 R_SV - w_sb * SB / sb_ref. */
+typedef struct {
+  float w1, kx1, kz1;     /* first-order deadzone weight and thresholds (Eq. 10) */
+  float w2, kx2, kz2;     /* second-order deadzone weight and thresholds (Eq. 11) */
+  float rho_thresh;       /* correlation threshold of a valid CMPE pair */
+  float w_sb, sb_ref;     /* speckle-brightness weight and reference (sb_ref > 0) */
+} af_loss_params;
+
+typedef struct { float lr, beta1, beta2, eps; } af_adam_params;
+
+/* Layout of the terms vector written by forward / loss_and_grad / autofocus_step. */
+enum {
+  AF_TERM_CMPE = 0, AF_TERM_TV = 1, AF_TERM_SV = 2, AF_TERM_SB = 3,
+  AF_TERM_TOTAL = 4, AF_TERM_NVALID = 5, AF_TERM_CMED = 6, AF_N_TERMS = 8
+};
+
+/* Create a context on HIP device `device`, enqueueing on `stream` (a hipStream_t;
+ * NULL = the null stream).  Errors: AF_ERR_ARG (bad device), AF_ERR_HIP. */
+af_status af_create(af_ctx** out, int device, void* stream);
+/* Free every device buffer the context owns.  Safe on NULL. */
+void af_destroy(af_ctx* ctx);
+/* Last error text of `ctx` (static string if ctx is NULL); never NULL. */
+const char* af_last_error(const af_ctx* ctx);
+
+/* Static acquisition and imaging geometry (Section II-A, Eqs. 2-5; Section III-A).
+ *   elem_xz   [n_elem][2] element centres (host, float64), on a circular arc
+ *             centred at the origin; element orientation follows Eq. 3.
+ *   pix_xz    [n_pix][2] patch centres (host, float64); each patch is a
+ *             patch x patch kernel of points at patch_spacing (lambda/2), point m
+ *             offset by ((m % patch - patch/2), (m / patch - patch/2)) * spacing.
+ *   n_samples, fs, t0, fd: channel-data samples per record, sampling rate,
+ *             time of sample 0 and demodulation frequency of Eq. 5.
+ *   block     S, elements per block; subapertures span two blocks (stride S).
+ *   fnum      F of the apodisation |x'| <= (F/2) z' (Eq. 4, literal form).
+ *   n_seg     ray segments after the lens (N_segments).
+ * Caller order of points: p = q * patch^2 + m for pixel q, patch point m.
+ * Errors: AF_ERR_ARG if n_elem < 3, block does not divide n_elem, patch is not
+ * 1 or 3, sizes are not positive, the active element set of a point is not
+ * contiguous, or a tile spans more than 17 active blocks. */
+af_status af_set_geometry(af_ctx* ctx, int n_elem, const double* elem_xz, int n_pix,
+                    const double* pix_xz, int patch, double patch_spacing,
+                    int n_samples, double fs, double t0, double fd, int block,
+                    double fnum, int n_seg);
+
+/* Lens of the bent-ray model (Eqs. 7-8): thickness d_lens (elements sit that far
+ * behind the concentric lens arc), lens speed c_lens, time-to-peak t_ttp added
+ * to every round trip.  Errors: AF_ERR_ARG for d_lens < 0 or c_lens <= 0. */
+af_status af_set_lens(af_ctx* ctx, double d_lens, double c_lens, double t_ttp);
+
+/* Slowness grid s ~ 1/c (Section III-A): node (i, j) at (x0 + j dx, z0 + i dz),
+ * values [nz][nx] float32 at `s_dev` (device), copied on the context stream.
+ * The grid box must contain every evaluation point and the lens arc over the
+ * angles of the elements and points (AF_ERR_ARG otherwise); needs geometry and
+ * lens first (AF_ERR_STATE).  Non-finite or non-positive values are reported as
+ * AF_ERR_NUMERIC by the next loss call's terms (total = NaN). */
+af_status af_set_slowness(af_ctx* ctx, int nx, int nz, double x0, double z0, double dx,
+                    double dz, const float* s_dev);
+
+/* Beamform at the current slowness (Eq. 5).  iq_dev: [n_elem][n_elem][n_samples]
+ * demodulated FSA data (device), transmit-major.  Optional outputs (NULL = skip):
+ *   blk_dev  [Nb][Nb][P] block-pair images B^blk[i][j](p), Nb = n_elem / block;
+ *   img_dev  [P] full-aperture image (sum over all block pairs);
+ *   maps_dev [2][n_pix] integrated CMPE (per-pixel mean phase error over valid
+ *            pairs) and coherence factor at the patch centres.
+ * Point order is the caller's (see af_set_geometry).  The CMPE map uses
+ * rho_thresh from the most recent loss call (default 0.9). */
+af_status af_beamform(af_ctx* ctx, const af_complex* iq_dev, af_complex* blk_dev,
+                af_complex* img_dev, float* maps_dev);
+
+/* Loss (Eq. 12, CMPE + regularisers - speckle term) and, if grad_dev != NULL,
+ * its gradient dL/ds [nz][nx] (device, overwritten).  terms_dev: float[8]
+ * (device), see AF_TERM_*.  Refraction points, c_med, apodisation and validity
+ * masks are held constant in the gradient. */
+af_status af_loss_and_grad(af_ctx* ctx, const af_complex* iq_dev, const af_loss_params* lp,
+                     float* terms_dev, float* grad_dev);
+
+/* Forward half of loss_and_grad for a split autograd: writes the terms and
+ * gblk_dev [Nb][Nb][P_internal] (device, size from af_query(AF_Q_GBLK_ELEMS)),
+ * the loss gradient with respect to the block images in the library's internal
+ * point order.  No travel-time table outlives the call. */
+af_status af_forward(af_ctx* ctx, const af_complex* iq_dev, const af_loss_params* lp,
+               float* terms_dev, af_complex* gblk_dev);
+
+/* Backward half: recomputes the travel-time table at the current slowness, runs
+ * the DAS adjoint with gblk_dev (from af_forward at the same slowness) and the
+ * path adjoint, adds the regulariser gradient, and writes grad_dev [nz][nx]. */
+af_status af_backward(af_ctx* ctx, const af_complex* iq_dev, const af_loss_params* lp,
+                const af_complex* gblk_dev, float* grad_dev);
+
+/* One plain-method iteration: loss_and_grad at s_dev, then an Adam step (the
+ * paper's Eq. 9 uses plain descent; Adam replaces it here) updating s_dev, m_dev,
+ * v_dev ([nz][nx], device, in place).  step is 1-based.  The context's slowness
+ * becomes the updated s. */
+af_status af_autofocus_step(af_ctx* ctx, const af_complex* iq_dev, const af_loss_params* lp,
+                      const af_adam_params* ap, int step, float* s_dev, float* m_dev,
+                      float* v_dev, float* terms_dev);
+
+/* One-way travel times T[a][p] (us) at the current slowness, caller point
+ * order, float32 [n_elem][P] (device); entries outside the apodisation are NaN. */
+af_status af_travel_times(af_ctx* ctx, float* t_dev);
+
+/* Channel-data simulator: point scatterers in a true slowness map, echoes at the
+ * bent-ray round-trip times (same ray model, `n_seg` segments, refraction at the
+ * node-mean speed), baseband Gaussian envelope of -6 dB fractional bandwidth
+ * frac_bw truncated at 6 sigma, phase exp(-j 2 pi fd tau).  Uses the geometry,
+ * lens and acquisition of af_set_geometry / af_set_lens.
+ *   scat_xz [n_scat][2] float64, amp [n_scat] float32 (host);
+ *   s_true_dev [nz][nx] float32 (device) on the node grid (x0, z0, dx, dz);
+ *   iq_dev [n_elem][n_elem][n_samples] output (device, overwritten). */
+af_status af_simulate(af_ctx* ctx, int n_scat, const double* scat_xz, const float* amp,
+                int nx, int nz, double x0, double z0, double dx, double dz,
+                const float* s_true_dev, int n_seg, double fc, double frac_bw,
+                af_complex* iq_dev);
+
+/* Kernel timing with HIP events on the context stream.  While enabled, every
+ * kernel the library launches is bracketed by two events; af_profile_read waits
+ * for the stream, returns the summed milliseconds and launch counts per kernel
+ * family (arrays of AF_K_COUNT entries, host) and clears the record. */
+enum {
+  AF_K_PREPARE = 0, AF_K_TABLE = 1, AF_K_DAS_FWD = 2, AF_K_CMPE = 3, AF_K_FINALIZE = 4,
+  AF_K_GSCALE = 5, AF_K_DAS_ADJ = 6, AF_K_PATH_ADJ = 7, AF_K_FOLD = 8, AF_K_ADAM = 9,
+  AF_K_EXPORT = 10, AF_K_COUNT = 11
+};
+af_status af_set_profiling(af_ctx* ctx, int enable);
+af_status af_profile_read(af_ctx* ctx, double* ms, long long* calls);
+
+/* Sizes and diagnostics. */
+enum {
+  AF_Q_P = 0,            /* caller points n_pix * patch^2 */
+  AF_Q_P_INTERNAL = 1,   /* internal (tiled, padded) points */
+  AF_Q_NBLK = 2,         /* blocks per aperture */
+  AF_Q_GBLK_ELEMS = 3,   /* complex elements of gblk_dev for af_forward */
+  AF_Q_ACTIVE_PAIRS = 4, /* sum over points of active elements (rays) */
+  AF_Q_ACTIVE_SAMPLES = 5, /* sum over points of active (t, r) pairs */
+  AF_Q_TILES = 6
+};
+af_status af_query(af_ctx* ctx, int what, long long* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AF_H_ */

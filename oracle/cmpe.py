@@ -16,7 +16,10 @@ at hand, so this module implements a reading of the translating-aperture idea:
 * the two images of a common-midpoint neighbour pair are X = B_{i,j+1} and
   Y = B_{i+1,j} (both have midpoint (i + j + 1)/2), i, j = 0..Nsub-2;
 * per patch q: C = sum_m X_m conj(Y_m), rho = |C| / sqrt(sum|X|^2 sum|Y|^2);
-  the pair is valid when both energies are positive and rho >= rho_thresh;
+  the pair is valid when both energies exceed MIN_ENERGY = 1e-30 (the smallest
+  energy whose pair phase is still differentiable in FP32, where |C|^2 would
+  otherwise underflow; any image of physical size is far above it) and
+  rho >= rho_thresh;
   its phase error is |arg C| (radians);
 * L_CMPE = mean of |arg C| over valid (patch, pair) entries (0 if none);
 * the integrated CMPE map is the per-patch mean over its valid pairs;
@@ -27,6 +30,8 @@ Points are stored pixel-major: point p = q * M + m for patch point m of pixel q.
 from __future__ import annotations
 
 import numpy as np
+
+MIN_ENERGY = 1e-30
 
 
 def subaperture_images(bblk: np.ndarray) -> np.ndarray:
@@ -61,7 +66,7 @@ def cmpe(bsub: np.ndarray, n_patch: int, rho_thresh: float):
     C = np.sum(X * np.conj(Y), axis=-1)
     ex = np.sum(np.abs(X) ** 2, axis=-1)
     ey = np.sum(np.abs(Y) ** 2, axis=-1)
-    pos = (ex > 0) & (ey > 0)
+    pos = (ex > MIN_ENERGY) & (ey > MIN_ENERGY)
     rho = np.where(pos, np.abs(C) / np.sqrt(np.where(pos, ex * ey, 1.0)), 0.0)
     valid = pos & (rho >= rho_thresh)
     err = np.abs(np.angle(C))

@@ -1,0 +1,228 @@
+"""Autofocus driver over the library.
+
+* ``Beamformer`` owns one library context for an acquisition (array, lens,
+  channel-data format), an evaluation grid and a slowness grid;
+* ``CmpeLoss`` is a ``torch.autograd.Function``: its forward runs the library's
+  forward pass (travel times, DAS, CMPE, regularisers) and keeps only the
+  gradient with respect to the block images; its backward recomputes the
+  travel-time table and runs the hand-written adjoints;
+* ``sweep`` is the global-speed initialisation with the dynamic CMPE grid and
+  ``plain_autofocus`` the plain iterative method (Sections II-C and III-A of the
+  paper; the optimiser is Adam instead of the plain descent of Eq. 9).
+
+Every numerical step runs in libaf.so; this module only moves arguments.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+@dataclass
+class Acquisition:
+    elem_xz: np.ndarray      # [N][2] mm, centre of curvature at the origin
+    d_lens: float            # mm
+    c_lens: float            # mm/us
+    t_ttp: float             # us
+    fs: float                # MHz
+    t0: float                # us
+    fd: float                # MHz (demodulation = centre frequency)
+    n_samples: int
+
+
+@dataclass
+class Imaging:
+    centres: np.ndarray      # [n_pix][2] patch centres, mm
+    patch: int               # 1 or 3
+    spacing: float           # mm (lambda/2)
+    block: int               # S
+    fnum: float              # F of |x'| <= (F/2) z'
+    n_seg: int
+
+
+@dataclass
+class Grid:
+    nx: int
+    nz: int
+    x0: float
+    z0: float
+    dx: float
+    dz: float
+
+    @property
+    def shape(self):
+        return (self.nz, self.nx)
+
+
+def lens_radius(acq: Acquisition) -> float:
+    return float(np.hypot(acq.elem_xz[0, 0], acq.elem_xz[0, 1])) + acq.d_lens
+
+
+def scaled_imaging(img: Imaging, acq: Acquisition, c_g: float, c_ref: float, fc: float) -> Imaging:
+    """Dynamic CMPE grid at speed c_g: every pixel's depth below the lens surface is
+    stretched by c_g/c_ref along its polar angle and the kernel spacing becomes
+    lambda_g/2 = c_g/(2 fc), so the same time samples are observed."""
+    rl = lens_radius(acq)
+    rho = np.hypot(img.centres[:, 0], img.centres[:, 1])
+    th = np.arctan2(img.centres[:, 0], img.centres[:, 1])
+    rho_g = rl + (rho - rl) * (c_g / c_ref)
+    cen = np.stack([rho_g * np.sin(th), rho_g * np.cos(th)], axis=1)
+    return replace(img, centres=cen, spacing=c_g / (2.0 * fc))
+
+
+class Beamformer:
+    """Library context bound to one acquisition, evaluation grid and slowness grid."""
+
+    def __init__(self, acq: Acquisition, img: Imaging, grid: Grid, device: int = 0):
+        self.acq, self.grid = acq, grid
+        self.device = torch.device("cuda", device)
+        self.ctx = _lib.Context(device)
+        self.ctx.set_lens(acq.d_lens, acq.c_lens, acq.t_ttp)
+        self.img = None
+        self.set_imaging(img)
+        self.s = None
+
+    def set_imaging(self, img: Imaging):
+        a = self.acq
+        self.ctx.set_geometry(a.elem_xz, img.centres, img.patch, img.spacing, a.n_samples, a.fs,
+                              a.t0, a.fd, img.block, img.fnum, img.n_seg)
+        self.img = img
+        if getattr(self, "s", None) is not None:
+            self.set_slowness(self.s)
+
+    def set_slowness(self, s: torch.Tensor):
+        g = self.grid
+        s = s.detach().to(self.device, torch.float32).contiguous()
+        self.ctx.set_slowness(g.nx, g.nz, g.x0, g.z0, g.dx, g.dz, s)
+        self.s = s
+
+    @property
+    def n_points(self) -> int:
+        return self.ctx.query(_lib.Q_P)
+
+    @property
+    def n_blk(self) -> int:
+        return self.ctx.query(_lib.Q_NBLK)
+
+    def empty_terms(self):
+        return torch.zeros(_lib.N_TERMS, device=self.device, dtype=torch.float32)
+
+    def loss_and_grad(self, iq, lp, s=None, want_grad=True):
+        if s is not None:
+            self.set_slowness(s)
+        terms = self.empty_terms()
+        grad = torch.empty(self.grid.shape, device=self.device) if want_grad else None
+        self.ctx.loss_and_grad(iq, lp, terms, grad)
+        return terms, grad
+
+    def beamform(self, iq, s=None, blocks=False, maps=True):
+        if s is not None:
+            self.set_slowness(s)
+        P = self.n_points
+        nb = self.n_blk
+        img = torch.empty(P, device=self.device, dtype=torch.complex64)
+        mp = torch.empty(2 * self.img.centres.shape[0], device=self.device) if maps else None
+        blk = torch.empty(nb * nb * P, device=self.device, dtype=torch.complex64) if blocks else None
+        self.ctx.beamform(iq, blk, img, mp)
+        return img, mp, blk
+
+    def travel_times(self, s=None):
+        if s is not None:
+            self.set_slowness(s)
+        out = torch.empty(self.acq.elem_xz.shape[0] * self.n_points, device=self.device)
+        self.ctx.travel_times(out)
+        return out.view(self.acq.elem_xz.shape[0], self.n_points)
+
+
+class CmpeLoss(torch.autograd.Function):
+    """total = L_CMPE + w1 R_TV + w2 R_SV - w_sb SB/SB_ref as a function of the slowness.
+
+    forward keeps only dL/dB^blk (no travel-time table); backward recomputes the
+    table at the same slowness and runs the DAS and path adjoints."""
+
+    @staticmethod
+    def forward(ctx, s, bf: Beamformer, iq, lp):
+        bf.set_slowness(s)
+        terms = bf.empty_terms()
+        gblk = torch.empty(bf.ctx.query(_lib.Q_GBLK_ELEMS), device=bf.device, dtype=torch.complex64)
+        bf.ctx.forward(iq, lp, terms, gblk)
+        ctx.bf, ctx.iq, ctx.lp, ctx.gblk = bf, iq, lp, gblk
+        ctx.save_for_backward(s)
+        ctx.mark_non_differentiable(terms)
+        return terms[_lib.TERM_TOTAL].clone(), terms
+
+    @staticmethod
+    def backward(ctx, g_total, g_terms):
+        (s,) = ctx.saved_tensors
+        bf = ctx.bf
+        bf.set_slowness(s)
+        grad = torch.empty(bf.grid.shape, device=bf.device)
+        bf.ctx.backward(ctx.iq, ctx.lp, ctx.gblk, grad)
+        return (g_total * grad).view_as(s), None, None, None
+
+
+def cmpe_loss(s: torch.Tensor, bf: Beamformer, iq: torch.Tensor, lp) -> tuple:
+    """(total, terms) with total differentiable in ``s`` through the library's adjoint."""
+    return CmpeLoss.apply(s, bf, iq, lp)
+
+
+def sweep_speeds(lo=1.340, hi=1.740, step=0.010) -> np.ndarray:
+    n = int(round((hi - lo) / step)) + 1
+    return lo + step * np.arange(n)
+
+
+def sweep(bf: Beamformer, iq, lp, fc: float, c_ref: float = 1.540, speeds=None, dynamic=True):
+    """CMPE of homogeneous speeds over the (dynamic) grid.  Leaves ``bf`` on the grid
+    of the best speed with a uniform slowness.  Returns (speeds, values, best)."""
+    speeds = sweep_speeds() if speeds is None else np.asarray(speeds)
+    base = bf.img
+    vals = []
+    terms = bf.empty_terms()
+    for c_g in speeds:
+        img = scaled_imaging(base, bf.acq, float(c_g), c_ref, fc) if dynamic else base
+        bf.set_imaging(img)
+        bf.set_slowness(torch.full(bf.grid.shape, 1.0 / float(c_g), device=bf.device))
+        bf.ctx.loss_and_grad(iq, lp, terms, None)
+        vals.append(float(terms[_lib.TERM_CMPE].item()))
+    vals = np.array(vals)
+    best = float(speeds[int(np.argmin(vals))])
+    bf.set_imaging(scaled_imaging(base, bf.acq, best, c_ref, fc) if dynamic else base)
+    bf.set_slowness(torch.full(bf.grid.shape, 1.0 / best, device=bf.device))
+    return speeds, vals, best
+
+
+@dataclass
+class History:
+    terms: list = field(default_factory=list)
+    times: list = field(default_factory=list)
+
+
+def plain_autofocus(bf: Beamformer, iq, lp, ap, n_iter: int, s0: torch.Tensor | None = None,
+                    record_every: int = 1, stop_below: float | None = None):
+    """Adam iterations of the plain method from ``s0`` (default: the context's slowness).
+
+    Returns (s, History).  With ``stop_below`` the loop stops at the first
+    iteration whose CMPE is at or below it (the terms of every iteration are read
+    back only when a stop criterion or recording needs them)."""
+    s = (bf.s if s0 is None else s0).detach().clone().to(bf.device, torch.float32).contiguous()
+    m = torch.zeros_like(s)
+    v = torch.zeros_like(s)
+    terms = bf.empty_terms()
+    hist = History()
+    t_start = time.perf_counter()
+    for it in range(1, n_iter + 1):
+        bf.ctx.autofocus_step(iq, lp, ap, it, s, m, v, terms)
+        if stop_below is not None or (record_every and it % record_every == 0):
+            t = terms.cpu().numpy().copy()
+            hist.terms.append(t)
+            hist.times.append(time.perf_counter() - t_start)
+            if stop_below is not None and t[_lib.TERM_CMPE] <= stop_below:
+                break
+    bf.s = s
+    return s, hist

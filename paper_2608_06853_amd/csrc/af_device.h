@@ -1,0 +1,170 @@
+// Device-side building blocks shared by the HIP kernels of the library:
+// the two-layer lens refraction (Fermat's principle, Eqs. 7-8), the Keys
+// bicubic weights and the trapezoid path sum of the slowness deviation
+// (Eq. 1 discretised as in Section III-A).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace af {
+
+constexpr int TILE = 256;           // points per tile = threads of a DAS workgroup
+constexpr int SUB = 64;             // points per CMPE sub-tile = one wavefront
+constexpr int MAX_NBA = 16;         // active blocks per tile the CMPE kernel supports
+constexpr int SENTINEL = -(1 << 29);  // sample index of a masked (element, point) entry
+
+// One travel-time table entry: sample position u = ui + uf of (T + t_ttp/2 - t0/2) * fs
+// and the apodised phasor h * exp(j 2 pi fd (T + t_ttp/2)).
+struct alignas(16) TabEntry {
+  int ui;
+  float uf;
+  float er, ei;
+};
+
+struct RayOut {
+  double t_hom;   // L1/c_lens + L2/c_med at the refraction point
+  float refx;     // refraction point on the lens arc (global frame)
+  float refz;
+  float l2;       // medium leg length
+};
+
+// Fermat ray through the concentric lens.  Element: radius R, polar unit vector
+// (sa, ca) = (sin, cos) of its polar angle.  Point: radius rho, polar unit vector
+// (sp, cp).  icl, icm: 1/c_lens and 1/c_med.
+//
+// The stationary point of T is found in the local frame of the element (element
+// on the z axis) by safeguarded FP32 Newton on the Snell residual
+//   G(alpha) = sin(i1)/c_lens - sin(i2)/c_med,
+// where alpha is the direction of the lens leg; G is close to linear in alpha.
+// The lens point is then projected onto the arc in FP64 and one FP64 second-order
+// step on T(phi) gives T at the stationary point (error O(dphi^3)) and the
+// refined refraction point.
+__device__ inline RayOut trace_lens(double R, double sa, double ca, double rho, double sp,
+                                    double cp, double dlens, double icl, double icm) {
+  const double RL = R + dlens;
+  const double cT = cp * ca + sp * sa;   // cos(theta_p - theta_a)
+  double sT = sp * ca - cp * sa;         // sin(theta_p - theta_a)
+  const double sgn = sT < 0.0 ? -1.0 : 1.0;
+  sT = fabs(sT);
+
+  const float Rf = (float)R;
+  const float RLf = (float)RL;
+  const float d2f = (float)((RL - R) * (RL + R));
+  const float pxf = (float)(rho * sT);
+  const float pzf = (float)(rho * cT);
+  const float iclf = (float)icl, icmf = (float)icm;
+  const float irl = (float)(1.0 / RL);
+
+  float lo = 0.f;
+  float hi = atan2f(pxf, pzf - Rf);   // straight direction from the element to the point
+  // thin-lens guess: Snell at the lens apex above the element
+  float vz0 = pzf - RLf;
+  float si2g = pxf * rsqrtf(fmaxf(pxf * pxf + vz0 * vz0, 1e-30f));
+  float si1g = fminf(fmaxf(si2g * (icmf / iclf), 0.f), 0.95f);
+  float x = fminf(fmaxf(asinf(si1g), lo), hi);
+  float lx = 0.f, lz = Rf + (float)(RL - R);
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    float s, c;
+    if (it < 3) {
+      s = __sinf(x);
+      c = __cosf(x);
+    } else {
+      sincosf(x, &s, &c);
+    }
+    const float Q = sqrtf(Rf * Rf * c * c + d2f);
+    const float iQ = 1.f / Q;
+    const float L1 = d2f / (Rf * c + Q);
+    const float dL1 = Rf * s * L1 * iQ;
+    lx = L1 * s;
+    lz = Rf + L1 * c;
+    const float dlx = dL1 * s + L1 * c;
+    const float dlz = dL1 * c - L1 * s;
+    const float nx = lx * irl, nz = lz * irl, dnx = dlx * irl, dnz = dlz * irl;
+    const float si1 = s * nz - c * nx;
+    const float dsi1 = (c * nz + s * nx) + (s * dnz - c * dnx);
+    const float vx = pxf - lx, vz = pzf - lz;
+    const float iL2 = rsqrtf(vx * vx + vz * vz);
+    const float cr = vx * nz - vz * nx;
+    const float dcr = (-dlx * nz + dlz * nx) + (vx * dnz - vz * dnx);
+    const float vdv = -(vx * dlx + vz * dlz);
+    const float si2 = cr * iL2;
+    const float dsi2 = dcr * iL2 - cr * vdv * iL2 * iL2 * iL2;
+    const float g = si1 * iclf - si2 * icmf;
+    const float dg = dsi1 * iclf - dsi2 * icmf;
+    if (it == 3) break;  // (lx, lz) is the lens point at the converged alpha
+    if (g < 0.f) lo = x; else hi = x;
+    const float nw = x - g / dg;
+    x = (nw >= lo && nw <= hi) ? nw : 0.5f * (lo + hi);
+  }
+
+  // FP64: project onto the arc, one second-order step in phi
+  const double lxd = lx, lzd = lz;
+  const double inv = 1.0 / sqrt(lxd * lxd + lzd * lzd);
+  const double s = lxd * inv, c = lzd * inv;       // sin, cos of phi'
+  const double omc = s * s / (1.0 + c);            // 1 - cos(phi')
+  const double dd = RL - R;
+  const double l1sq = dd * dd + 2.0 * R * RL * omc;
+  const double cw = cT * c + sT * s;               // cos(Theta - phi')
+  const double sw = sT * c - cT * s;               // sin(Theta - phi')
+  const double omw = cw > 0.0 ? sw * sw / (1.0 + cw) : 1.0 - cw;
+  const double hh = rho - RL;
+  const double l2sq = hh * hh + 2.0 * rho * RL * omw;
+  const double L1 = sqrt(l1sq), L2 = sqrt(l2sq);
+  const double i1 = 1.0 / L1, i2 = 1.0 / L2;
+  const double d1 = R * RL * s * i1;
+  const double d2 = -rho * RL * sw * i2;
+  const double Tp = d1 * icl + d2 * icm;
+  const double Tpp = (R * RL * c - d1 * d1) * i1 * icl + (rho * RL * cw - d2 * d2) * i2 * icm;
+  const double del = Tpp > 0.0 ? -Tp / Tpp : 0.0;
+  RayOut o;
+  o.t_hom = L1 * icl + L2 * icm + 0.5 * Tp * del;
+  // refined refraction point (first-order rotation by del) in the global frame
+  const double cs = c - s * del, ss = (s + c * del) * sgn;
+  o.refx = (float)(RL * (sa * cs + ca * ss));
+  o.refz = (float)(RL * (ca * cs - sa * ss));
+  o.l2 = (float)(L2 + d2 * del);
+  return o;
+}
+
+// Keys cubic-convolution weights (a = -0.5) of the taps at offsets -1, 0, 1, 2
+// for fractional position f in [0, 1].
+__device__ inline void keys_weights(float f, float& w0, float& w1, float& w2, float& w3) {
+  const float f2 = f * f;
+  w0 = f * (-0.5f + f * (1.0f - 0.5f * f));
+  w1 = 1.0f + f2 * (-2.5f + 1.5f * f);
+  w2 = f * (0.5f + f * (2.0f - 1.5f * f));
+  w3 = f2 * (-0.5f + 0.5f * f);
+}
+
+// Trapezoid sum over k = 0..nseg of the bicubic value of a padded node grid at
+// grid coordinates (u0 + k du, v0 + k dv), clamped to the node range.  The padded
+// grid has row stride W = nx + 3 and holds node (i, j) at (i + 1) * W + (j + 1)
+// for i in [-1, nz + 1], j in [-1, nx + 1] (edge values replicated).  Returns
+// sum_k w_k value_k with w = 1/2 at both ends and 1 inside (caller divides by nseg).
+template <class GridPtr>
+__device__ inline float path_sum(GridPtr G, int W, float u0, float v0, float du, float dv,
+                                 int nseg, float umax, float vmax) {
+  float acc = 0.f, first = 0.f, last = 0.f;
+  for (int k = 0; k <= nseg; ++k) {
+    const float u = fminf(fmaxf(fmaf((float)k, du, u0), 0.f), umax);
+    const float v = fminf(fmaxf(fmaf((float)k, dv, v0), 0.f), vmax);
+    const int j0 = (int)u, i0 = (int)v;
+    float wx0, wx1, wx2, wx3, wz0, wz1, wz2, wz3;
+    keys_weights(u - (float)j0, wx0, wx1, wx2, wx3);
+    keys_weights(v - (float)i0, wz0, wz1, wz2, wz3);
+    const int b = i0 * W + j0;
+    const float r0 = wx0 * G[b] + wx1 * G[b + 1] + wx2 * G[b + 2] + wx3 * G[b + 3];
+    const float r1 = wx0 * G[b + W] + wx1 * G[b + W + 1] + wx2 * G[b + W + 2] + wx3 * G[b + W + 3];
+    const int b2 = b + 2 * W;
+    const float r2 = wx0 * G[b2] + wx1 * G[b2 + 1] + wx2 * G[b2 + 2] + wx3 * G[b2 + 3];
+    const float r3 = wx0 * G[b2 + W] + wx1 * G[b2 + W + 1] + wx2 * G[b2 + W + 2] + wx3 * G[b2 + W + 3];
+    const float val = wz0 * r0 + wz1 * r1 + wz2 * r2 + wz3 * r3;
+    acc += val;
+    if (k == 0) first = val;
+    if (k == nseg) last = val;
+  }
+  return acc - 0.5f * (first + last);
+}
+
+}  // namespace af

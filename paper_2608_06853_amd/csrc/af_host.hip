@@ -1,0 +1,607 @@
+// Host side of the C ABI: context, geometry set-up (element orientation, active
+// element ranges, spatial tiling of the evaluation points, work lists), buffer
+// management and the sequence of kernels behind each entry point.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <numeric>
+
+#include "af_internal.h"
+
+using af::DBuf;
+using af::TILE;
+using af::SUB;
+
+namespace {
+
+const char* kNoCtx = "af: null context";
+
+af_status fail(af_ctx* c, af_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+af_status hip_fail(af_ctx* c, hipError_t e, const char* where) {
+  return fail(c, AF_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define AF_HIP(call, where)                                   \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) return hip_fail(c, e_, where);      \
+  } while (0)
+
+// Launch `call` (a launch wrapper) and, when profiling, bracket it with events.
+#define AF_KERNEL(kid, call, where)                                            \
+  do {                                                                         \
+    hipEvent_t a_ = nullptr, b_ = nullptr;                                     \
+    if (c->prof_on && (a_ = c->ev_get())) (void)hipEventRecord(a_, c->stream); \
+    AF_HIP(call, where);                                                       \
+    if (a_ && (b_ = c->ev_get())) {                                            \
+      (void)hipEventRecord(b_, c->stream);                                     \
+      c->ev_pending.push_back({(kid), {a_, b_}});                              \
+    } else if (a_) {                                                           \
+      c->ev_pool.push_back(a_);                                                \
+    }                                                                          \
+  } while (0)
+
+#define AF_ALLOC(buf, bytes, what)                                                    \
+  do {                                                                                \
+    if ((buf).ensure(bytes) != hipSuccess)                                            \
+      return fail(c, AF_ERR_OOM, std::string("af: cannot allocate ") + (what));       \
+  } while (0)
+
+uint64_t spread16(uint32_t v) {
+  uint64_t x = v & 0xffff;
+  x = (x | (x << 8)) & 0x00ff00ffULL;
+  x = (x | (x << 4)) & 0x0f0f0f0fULL;
+  x = (x | (x << 2)) & 0x33333333ULL;
+  x = (x | (x << 1)) & 0x55555555ULL;
+  return x;
+}
+
+template <class T>
+af_status upload(af_ctx* c, DBuf& b, const std::vector<T>& v, const char* what) {
+  AF_ALLOC(b, sizeof(T) * std::max<size_t>(v.size(), 1), what);
+  if (!v.empty())
+    AF_HIP(hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, c->stream), what);
+  // host vectors die at return: wait for the copy
+  AF_HIP(hipStreamSynchronize(c->stream), what);
+  return AF_OK;
+}
+
+}  // namespace
+
+af::Geo af_ctx::geo() const {
+  af::Geo g{};
+  g.n_elem = N;
+  g.ns = Ns;
+  g.block = S;
+  g.nblk = nb;
+  g.nsub = nsub;
+  g.n_seg = n_seg;
+  g.patch2 = M;
+  g.pps = pps;
+  g.P = P_int;
+  g.fs = fs;
+  g.fd = fd;
+  g.t0 = t0;
+  g.t_ttp = t_ttp;
+  g.dlens = d_lens;
+  g.icl = 1.0 / c_lens;
+  g.nx = nx;
+  g.nz = nz;
+  g.W = nx + 3;
+  g.x0 = (float)x0;
+  g.z0 = (float)z0;
+  g.idx = (float)(1.0 / dx);
+  g.idz = (float)(1.0 / dz);
+  return g;
+}
+
+extern "C" {
+
+af_status af_create(af_ctx** out, int device, void* stream) {
+  if (!out) return AF_ERR_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return AF_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return AF_ERR_HIP;
+  af_ctx* c = new af_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  if (c->d_scal.ensure(sizeof(double) * 16) != hipSuccess) {
+    delete c;
+    return AF_ERR_OOM;
+  }
+  *out = c;
+  return AF_OK;
+}
+
+void af_destroy(af_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  delete c;
+}
+
+const char* af_last_error(const af_ctx* c) { return c ? c->err.c_str() : kNoCtx; }
+
+af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pix,
+                          const double* pix_xz, int patch, double spacing, int n_samples,
+                          double fs, double t0, double fd, int block, double fnum, int n_seg) {
+  if (!c) return AF_ERR_ARG;
+  if (!elem_xz || !pix_xz) return fail(c, AF_ERR_ARG, "af_set_geometry: null array");
+  if (n_elem < 3) return fail(c, AF_ERR_ARG, "af_set_geometry: need at least 3 elements");
+  if (block <= 0 || n_elem % block != 0 || (block & (block - 1)) != 0 || block > 16)
+    return fail(c, AF_ERR_ARG, "af_set_geometry: block must be a power of two <= 16 dividing n_elem");
+  if (n_elem / block < 3)
+    return fail(c, AF_ERR_ARG, "af_set_geometry: need at least 3 blocks (2 subapertures)");
+  if (patch != 1 && patch != 3) return fail(c, AF_ERR_ARG, "af_set_geometry: patch must be 1 or 3");
+  if (n_pix <= 0 || n_samples < 2 || !(fs > 0) || n_seg <= 0 || !(fnum > 0) || !(spacing >= 0))
+    return fail(c, AF_ERR_ARG, "af_set_geometry: non-positive size or rate");
+  AF_HIP(hipSetDevice(c->device), "hipSetDevice");
+
+  c->has_geom = false;
+  c->has_grid = false;
+  c->N = n_elem;
+  c->n_pix = n_pix;
+  c->patch = patch;
+  c->M = patch * patch;
+  c->Ns = n_samples;
+  c->fs = fs;
+  c->t0 = t0;
+  c->fd = fd;
+  c->S = block;
+  c->nb = n_elem / block;
+  c->nsub = c->nb - 1;
+  c->fnum = fnum;
+  c->n_seg = n_seg;
+  c->spacing = spacing;
+  const int N = n_elem, M = c->M;
+  c->elem_xz.assign(elem_xz, elem_xz + 2 * N);
+
+  // element polar geometry (centre of curvature at the origin)
+  c->elem_R.resize(N);
+  c->elem_pol.resize(N);
+  std::vector<double4> el(N);
+  for (int a = 0; a < N; ++a) {
+    const double x = elem_xz[2 * a], z = elem_xz[2 * a + 1];
+    const double R = std::sqrt(x * x + z * z);
+    c->elem_R[a] = R;
+    c->elem_pol[a] = std::atan2(x, z);
+    el[a] = make_double4(R, x / R, z / R, 0.0);
+  }
+  for (int a = 1; a < N; ++a)
+    if (!(c->elem_pol[a] > c->elem_pol[a - 1]))
+      return fail(c, AF_ERR_ARG, "af_set_geometry: elements must be ordered by increasing polar angle");
+  // element orientation, Eq. 3 (one-sided differences at the two ends)
+  std::vector<double> th(N), cth(N), sth(N);
+  for (int a = 0; a < N; ++a) {
+    const int lo = std::max(a - 1, 0), hi = std::min(a + 1, N - 1);
+    th[a] = -std::atan((elem_xz[2 * hi + 1] - elem_xz[2 * lo + 1]) / (elem_xz[2 * hi] - elem_xz[2 * lo]));
+    cth[a] = std::cos(th[a]);
+    sth[a] = std::sin(th[a]);
+  }
+
+  // evaluation points (caller order p = q * M + m)
+  const long long P = (long long)n_pix * M;
+  c->P = P;
+  c->pts_xz.resize(2 * P);
+  const int h = patch / 2;
+  for (int q = 0; q < n_pix; ++q)
+    for (int m = 0; m < M; ++m) {
+      const double ox = (double)(m % patch - h) * spacing, oz = (double)(m / patch - h) * spacing;
+      c->pts_xz[2 * (q * M + m)] = pix_xz[2 * q] + ox;
+      c->pts_xz[2 * (q * M + m) + 1] = pix_xz[2 * q + 1] + oz;
+    }
+
+  // active element range of every caller point (Eqs. 2 and 4, FP64)
+  std::vector<int> lo_c(P), hi_c(P);
+  const double half_f = fnum / 2.0;
+  for (long long p = 0; p < P; ++p) {
+    const double px = c->pts_xz[2 * p], pz = c->pts_xz[2 * p + 1];
+    int lo = N, hi = -1, cnt = 0;
+    for (int a = 0; a < N; ++a) {
+      const double dx = px - elem_xz[2 * a], dz = pz - elem_xz[2 * a + 1];
+      const double xp = cth[a] * dx - sth[a] * dz;
+      const double zp = sth[a] * dx + cth[a] * dz;
+      if (std::fabs(xp) <= half_f * zp) {
+        lo = std::min(lo, a);
+        hi = std::max(hi, a);
+        ++cnt;
+      }
+    }
+    if (cnt > 0 && cnt != hi - lo + 1)
+      return fail(c, AF_ERR_ARG, "af_set_geometry: active elements of a point are not contiguous");
+    lo_c[p] = cnt > 0 ? lo : 1;
+    hi_c[p] = cnt > 0 ? hi : 0;
+  }
+
+  // spatial tiling of the pixels: Morton order of quantised (radius, angle)
+  const int pps = SUB / M;          // whole patches per 64-point sub-tile
+  const int ppt = 4 * pps;          // patches per 256-point tile
+  c->pps = pps;
+  c->ppt = ppt;
+  std::vector<double> prho(n_pix), pang(n_pix);
+  double rmin = 1e300, rmax = -1e300, amin = 1e300, amax = -1e300;
+  for (int q = 0; q < n_pix; ++q) {
+    prho[q] = std::hypot(pix_xz[2 * q], pix_xz[2 * q + 1]);
+    pang[q] = std::atan2(pix_xz[2 * q], pix_xz[2 * q + 1]);
+    rmin = std::min(rmin, prho[q]);
+    rmax = std::max(rmax, prho[q]);
+    amin = std::min(amin, pang[q]);
+    amax = std::max(amax, pang[q]);
+  }
+  std::vector<uint64_t> key(n_pix);
+  for (int q = 0; q < n_pix; ++q) {
+    const uint32_t qr = (uint32_t)std::lround((prho[q] - rmin) / std::max(rmax - rmin, 1e-12) * 65535.0);
+    const uint32_t qa = (uint32_t)std::lround((pang[q] - amin) / std::max(amax - amin, 1e-12) * 65535.0);
+    key[q] = (spread16(qr) << 1) | spread16(qa);
+  }
+  std::vector<int> ord(n_pix);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return key[a] < key[b]; });
+
+  const int n_tiles = (n_pix + ppt - 1) / ppt;
+  const long long P_int = (long long)n_tiles * TILE;
+  c->n_tiles = n_tiles;
+  c->P_int = P_int;
+  c->i2c.assign(P_int, -1);
+  c->c2i.assign(P, -1);
+  for (int k = 0; k < n_pix; ++k) {
+    const int q = ord[k];
+    const int tile = k / ppt, w = (k % ppt) / pps, s = (k % ppt) % pps;
+    for (int m = 0; m < M; ++m) {
+      const long long pi = (long long)tile * TILE + w * SUB + s * M + m;
+      c->i2c[pi] = q * M + m;
+      c->c2i[(long long)q * M + m] = (int)pi;
+    }
+  }
+  std::vector<double4> ptpol(P_int);
+  std::vector<float2> ptxy(P_int);
+  std::vector<int2> prange(P_int);
+  c->tile_lo.assign(n_tiles, N);
+  c->tile_hi.assign(n_tiles, -1);
+  c->active_pairs = 0;
+  c->active_samples = 0;
+  for (long long pi = 0; pi < P_int; ++pi) {
+    const int pc = c->i2c[pi];
+    const long long src = pc >= 0 ? pc : c->i2c[(pi / TILE) * TILE];
+    const double x = c->pts_xz[2 * src], z = c->pts_xz[2 * src + 1];
+    const double rho = std::sqrt(x * x + z * z);
+    ptpol[pi] = make_double4(rho, x / rho, z / rho, 0.0);
+    ptxy[pi] = make_float2((float)x, (float)z);
+    int lo = 1, hi = 0;
+    if (pc >= 0) {
+      lo = lo_c[pc];
+      hi = hi_c[pc];
+    }
+    prange[pi] = make_int2(lo, hi);
+    if (lo <= hi) {
+      const int t = (int)(pi / TILE);
+      c->tile_lo[t] = std::min(c->tile_lo[t], lo);
+      c->tile_hi[t] = std::max(c->tile_hi[t], hi);
+      c->active_pairs += hi - lo + 1;
+      c->active_samples += (long long)(hi - lo + 1) * (hi - lo + 1);
+    }
+  }
+  std::vector<int4> tiles(n_tiles);
+  std::vector<int2> tabwork, daswork;
+  std::vector<std::pair<long long, int>> load;
+  c->na_max = 1;
+  c->nba_max = 1;
+  for (int t = 0; t < n_tiles; ++t) {
+    const int LO = c->tile_lo[t], HI = c->tile_hi[t];
+    if (LO > HI) {
+      tiles[t] = make_int4(1, 0, 1, 0);
+      continue;
+    }
+    const int bLO = LO / block, bHI = HI / block;
+    tiles[t] = make_int4(LO, HI, bLO, bHI);
+    c->na_max = std::max(c->na_max, HI - LO + 1);
+    c->nba_max = std::max(c->nba_max, bHI - bLO + 1);
+    for (int a0 = LO; a0 <= HI; a0 += af::TAB_CHUNK) tabwork.push_back(make_int2(t, a0));
+    load.push_back({(long long)(HI - LO + 1) * (HI - LO + 1), t});
+  }
+  if (c->nba_max > af::MAX_NBA)
+    return fail(c, AF_ERR_ARG, "af_set_geometry: a tile spans more than 16 active blocks (aperture too wide for the block size)");
+  std::stable_sort(load.begin(), load.end(), [](auto& a, auto& b) { return a.first > b.first; });
+  c->tile_order.clear();
+  for (auto& l : load) {
+    c->tile_order.push_back(l.second);
+    const int4 tr = tiles[l.second];
+    for (int jb = tr.z; jb <= tr.w; ++jb) daswork.push_back(make_int2(l.second, jb));
+  }
+  c->n_tab_work = (int)tabwork.size();
+  c->n_das_work = (int)daswork.size();
+  c->n_order = (int)c->tile_order.size();
+
+  af_status st;
+  if ((st = upload(c, c->d_elem, el, "elements")) != AF_OK) return st;
+  if ((st = upload(c, c->d_ptpol, ptpol, "points")) != AF_OK) return st;
+  if ((st = upload(c, c->d_ptxy, ptxy, "points")) != AF_OK) return st;
+  if ((st = upload(c, c->d_prange, prange, "point ranges")) != AF_OK) return st;
+  if ((st = upload(c, c->d_tiles, tiles, "tiles")) != AF_OK) return st;
+  if ((st = upload(c, c->d_tabwork, tabwork, "work list")) != AF_OK) return st;
+  if ((st = upload(c, c->d_daswork, daswork, "work list")) != AF_OK) return st;
+  if ((st = upload(c, c->d_order, c->tile_order, "tile order")) != AF_OK) return st;
+  if ((st = upload(c, c->d_c2i, c->c2i, "point map")) != AF_OK) return st;
+  if ((st = upload(c, c->d_i2c, c->i2c, "point map")) != AF_OK) return st;
+
+  AF_ALLOC(c->d_tab, sizeof(af::TabEntry) * (size_t)N * P_int, "travel-time table");
+  AF_ALLOC(c->d_bblk, sizeof(float2) * (size_t)c->nb * c->nb * P_int, "block images");
+  AF_ALLOC(c->d_gT, sizeof(float) * (size_t)N * P_int, "time gradient");
+  AF_ALLOC(c->d_gsb, sizeof(float2) * (size_t)P_int, "brightness gradient");
+  AF_ALLOC(c->d_part, sizeof(double) * 4 * (size_t)(P_int / SUB), "partials");
+  AF_ALLOC(c->d_maps, sizeof(float) * 2 * (size_t)n_tiles * ppt, "maps");
+  c->has_geom = true;
+  return AF_OK;
+}
+
+af_status af_set_lens(af_ctx* c, double d_lens, double c_lens, double t_ttp) {
+  if (!c) return AF_ERR_ARG;
+  if (!(d_lens >= 0) || !(c_lens > 0) || !std::isfinite(t_ttp))
+    return fail(c, AF_ERR_ARG, "af_set_lens: need d_lens >= 0, c_lens > 0, finite t_ttp");
+  c->d_lens = d_lens;
+  c->c_lens = c_lens;
+  c->t_ttp = t_ttp;
+  c->has_lens = true;
+  c->has_grid = false;
+  return AF_OK;
+}
+
+af_status af_set_slowness(af_ctx* c, int nx, int nz, double x0, double z0, double dx, double dz,
+                          const float* s_dev) {
+  if (!c) return AF_ERR_ARG;
+  if (!c->has_geom || !c->has_lens)
+    return fail(c, AF_ERR_STATE, "af_set_slowness: set geometry and lens first");
+  if (nx < 2 || nz < 2 || !(dx > 0) || !(dz > 0) || !s_dev)
+    return fail(c, AF_ERR_ARG, "af_set_slowness: bad grid");
+  if ((size_t)(nx + 3) * (nz + 3) > 16384)
+    return fail(c, AF_ERR_ARG, "af_set_slowness: grid larger than (nx+3)(nz+3) <= 16384 nodes");
+  const double x1 = x0 + (nx - 1) * dx, z1 = z0 + (nz - 1) * dz, tol = 1e-9;
+  auto inside = [&](double x, double z) {
+    return x >= x0 - tol && x <= x1 + tol && z >= z0 - tol && z <= z1 + tol;
+  };
+  double amin = 1e300, amax = -1e300;
+  for (int a = 0; a < c->N; ++a) {
+    amin = std::min(amin, c->elem_pol[a]);
+    amax = std::max(amax, c->elem_pol[a]);
+  }
+  for (long long p = 0; p < c->P; ++p) {
+    const double x = c->pts_xz[2 * p], z = c->pts_xz[2 * p + 1];
+    if (!inside(x, z)) return fail(c, AF_ERR_ARG, "af_set_slowness: grid does not cover every point");
+    const double ang = std::atan2(x, z);
+    amin = std::min(amin, ang);
+    amax = std::max(amax, ang);
+  }
+  // lens arc over [amin, amax] (both ends and the apex if it is inside)
+  for (int a = 0; a < c->N; ++a) {
+    const double RL = c->elem_R[a] + c->d_lens;
+    const double cand[3] = {amin, amax, 0.0};
+    for (int k = 0; k < 3; ++k) {
+      if (k == 2 && !(amin <= 0.0 && amax >= 0.0)) continue;
+      if (!inside(RL * std::sin(cand[k]), RL * std::cos(cand[k])))
+        return fail(c, AF_ERR_ARG, "af_set_slowness: grid does not cover the lens arc");
+    }
+  }
+  c->nx = nx;
+  c->nz = nz;
+  c->x0 = x0;
+  c->z0 = z0;
+  c->dx = dx;
+  c->dz = dz;
+  const size_t n = (size_t)nx * nz, np = (size_t)(nx + 3) * (nz + 3);
+  AF_ALLOC(c->d_s, sizeof(float) * n, "slowness");
+  AF_ALLOC(c->d_regg, sizeof(float) * n, "regulariser gradient");
+  AF_ALLOC(c->d_grad, sizeof(float) * n, "gradient");
+  AF_ALLOC(c->d_gdev, sizeof(float) * np, "deviation grid");
+  AF_ALLOC(c->d_gpad, sizeof(float) * np, "padded gradient");
+  AF_ALLOC(c->d_terms, sizeof(float) * 8, "terms");
+  AF_HIP(hipMemcpyAsync(c->d_s.p, s_dev, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream),
+         "af_set_slowness copy");
+  c->has_grid = true;
+  return AF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+af_status ready(af_ctx* c, const void* iq) {
+  if (!c) return AF_ERR_ARG;
+  if (!c->has_geom || !c->has_lens || !c->has_grid)
+    return fail(c, AF_ERR_STATE, "af: set geometry, lens and slowness first");
+  if (!iq) return fail(c, AF_ERR_ARG, "af: null channel data");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AF_ERR_HIP, "hipSetDevice");
+  return AF_OK;
+}
+
+// grid prep (c_med, deviation grid, regulariser) + travel-time table
+af_status run_tables(af_ctx* c, const af_loss_params* lp) {
+  AF_KERNEL(AF_K_PREPARE,
+            af::launch_prepare_grid(c, c->d_s.as<float>(), c->nx, c->nz, c->d_gdev.as<float>(),
+                                    c->d_scal.as<double>(), lp ? 1 : 0, lp, c->d_regg.as<float>()),
+            "prepare_grid");
+  AF_KERNEL(AF_K_TABLE, af::launch_table(c), "table");
+  return AF_OK;
+}
+
+// forward: tables, DAS, CMPE (+G), terms; G goes to `gout` (or in place into the block images)
+af_status run_forward(af_ctx* c, const af_complex* iq, const af_loss_params* lp, float* terms,
+                      float2* gout, bool write_g) {
+  af_status st = run_tables(c, lp);
+  if (st != AF_OK) return st;
+  const float2* iqf = reinterpret_cast<const float2*>(iq);
+  AF_KERNEL(AF_K_DAS_FWD, af::launch_das_fwd(c, iqf, c->d_bblk.as<float2>()), "das_fwd");
+  const float sb_scale = (float)(-2.0 * lp->w_sb / ((double)lp->sb_ref * c->n_pix));
+  float2* g = gout ? gout : c->d_bblk.as<float2>();
+  AF_KERNEL(AF_K_CMPE,
+            af::launch_cmpe(c, c->d_bblk.as<float2>(), g, write_g ? 1 : 0, lp->rho_thresh,
+                            sb_scale, c->d_maps.as<float>(),
+                            c->d_maps.as<float>() + c->n_tiles * c->ppt, nullptr),
+            "cmpe");
+  AF_KERNEL(AF_K_FINALIZE, af::launch_finalize(c, lp, terms), "finalize");
+  if (write_g) AF_KERNEL(AF_K_GSCALE, af::launch_gscale(c, g), "gscale");
+  c->rho_last = lp->rho_thresh;
+  return AF_OK;
+}
+
+af_status run_backward(af_ctx* c, const af_complex* iq, const float2* gblk, float* grad) {
+  AF_KERNEL(AF_K_DAS_ADJ, af::launch_das_adj(c, reinterpret_cast<const float2*>(iq), gblk),
+            "das_adj");
+  AF_KERNEL(AF_K_PATH_ADJ, af::launch_path_adj(c), "path_adj");
+  AF_KERNEL(AF_K_FOLD, af::launch_grad_fold(c, grad), "grad_fold");
+  return AF_OK;
+}
+
+af_status check_lp(af_ctx* c, const af_loss_params* lp) {
+  if (!lp) return fail(c, AF_ERR_ARG, "af: null loss parameters");
+  if (!(lp->sb_ref > 0)) return fail(c, AF_ERR_ARG, "af: sb_ref must be > 0");
+  return AF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+af_status af_beamform(af_ctx* c, const af_complex* iq, af_complex* blk, af_complex* img,
+                      float* maps) {
+  af_status st = ready(c, iq);
+  if (st != AF_OK) return st;
+  if ((st = run_tables(c, nullptr)) != AF_OK) return st;
+  AF_HIP(af::launch_das_fwd(c, reinterpret_cast<const float2*>(iq), c->d_bblk.as<float2>()), "das_fwd");
+  if (maps)
+    AF_HIP(af::launch_cmpe(c, c->d_bblk.as<float2>(), nullptr, 0, c->rho_last, 0.f,
+                           c->d_maps.as<float>(), c->d_maps.as<float>() + c->n_tiles * c->ppt,
+                           nullptr),
+           "cmpe maps");
+  if (blk || img || maps)
+    AF_HIP(af::launch_export_images(c, c->d_bblk.as<float2>(), reinterpret_cast<float2*>(blk),
+                                    reinterpret_cast<float2*>(img), maps),
+           "export images");
+  return AF_OK;
+}
+
+af_status af_loss_and_grad(af_ctx* c, const af_complex* iq, const af_loss_params* lp, float* terms,
+                           float* grad) {
+  af_status st = ready(c, iq);
+  if (st != AF_OK) return st;
+  if ((st = check_lp(c, lp)) != AF_OK) return st;
+  if (!terms) return fail(c, AF_ERR_ARG, "af_loss_and_grad: null terms");
+  if ((st = run_forward(c, iq, lp, terms, nullptr, grad != nullptr)) != AF_OK) return st;
+  if (!grad) return AF_OK;
+  // the table of this call is still current: the adjoint uses it directly
+  return run_backward(c, iq, c->d_bblk.as<float2>(), grad);
+}
+
+af_status af_forward(af_ctx* c, const af_complex* iq, const af_loss_params* lp, float* terms,
+                     af_complex* gblk) {
+  af_status st = ready(c, iq);
+  if (st != AF_OK) return st;
+  if ((st = check_lp(c, lp)) != AF_OK) return st;
+  if (!terms || !gblk) return fail(c, AF_ERR_ARG, "af_forward: null output");
+  return run_forward(c, iq, lp, terms, reinterpret_cast<float2*>(gblk), true);
+}
+
+af_status af_backward(af_ctx* c, const af_complex* iq, const af_loss_params* lp,
+                      const af_complex* gblk, float* grad) {
+  af_status st = ready(c, iq);
+  if (st != AF_OK) return st;
+  if ((st = check_lp(c, lp)) != AF_OK) return st;
+  if (!gblk || !grad) return fail(c, AF_ERR_ARG, "af_backward: null buffer");
+  if ((st = run_tables(c, lp)) != AF_OK) return st;  // recompute: no table is stored between calls
+  return run_backward(c, iq, reinterpret_cast<const float2*>(gblk), grad);
+}
+
+af_status af_autofocus_step(af_ctx* c, const af_complex* iq, const af_loss_params* lp,
+                            const af_adam_params* ap, int step, float* s, float* m, float* v,
+                            float* terms) {
+  af_status st = ready(c, iq);
+  if (st != AF_OK) return st;
+  if (!ap || !s || !m || !v || !terms || step < 1)
+    return fail(c, AF_ERR_ARG, "af_autofocus_step: bad argument");
+  const size_t n = (size_t)c->nx * c->nz;
+  AF_HIP(hipMemcpyAsync(c->d_s.p, s, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream), "copy s");
+  if ((st = af_loss_and_grad(c, iq, lp, terms, c->d_grad.as<float>())) != AF_OK) return st;
+  AF_KERNEL(AF_K_ADAM, af::launch_adam(c, ap, step, s, m, v, c->d_grad.as<float>()), "adam");
+  return AF_OK;
+}
+
+af_status af_travel_times(af_ctx* c, float* t_dev) {
+  af_status st = ready(c, t_dev);
+  if (st != AF_OK) return st;
+  if ((st = run_tables(c, nullptr)) != AF_OK) return st;
+  AF_HIP(af::launch_export_T(c, t_dev), "export T");
+  return AF_OK;
+}
+
+af_status af_simulate(af_ctx* c, int n_scat, const double* scat_xz, const float* amp, int nx, int nz,
+                      double x0, double z0, double dx, double dz, const float* s_true, int n_seg,
+                      double fc, double frac_bw, af_complex* iq) {
+  if (!c) return AF_ERR_ARG;
+  if (!c->has_geom || !c->has_lens) return fail(c, AF_ERR_STATE, "af_simulate: set geometry and lens first");
+  if (n_scat <= 0 || !scat_xz || !amp || !s_true || !iq || nx < 2 || nz < 2 || n_seg <= 0 ||
+      !(fc > 0) || !(frac_bw > 0) || !(dx > 0) || !(dz > 0))
+    return fail(c, AF_ERR_ARG, "af_simulate: bad argument");
+  const double x1 = x0 + (nx - 1) * dx, z1 = z0 + (nz - 1) * dz;
+  for (int k = 0; k < n_scat; ++k) {
+    const double x = scat_xz[2 * k], z = scat_xz[2 * k + 1];
+    if (!(x >= x0 && x <= x1 && z >= z0 && z <= z1))
+      return fail(c, AF_ERR_ARG, "af_simulate: grid does not cover every scatterer");
+  }
+  if ((size_t)2 * c->Ns * sizeof(float) > 64 * 1024)
+    return fail(c, AF_ERR_ARG, "af_simulate: records longer than 8192 samples");
+  AF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  AF_HIP(af::launch_simulate(c, n_scat, scat_xz, amp, nx, nz, x0, z0, dx, dz, s_true, n_seg, fc,
+                             frac_bw, reinterpret_cast<float2*>(iq)),
+         "simulate");
+  return AF_OK;
+}
+
+af_status af_set_profiling(af_ctx* c, int enable) {
+  if (!c) return AF_ERR_ARG;
+  c->prof_on = enable != 0;
+  return AF_OK;
+}
+
+af_status af_profile_read(af_ctx* c, double* ms, long long* calls) {
+  if (!c || !ms || !calls) return AF_ERR_ARG;
+  for (int k = 0; k < AF_K_COUNT; ++k) {
+    ms[k] = 0.0;
+    calls[k] = 0;
+  }
+  AF_HIP(c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "profile sync");
+  for (auto& pe : c->ev_pending) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, pe.second.first, pe.second.second) == hipSuccess) {
+      ms[pe.first] += t;
+      calls[pe.first] += 1;
+    }
+    c->ev_pool.push_back(pe.second.first);
+    c->ev_pool.push_back(pe.second.second);
+  }
+  c->ev_pending.clear();
+  return AF_OK;
+}
+
+af_status af_query(af_ctx* c, int what, long long* out) {
+  if (!c || !out) return AF_ERR_ARG;
+  if (!c->has_geom) return fail(c, AF_ERR_STATE, "af_query: no geometry");
+  switch (what) {
+    case AF_Q_P: *out = c->P; break;
+    case AF_Q_P_INTERNAL: *out = c->P_int; break;
+    case AF_Q_NBLK: *out = c->nb; break;
+    case AF_Q_GBLK_ELEMS: *out = (long long)c->nb * c->nb * c->P_int; break;
+    case AF_Q_ACTIVE_PAIRS: *out = c->active_pairs; break;
+    case AF_Q_ACTIVE_SAMPLES: *out = c->active_samples; break;
+    case AF_Q_TILES: *out = c->n_tiles; break;
+    default: return fail(c, AF_ERR_ARG, "af_query: unknown item");
+  }
+  return AF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,190 @@
+// Internal declarations of the library: context, device buffers and the launch
+// wrappers of every kernel (one translation unit per kernel family).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/af.h"
+#include "af_device.h"
+
+namespace af {
+
+// Growable device buffer owned by a context.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  hipError_t ensure(size_t n) {
+    if (n <= bytes) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipMalloc(&p, n);
+    if (e == hipSuccess) bytes = n;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Static geometry passed by value to kernels.
+struct Geo {
+  int n_elem, ns, block, nblk, nsub, n_seg, patch2, pps;
+  long long P;            // internal points (multiple of TILE)
+  double fs, fd, t0, t_ttp;
+  double dlens, icl;      // lens thickness, 1/c_lens
+  // slowness grid
+  int nx, nz, W;          // W = nx + 3 (padded row stride)
+  float x0, z0, idx, idz;
+};
+
+struct TableArgs {
+  Geo g;
+  const double4* elem;    // (R, sin, cos, 0) polar geometry of each element
+  const double4* ptpol;   // (rho, sin, cos, 0) polar geometry of each point
+  const float2* ptxy;     // point (x, z)
+  const int2* prange;     // active element range [lo, hi] of each point
+  const int4* tiles;      // (LO, HI, bLO, bHI)
+  const int2* work;       // (tile, first element of a chunk of TAB_CHUNK)
+  const float* gdev;      // padded deviation grid s - s_med
+  const double* scal;     // scal[0] = c_med, scal[1] = s_med
+  TabEntry* tab;          // [n_elem][P]
+};
+constexpr int TAB_CHUNK = 8;
+
+struct DasArgs {
+  Geo g;
+  const TabEntry* tab;
+  const float2* iq;       // [N][N][ns]
+  const int4* tiles;
+  const int2* work;       // (tile, rx block) for the forward
+  const int* order;       // tile order for the adjoint
+  float2* bblk;           // [nb][nb][P]  (forward output)
+  const float2* gblk;     // [nb][nb][P]  (adjoint input, final scale applied)
+  float* gT;              // [n_elem][P]  dL/dT (adjoint output)
+};
+
+struct CmpeArgs {
+  Geo g;
+  const int4* tiles;
+  const float2* bblk;     // input block images
+  float2* gout;           // output: unscaled dL_sum/dB^blk (may alias bblk)
+  float2* gsb;            // [P] speckle-brightness gradient per centre point
+  double* part;           // [n_sub_tiles][4] (sum err, n_valid, sum |B|^2, 0)
+  float* map_cmpe;        // [P/patch2 internal pixel slots] or null
+  float* map_cf;          // same, or null
+  float2* img;            // [P] full image or null
+  float rho_thresh;
+  float sb_scale;         // -2 w_sb / (sb_ref n_pix)
+  int write_g;
+};
+
+struct PathArgs {
+  Geo g;
+  const double4* elem;
+  const double4* ptpol;
+  const float2* ptxy;
+  const int2* prange;
+  const int4* tiles;
+  const int* order;
+  const float* gT;        // dL/dT [n_elem][P]
+  const double* scal;
+  float* gpad;            // padded grid gradient (global atomics)
+  int copies;             // interleaved private copies in LDS
+};
+
+}  // namespace af
+
+struct af_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool has_geom = false, has_lens = false, has_grid = false;
+
+  // geometry (host, caller order)
+  int N = 0, n_pix = 0, patch = 3, M = 9, Ns = 0, S = 1, nb = 0, nsub = 0, n_seg = 0;
+  double spacing = 0, fs = 0, t0 = 0, fd = 0, fnum = 0;
+  std::vector<double> elem_xz, pts_xz;      // [N][2], [P][2] caller order
+  std::vector<double> elem_R, elem_pol;     // radius, polar angle
+  // internal layout
+  int pps = 0, ppt = 0, n_tiles = 0;
+  long long P = 0, P_int = 0;
+  std::vector<int> i2c;                     // internal point -> caller point (-1 pad)
+  std::vector<int> c2i;                     // caller point -> internal point
+  std::vector<int> prange_lo, prange_hi;    // per internal point
+  std::vector<int> tile_lo, tile_hi;
+  int na_max = 0, nba_max = 0;
+  long long active_pairs = 0, active_samples = 0;
+  std::vector<int> tile_order;              // tiles with work, heaviest first
+  int n_tab_work = 0, n_das_work = 0, n_order = 0;
+
+  // lens
+  double d_lens = 0, c_lens = 1, t_ttp = 0;
+  // grid
+  int nx = 0, nz = 0;
+  double x0 = 0, z0 = 0, dx = 1, dz = 1;
+  float rho_last = 0.9f;
+
+  // device buffers
+  af::DBuf d_elem, d_ptpol, d_ptxy, d_prange, d_tiles, d_tabwork, d_daswork, d_order, d_i2c,
+      d_c2i;
+  af::DBuf d_s, d_gdev, d_regg, d_scal, d_tab, d_bblk, d_g, d_gT, d_gsb, d_part, d_gpad,
+      d_grad, d_terms, d_maps, d_img;
+
+  af::Geo geo() const;
+
+  // kernel timing (af_set_profiling)
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  hipEvent_t ev_get() {
+    hipEvent_t e = nullptr;
+    if (!ev_pool.empty()) {
+      e = ev_pool.back();
+      ev_pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+  ~af_ctx() {
+    for (auto& p : ev_pending) {
+      (void)hipEventDestroy(p.second.first);
+      (void)hipEventDestroy(p.second.second);
+    }
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace af {
+// launch wrappers (return hipGetLastError())
+hipError_t launch_prepare_grid(af_ctx* c, const float* s, int nx, int nz, float* gdev, double* scal,
+                               int do_reg, const af_loss_params* lp, float* regg);
+hipError_t launch_table(af_ctx* c);
+hipError_t launch_das_fwd(af_ctx* c, const float2* iq, float2* bblk);
+hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g, float rho,
+                       float sb_scale, float* map_cmpe, float* map_cf, float2* img);
+hipError_t launch_finalize(af_ctx* c, const af_loss_params* lp, float* terms);
+hipError_t launch_gscale(af_ctx* c, float2* gblk);
+hipError_t launch_das_adj(af_ctx* c, const float2* iq, const float2* gblk);
+hipError_t launch_path_adj(af_ctx* c);
+hipError_t launch_grad_fold(af_ctx* c, float* grad);
+hipError_t launch_adam(af_ctx* c, const af_adam_params* ap, int step, float* s, float* m,
+                       float* v, const float* grad);
+hipError_t launch_export_T(af_ctx* c, float* out);
+hipError_t launch_export_images(af_ctx* c, const float2* bblk, float2* blk_out, float2* img_out,
+                                float* maps_out);
+hipError_t launch_simulate(af_ctx* c, int n_scat, const double* scat_xz, const float* amp,
+                           int nx, int nz, double x0, double z0, double dx, double dz,
+                           const float* s_true, int n_seg, double fc, double frac_bw,
+                           float2* iq);
+}  // namespace af

@@ -1,0 +1,289 @@
+// Common-midpoint phase error on subaperture images built from block pairs, its
+// gradient with respect to the block images, speckle brightness, coherence
+// factor and the per-pixel integrated CMPE map (Objective Function subsection;
+// Model Implementation: 3x3 patches at lambda/2).
+//
+// Reading of the CMPE (the exact definition is in the cited Simson et al.
+// paper): subaperture i spans blocks {i, i+1}; the common-midpoint neighbour
+// pair (i, j) compares X = B_{i,j+1} and Y = B_{i+1,j} over a patch through
+// C = sum X conj(Y); it is valid when both energies exceed 1e-30 and
+// rho = |C| / sqrt(sum|X|^2 sum|Y|^2) >= rho_thresh; its error is |arg C|.
+//
+// One wavefront owns one sub-tile of 64 points (whole patches plus padding) and
+// stages every active block image of the sub-tile in LDS.  Partial sums go to a
+// per-sub-tile slot and are reduced in fixed order afterwards (deterministic).
+#include "af_internal.h"
+
+namespace af {
+namespace {
+
+// Smallest energy sum|X|^2 of a valid pair: below it |C|^2 leaves the FP32 range.
+constexpr float kMinEnergy = 1e-30f;
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_cmpe(CmpeArgs A) {
+  extern __shared__ float2 Bs[];
+  const Geo& g = A.g;
+  const int tid = threadIdx.x;
+  const long long st = blockIdx.x;
+  const long long p0 = st * SUB;
+  const long long tile = p0 / TILE;
+  const int w = (int)((p0 % TILE) / SUB);
+  const int4 tr = A.tiles[tile];
+  const int M = g.patch2, pps = g.pps;
+  const long long P = g.P;
+  const int ppt = 4 * pps;
+  const long long slot0 = tile * ppt + (long long)w * pps;
+
+  if (tr.x > tr.y) {
+    if (tid == 0) {
+      A.part[4 * st + 0] = 0.0;
+      A.part[4 * st + 1] = 0.0;
+      A.part[4 * st + 2] = 0.0;
+      A.part[4 * st + 3] = 0.0;
+    }
+    A.gsb[p0 + tid] = make_float2(0.f, 0.f);
+    if (A.img) A.img[p0 + tid] = make_float2(0.f, 0.f);
+    if (tid < pps) {
+      if (A.map_cmpe) A.map_cmpe[slot0 + tid] = 0.f;
+      if (A.map_cf) A.map_cf[slot0 + tid] = 0.f;
+    }
+    return;
+  }
+  const int bLO = tr.z, nbA = tr.w - tr.z + 1;
+  const int nbb = nbA * nbA;
+  for (int idx = tid; idx < nbb * SUB; idx += SUB) {
+    const int blk = idx / SUB, l = idx - blk * SUB;
+    const int bi = blk / nbA, bj = blk - bi * nbA;
+    Bs[idx] = A.bblk[((long long)(bLO + bi) * g.nblk + (bLO + bj)) * P + p0 + l];
+  }
+  __syncthreads();
+
+  auto blk = [&](int i, int j, int l) -> float2 {
+    const int bi = i - bLO, bj = j - bLO;
+    if (bi < 0 || bj < 0 || bi >= nbA || bj >= nbA) return make_float2(0.f, 0.f);
+    return Bs[(bi * nbA + bj) * SUB + l];
+  };
+  auto sub = [&](int i, int j, int l) -> float2 {
+    const float2 a = blk(i, j, l), b = blk(i + 1, j, l), c = blk(i, j + 1, l), d = blk(i + 1, j + 1, l);
+    return make_float2(a.x + b.x + c.x + d.x, a.y + b.y + c.y + d.y);
+  };
+
+  const int pLo = max(0, bLO - 1);
+  const int pHi = min(g.nsub - 2, tr.w - 1);
+  const int npr = max(0, pHi - pLo + 1);
+  const int np2 = npr * npr;
+  float2* gC = Bs + nbb * SUB;
+  float* er = reinterpret_cast<float*>(gC + pps * np2);
+
+  double e_acc = 0.0, nv = 0.0;
+  for (int item = tid; item < pps * np2; item += SUB) {
+    const int q = item / np2, pr = item - q * np2;
+    const int i = pLo + pr / npr, j = pLo + pr % npr;
+    float cx = 0.f, cy = 0.f, ex = 0.f, ey = 0.f;
+    for (int m = 0; m < M; ++m) {
+      const int l = q * M + m;
+      const float2 X = sub(i, j + 1, l);
+      const float2 Y = sub(i + 1, j, l);
+      cx += X.x * Y.x + X.y * Y.y;
+      cy += X.y * Y.x - X.x * Y.y;
+      ex += X.x * X.x + X.y * X.y;
+      ey += Y.x * Y.x + Y.y * Y.y;
+    }
+    const float mag = sqrtf(cx * cx + cy * cy);
+    bool valid = ex > kMinEnergy && ey > kMinEnergy;
+    if (valid) valid = mag / (sqrtf(ex) * sqrtf(ey)) >= A.rho_thresh;
+    const float ang = atan2f(cy, cx);
+    float2 gc = make_float2(0.f, 0.f);
+    if (valid) {
+      // d|arg C|/dC = sign(arg C) j C / |C|^2, formed as (j C/|C|) (sign/|C|) so that
+      // no intermediate leaves the FP32 range
+      if (ang != 0.f && mag > kMinEnergy) {
+        const float im = 1.f / mag;
+        const float sg = ang > 0.f ? im : -im;
+        gc = make_float2(-cy * im * sg, cx * im * sg);
+      }
+      e_acc += fabsf(ang);
+      nv += 1.0;
+    }
+    gC[item] = gc;
+    er[item] = valid ? fabsf(ang) : -1.f;
+  }
+  __syncthreads();
+
+  if (tid < pps && A.map_cmpe) {
+    float s = 0.f;
+    int n = 0;
+    for (int k = 0; k < np2; ++k) {
+      const float e = er[tid * np2 + k];
+      if (e >= 0.f) {
+        s += e;
+        ++n;
+      }
+    }
+    A.map_cmpe[slot0 + tid] = n > 0 ? s / (float)n : 0.f;
+  }
+
+  if (A.write_g) {
+    for (int idx = tid; idx < nbb * SUB; idx += SUB) {
+      const int b = idx / SUB, l = idx - b * SUB;
+      const int i0 = bLO + b / nbA, j0 = bLO + b % nbA;
+      float2 G = make_float2(0.f, 0.f);
+      if (l < pps * M && npr > 0) {
+        const int q = l / M;
+        const float2* gq = gC + q * np2;
+        for (int di = -1; di <= 0; ++di)
+          for (int dj = -1; dj <= 0; ++dj) {
+            const int i = i0 + di, j = j0 + dj;
+            if (i < 0 || j < 0 || i > g.nsub - 1 || j > g.nsub - 1) continue;
+            // B_{i,j} is X of pair (i, j-1): G += gC * Y, Y = B_{i+1, j-1}
+            if (i >= pLo && i <= pHi && j - 1 >= pLo && j - 1 <= pHi) {
+              const float2 c = gq[(i - pLo) * npr + (j - 1 - pLo)];
+              const float2 y = sub(i + 1, j - 1, l);
+              G.x += c.x * y.x - c.y * y.y;
+              G.y += c.x * y.y + c.y * y.x;
+            }
+            // B_{i,j} is Y of pair (i-1, j): G += conj(gC) * X, X = B_{i-1, j+1}
+            if (i - 1 >= pLo && i - 1 <= pHi && j >= pLo && j <= pHi) {
+              const float2 c = gq[(i - 1 - pLo) * npr + (j - pLo)];
+              const float2 x = sub(i - 1, j + 1, l);
+              G.x += c.x * x.x + c.y * x.y;
+              G.y += c.x * x.y - c.y * x.x;
+            }
+          }
+      }
+      A.gout[((long long)i0 * g.nblk + j0) * P + p0 + l] = G;
+    }
+  }
+
+  // full image, speckle brightness and coherence factor at this thread's point
+  float bx = 0.f, by = 0.f, e2 = 0.f;
+  for (int b = 0; b < nbb; ++b) {
+    const float2 v = Bs[b * SUB + tid];
+    bx += v.x;
+    by += v.y;
+    e2 += v.x * v.x + v.y * v.y;
+  }
+  if (A.img) A.img[p0 + tid] = make_float2(bx, by);
+  const bool centre = tid < pps * M && (tid % M) == M / 2;
+  double sbp = 0.0;
+  if (centre) {
+    const float b2 = bx * bx + by * by;
+    sbp = (double)b2;
+    if (A.map_cf)
+      A.map_cf[slot0 + tid / M] = e2 > 0.f ? b2 / ((float)g.nblk * (float)g.nblk * e2) : 0.f;
+    A.gsb[p0 + tid] = make_float2(A.sb_scale * bx, A.sb_scale * by);
+  } else {
+    A.gsb[p0 + tid] = make_float2(0.f, 0.f);
+  }
+  e_acc = wave_sum(e_acc);
+  nv = wave_sum(nv);
+  sbp = wave_sum(sbp);
+  if (tid == 0) {
+    A.part[4 * st + 0] = e_acc;
+    A.part[4 * st + 1] = nv;
+    A.part[4 * st + 2] = sbp;
+    A.part[4 * st + 3] = 0.0;
+  }
+}
+
+// Internal -> caller order: travel times.
+__global__ __launch_bounds__(256) void k_export_T(Geo g, const TabEntry* __restrict__ tab,
+                                                  const int* __restrict__ c2i,
+                                                  const int2* __restrict__ prange, long long Pc,
+                                                  float* __restrict__ out) {
+  const long long pc = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int a = blockIdx.y;
+  if (pc >= Pc) return;
+  const long long p = c2i[pc];
+  const int2 pr = prange[p];
+  float v = __int_as_float(0x7fc00000);
+  if (a >= pr.x && a <= pr.y) {
+    const TabEntry e = tab[(long long)a * g.P + p];
+    const double u = (double)e.ui + (double)e.uf;
+    v = (float)(u / g.fs - 0.5 * g.t_ttp + 0.5 * g.t0);
+  }
+  out[(long long)a * Pc + pc] = v;
+}
+
+// Internal -> caller order: block images, full image and per-pixel maps.
+__global__ __launch_bounds__(256) void k_export_img(Geo g, const float2* __restrict__ bblk,
+                                                    const int4* __restrict__ tiles,
+                                                    const int* __restrict__ c2i, long long Pc,
+                                                    int n_pix, const float* __restrict__ mc,
+                                                    const float* __restrict__ mcf,
+                                                    float2* __restrict__ blk_out,
+                                                    float2* __restrict__ img_out,
+                                                    float* __restrict__ maps_out) {
+  const long long pc = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (pc >= Pc) return;
+  const long long p = c2i[pc];
+  const int4 tr = tiles[p / TILE];
+  float2 acc = make_float2(0.f, 0.f);
+  for (int i = 0; i < g.nblk; ++i)
+    for (int j = 0; j < g.nblk; ++j) {
+      float2 v = make_float2(0.f, 0.f);
+      if (tr.x <= tr.y && i >= tr.z && i <= tr.w && j >= tr.z && j <= tr.w)
+        v = bblk[((long long)i * g.nblk + j) * g.P + p];
+      acc.x += v.x;
+      acc.y += v.y;
+      if (blk_out) blk_out[((long long)i * g.nblk + j) * Pc + pc] = v;
+    }
+  if (img_out) img_out[pc] = acc;
+  if (maps_out && (pc % g.patch2) == g.patch2 / 2) {
+    const long long l = p % TILE;
+    const long long slot = (p / TILE) * 4 * g.pps + (l / SUB) * g.pps + (l % SUB) / g.patch2;
+    const long long q = pc / g.patch2;
+    maps_out[q] = mc[slot];
+    maps_out[n_pix + q] = mcf[slot];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g, float rho,
+                       float sb_scale, float* map_cmpe, float* map_cf, float2* img) {
+  CmpeArgs A{};
+  A.g = c->geo();
+  A.tiles = c->d_tiles.as<int4>();
+  A.bblk = bblk;
+  A.gout = gout;
+  A.gsb = c->d_gsb.as<float2>();
+  A.part = c->d_part.as<double>();
+  A.map_cmpe = map_cmpe;
+  A.map_cf = map_cf;
+  A.img = img;
+  A.rho_thresh = rho;
+  A.sb_scale = sb_scale;
+  A.write_g = write_g;
+  const int nba = c->nba_max;
+  const int npr = nba;  // upper bound of pair rows
+  const size_t lds = sizeof(float2) * (size_t)nba * nba * SUB +
+                     (sizeof(float2) + sizeof(float)) * (size_t)c->pps * npr * npr;
+  hipLaunchKernelGGL(k_cmpe, dim3((unsigned)(c->P_int / SUB)), dim3(SUB), lds, c->stream, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_T(af_ctx* c, float* out) {
+  const long long Pc = c->P;
+  dim3 grid((unsigned)((Pc + 255) / 256), (unsigned)c->N);
+  hipLaunchKernelGGL(k_export_T, grid, dim3(256), 0, c->stream, c->geo(), c->d_tab.as<TabEntry>(),
+                     c->d_c2i.as<int>(), c->d_prange.as<int2>(), Pc, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_images(af_ctx* c, const float2* bblk, float2* blk_out, float2* img_out,
+                                float* maps_out) {
+  const long long Pc = c->P;
+  hipLaunchKernelGGL(k_export_img, dim3((unsigned)((Pc + 255) / 256)), dim3(256), 0, c->stream,
+                     c->geo(), bblk, c->d_tiles.as<int4>(), c->d_c2i.as<int>(), Pc, c->n_pix,
+                     c->d_maps.as<float>(), c->d_maps.as<float>() + c->n_tiles * c->ppt, blk_out,
+                     img_out, maps_out);
+  return hipGetLastError();
+}
+
+}  // namespace af

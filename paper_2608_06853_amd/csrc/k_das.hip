@@ -1,0 +1,217 @@
+// Synthetic-aperture delay-and-sum with phase rotation (Eq. 5) over block pairs,
+// and its adjoint with respect to the one-way travel times.
+//
+// A workgroup owns one tile of 256 spatially compact points (one point per
+// thread) and loops only over the elements that are active (apodisation,
+// Eq. 4) for some point of the tile.  Each sample is a linear interpolation of
+// two adjacent IQ samples of channel (t, r) at u = u_t + u_r, rotated by the
+// product of the two per-element phasors from the travel-time table.
+#include "af_internal.h"
+
+namespace af {
+namespace {
+
+struct Rx {
+  int ui;
+  float uf;
+  float2 e;
+};
+
+__device__ inline Rx load_rx(const TabEntry* __restrict__ tab, long long P, long long p, int r,
+                             int LO, int HI) {
+  Rx x;
+  if (r >= LO && r <= HI) {
+    const TabEntry te = tab[(long long)r * P + p];
+    x.ui = te.ui;
+    x.uf = te.uf;
+    x.e = make_float2(te.er, te.ei);
+  } else {
+    x.ui = SENTINEL;
+    x.uf = 0.f;
+    x.e = make_float2(0.f, 0.f);
+  }
+  return x;
+}
+
+// Sample index of channel (t, r): returns false when u lies outside [0, ns-1].
+__device__ inline bool sample_pos(int ui_t, float uf_t, int ui_r, float uf_r, int ns, int& k,
+                                  float& f) {
+  int kk = ui_t + ui_r;
+  float fsum = uf_t + uf_r;
+  const int carry = fsum >= 1.f ? 1 : 0;
+  kk += carry;
+  f = fsum - (float)carry;
+  if (kk == ns - 1 && f == 0.f) {
+    kk = ns - 2;
+    f = 1.f;
+  }
+  k = kk;
+  return (unsigned)kk <= (unsigned)(ns - 2);
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_das_fwd(DasArgs A) {
+  const Geo& g = A.g;
+  const int2 w = A.work[blockIdx.x];
+  const int tile = w.x, jb = w.y;
+  const int4 tr = A.tiles[tile];
+  const long long P = g.P;
+  const long long p = (long long)tile * TILE + threadIdx.x;
+  const int N = g.n_elem, ns = g.ns;
+
+  Rx rx[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) rx[k] = load_rx(A.tab, P, p, jb * S + k, tr.x, tr.y);
+
+  float2 acc = make_float2(0.f, 0.f);
+  for (int t = tr.x; t <= tr.y; ++t) {
+    const TabEntry et = A.tab[(long long)t * P + p];
+    const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
+    float ax = 0.f, ay = 0.f;
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      int kk;
+      float f;
+      if (sample_pos(et.ui, et.uf, rx[k].ui, rx[k].uf, ns, kk, f)) {
+        const float2* q = base + (long long)k * ns + kk;
+        const float2 a0 = q[0], a1 = q[1];
+        const float vx = fmaf(f, a1.x - a0.x, a0.x);
+        const float vy = fmaf(f, a1.y - a0.y, a0.y);
+        ax = fmaf(vx, rx[k].e.x, fmaf(-vy, rx[k].e.y, ax));
+        ay = fmaf(vx, rx[k].e.y, fmaf(vy, rx[k].e.x, ay));
+      }
+    }
+    acc.x = fmaf(ax, et.er, fmaf(-ay, et.ei, acc.x));
+    acc.y = fmaf(ax, et.ei, fmaf(ay, et.er, acc.y));
+    if (((t + 1) % S) == 0 || t == tr.y) {
+      const int ib = t / S;
+      A.bblk[((long long)ib * g.nblk + jb) * P + p] = acc;
+      acc = make_float2(0.f, 0.f);
+    }
+  }
+}
+
+// dL/dT[a][p]: for each sample, D = Re(conj(G) (v' + j w v) E_t E_r) feeds the
+// transmit element t and the receive element r.  The workgroup owns every
+// active element of its tile, so the sums are complete in LDS (no atomics).
+template <int S>
+__global__ __launch_bounds__(256) void k_das_adj(DasArgs A) {
+  extern __shared__ float gl[];  // [na][256]
+  const Geo& g = A.g;
+  const int tile = A.order[blockIdx.x];
+  const int4 tr = A.tiles[tile];
+  const long long P = g.P;
+  const int tid = threadIdx.x;
+  const long long p = (long long)tile * TILE + tid;
+  const int N = g.n_elem, ns = g.ns;
+  const int na = tr.y - tr.x + 1;
+  for (int a = 0; a < na; ++a) gl[a * TILE + tid] = 0.f;
+  const float fsf = (float)g.fs;
+  const float om = (float)(2.0 * 3.14159265358979323846 * g.fd);
+
+  for (int jb = tr.z; jb <= tr.w; ++jb) {
+    Rx rx[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) rx[k] = load_rx(A.tab, P, p, jb * S + k, tr.x, tr.y);
+    float grx[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) grx[k] = 0.f;
+    float2 G = make_float2(0.f, 0.f);
+    int gib = -1;
+    for (int t = tr.x; t <= tr.y; ++t) {
+      const int ib = t / S;
+      if (ib != gib) {
+        G = A.gblk[((long long)ib * g.nblk + jb) * P + p];
+        gib = ib;
+      }
+      const TabEntry et = A.tab[(long long)t * P + p];
+      // Q = conj(G) * E_t
+      const float qx = G.x * et.er + G.y * et.ei;
+      const float qy = G.x * et.ei - G.y * et.er;
+      const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
+      float gtx = 0.f;
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        int kk;
+        float f;
+        if (sample_pos(et.ui, et.uf, rx[k].ui, rx[k].uf, ns, kk, f)) {
+          const float2* q = base + (long long)k * ns + kk;
+          const float2 a0 = q[0], a1 = q[1];
+          const float dx = a1.x - a0.x, dy = a1.y - a0.y;
+          const float vx = fmaf(f, dx, a0.x), vy = fmaf(f, dy, a0.y);
+          const float wx = fmaf(fsf, dx, -om * vy);
+          const float wy = fmaf(fsf, dy, om * vx);
+          const float zx = wx * rx[k].e.x - wy * rx[k].e.y;
+          const float zy = wx * rx[k].e.y + wy * rx[k].e.x;
+          const float D = qx * zx - qy * zy;
+          gtx += D;
+          grx[k] += D;
+        }
+      }
+      gl[(t - tr.x) * TILE + tid] += gtx;
+    }
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const int r = jb * S + k;
+      if (r >= tr.x && r <= tr.y) gl[(r - tr.x) * TILE + tid] += grx[k];
+    }
+  }
+  for (int a = 0; a < na; ++a) A.gT[(long long)(tr.x + a) * P + p] = gl[a * TILE + tid];
+}
+
+template <int S>
+hipError_t das_fwd_s(af_ctx* c, const DasArgs& A) {
+  hipLaunchKernelGGL(k_das_fwd<S>, dim3(c->n_das_work), dim3(256), 0, c->stream, A);
+  return hipGetLastError();
+}
+
+template <int S>
+hipError_t das_adj_s(af_ctx* c, const DasArgs& A) {
+  const size_t lds = sizeof(float) * (size_t)c->na_max * TILE;
+  hipLaunchKernelGGL(k_das_adj<S>, dim3(c->n_order), dim3(256), lds, c->stream, A);
+  return hipGetLastError();
+}
+
+DasArgs das_args(af_ctx* c, const float2* iq) {
+  DasArgs A{};
+  A.g = c->geo();
+  A.tab = c->d_tab.as<TabEntry>();
+  A.iq = iq;
+  A.tiles = c->d_tiles.as<int4>();
+  A.work = c->d_daswork.as<int2>();
+  A.order = c->d_order.as<int>();
+  return A;
+}
+
+}  // namespace
+
+hipError_t launch_das_fwd(af_ctx* c, const float2* iq, float2* bblk) {
+  if (c->n_das_work == 0) return hipSuccess;
+  DasArgs A = das_args(c, iq);
+  A.bblk = bblk;
+  switch (c->S) {
+    case 1: return das_fwd_s<1>(c, A);
+    case 2: return das_fwd_s<2>(c, A);
+    case 4: return das_fwd_s<4>(c, A);
+    case 8: return das_fwd_s<8>(c, A);
+    case 16: return das_fwd_s<16>(c, A);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_das_adj(af_ctx* c, const float2* iq, const float2* gblk) {
+  if (c->n_order == 0) return hipSuccess;
+  DasArgs A = das_args(c, iq);
+  A.gblk = gblk;
+  A.gT = c->d_gT.as<float>();
+  switch (c->S) {
+    case 1: return das_adj_s<1>(c, A);
+    case 2: return das_adj_s<2>(c, A);
+    case 4: return das_adj_s<4>(c, A);
+    case 8: return das_adj_s<8>(c, A);
+    case 16: return das_adj_s<16>(c, A);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace af

@@ -1,0 +1,89 @@
+// Travel-time table: for every active (element, point) pair, the bent-ray time
+// T = L1/c_lens + L2 * (trapezoid sum of bicubic slowness)/N (Eqs. 1, 7-8 and
+// Section III-A), stored as the sample position and apodised phasor DAS needs.
+//
+// FP64 appears only inside the lens refraction (trace_lens): the homogeneous
+// time T_hom = L1/c_lens + L2/c_med at the stationary point.  The path integral
+// is taken over the deviation s - s_med in FP32, so T = T_hom + dT with dT small;
+// the sample index and the phase are reduced from T_hom in FP64 before dT is
+// added in FP32.
+#include "af_internal.h"
+
+namespace af {
+namespace {
+
+__global__ __launch_bounds__(256) void k_table(TableArgs A) {
+  extern __shared__ float G[];
+  const Geo& g = A.g;
+  const int2 w = A.work[blockIdx.x];
+  const int tile = w.x, a0 = w.y;
+  const int4 tr = A.tiles[tile];
+  const int gsz = g.W * (g.nz + 3);
+  for (int i = threadIdx.x; i < gsz; i += 256) G[i] = A.gdev[i];
+  __syncthreads();
+
+  const long long p = (long long)tile * TILE + threadIdx.x;
+  const int2 pr = A.prange[p];
+  const double4 pp = A.ptpol[p];
+  const float2 pxy = A.ptxy[p];
+  const double icm = A.scal[1];
+  const float inv_n = 1.f / (float)g.n_seg;
+  const float up = (pxy.x - g.x0) * g.idx, vp = (pxy.y - g.z0) * g.idz;
+  const float umax = (float)(g.nx - 1), vmax = (float)(g.nz - 1);
+  const double half_ttp = 0.5 * g.t_ttp;
+  const double u_off = half_ttp - 0.5 * g.t0;
+  const float fsf = (float)g.fs, fdf = (float)g.fd;
+  const int a1 = min(a0 + TAB_CHUNK - 1, tr.y);
+  for (int a = a0; a <= a1; ++a) {
+    TabEntry e;
+    if (a < pr.x || a > pr.y) {
+      e.ui = SENTINEL;
+      e.uf = 0.f;
+      e.er = 0.f;
+      e.ei = 0.f;
+    } else {
+      const double4 el = A.elem[a];
+      const RayOut r = trace_lens(el.x, el.y, el.z, pp.x, pp.y, pp.z, g.dlens, g.icl, icm);
+      const float u0 = (r.refx - g.x0) * g.idx, v0 = (r.refz - g.z0) * g.idz;
+      const float acc = path_sum(G, g.W, u0, v0, (up - u0) * inv_n, (vp - v0) * inv_n, g.n_seg,
+                                 umax, vmax);
+      const float dT = r.l2 * acc * inv_n;
+      const double uh = (r.t_hom + u_off) * g.fs;
+      const double kh = floor(uh);
+      float uf = (float)(uh - kh) + dT * fsf;
+      const float cf = floorf(uf);
+      e.ui = (int)kh + (int)cf;
+      e.uf = uf - cf;
+      double cyc = (r.t_hom + half_ttp) * g.fd;
+      cyc -= rint(cyc);
+      const float cy = (float)cyc + dT * fdf;
+      float sn, cs;
+      sincospif(2.f * cy, &sn, &cs);
+      e.er = cs;
+      e.ei = sn;
+    }
+    A.tab[(size_t)a * g.P + p] = e;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_table(af_ctx* c) {
+  TableArgs A;
+  A.g = c->geo();
+  A.elem = c->d_elem.as<double4>();
+  A.ptpol = c->d_ptpol.as<double4>();
+  A.ptxy = c->d_ptxy.as<float2>();
+  A.prange = c->d_prange.as<int2>();
+  A.tiles = c->d_tiles.as<int4>();
+  A.work = c->d_tabwork.as<int2>();
+  A.gdev = c->d_gdev.as<float>();
+  A.scal = c->d_scal.as<double>();
+  A.tab = c->d_tab.as<TabEntry>();
+  if (c->n_tab_work == 0) return hipSuccess;
+  const size_t lds = sizeof(float) * (size_t)(c->nx + 3) * (c->nz + 3);
+  hipLaunchKernelGGL(k_table, dim3(c->n_tab_work), dim3(256), lds, c->stream, A);
+  return hipGetLastError();
+}
+
+}  // namespace af

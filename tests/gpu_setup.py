@@ -1,0 +1,86 @@
+"""Shared set-up of GPU parity tests: one seeded workload fed to both the oracle
+and the library (inputs come from afsynth / the oracle simulator only)."""
+from __future__ import annotations
+
+import functools
+import os
+from dataclasses import replace
+
+import numpy as np
+
+import afsynth
+import problems
+from oracle import model
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def ensure_built():
+    lib = os.path.join(ROOT, "paper_2608_06853_amd", "libaf.so")
+    if not os.path.exists(lib):
+        from paper_2608_06853_amd import build
+        build.build()
+    return lib
+
+
+def gpu_available() -> bool:
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+# A configs[0]-geometry case small enough for the oracle: 32 elements (8 blocks),
+# 24 x 20 pixels (480 patches -> 18 tiles, ragged tail), 8 x 8 slowness grid.
+C1_SMALL = afsynth.configs.C1.with_(
+    name="c1_small",
+    img=afsynth.ImgCfg(n_depth=24, n_angle=20, depth_min=3.0, depth_max=55.0),
+    n_scat_random=1200,
+)
+
+MICRO = afsynth.configs.MICRO
+
+
+@functools.lru_cache(maxsize=8)
+def case(name: str, t0: float = 0.0, t_ttp: float = 0.0, patch: int = 3, block: int | None = None,
+         perturb: float = 0.01):
+    """(cfg, oracle problem, iq complex64, s [nz][nx] float32, loss params)."""
+    base = {"micro": MICRO, "c1_small": C1_SMALL}[name]
+    cfg = base.with_(array=replace(base.array, t_ttp=t_ttp), acq=replace(base.acq, t0=t0),
+                     img=replace(base.img, patch=patch))
+    if block is not None:
+        cfg = cfg.with_(method=replace(cfg.method, block=block))
+    med = afsynth.medium_for(cfg)
+    iq = problems.simulate_iq(cfg, med, n_seg=64).astype(np.complex64)
+    prob = problems.problem(cfg, iq.astype(np.complex128))
+    s_true = problems.true_slowness(cfg, med, prob)
+    rng = np.random.default_rng(cfg.seed + 11)
+    s = (s_true * (1.0 + perturb * rng.standard_normal(s_true.shape))).astype(np.float32)
+    lp = problems.loss_params(cfg, sb_ref=float(np.mean(np.abs(iq)) ** 2 * 50.0))
+    lp = model.LossParams(**{**lp.__dict__, "w_sb": 0.05, "rho_thresh": 0.5})
+    return cfg, prob, iq, s, lp
+
+
+def lib_params(lp):
+    from paper_2608_06853_amd import _lib
+    return _lib.loss_params(lp.w1, lp.kx1, lp.kz1, lp.w2, lp.kx2, lp.kz2, lp.rho_thresh, lp.w_sb,
+                            lp.sb_ref)
+
+
+def beamformer(cfg, prob, device=0):
+    from paper_2608_06853_amd import autofocus as af
+    acq = af.Acquisition(elem_xz=prob.elem_xz, d_lens=prob.d_lens, c_lens=prob.c_lens,
+                         t_ttp=prob.t_ttp, fs=prob.fs, t0=prob.t0, fd=prob.fd,
+                         n_samples=prob.iq.shape[2])
+    img = af.Imaging(centres=prob.centres, patch=prob.patch, spacing=prob.spacing,
+                     block=prob.block, fnum=prob.fnum, n_seg=prob.n_seg)
+    x0, z0, dx, dz, nx, nz = prob.grid
+    grid = af.Grid(nx=nx, nz=nz, x0=x0, z0=z0, dx=dx, dz=dz)
+    return af.Beamformer(acq, img, grid, device)
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-30))

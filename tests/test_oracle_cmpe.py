@@ -36,6 +36,9 @@ def test_threshold_and_zero_energy():
     assert nv == (ns - 1) ** 2 * n_pix - 1
     _, nv_hi, _, d = cmpe.cmpe_loss(bsub, M, 0.9)
     assert np.all(d["valid"] == (d["rho"] >= 0.9) & (d["ex"] > 0) & (d["ey"] > 0))
+    # energies too small for FP32 (|C|^2 underflows) count as empty
+    tiny = bsub * 1e-18
+    assert cmpe.cmpe_loss(tiny, M, 0.0)[1] == 0
     assert cmpe.cmpe_loss(np.zeros_like(bsub), M, 0.5)[0] == 0.0
 
 
