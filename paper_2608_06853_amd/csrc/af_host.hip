@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -333,7 +334,7 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
 
   AF_ALLOC(c->d_tab, sizeof(af::TabEntry) * (size_t)N * P_int, "travel-time table");
   AF_ALLOC(c->d_bblk, sizeof(float2) * (size_t)c->nb * c->nb * P_int, "block images");
-  AF_ALLOC(c->d_gT, sizeof(float) * (size_t)N * P_int, "time gradient");
+  AF_ALLOC(c->d_gT, sizeof(float) * 2 * (size_t)N * P_int, "time gradient");
   AF_ALLOC(c->d_gsb, sizeof(float2) * (size_t)P_int, "brightness gradient");
   AF_ALLOC(c->d_part, sizeof(double) * 4 * (size_t)(P_int / SUB), "partials");
   AF_ALLOC(c->d_maps, sizeof(float) * 2 * (size_t)n_tiles * ppt, "maps");
@@ -400,6 +401,7 @@ af_status af_set_slowness(af_ctx* c, int nx, int nz, double x0, double z0, doubl
   AF_ALLOC(c->d_grad, sizeof(float) * n, "gradient");
   AF_ALLOC(c->d_gdev, sizeof(float) * np, "deviation grid");
   AF_ALLOC(c->d_gpad, sizeof(float) * np, "padded gradient");
+  AF_ALLOC(c->d_gpart, sizeof(float) * np * std::max(c->n_order, 1), "partial gradients");
   AF_ALLOC(c->d_terms, sizeof(float) * 8, "terms");
   AF_HIP(hipMemcpyAsync(c->d_s.p, s_dev, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream),
          "af_set_slowness copy");

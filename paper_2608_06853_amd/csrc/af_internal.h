@@ -70,7 +70,8 @@ struct DasArgs {
   const int* order;       // tile order for the adjoint
   float2* bblk;           // [nb][nb][P]  (forward output)
   const float2* gblk;     // [nb][nb][P]  (adjoint input, final scale applied)
-  float* gT;              // [n_elem][P]  dL/dT (adjoint output)
+  float* gT;              // [n_elem][P]  dL/dT, receive role (adjoint output)
+  float* gT2;             // [n_elem][P]  dL/dT, transmit role (atomic adds)
 };
 
 struct CmpeArgs {
@@ -96,10 +97,10 @@ struct PathArgs {
   const int2* prange;
   const int4* tiles;
   const int* order;
-  const float* gT;        // dL/dT [n_elem][P]
+  const float* gT;        // dL/dT [n_elem][P], receive role
+  const float* gT2;       // dL/dT [n_elem][P], transmit role
   const double* scal;
-  float* gpad;            // padded grid gradient (global atomics)
-  int copies;             // interleaved private copies in LDS
+  float* gpart;           // [n_wg][padded nodes] per-workgroup partial grids
 };
 
 }  // namespace af
@@ -137,7 +138,7 @@ struct af_ctx {
   // device buffers
   af::DBuf d_elem, d_ptpol, d_ptxy, d_prange, d_tiles, d_tabwork, d_daswork, d_order, d_i2c,
       d_c2i;
-  af::DBuf d_s, d_gdev, d_regg, d_scal, d_tab, d_bblk, d_g, d_gT, d_gsb, d_part, d_gpad,
+  af::DBuf d_s, d_gdev, d_regg, d_scal, d_tab, d_bblk, d_g, d_gT, d_gsb, d_part, d_gpad, d_gpart,
       d_grad, d_terms, d_maps, d_img;
 
   af::Geo geo() const;

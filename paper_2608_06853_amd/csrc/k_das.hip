@@ -92,71 +92,76 @@ __global__ __launch_bounds__(256) void k_das_fwd(DasArgs A) {
 }
 
 // dL/dT[a][p]: for each sample, D = Re(conj(G) (v' + j w v) E_t E_r) feeds the
-// transmit element t and the receive element r.  The workgroup owns every
-// active element of its tile, so the sums are complete in LDS (no atomics).
+// transmit element t and the receive element r.  One workgroup per (tile,
+// receive block) as in the forward: the receive-role sums of its S elements are
+// complete and written directly; the transmit-role sums of every t are partial
+// (one per receive block) and are added with global atomics.
 template <int S>
 __global__ __launch_bounds__(256) void k_das_adj(DasArgs A) {
-  extern __shared__ float gl[];  // [na][256]
   const Geo& g = A.g;
-  const int tile = A.order[blockIdx.x];
+  const int2 w = A.work[blockIdx.x];
+  const int tile = w.x, jb = w.y;
   const int4 tr = A.tiles[tile];
   const long long P = g.P;
-  const int tid = threadIdx.x;
-  const long long p = (long long)tile * TILE + tid;
+  const long long p = (long long)tile * TILE + threadIdx.x;
   const int N = g.n_elem, ns = g.ns;
-  const int na = tr.y - tr.x + 1;
-  for (int a = 0; a < na; ++a) gl[a * TILE + tid] = 0.f;
   const float fsf = (float)g.fs;
   const float om = (float)(2.0 * 3.14159265358979323846 * g.fd);
 
-  for (int jb = tr.z; jb <= tr.w; ++jb) {
-    Rx rx[S];
+  Rx rx[S];
 #pragma unroll
-    for (int k = 0; k < S; ++k) rx[k] = load_rx(A.tab, P, p, jb * S + k, tr.x, tr.y);
-    float grx[S];
+  for (int k = 0; k < S; ++k) rx[k] = load_rx(A.tab, P, p, jb * S + k, tr.x, tr.y);
+  float grx[S];
 #pragma unroll
-    for (int k = 0; k < S; ++k) grx[k] = 0.f;
-    float2 G = make_float2(0.f, 0.f);
-    int gib = -1;
-    for (int t = tr.x; t <= tr.y; ++t) {
-      const int ib = t / S;
-      if (ib != gib) {
-        G = A.gblk[((long long)ib * g.nblk + jb) * P + p];
-        gib = ib;
-      }
-      const TabEntry et = A.tab[(long long)t * P + p];
-      // Q = conj(G) * E_t
-      const float qx = G.x * et.er + G.y * et.ei;
-      const float qy = G.x * et.ei - G.y * et.er;
-      const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
-      float gtx = 0.f;
-#pragma unroll
-      for (int k = 0; k < S; ++k) {
-        int kk;
-        float f;
-        if (sample_pos(et.ui, et.uf, rx[k].ui, rx[k].uf, ns, kk, f)) {
-          const float2* q = base + (long long)k * ns + kk;
-          const float2 a0 = q[0], a1 = q[1];
-          const float dx = a1.x - a0.x, dy = a1.y - a0.y;
-          const float vx = fmaf(f, dx, a0.x), vy = fmaf(f, dy, a0.y);
-          const float wx = fmaf(fsf, dx, -om * vy);
-          const float wy = fmaf(fsf, dy, om * vx);
-          const float zx = wx * rx[k].e.x - wy * rx[k].e.y;
-          const float zy = wx * rx[k].e.y + wy * rx[k].e.x;
-          const float D = qx * zx - qy * zy;
-          gtx += D;
-          grx[k] += D;
-        }
-      }
-      gl[(t - tr.x) * TILE + tid] += gtx;
+  for (int k = 0; k < S; ++k) grx[k] = 0.f;
+  float2 G = make_float2(0.f, 0.f);
+  int gib = -1;
+  for (int t = tr.x; t <= tr.y; ++t) {
+    const int ib = t / S;
+    if (ib != gib) {
+      G = A.gblk[((long long)ib * g.nblk + jb) * P + p];
+      gib = ib;
     }
+    const TabEntry et = A.tab[(long long)t * P + p];
+    // Q = conj(G) * E_t
+    const float qx = G.x * et.er + G.y * et.ei;
+    const float qy = G.x * et.ei - G.y * et.er;
+    const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
+    float gtx = 0.f;
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-      const int r = jb * S + k;
-      if (r >= tr.x && r <= tr.y) gl[(r - tr.x) * TILE + tid] += grx[k];
+      int kk;
+      float f;
+      if (sample_pos(et.ui, et.uf, rx[k].ui, rx[k].uf, ns, kk, f)) {
+        const float2* q = base + (long long)k * ns + kk;
+        const float2 a0 = q[0], a1 = q[1];
+        const float dx = a1.x - a0.x, dy = a1.y - a0.y;
+        const float vx = fmaf(f, dx, a0.x), vy = fmaf(f, dy, a0.y);
+        const float wx = fmaf(fsf, dx, -om * vy);
+        const float wy = fmaf(fsf, dy, om * vx);
+        const float zx = wx * rx[k].e.x - wy * rx[k].e.y;
+        const float zy = wx * rx[k].e.y + wy * rx[k].e.x;
+        const float D = qx * zx - qy * zy;
+        gtx += D;
+        grx[k] += D;
+      }
     }
+    if (gtx != 0.f) atomicAdd(A.gT2 + (long long)t * P + p, gtx);
   }
-  for (int a = 0; a < na; ++a) A.gT[(long long)(tr.x + a) * P + p] = gl[a * TILE + tid];
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const int r = jb * S + k;
+    if (r >= tr.x && r <= tr.y) A.gT[(long long)r * P + p] = grx[k];
+  }
+}
+
+// Zero the transmit-role sums over the active elements of every tile.
+__global__ __launch_bounds__(256) void k_zero_tx(Geo g, const int4* __restrict__ tiles,
+                                                 float* __restrict__ gT2) {
+  const int tile = blockIdx.x;
+  const int4 tr = tiles[tile];
+  const long long p = (long long)tile * TILE + threadIdx.x;
+  for (int a = tr.x; a <= tr.y; ++a) gT2[(long long)a * g.P + p] = 0.f;
 }
 
 template <int S>
@@ -167,8 +172,10 @@ hipError_t das_fwd_s(af_ctx* c, const DasArgs& A) {
 
 template <int S>
 hipError_t das_adj_s(af_ctx* c, const DasArgs& A) {
-  const size_t lds = sizeof(float) * (size_t)c->na_max * TILE;
-  hipLaunchKernelGGL(k_das_adj<S>, dim3(c->n_order), dim3(256), lds, c->stream, A);
+  hipLaunchKernelGGL(k_zero_tx, dim3(c->n_tiles), dim3(256), 0, c->stream, A.g, A.tiles, A.gT2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_das_adj<S>, dim3(c->n_das_work), dim3(256), 0, c->stream, A);
   return hipGetLastError();
 }
 
@@ -200,10 +207,11 @@ hipError_t launch_das_fwd(af_ctx* c, const float2* iq, float2* bblk) {
 }
 
 hipError_t launch_das_adj(af_ctx* c, const float2* iq, const float2* gblk) {
-  if (c->n_order == 0) return hipSuccess;
+  if (c->n_das_work == 0) return hipSuccess;
   DasArgs A = das_args(c, iq);
   A.gblk = gblk;
   A.gT = c->d_gT.as<float>();
+  A.gT2 = c->d_gT.as<float>() + (size_t)c->N * c->P_int;
   switch (c->S) {
     case 1: return das_adj_s<1>(c, A);
     case 2: return das_adj_s<2>(c, A);

@@ -2,28 +2,62 @@
 // dL/dT * L2 * w_k * (bicubic weight of the node at r_k) / N.  Refraction points
 // and c_med are held constant (they follow the global mean speed).
 //
-// A workgroup takes one tile of points and every active element of it.  The
-// rays of a wavefront are nearly parallel, so at a given k their lanes touch the
-// same grid nodes; the workgroup therefore scatters into `copies` interleaved
-// private copies of the padded grid in LDS (copy = lane mod copies) so lanes
-// that hit one node land in different banks.  The copies are summed at the end
-// and added to the global padded grid with one atomic per node.
+// A workgroup takes one tile of points and every active element of it; a
+// wavefront walks the rays from one element to its 64 points in lock step.  The
+// rays are nearly parallel, so at a given step the lanes usually sit in one grid
+// cell: the 16 tap weights are then summed across the wavefront with a
+// reduce-scatter (17 lane shuffles) and 16 lanes add the sums to the
+// wavefront's private copy of the padded grid with plain LDS read-add-writes
+// (no LDS atomics).  Lanes spread over several cells are handled one cell at a
+// time.  The copies are summed into one partial grid per workgroup, and a
+// second kernel adds the partial grids node by node in a fixed order.
 #include "af_internal.h"
 
 namespace af {
 namespace {
 
+// Sum over the wavefront of v[i], i = 0..15; lane l (l % 4 == 0) returns the sum
+// of v[l / 4] (every lane returns the sum of v[(l >> 2) & 15]).
+__device__ inline float reduce_scatter16(const float v[16], int lane) {
+  float h8[8], h4[4], h2[2];
+  const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0, b3 = (lane & 8) != 0,
+             b2 = (lane & 4) != 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float send = b5 ? v[i] : v[8 + i];
+    const float keep = b5 ? v[8 + i] : v[i];
+    h8[i] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float send = b4 ? h8[i] : h8[4 + i];
+    const float keep = b4 ? h8[4 + i] : h8[i];
+    h4[i] = keep + __shfl_xor(send, 16, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float send = b3 ? h4[i] : h4[2 + i];
+    const float keep = b3 ? h4[2 + i] : h4[i];
+    h2[i] = keep + __shfl_xor(send, 8, 64);
+  }
+  float h1 = (b2 ? h2[1] : h2[0]) + __shfl_xor(b2 ? h2[0] : h2[1], 4, 64);
+  h1 += __shfl_xor(h1, 2, 64);
+  h1 += __shfl_xor(h1, 1, 64);
+  return h1;
+}
+
 __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
-  extern __shared__ float sg[];
+  extern __shared__ float sg[];  // [4 wavefronts][nodes]
   const Geo& g = A.g;
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
   const int tile = A.order[blockIdx.x];
   const int4 tr = A.tiles[tile];
-  const int C = A.copies;
   const int W = g.W;
   const int nodes = W * (g.nz + 3);
-  for (int i = tid; i < nodes * C; i += 256) sg[i] = 0.f;
+  for (int i = tid; i < 4 * nodes; i += 256) sg[i] = 0.f;
   __syncthreads();
+  float* grid = sg + (tid >> 6) * nodes;
 
   const long long p = (long long)tile * TILE + tid;
   const int2 pr = A.prange[p];
@@ -33,16 +67,23 @@ __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
   const float inv_n = 1.f / (float)g.n_seg;
   const float up = (pxy.x - g.x0) * g.idx, vp = (pxy.y - g.z0) * g.idz;
   const float umax = (float)(g.nx - 1), vmax = (float)(g.nz - 1);
-  const int lc = tid % C;
-  const int a_lo = max(tr.x, pr.x), a_hi = min(tr.y, pr.y);
-  for (int a = a_lo; a <= a_hi; ++a) {
-    const float gbar = A.gT[(long long)a * g.P + p];
-    if (gbar == 0.f) continue;
+  // tap (r, c) of value index i = 4 r + c; this lane's reduced tap
+  const int my_tap = (lane >> 2) & 15;
+  const int my_off = (my_tap >> 2) * W + (my_tap & 3);
+
+  for (int a = tr.x; a <= tr.y; ++a) {  // wavefront-uniform loop
+    const bool act = a >= pr.x && a <= pr.y;
+    float gbar = 0.f;
+    if (act) gbar = A.gT[(long long)a * g.P + p] + A.gT2[(long long)a * g.P + p];
+    const bool live = act && gbar != 0.f;
+    const unsigned long long lmask = __ballot(live);
+    if (lmask == 0ull) continue;
     const double4 el = A.elem[a];
     const RayOut r = trace_lens(el.x, el.y, el.z, pp.x, pp.y, pp.z, g.dlens, g.icl, icm);
-    const float coef = gbar * r.l2 * inv_n;
+    const float coef = live ? gbar * r.l2 * inv_n : 0.f;
     const float u0 = (r.refx - g.x0) * g.idx, v0 = (r.refz - g.z0) * g.idz;
     const float du = (up - u0) * inv_n, dv = (vp - v0) * inv_n;
+    const int lead = __ffsll((long long)lmask) - 1;
     for (int k = 0; k <= g.n_seg; ++k) {
       const float u = fminf(fmaxf(fmaf((float)k, du, u0), 0.f), umax);
       const float v = fminf(fmaxf(fmaf((float)k, dv, v0), 0.f), vmax);
@@ -51,21 +92,49 @@ __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
       keys_weights(u - (float)j0, wx[0], wx[1], wx[2], wx[3]);
       keys_weights(v - (float)i0, wz[0], wz[1], wz[2], wz[3]);
       const float ck = (k == 0 || k == g.n_seg) ? 0.5f * coef : coef;
-      float* base = sg + (i0 * W + j0) * C + lc;
+      float val[16];
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const float cr = ck * wz[rr];
+      for (int i = 0; i < 16; ++i) val[i] = ck * wz[i >> 2] * wx[i & 3];
+      int cell = i0 * W + j0;
+      const int c0 = __shfl(cell, lead, 64);
+      if (!live) cell = c0;  // idle lanes (zero weights) join the leader's cell
+      bool done = false;
+      int ccur = c0;
+      // one round per distinct cell among the wavefront's lanes (usually one)
+      while (true) {
+        const bool in = !done && cell == ccur;
+        float vv[16];
 #pragma unroll
-        for (int cc = 0; cc < 4; ++cc) atomicAdd(base + (rr * W + cc) * C, cr * wx[cc]);
+        for (int i = 0; i < 16; ++i) vv[i] = in ? val[i] : 0.f;
+        const float sum = reduce_scatter16(vv, lane);
+        if ((lane & 3) == 0) grid[ccur + my_off] += sum;
+        done = done || in;
+        const unsigned long long rest = __ballot(!done);
+        if (rest == 0ull) break;
+        ccur = __shfl(cell, __ffsll((long long)rest) - 1, 64);
       }
     }
   }
   __syncthreads();
-  for (int n = tid; n < nodes; n += 256) {
-    float s = 0.f;
-    for (int cc = 0; cc < C; ++cc) s += sg[n * C + cc];
-    if (s != 0.f) atomicAdd(A.gpad + n, s);
-  }
+  // per-workgroup partial grid (plain stores); summed in fixed order by k_path_reduce
+  float* part = A.gpart + (long long)blockIdx.x * nodes;
+  for (int n = tid; n < nodes; n += 256)
+    part[n] = (sg[n] + sg[nodes + n]) + (sg[2 * nodes + n] + sg[3 * nodes + n]);
+}
+
+// gpad[n] = sum over workgroups of their partial grids (fixed order: deterministic).
+__global__ __launch_bounds__(256) void k_path_reduce(const float* __restrict__ gpart, int n_wg,
+                                                     int nodes, float* __restrict__ gpad) {
+  const int n = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int lane_grp = threadIdx.x >> 6;  // 4 groups stride over the workgroups
+  __shared__ float red[4][64];
+  float s = 0.f;
+  if (n < nodes)
+    for (int w = lane_grp; w < n_wg; w += 4) s += gpart[(long long)w * nodes + n];
+  red[lane_grp][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (lane_grp == 0 && n < nodes)
+    gpad[n] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
 __global__ __launch_bounds__(256) void k_zero(float* __restrict__ x, long long n) {
@@ -77,11 +146,11 @@ __global__ __launch_bounds__(256) void k_zero(float* __restrict__ x, long long n
 
 hipError_t launch_path_adj(af_ctx* c) {
   const int nodes = (c->nx + 3) * (c->nz + 3);
-  hipLaunchKernelGGL(k_zero, dim3((nodes + 255) / 256), dim3(256), 0, c->stream,
-                     c->d_gpad.as<float>(), (long long)nodes);
-  if (c->n_order == 0) return hipGetLastError();
-  int copies = 16;
-  while (copies > 1 && (size_t)nodes * copies * sizeof(float) > 80 * 1024) copies >>= 1;
+  if (c->n_order == 0) {
+    hipLaunchKernelGGL(k_zero, dim3((nodes + 255) / 256), dim3(256), 0, c->stream,
+                       c->d_gpad.as<float>(), (long long)nodes);
+    return hipGetLastError();
+  }
   PathArgs A{};
   A.g = c->geo();
   A.elem = c->d_elem.as<double4>();
@@ -91,11 +160,15 @@ hipError_t launch_path_adj(af_ctx* c) {
   A.tiles = c->d_tiles.as<int4>();
   A.order = c->d_order.as<int>();
   A.gT = c->d_gT.as<float>();
+  A.gT2 = c->d_gT.as<float>() + (size_t)c->N * c->P_int;
   A.scal = c->d_scal.as<double>();
-  A.gpad = c->d_gpad.as<float>();
-  A.copies = copies;
-  const size_t lds = sizeof(float) * (size_t)nodes * copies;
+  A.gpart = c->d_gpart.as<float>();
+  const size_t lds = sizeof(float) * (size_t)nodes * 4;
   hipLaunchKernelGGL(k_path_adj, dim3(c->n_order), dim3(256), lds, c->stream, A);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_path_reduce, dim3((nodes + 63) / 64), dim3(256), 0, c->stream,
+                     c->d_gpart.as<float>(), c->n_order, nodes, c->d_gpad.as<float>());
   return hipGetLastError();
 }
 
