@@ -188,7 +188,10 @@ def main():
                                f"x 3x3 patch to {cfg.img.depth_max} mm, {met.nx}x{met.nz} slowness grid, "
                                f"one loss_and_grad per step",
                    "nominal_samples": nominal, "active_samples": active_samples,
-                   "active_rays": active_rays, "active_Gsamples_per_s":
+                   "active_rays": active_rays, "tiles": bf.ctx.query(_lib.Q_TILES),
+                   "tile_active_elements_max": bf.ctx.query(_lib.Q_NA_MAX),
+                   "tile_active_blocks_max": bf.ctx.query(_lib.Q_NBA_MAX),
+                   "active_Gsamples_per_s":
                        round(active_samples * args.steps / dt / 1e9, 2)},
         "roofline": roof,
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in sorted(prof.items())},

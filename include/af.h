@@ -178,7 +178,9 @@ enum {
   AF_Q_GBLK_ELEMS = 3,   /* complex elements of gblk_dev for af_forward */
   AF_Q_ACTIVE_PAIRS = 4, /* sum over points of active elements (rays) */
   AF_Q_ACTIVE_SAMPLES = 5, /* sum over points of active (t, r) pairs */
-  AF_Q_TILES = 6
+  AF_Q_TILES = 6,
+  AF_Q_NA_MAX = 7,       /* largest active element range of a tile */
+  AF_Q_NBA_MAX = 8       /* largest active block range of a tile */
 };
 af_status af_query(af_ctx* ctx, int what, long long* out);
 

@@ -24,7 +24,8 @@ _lib = C.CDLL(LIB_PATH)
 AF_OK, AF_ERR_ARG, AF_ERR_STATE, AF_ERR_HIP, AF_ERR_OOM, AF_ERR_NUMERIC = 0, -1, -2, -3, -4, -5
 TERM_CMPE, TERM_TV, TERM_SV, TERM_SB, TERM_TOTAL, TERM_NVALID, TERM_CMED = range(7)
 N_TERMS = 8
-Q_P, Q_P_INTERNAL, Q_NBLK, Q_GBLK_ELEMS, Q_ACTIVE_PAIRS, Q_ACTIVE_SAMPLES, Q_TILES = range(7)
+(Q_P, Q_P_INTERNAL, Q_NBLK, Q_GBLK_ELEMS, Q_ACTIVE_PAIRS, Q_ACTIVE_SAMPLES, Q_TILES, Q_NA_MAX,
+ Q_NBA_MAX) = range(9)
 
 EXPORTS = [
     "af_create", "af_destroy", "af_last_error", "af_set_geometry", "af_set_lens",

@@ -53,13 +53,28 @@ af_status hip_fail(af_ctx* c, hipError_t e, const char* where) {
       return fail(c, AF_ERR_OOM, std::string("af: cannot allocate ") + (what));       \
   } while (0)
 
-uint64_t spread16(uint32_t v) {
-  uint64_t x = v & 0xffff;
-  x = (x | (x << 8)) & 0x00ff00ffULL;
-  x = (x | (x << 4)) & 0x0f0f0f0fULL;
-  x = (x | (x << 2)) & 0x33333333ULL;
-  x = (x | (x << 1)) & 0x55555555ULL;
-  return x;
+// Orders idx[0..n) so that consecutive runs of `unit` items (and of `sub` items
+// inside them) are spatially compact: recursive median split along the longer
+// extent of (u, v), with the left part always a whole number of units.
+void kd_partition(int* idx, int n, int unit, int sub, const std::vector<double>& u,
+                  const std::vector<double>& v) {
+  if (n <= sub) return;
+  const int q = n > unit ? unit : sub;
+  const int n_left = q * ((n + 2 * q - 1) / (2 * q));
+  if (n_left >= n) return;
+  double ulo = 1e300, uhi = -1e300, vlo = 1e300, vhi = -1e300;
+  for (int k = 0; k < n; ++k) {
+    ulo = std::min(ulo, u[idx[k]]);
+    uhi = std::max(uhi, u[idx[k]]);
+    vlo = std::min(vlo, v[idx[k]]);
+    vhi = std::max(vhi, v[idx[k]]);
+  }
+  const std::vector<double>& key = (uhi - ulo) >= (vhi - vlo) ? u : v;
+  std::nth_element(idx, idx + n_left, idx + n, [&](int a, int b) {
+    return key[a] < key[b] || (key[a] == key[b] && a < b);
+  });
+  kd_partition(idx, n_left, unit, sub, u, v);
+  kd_partition(idx + n_left, n - n_left, unit, sub, u, v);
 }
 
 template <class T>
@@ -221,31 +236,26 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
     hi_c[p] = cnt > 0 ? hi : 0;
   }
 
-  // spatial tiling of the pixels: Morton order of quantised (radius, angle)
+  // spatial tiling of the pixels: k-d partition in (depth, arc length) whose
+  // splits are multiples of the tile (ppt pixels) and sub-tile (pps pixels)
+  // sizes, so every tile and sub-tile is a compact blob
   const int pps = SUB / M;          // whole patches per 64-point sub-tile
   const int ppt = 4 * pps;          // patches per 256-point tile
   c->pps = pps;
   c->ppt = ppt;
-  std::vector<double> prho(n_pix), pang(n_pix);
-  double rmin = 1e300, rmax = -1e300, amin = 1e300, amax = -1e300;
-  for (int q = 0; q < n_pix; ++q) {
-    prho[q] = std::hypot(pix_xz[2 * q], pix_xz[2 * q + 1]);
-    pang[q] = std::atan2(pix_xz[2 * q], pix_xz[2 * q + 1]);
-    rmin = std::min(rmin, prho[q]);
-    rmax = std::max(rmax, prho[q]);
-    amin = std::min(amin, pang[q]);
-    amax = std::max(amax, pang[q]);
-  }
-  std::vector<uint64_t> key(n_pix);
-  for (int q = 0; q < n_pix; ++q) {
-    const uint32_t qr = (uint32_t)std::lround((prho[q] - rmin) / std::max(rmax - rmin, 1e-12) * 65535.0);
-    const uint32_t qa = (uint32_t)std::lround((pang[q] - amin) / std::max(amax - amin, 1e-12) * 65535.0);
-    key[q] = (spread16(qr) << 1) | spread16(qa);
+  std::vector<double> cu(n_pix), cv(n_pix);
+  {
+    double rsum = 0;
+    for (int q = 0; q < n_pix; ++q) rsum += std::hypot(pix_xz[2 * q], pix_xz[2 * q + 1]);
+    const double rref = rsum / n_pix;
+    for (int q = 0; q < n_pix; ++q) {
+      cu[q] = std::hypot(pix_xz[2 * q], pix_xz[2 * q + 1]);
+      cv[q] = std::atan2(pix_xz[2 * q], pix_xz[2 * q + 1]) * rref;
+    }
   }
   std::vector<int> ord(n_pix);
   std::iota(ord.begin(), ord.end(), 0);
-  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return key[a] < key[b]; });
-
+  kd_partition(ord.data(), n_pix, ppt, pps, cu, cv);
   const int n_tiles = (n_pix + ppt - 1) / ppt;
   const long long P_int = (long long)n_tiles * TILE;
   c->n_tiles = n_tiles;
@@ -601,6 +611,8 @@ af_status af_query(af_ctx* c, int what, long long* out) {
     case AF_Q_ACTIVE_PAIRS: *out = c->active_pairs; break;
     case AF_Q_ACTIVE_SAMPLES: *out = c->active_samples; break;
     case AF_Q_TILES: *out = c->n_tiles; break;
+    case AF_Q_NA_MAX: *out = c->na_max; break;
+    case AF_Q_NBA_MAX: *out = c->nba_max; break;
     default: return fail(c, AF_ERR_ARG, "af_query: unknown item");
   }
   return AF_OK;
