@@ -56,34 +56,8 @@ def parse():
 
 
 def workload(cfg, device=0):
-    import torch
-    import afsynth
-    from paper_2608_06853_amd import autofocus as af
-
-    arr, acq, img, met = cfg.array, cfg.acq, cfg.img, cfg.method
-    elem = afsynth.element_positions(arr)
-    centres = afsynth.pixel_centres(arr, img)
-    sp = afsynth.patch_spacing(img, acq)
-    smax = 1.74 / img.c_ref   # the grid also covers the deepest dynamic-grid sweep layout
-    cover = np.concatenate([centres, afsynth.pixel_centres(arr, img, depth_scale=smax)])
-    x0, z0, dx, dz = afsynth.slowness_box(arr, cover, sp * smax, met.nx, met.nz)
-    bf = af.Beamformer(
-        af.Acquisition(elem_xz=elem, d_lens=arr.d_lens, c_lens=arr.c_lens, t_ttp=arr.t_ttp,
-                       fs=acq.fs, t0=acq.t0, fd=acq.fc, n_samples=acq.n_samples),
-        af.Imaging(centres=centres, patch=img.patch, spacing=sp, block=met.block, fnum=met.fnum,
-                   n_seg=met.n_seg),
-        af.Grid(nx=met.nx, nz=met.nz, x0=x0, z0=z0, dx=dx, dz=dz), device)
-    med = afsynth.medium_for(cfg)
-    sx0, sz0, sdx, sdz, snx, snz = afsynth.sim_box(arr, np.concatenate([cover, med.scat_xz]), sp,
-                                                   cfg.sim_spacing)
-    s_true = torch.from_numpy(
-        (1.0 / afsynth.speed_on_grid(med, sx0, sz0, sdx, sdz, snx, snz)).astype(np.float32)).cuda()
-    n = arr.n_elem
-    iq = torch.empty(n * n * acq.n_samples, device="cuda", dtype=torch.complex64)
-    bf.ctx.simulate(med.scat_xz, med.scat_amp.astype(np.float32), snx, snz, sx0, sz0, sdx, sdz,
-                    s_true, cfg.sim_nseg, acq.fc, acq.frac_bw, iq)
-    bf.set_slowness(torch.full((met.nz, met.nx), 1.0 / img.c_ref, device="cuda"))
-    return bf, iq, med
+    from paper_2608_06853_amd import workloads
+    return workloads.build(cfg, device=device)
 
 
 def cpu_baseline(cfg, n_pix_sample: int):

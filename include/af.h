@@ -133,10 +133,11 @@ af_status af_forward(af_ctx* ctx, const af_complex* iq_dev, const af_loss_params
 af_status af_backward(af_ctx* ctx, const af_complex* iq_dev, const af_loss_params* lp,
                 const af_complex* gblk_dev, float* grad_dev);
 
-/* One plain-method iteration: loss_and_grad at s_dev, then an Adam step (the
- * paper's Eq. 9 uses plain descent; Adam replaces it here) updating s_dev, m_dev,
- * v_dev ([nz][nx], device, in place).  step is 1-based.  The context's slowness
- * becomes the updated s. */
+/* One plain-method iteration: the loss at s_dev (terms_dev), its gradient by a
+ * backward pass that recomputes the travel-time table instead of keeping the
+ * forward's, then an Adam step (the paper's Eq. 9 uses plain descent; Adam
+ * replaces it here) updating s_dev, m_dev, v_dev ([nz][nx], device, in place).
+ * step is 1-based.  The context's slowness becomes the updated s. */
 af_status af_autofocus_step(af_ctx* ctx, const af_complex* iq_dev, const af_loss_params* lp,
                       const af_adam_params* ap, int step, float* s_dev, float* m_dev,
                       float* v_dev, float* terms_dev);

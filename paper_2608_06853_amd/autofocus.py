@@ -203,14 +203,31 @@ class History:
     times: list = field(default_factory=list)
 
 
+def calibrated(bf: Beamformer, iq, lp, s: torch.Tensor):
+    """Copy of ``lp`` whose speckle-brightness reference is SB at slowness ``s``."""
+    probe = _lib.LossParams(*[getattr(lp, n) for n, _ in _lib.LossParams._fields_])
+    probe.sb_ref = 1.0
+    bf.set_slowness(s)
+    terms = bf.empty_terms()
+    bf.ctx.loss_and_grad(iq, probe, terms, None)
+    sb = float(terms[_lib.TERM_SB].item())
+    out = _lib.LossParams(*[getattr(lp, n) for n, _ in _lib.LossParams._fields_])
+    out.sb_ref = sb if sb > 0 else 1.0
+    return out
+
+
 def plain_autofocus(bf: Beamformer, iq, lp, ap, n_iter: int, s0: torch.Tensor | None = None,
-                    record_every: int = 1, stop_below: float | None = None):
+                    record_every: int = 1, stop_below: float | None = None,
+                    calibrate_sb: bool = True):
     """Adam iterations of the plain method from ``s0`` (default: the context's slowness).
 
     Returns (s, History).  With ``stop_below`` the loop stops at the first
     iteration whose CMPE is at or below it (the terms of every iteration are read
-    back only when a stop criterion or recording needs them)."""
+    back only when a stop criterion or recording needs them).  With a speckle
+    term, its reference SB_ref is the speckle brightness at the starting slowness."""
     s = (bf.s if s0 is None else s0).detach().clone().to(bf.device, torch.float32).contiguous()
+    if lp.w_sb != 0.0 and calibrate_sb:
+        lp = calibrated(bf, iq, lp, s)
     m = torch.zeros_like(s)
     v = torch.zeros_like(s)
     terms = bf.empty_terms()

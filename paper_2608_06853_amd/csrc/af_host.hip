@@ -536,9 +536,14 @@ af_status af_autofocus_step(af_ctx* c, const af_complex* iq, const af_loss_param
   if (st != AF_OK) return st;
   if (!ap || !s || !m || !v || !terms || step < 1)
     return fail(c, AF_ERR_ARG, "af_autofocus_step: bad argument");
+  if ((st = check_lp(c, lp)) != AF_OK) return st;
   const size_t n = (size_t)c->nx * c->nz;
   AF_HIP(hipMemcpyAsync(c->d_s.p, s, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream), "copy s");
-  if ((st = af_loss_and_grad(c, iq, lp, terms, c->d_grad.as<float>())) != AF_OK) return st;
+  // forward, then a backward that rebuilds the travel-time table (no table is
+  // kept from the forward pass)
+  if ((st = run_forward(c, iq, lp, terms, nullptr, true)) != AF_OK) return st;
+  if ((st = run_tables(c, lp)) != AF_OK) return st;
+  if ((st = run_backward(c, iq, c->d_bblk.as<float2>(), c->d_grad.as<float>())) != AF_OK) return st;
   AF_KERNEL(AF_K_ADAM, af::launch_adam(c, ap, step, s, m, v, c->d_grad.as<float>()), "adam");
   return AF_OK;
 }

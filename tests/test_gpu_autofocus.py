@@ -1,0 +1,84 @@
+"""Plain autofocus method on the GPU against the oracle: Adam trajectory on the
+configs[0] workload, dynamic-grid sweep values, and descent of the objective."""
+import numpy as np
+import pytest
+
+import afsynth
+import gpu_setup as G
+import problems
+from oracle import adam, model, sweep as osweep
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    G.ensure_built()
+
+
+def test_five_adam_steps_tiny_config():
+    """configs[0]: 32 elements, 64x64 pixels, 8x8 grid, 5 Adam steps, FP32 GPU vs FP64 oracle."""
+    import torch
+    from paper_2608_06853_amd import _lib
+    cfg = afsynth.configs.C1
+    med = afsynth.medium_for(cfg)
+    iq = problems.simulate_iq(cfg, med).astype(np.complex64)
+    prob = problems.problem(cfg, iq.astype(np.complex128), depth_scale_max=1.74 / 1.54)
+    lp = problems.loss_params(cfg)
+    bf = G.beamformer(cfg, prob)
+    x0, z0, dx, dz, nx, nz = prob.grid
+    s0 = np.full((nz, nx), 1.0 / 1.54)
+    lr = cfg.method.lr
+    s_d = torch.from_numpy(s0.astype(np.float32)).cuda()
+    bf.set_slowness(s_d)
+    m_d = torch.zeros_like(s_d)
+    v_d = torch.zeros_like(s_d)
+    iq_d = torch.from_numpy(iq).cuda()
+    terms = bf.empty_terms()
+    so, mo, vo = s0.copy(), np.zeros_like(s0), np.zeros_like(s0)
+    for step in range(1, 6):
+        bf.ctx.autofocus_step(iq_d, G.lib_params(lp), _lib.adam_params(lr=lr), step, s_d, m_d, v_d,
+                              terms)
+        f, g = model.loss_and_grad(prob, so, lp)
+        so, mo, vo = adam.adam_step(so, mo, vo, g, step, lr)
+        t = terms.cpu().numpy()
+        print(f"step {step}: total gpu {t[4]:.7f} oracle {f['total']:.7f}  nvalid {t[5]:.0f} "
+              f"{f['n_valid']}", flush=True)
+        assert abs(t[4] - f["total"]) <= 2e-4 * abs(f["total"])
+    sg = s_d.cpu().numpy().astype(np.float64)
+    dev = np.linalg.norm(sg - so) / np.linalg.norm(so - s0)
+    print("trajectory deviation / step size", dev, flush=True)
+    assert dev < 1e-2
+
+
+def test_dynamic_grid_sweep_matches_oracle():
+    import torch
+    from paper_2608_06853_amd import autofocus as af
+    cfg = G.C1_SMALL
+    med = afsynth.medium_for(cfg)
+    iq = problems.simulate_iq(cfg, med, n_seg=64).astype(np.complex64)
+    speeds = np.array([1.46, 1.49, 1.52, 1.55, 1.58])
+    prob = problems.problem(cfg, iq.astype(np.complex128), depth_scale_max=1.60 / 1.54)
+    lp = problems.loss_params(cfg)
+    _, vo, best_o = osweep.sweep(prob, lp, cfg.acq.fc, speeds=speeds)
+    bf = G.beamformer(cfg, prob)
+    _, vg, best_g = af.sweep(bf, torch.from_numpy(iq).cuda(), G.lib_params(lp), cfg.acq.fc,
+                             speeds=speeds)
+    print("oracle", vo, "gpu", vg, flush=True)
+    assert np.max(np.abs(vg - vo) / vo) < 2e-3
+    assert best_g == best_o
+
+
+def test_plain_loop_descends():
+    import torch
+    from paper_2608_06853_amd import _lib, autofocus as af, workloads
+    cfg = afsynth.configs.C3
+    bf, iq, med = workloads.build(cfg)
+    _, vals, best = af.sweep(bf, iq, workloads.loss_params(cfg), cfg.acq.fc)
+    s, hist = af.plain_autofocus(bf, iq, workloads.loss_params(cfg),
+                                 _lib.adam_params(lr=cfg.method.lr), 40)
+    tot = np.array([h[_lib.TERM_TOTAL] for h in hist.terms])
+    cm = np.array([h[_lib.TERM_CMPE] for h in hist.terms])
+    print("sweep best", best, "cmpe first/last", cm[0], cm[-1], flush=True)
+    assert np.all(np.isfinite(tot))
+    assert cm[-5:].mean() < cm[0]
