@@ -159,6 +159,57 @@ af_status af_simulate(af_ctx* ctx, int n_scat, const double* scat_xz, const floa
                 const float* s_true_dev, int n_seg, double fc, double frac_bw,
                 af_complex* iq_dev);
 
+/* ---- Learned warm start: BF16 matrix-core 3x3 convolutions ------------------------
+ * Layer of the small CNN that predicts a slowness map from features of a
+ * homogeneous beamform.  Convolutions are 3x3, padding 1, stride 1 or 2, tensors
+ * NHWC; activations and packed weights are BF16 (raw 16-bit words), accumulation
+ * FP32.  Ho = (H - 1) / stride + 1, likewise Wo.  Kp = 9 Cin and Ktp = 9 Cout,
+ * each rounded up to a multiple of 16.  All pointers are device pointers; every
+ * call only enqueues on the context stream.  These calls need no geometry.
+ * Errors: AF_ERR_ARG for Cin or Cout outside 1..32, stride not 1 or 2, non-
+ * positive sizes or a null required pointer. */
+
+/* Packs FP32 weights w[Cout][3][3][Cin] into the BF16 operands of the forward,
+ * wpack [32][Kp] (row = output channel), and of the backward-data pass, wtpack
+ * [32][Ktp] (row = input channel, column = tap * Cout + co); zero padding.
+ * wtpack may be NULL. */
+af_status af_conv3x3_pack(af_ctx* ctx, int Cin, int Cout, const float* w, void* wpack,
+                          void* wtpack);
+/* out = act(conv(in, w) + bias): in [B][H][W][Cin] BF16, bias [Cout] FP32;
+ * out_bf16 [B][Ho][Wo][Cout] BF16 after ReLU if relu != 0 (may be NULL);
+ * out_f32 the same before ReLU in FP32 (may be NULL). */
+af_status af_conv3x3_fwd(af_ctx* ctx, int B, int H, int W, int Cin, int Cout, int stride,
+                         int relu, const void* in_bf16, const void* wpack, const float* bias,
+                         void* out_bf16, float* out_f32);
+/* din [B][H][W][Cin] BF16 = transposed convolution of dout [B][Ho][Wo][Cout] BF16
+ * with the weights, times the ReLU mask act > 0 of the layer below when act_bf16
+ * ([B][H][W][Cin], that layer's output) is not NULL. */
+af_status af_conv3x3_bwd_data(af_ctx* ctx, int B, int H, int W, int Cin, int Cout, int stride,
+                              const void* dout_bf16, const void* wtpack, const void* act_bf16,
+                              void* din_bf16);
+/* dw [Cout][3][3][Cin] and dbias [Cout] (FP32, overwritten) from the layer input
+ * in_bf16 and dout_bf16.  Split over pixels, partial sums reduced in fixed order. */
+af_status af_conv3x3_bwd_weight(af_ctx* ctx, int B, int H, int W, int Cin, int Cout, int stride,
+                                const void* in_bf16, const void* dout_bf16, float* dw,
+                                float* dbias);
+/* Squared error: loss_parts[ceil(n/256)] = block sums of scale (out - label)^2 and
+ * dout_bf16[n] = 2 scale (out - label). */
+af_status af_mse_loss(af_ctx* ctx, int n, const float* out, const float* label, float scale,
+                      float* loss_parts, void* dout_bf16);
+/* Adam (with bias correction) on n FP32 parameters p with moments m, v and gradient g. */
+af_status af_adam_update(af_ctx* ctx, int n, const af_adam_params* ap, int step, float* p,
+                         float* m, float* v, const float* g);
+/* NHWC BF16 network input from C channel-major FP32 maps [C][n]:
+ * out[i][c] = (maps[c][i] - shift[c]) * scale[c] (shift, scale: device, C floats). */
+af_status af_features(af_ctx* ctx, long long n, int C, const float* maps, const float* shift,
+                      const float* scale, void* out_bf16);
+/* Slowness grid [nz][nx] (node (i, j) at (x0 + j dx, z0 + i dz)) from a polar map
+ * [nr][nt] (rows: radius r0 + a dr; columns: polar angle t0 + b dt):
+ * s = s_base + scale * bilinear(map) at the node's radius and angle, clamped. */
+af_status af_polar_to_grid(af_ctx* ctx, const float* map, int nr, int nt, double r0, double dr,
+                           double t0, double dt, int nx, int nz, double x0, double z0,
+                           double dx, double dz, float s_base, float scale, float* s_dev);
+
 /* Kernel timing with HIP events on the context stream.  While enabled, every
  * kernel the library launches is bracketed by two events; af_profile_read waits
  * for the stream, returns the summed milliseconds and launch counts per kernel

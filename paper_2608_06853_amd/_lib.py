@@ -31,7 +31,8 @@ EXPORTS = [
     "af_create", "af_destroy", "af_last_error", "af_set_geometry", "af_set_lens",
     "af_set_slowness", "af_beamform", "af_loss_and_grad", "af_forward", "af_backward",
     "af_autofocus_step", "af_travel_times", "af_simulate", "af_query", "af_set_profiling",
-    "af_profile_read",
+    "af_profile_read", "af_conv3x3_pack", "af_conv3x3_fwd", "af_conv3x3_bwd_data",
+    "af_conv3x3_bwd_weight", "af_mse_loss", "af_adam_update", "af_features", "af_polar_to_grid",
 ]
 KERNELS = ["prepare_grid", "table", "das_fwd", "cmpe", "finalize", "gscale", "das_adj",
            "path_adj", "grad_fold", "adam", "export"]
@@ -67,6 +68,15 @@ _sig = {
     "af_query": (C.c_int, [_vp, _i, C.POINTER(C.c_longlong)]),
     "af_set_profiling": (C.c_int, [_vp, _i]),
     "af_profile_read": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
+    "af_conv3x3_pack": (C.c_int, [_vp, _i, _i, _vp, _vp, _vp]),
+    "af_conv3x3_fwd": (C.c_int, [_vp, _i, _i, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
+    "af_conv3x3_bwd_data": (C.c_int, [_vp, _i, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp]),
+    "af_conv3x3_bwd_weight": (C.c_int, [_vp, _i, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp]),
+    "af_mse_loss": (C.c_int, [_vp, _i, _vp, _vp, C.c_float, _vp, _vp]),
+    "af_adam_update": (C.c_int, [_vp, _i, C.POINTER(AdamParams), _i, _vp, _vp, _vp, _vp]),
+    "af_features": (C.c_int, [_vp, C.c_longlong, _i, _vp, _vp, _vp, _vp]),
+    "af_polar_to_grid": (C.c_int, [_vp, _vp, _i, _i, _d, _d, _d, _d, _i, _i, _d, _d, _d, _d,
+                                   C.c_float, C.c_float, _vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -230,6 +240,81 @@ class Context:
         calls = (C.c_longlong * n)()
         self._chk(_lib.af_profile_read(self._h, ms, calls))
         return {k: (ms[i], calls[i]) for i, k in enumerate(KERNELS) if calls[i] > 0}
+
+    # --- learned warm start (BF16 tensors are torch.bfloat16) -------------------------
+    @staticmethod
+    def conv_shapes(Cin, Cout):
+        kp = (9 * Cin + 15) // 16 * 16
+        ktp = (9 * Cout + 15) // 16 * 16
+        return kp, ktp
+
+    def conv3x3_pack(self, Cin, Cout, w, wpack, wtpack=None):
+        import torch
+        kp, ktp = self.conv_shapes(Cin, Cout)
+        self._chk(_lib.af_conv3x3_pack(self._h, Cin, Cout, _dev(w, torch.float32, Cout * 9 * Cin, "w"),
+                                       _dev(wpack, torch.bfloat16, 32 * kp, "wpack"),
+                                       _dev(wtpack, torch.bfloat16, 32 * ktp, "wtpack")))
+
+    def conv3x3_fwd(self, B, H, W, Cin, Cout, stride, relu, x, wpack, bias, out=None, outf=None):
+        import torch
+        ho, wo = (H - 1) // stride + 1, (W - 1) // stride + 1
+        kp, _ = self.conv_shapes(Cin, Cout)
+        self._chk(_lib.af_conv3x3_fwd(self._h, B, H, W, Cin, Cout, stride, int(relu),
+                                      _dev(x, torch.bfloat16, B * H * W * Cin, "x"),
+                                      _dev(wpack, torch.bfloat16, 32 * kp, "wpack"),
+                                      _dev(bias, torch.float32, Cout, "bias"),
+                                      _dev(out, torch.bfloat16, B * ho * wo * Cout, "out"),
+                                      _dev(outf, torch.float32, B * ho * wo * Cout, "outf")))
+
+    def conv3x3_bwd_data(self, B, H, W, Cin, Cout, stride, dout, wtpack, act, din):
+        import torch
+        ho, wo = (H - 1) // stride + 1, (W - 1) // stride + 1
+        _, ktp = self.conv_shapes(Cin, Cout)
+        self._chk(_lib.af_conv3x3_bwd_data(self._h, B, H, W, Cin, Cout, stride,
+                                           _dev(dout, torch.bfloat16, B * ho * wo * Cout, "dout"),
+                                           _dev(wtpack, torch.bfloat16, 32 * ktp, "wtpack"),
+                                           _dev(act, torch.bfloat16, B * H * W * Cin, "act"),
+                                           _dev(din, torch.bfloat16, B * H * W * Cin, "din")))
+
+    def conv3x3_bwd_weight(self, B, H, W, Cin, Cout, stride, x, dout, dw, db):
+        import torch
+        ho, wo = (H - 1) // stride + 1, (W - 1) // stride + 1
+        self._chk(_lib.af_conv3x3_bwd_weight(self._h, B, H, W, Cin, Cout, stride,
+                                             _dev(x, torch.bfloat16, B * H * W * Cin, "x"),
+                                             _dev(dout, torch.bfloat16, B * ho * wo * Cout, "dout"),
+                                             _dev(dw, torch.float32, Cout * 9 * Cin, "dw"),
+                                             _dev(db, torch.float32, Cout, "db")))
+
+    def mse_loss(self, out, label, scale, loss_parts, dout):
+        import torch
+        n = out.numel()
+        self._chk(_lib.af_mse_loss(self._h, n, _dev(out, torch.float32, n, "out"),
+                                   _dev(label, torch.float32, n, "label"), float(scale),
+                                   _dev(loss_parts, torch.float32, (n + 255) // 256, "loss_parts"),
+                                   _dev(dout, torch.bfloat16, n, "dout")))
+
+    def adam_update(self, ap: AdamParams, step, p, m, v, g):
+        import torch
+        n = p.numel()
+        self._chk(_lib.af_adam_update(self._h, n, C.byref(ap), int(step),
+                                      _dev(p, torch.float32, n, "p"), _dev(m, torch.float32, n, "m"),
+                                      _dev(v, torch.float32, n, "v"), _dev(g, torch.float32, n, "g")))
+
+    def features(self, maps, shift, scale, out):
+        import torch
+        C_ = shift.numel()
+        n = maps.numel() // C_
+        self._chk(_lib.af_features(self._h, n, C_, _dev(maps, torch.float32, n * C_, "maps"),
+                                   _dev(shift, torch.float32, C_, "shift"),
+                                   _dev(scale, torch.float32, C_, "scale"),
+                                   _dev(out, torch.bfloat16, n * C_, "out")))
+
+    def polar_to_grid(self, pmap, nr, nt, r0, dr, t0, dt, nx, nz, x0, z0, dx, dz, s_base, scale, s):
+        import torch
+        self._chk(_lib.af_polar_to_grid(self._h, _dev(pmap, torch.float32, nr * nt, "map"), nr, nt,
+                                        float(r0), float(dr), float(t0), float(dt), nx, nz,
+                                        float(x0), float(z0), float(dx), float(dz), float(s_base),
+                                        float(scale), _dev(s, torch.float32, nx * nz, "s")))
 
     def query(self, what: int) -> int:
         out = C.c_longlong(0)

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "af_internal.h"
 
@@ -214,27 +215,58 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
       c->pts_xz[2 * (q * M + m) + 1] = pix_xz[2 * q + 1] + oz;
     }
 
-  // active element range of every caller point (Eqs. 2 and 4, FP64)
+  // active element range of every caller point (Eqs. 2 and 4, FP64).  Small
+  // problems scan every element and check that the active set is contiguous;
+  // large ones expand from the element nearest in polar angle (on a convex arc
+  // the active set is the contiguous run around it).  Split over host threads.
   std::vector<int> lo_c(P), hi_c(P);
   const double half_f = fnum / 2.0;
-  for (long long p = 0; p < P; ++p) {
-    const double px = c->pts_xz[2 * p], pz = c->pts_xz[2 * p + 1];
-    int lo = N, hi = -1, cnt = 0;
-    for (int a = 0; a < N; ++a) {
-      const double dx = px - elem_xz[2 * a], dz = pz - elem_xz[2 * a + 1];
-      const double xp = cth[a] * dx - sth[a] * dz;
-      const double zp = sth[a] * dx + cth[a] * dz;
-      if (std::fabs(xp) <= half_f * zp) {
-        lo = std::min(lo, a);
-        hi = std::max(hi, a);
-        ++cnt;
+  auto active = [&](long long p, int a) {
+    const double dx = c->pts_xz[2 * p] - elem_xz[2 * a], dz = c->pts_xz[2 * p + 1] - elem_xz[2 * a + 1];
+    const double xp = cth[a] * dx - sth[a] * dz;
+    const double zp = sth[a] * dx + cth[a] * dz;
+    return std::fabs(xp) <= half_f * zp;
+  };
+  const bool full_scan = (double)P * N <= 2e7;
+  std::vector<char> bad_flag(64, 0);
+  auto work = [&](int tid, int nthr) {
+    for (long long p = tid; p < P; p += nthr) {
+      int lo = N, hi = -1, cnt = 0;
+      if (full_scan) {
+        for (int a = 0; a < N; ++a)
+          if (active(p, a)) {
+            lo = std::min(lo, a);
+            hi = std::max(hi, a);
+            ++cnt;
+          }
+        if (cnt > 0 && cnt != hi - lo + 1) bad_flag[tid] = 1;
+      } else {
+        const double ang = std::atan2(c->pts_xz[2 * p], c->pts_xz[2 * p + 1]);
+        int a0 = (int)(std::upper_bound(c->elem_pol.begin(), c->elem_pol.end(), ang) - c->elem_pol.begin());
+        int best = -1;
+        for (int a = std::max(a0 - 1, 0); a <= std::min(a0, N - 1); ++a)
+          if (active(p, a)) { best = a; break; }
+        if (best >= 0) {
+          lo = hi = best;
+          while (lo > 0 && active(p, lo - 1)) --lo;
+          while (hi < N - 1 && active(p, hi + 1)) ++hi;
+          cnt = hi - lo + 1;
+        }
       }
+      lo_c[p] = cnt > 0 ? lo : 1;
+      hi_c[p] = cnt > 0 ? hi : 0;
     }
-    if (cnt > 0 && cnt != hi - lo + 1)
-      return fail(c, AF_ERR_ARG, "af_set_geometry: active elements of a point are not contiguous");
-    lo_c[p] = cnt > 0 ? lo : 1;
-    hi_c[p] = cnt > 0 ? hi : 0;
+  };
+  {
+    const int nthr = (int)std::min<long long>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())),
+                                             std::max<long long>(1, P / 4096));
+    std::vector<std::thread> th_pool;
+    for (int t = 1; t < nthr; ++t) th_pool.emplace_back(work, t, nthr);
+    work(0, nthr);
+    for (auto& t : th_pool) t.join();
   }
+  for (char b : bad_flag)
+    if (b) return fail(c, AF_ERR_ARG, "af_set_geometry: active elements of a point are not contiguous");
 
   // spatial tiling of the pixels: k-d partition in (depth, arc length) whose
   // splits are multiples of the tile (ppt pixels) and sub-tile (pps pixels)
@@ -576,6 +608,94 @@ af_status af_simulate(af_ctx* c, int n_scat, const double* scat_xz, const float*
   AF_HIP(af::launch_simulate(c, n_scat, scat_xz, amp, nx, nz, x0, z0, dx, dz, s_true, n_seg, fc,
                              frac_bw, reinterpret_cast<float2*>(iq)),
          "simulate");
+  return AF_OK;
+}
+
+static af_status conv_args(af_ctx* c, int B, int H, int W, int Cin, int Cout, int stride) {
+  if (!c) return AF_ERR_ARG;
+  if (B <= 0 || H <= 0 || W <= 0 || Cin < 1 || Cin > 32 || Cout < 1 || Cout > 32 ||
+      (stride != 1 && stride != 2))
+    return fail(c, AF_ERR_ARG, "af_conv3x3: need 1 <= Cin, Cout <= 32, stride 1 or 2, positive sizes");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AF_ERR_HIP, "hipSetDevice");
+  return AF_OK;
+}
+
+af_status af_conv3x3_pack(af_ctx* c, int Cin, int Cout, const float* w, void* wpack, void* wtpack) {
+  af_status st = conv_args(c, 1, 1, 1, Cin, Cout, 1);
+  if (st != AF_OK) return st;
+  if (!w || !wpack) return fail(c, AF_ERR_ARG, "af_conv3x3_pack: null pointer");
+  AF_HIP(af::launch_conv_pack(c, Cin, Cout, w, wpack, wtpack), "conv pack");
+  return AF_OK;
+}
+
+af_status af_conv3x3_fwd(af_ctx* c, int B, int H, int W, int Cin, int Cout, int stride, int relu,
+                         const void* in, const void* wpack, const float* bias, void* out,
+                         float* outf) {
+  af_status st = conv_args(c, B, H, W, Cin, Cout, stride);
+  if (st != AF_OK) return st;
+  if (!in || !wpack || !bias || (!out && !outf)) return fail(c, AF_ERR_ARG, "af_conv3x3_fwd: null pointer");
+  AF_HIP(af::launch_conv_fwd(c, B, H, W, Cin, Cout, stride, relu, in, wpack, bias, out, outf),
+         "conv fwd");
+  return AF_OK;
+}
+
+af_status af_conv3x3_bwd_data(af_ctx* c, int B, int H, int W, int Cin, int Cout, int stride,
+                              const void* dout, const void* wtpack, const void* act, void* din) {
+  af_status st = conv_args(c, B, H, W, Cin, Cout, stride);
+  if (st != AF_OK) return st;
+  if (!dout || !wtpack || !din) return fail(c, AF_ERR_ARG, "af_conv3x3_bwd_data: null pointer");
+  AF_HIP(af::launch_conv_bwd_data(c, B, H, W, Cin, Cout, stride, dout, wtpack, act, din),
+         "conv bwd data");
+  return AF_OK;
+}
+
+af_status af_conv3x3_bwd_weight(af_ctx* c, int B, int H, int W, int Cin, int Cout, int stride,
+                                const void* in, const void* dout, float* dw, float* db) {
+  af_status st = conv_args(c, B, H, W, Cin, Cout, stride);
+  if (st != AF_OK) return st;
+  if (!in || !dout || !dw || !db) return fail(c, AF_ERR_ARG, "af_conv3x3_bwd_weight: null pointer");
+  AF_HIP(af::launch_conv_bwd_weight(c, B, H, W, Cin, Cout, stride, in, dout, dw, db),
+         "conv bwd weight");
+  return AF_OK;
+}
+
+af_status af_mse_loss(af_ctx* c, int n, const float* out, const float* label, float scale,
+                      float* loss_parts, void* dout) {
+  if (!c) return AF_ERR_ARG;
+  if (n <= 0 || !out || !label || !loss_parts || !dout) return fail(c, AF_ERR_ARG, "af_mse_loss: bad argument");
+  AF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  AF_HIP(af::launch_mse(c, n, out, label, scale, loss_parts, dout), "mse");
+  return AF_OK;
+}
+
+af_status af_adam_update(af_ctx* c, int n, const af_adam_params* ap, int step, float* p, float* m,
+                         float* v, const float* g) {
+  if (!c) return AF_ERR_ARG;
+  if (n <= 0 || !ap || step < 1 || !p || !m || !v || !g) return fail(c, AF_ERR_ARG, "af_adam_update: bad argument");
+  AF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  AF_HIP(af::launch_adam_vec(c, n, ap, step, p, m, v, g), "adam");
+  return AF_OK;
+}
+
+af_status af_features(af_ctx* c, long long n, int C, const float* maps, const float* shift,
+                      const float* scale, void* out) {
+  if (!c) return AF_ERR_ARG;
+  if (n <= 0 || C <= 0 || !maps || !shift || !scale || !out) return fail(c, AF_ERR_ARG, "af_features: bad argument");
+  AF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  AF_HIP(af::launch_features(c, n, C, maps, shift, scale, out), "features");
+  return AF_OK;
+}
+
+af_status af_polar_to_grid(af_ctx* c, const float* map, int nr, int nt, double r0, double dr,
+                           double t0, double dt, int nx, int nz, double x0, double z0, double dx,
+                           double dz, float s_base, float scale, float* s) {
+  if (!c) return AF_ERR_ARG;
+  if (!map || !s || nr < 2 || nt < 2 || nx < 1 || nz < 1 || !(dr > 0) || !(dt > 0))
+    return fail(c, AF_ERR_ARG, "af_polar_to_grid: bad argument");
+  AF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  AF_HIP(af::launch_polar_to_grid(c, map, nr, nt, r0, dr, t0, dt, nx, nz, x0, z0, dx, dz, s_base,
+                                  scale, s),
+         "polar_to_grid");
   return AF_OK;
 }
 

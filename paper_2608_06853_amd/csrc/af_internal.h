@@ -138,6 +138,7 @@ struct af_ctx {
   // device buffers
   af::DBuf d_elem, d_ptpol, d_ptxy, d_prange, d_tiles, d_tabwork, d_daswork, d_order, d_i2c,
       d_c2i;
+  af::DBuf d_cnn_part;
   af::DBuf d_s, d_gdev, d_regg, d_scal, d_tab, d_bblk, d_g, d_gT, d_gsb, d_part, d_gpad, d_gpart,
       d_grad, d_terms, d_maps, d_img;
 
@@ -188,4 +189,21 @@ hipError_t launch_simulate(af_ctx* c, int n_scat, const double* scat_xz, const f
                            int nx, int nz, double x0, double z0, double dx, double dz,
                            const float* s_true, int n_seg, double fc, double frac_bw,
                            float2* iq);
+hipError_t launch_conv_fwd(af_ctx* c, int B, int H, int W, int Cin, int Cout, int stride, int relu,
+                           const void* in, const void* wp, const float* bias, void* out,
+                           float* outf);
+hipError_t launch_conv_bwd_data(af_ctx* c, int B, int H, int W, int Cin, int Cout, int stride,
+                                const void* dout, const void* wtp, const void* act, void* din);
+hipError_t launch_conv_bwd_weight(af_ctx* c, int B, int H, int W, int Cin, int Cout, int stride,
+                                  const void* in, const void* dout, float* dw, float* db);
+hipError_t launch_conv_pack(af_ctx* c, int Cin, int Cout, const float* w, void* wp, void* wtp);
+hipError_t launch_mse(af_ctx* c, int n, const float* out, const float* label, float scale,
+                      float* loss_parts, void* dout);
+hipError_t launch_adam_vec(af_ctx* c, int n, const af_adam_params* ap, int step, float* p, float* m,
+                           float* v, const float* g);
+hipError_t launch_features(af_ctx* c, long long n, int C, const float* maps, const float* shift,
+                           const float* scale, void* out);
+hipError_t launch_polar_to_grid(af_ctx* c, const float* map, int nr, int nt, double r0, double dr,
+                                double t0, double dt, int nx, int nz, double x0, double z0,
+                                double dx, double dz, float s_base, float scale, float* s);
 }  // namespace af

@@ -1,0 +1,110 @@
+"""BF16 matrix-core convolution kernels of the learned warm start against the FP64
+oracle.  Inputs are BF16-representable, so single layers differ from the oracle
+only by FP32 accumulation order (outputs rounded to BF16 add 2^-9 relative);
+whole-network gradients also carry the BF16 rounding of every activation."""
+import numpy as np
+import pytest
+
+import gpu_setup as G
+from oracle import cnn as ocnn
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    G.ensure_built()
+
+
+def _bf16(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16)
+
+
+def _ctx():
+    from paper_2608_06853_amd import _lib
+    return _lib.Context(0)
+
+
+@pytest.mark.parametrize("ci,co,st", [(2, 32, 1), (32, 32, 2), (32, 32, 1), (32, 1, 1), (16, 24, 2)])
+def test_single_layer(ci, co, st):
+    import torch
+    rng = np.random.default_rng(ci * 100 + co + st)
+    B, H, W = 2, 13, 10
+    ctx = _ctx()
+    x = _bf16(rng.standard_normal((B, H, W, ci)))
+    w32 = rng.standard_normal((co, 9 * ci)).astype(np.float32) * 0.3
+    wq = _bf16(w32).float().numpy().reshape(co, 3, 3, ci).astype(np.float64)
+    b = rng.standard_normal(co).astype(np.float32)
+    kp, ktp = ctx.conv_shapes(ci, co)
+    wp = torch.empty(32 * kp, device="cuda", dtype=torch.bfloat16)
+    wtp = torch.empty(32 * ktp, device="cuda", dtype=torch.bfloat16)
+    ctx.conv3x3_pack(ci, co, torch.from_numpy(w32).cuda(), wp, wtp)
+    Ho, Wo = (H - 1) // st + 1, (W - 1) // st + 1
+    outf = torch.empty(B * Ho * Wo * co, device="cuda")
+    xd = x.cuda().contiguous()
+    ctx.conv3x3_fwd(B, H, W, ci, co, st, False, xd.view(-1), wp, torch.from_numpy(b).cuda(), outf=outf)
+    xo = x.float().numpy().astype(np.float64)
+    ref = ocnn.conv3x3(xo, wq, b.astype(np.float64), st)
+    e = G.rel(outf.cpu().numpy().reshape(ref.shape), ref)
+    print("fwd", ci, co, st, e, flush=True)
+    assert e < 1e-5
+    # backward data (with the ReLU mask of a random layer below) and weight
+    dout = _bf16(rng.standard_normal((B, Ho, Wo, co)))
+    act = _bf16(rng.standard_normal((B, H, W, ci)))
+    din = torch.empty(B * H * W * ci, device="cuda", dtype=torch.bfloat16)
+    ctx.conv3x3_bwd_data(B, H, W, ci, co, st, dout.cuda().view(-1), wtp, act.cuda().view(-1), din)
+    dw = torch.empty(co * 9 * ci, device="cuda")
+    db = torch.empty(co, device="cuda")
+    ctx.conv3x3_bwd_weight(B, H, W, ci, co, st, xd.view(-1), dout.cuda().view(-1), dw, db)
+    do = dout.float().numpy().astype(np.float64)
+    dx, dwo, dbo = ocnn.conv3x3_backward(xo, wq, st, do)
+    dx = dx * (act.float().numpy() > 0)
+    e_dx = G.rel(din.float().cpu().numpy().reshape(dx.shape), dx)
+    e_dw = G.rel(dw.cpu().numpy().reshape(dwo.shape), dwo)
+    e_db = G.rel(db.cpu().numpy(), dbo)
+    print("bwd", e_dx, e_dw, e_db, flush=True)
+    assert e_dx < 4e-3 and e_dw < 1e-5 and e_db < 1e-5
+
+
+def test_network_gradients_match_oracle():
+    import torch
+    from paper_2608_06853_amd import cnn
+    ctx = _ctx()
+    net = cnn.WarmStartNet(ctx, seed=3)
+    rng = np.random.default_rng(5)
+    B = 2
+    x = _bf16(rng.standard_normal((B, 128, 128, 2)))
+    label = rng.standard_normal((B, 32, 32)).astype(np.float32)
+    net.forward(x.cuda().contiguous().view(-1), B)
+    loss = float(net.loss(torch.from_numpy(label).cuda(), B).item())
+    net.backward(B)
+    params = []
+    for i, (ci, co, st, relu) in enumerate(ocnn.LAYERS):
+        wq = _bf16(net.w[i].cpu().numpy()).float().numpy().reshape(co, 3, 3, ci).astype(np.float64)
+        params.append((wq, net.b[i].cpu().numpy().astype(np.float64)))
+    out, acts = ocnn.forward(params, x.float().numpy().astype(np.float64))
+    lo, dout = ocnn.mse(out, label.reshape(B, 32, 32, 1).astype(np.float64), 1.0 / (B * 32 * 32))
+    grads = ocnn.backward(params, acts, dout)
+    print("loss", loss, lo, flush=True)
+    assert abs(loss - lo) < 1e-2 * abs(lo)
+    n = len(ocnn.LAYERS)
+    for i in range(n):
+        ew = G.rel(net.grads[i].cpu().numpy().reshape(grads[i][0].shape), grads[i][0])
+        eb = G.rel(net.grads[n + i].cpu().numpy(), grads[i][1])
+        print("layer", i, "dw", ew, "db", eb, flush=True)
+        assert ew < 3e-2 and eb < 3e-2
+
+
+def test_training_fits_a_batch():
+    import torch
+    from paper_2608_06853_amd import cnn
+    ctx = _ctx()
+    net = cnn.WarmStartNet(ctx, seed=1)
+    rng = np.random.default_rng(7)
+    B = 4
+    x = _bf16(rng.standard_normal((B, 128, 128, 2))).cuda().contiguous().view(-1)
+    y = torch.from_numpy(rng.standard_normal((B, 32, 32)).astype(np.float32) * 0.5).cuda()
+    losses = [float(net.train_step(x, y, B, 3e-3).item()) for _ in range(150)]
+    print("loss first/last", losses[0], losses[-1], flush=True)
+    assert losses[-1] < 0.2 * losses[0]
