@@ -3,8 +3,11 @@
 Each configuration fixes the array, the acquisition, the pixel grid, the
 slowness-grid size and the method's hyperparameters.  Lens constants follow
 the paper's calibration table (Table I) only where a configuration names them;
-the hyperparameter defaults are the C5-2v phantom and in-vivo columns of the
-paper's hyperparameter table (Table II).
+the regulariser, threshold, F and N_segments defaults are the C5-2v phantom and
+in-vivo columns of the paper's hyperparameter table (Table II).  The learning
+rate is an Adam step on the slowness in us/mm, whose scale the paper does not
+fix: 0.003 for the 32-element configurations and 0.001 for the 128/192-element
+ones (0.05, the in-vivo value read in these units, diverges).
 """
 from __future__ import annotations
 
@@ -94,7 +97,7 @@ C2 = Config(
     array=ArrayCfg(n_elem=128, radius=60.0, pitch=0.37, d_lens=1.2, c_lens=1.000),
     acq=AcqCfg(fc=3.5, fs=14.0, n_samples=2560),
     img=ImgCfg(n_depth=256, n_angle=256, depth_min=1.0, depth_max=160.0),
-    method=MethodCfg(block=8, fnum=0.4, n_seg=32, nx=32, nz=32, lr=0.05,
+    method=MethodCfg(block=8, fnum=0.4, n_seg=32, nx=32, nz=32, lr=0.001,
                      w1=100.0, kx2=0.002, kz2=0.002, n_iter=1),
     medium="liver_wall", seed=2, sim_spacing=1.0,
 )
@@ -116,7 +119,7 @@ C5 = Config(
     array=ArrayCfg(n_elem=192, radius=60.0, pitch=0.37, d_lens=1.2, c_lens=1.000),
     acq=AcqCfg(fc=3.5, fs=14.0, n_samples=4096),
     img=ImgCfg(n_depth=512, n_angle=512, depth_min=1.0, depth_max=200.0),
-    method=MethodCfg(block=8, fnum=0.4, n_seg=64, nx=64, nz=64, lr=0.05,
+    method=MethodCfg(block=8, fnum=0.4, n_seg=64, nx=64, nz=64, lr=0.001,
                      w1=100.0, kx2=0.002, kz2=0.002, n_iter=200),
     medium="liver_wall_deep", seed=5, sim_spacing=1.0,
 )

@@ -1,0 +1,180 @@
+"""Training of the warm-start network and the wall-clock comparison of the learned
+initialisation against the plain adaptive-grid initialisation.
+
+Training data: media of the randomised configs[0] type (seeds 1000...), each with
+its channel data simulated on the GPU, the feature maps of a homogeneous 1540 m/s
+beamform and its true slowness on the network's polar output grid.
+
+Comparison ("s-to-target"): from channel data resident on the GPU, the time each
+method needs to reach the CMP phase error that the plain method reaches after its
+full run (sweep + n_iter Adam steps).  Both methods run the same Adam iterations on
+the dynamic CMPE grid laid out for their initial global speed (plain: the sweep's
+best speed; learned: the mean speed of the predicted map).  The learned path falls
+back to the plain sweep when its initial loss exceeds that of the homogeneous
+1540 m/s guess.
+
+    python -m paper_2608_06853_amd.warmstart --train 4096 --epochs 20 --out FILE
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+import torch
+
+import afsynth
+from . import _lib, autofocus as af, cnn, workloads
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "warmstart_c4.npz")
+
+
+def train_network(n_train: int, epochs: int, batch: int = 32, lr: float = 1e-3, seed0: int = 1000,
+                  progress: bool = True, device: int = 0):
+    cfg = afsynth.configs.C4
+    ctx = _lib.Context(device)
+    t0 = time.perf_counter()
+    X, Y = cnn.make_dataset(cfg, list(range(seed0, seed0 + n_train)), device, progress)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = cnn.WarmStartNet(ctx, seed=0, device=device)
+    t0 = time.perf_counter()
+    hist = cnn.train(net, X, Y, epochs, batch, lr, progress=progress)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    return net, {"n_train": n_train, "epochs": epochs, "batch": batch, "lr": lr,
+                 "data_s": t_data, "train_s": t_train, "loss_per_epoch": hist}
+
+
+def load_network(path: str = DEFAULT_WEIGHTS, device: int = 0):
+    ctx = _lib.Context(device)
+    net = cnn.WarmStartNet(ctx, seed=0, device=device)
+    with np.load(path, allow_pickle=False) as f:
+        net.load({k: f[k] for k in f.files})
+    return net
+
+
+def run_plain(bf: af.Beamformer, iq, cfg, n_iter: int, lp=None):
+    """Sweep + n_iter Adam steps; returns (s, per-iteration CMPE, times, sweep time)."""
+    lp = lp or workloads.loss_params(cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, vals, best = af.sweep(bf, iq, lp, cfg.acq.fc)
+    torch.cuda.synchronize()
+    t_sweep = time.perf_counter() - t0
+    s, hist = af.plain_autofocus(bf, iq, lp, _lib.adam_params(lr=cfg.method.lr), n_iter)
+    times = [t_sweep + t for t in hist.times]
+    cm = [float(t[_lib.TERM_CMPE]) for t in hist.terms]
+    return s, cm, times, t_sweep, best
+
+
+def run_learned(bf: af.Beamformer, iq, cfg, net, fm: cnn.FeatureMaker, target: float,
+                max_iter: int, lp=None):
+    """Warm start + Adam until CMPE <= target.  Returns a dict of timings and results."""
+    lp = lp or workloads.loss_params(cfg)
+    base = bf.img
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s0 = cnn.predict_slowness(net, fm, iq, cfg, bf.grid)
+    c_mean = float((1.0 / s0).mean().item())
+    c_mean = min(max(c_mean, 1.340), 1.740)
+    bf.set_imaging(af.scaled_imaging(base, bf.acq, c_mean, cfg.img.c_ref, cfg.acq.fc))
+    terms = bf.empty_terms()
+    bf.set_slowness(s0)
+    bf.ctx.loss_and_grad(iq, lp, terms, None)
+    l_net = float(terms[_lib.TERM_TOTAL].item())
+    bf.set_imaging(base)
+    bf.set_slowness(torch.full(bf.grid.shape, 1.0 / cfg.img.c_ref, device=bf.device))
+    bf.ctx.loss_and_grad(iq, lp, terms, None)
+    l_hom = float(terms[_lib.TERM_TOTAL].item())
+    fallback = not (l_net <= l_hom)
+    if fallback:
+        _, _, best = af.sweep(bf, iq, lp, cfg.acq.fc)
+        s_init = bf.s
+    else:
+        bf.set_imaging(af.scaled_imaging(base, bf.acq, c_mean, cfg.img.c_ref, cfg.acq.fc))
+        s_init = s0
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    s, hist = af.plain_autofocus(bf, iq, lp, _lib.adam_params(lr=cfg.method.lr), max_iter,
+                                 s0=s_init, stop_below=target)
+    cm = [float(t[_lib.TERM_CMPE]) for t in hist.terms]
+    reached = bool(cm and cm[-1] <= target)
+    t_total = t_init + (hist.times[-1] if hist.times else 0.0)
+    bf.set_imaging(base)
+    return {"fallback": fallback, "loss_net": l_net, "loss_homogeneous": l_hom, "init_s": t_init,
+            "iters": len(cm), "reached": reached, "seconds": t_total, "final_cmpe": cm[-1] if cm else None,
+            "s": s}
+
+
+def s_to_target(cfg, net, n_iter: int = 200, max_iter: int = 400, seed=None, device: int = 0):
+    """Wall-clock seconds to the plain method's final CMPE: learned vs plain."""
+    bf, iq, med = workloads.build(cfg, seed=seed, device=device)
+    fm = cnn.FeatureMaker(cfg, device)
+    base = bf.img
+    s_plain, cm, times, t_sweep, best = run_plain(bf, iq, cfg, n_iter)
+    target = cm[-1]
+    k = next(i for i, v in enumerate(cm) if v <= target)
+    t_plain = times[k]
+    bf.set_imaging(base)
+    res = run_learned(bf, iq, cfg, net, fm, target, max_iter)
+    c_true = workloads.true_speed_nodes(cfg, med, bf.grid)
+    from . import metrics
+    out = {"config": cfg.name, "target_cmpe": target, "plain_seconds": t_plain,
+           "plain_sweep_seconds": t_sweep, "plain_best_speed": best, "plain_iters": k + 1,
+           "learned_seconds": res["seconds"], "learned_iters": res["iters"],
+           "learned_reached": res["reached"], "learned_fallback": res["fallback"],
+           "learned_init_seconds": res["init_s"],
+           "speedup": t_plain / res["seconds"] if res["reached"] else None,
+           "plain_rmse_mps": metrics.speed_errors(s_plain.cpu().numpy(), c_true)["rmse_mps"],
+           "learned_rmse_mps": metrics.speed_errors(res["s"].cpu().numpy(), c_true)["rmse_mps"]}
+    return out
+
+
+def evaluate_init(net, seeds, device: int = 0):
+    """RMSE (m/s) of the slowness grid from the network, from the homogeneous 1540 m/s
+    guess and from the plain sweep, on held-out configs[0]-type media."""
+    from . import metrics
+    cfg = afsynth.configs.C4
+    fm = cnn.FeatureMaker(cfg, device)
+    acqd, imgd, grid, cover = workloads.geometry(cfg)
+    bf = af.Beamformer(acqd, imgd, grid, device)
+    lp = workloads.loss_params(cfg)
+    rows = []
+    for sd in seeds:
+        med = afsynth.medium_for(cfg, int(sd))
+        iq = workloads.simulate(bf, cfg, med, cover)
+        c_true = workloads.true_speed_nodes(cfg, med, grid)
+        s_net = cnn.predict_slowness(net, fm, iq, cfg, grid).cpu().numpy()
+        bf.set_imaging(imgd)
+        _, _, best = af.sweep(bf, iq, lp, cfg.acq.fc)
+        bf.set_imaging(imgd)
+        rows.append({
+            "net": metrics.speed_errors(s_net, c_true)["rmse_mps"],
+            "homogeneous_1540": metrics.speed_errors(np.full(grid.shape, 1 / 1.54), c_true)["rmse_mps"],
+            "sweep": metrics.speed_errors(np.full(grid.shape, 1 / best), c_true)["rmse_mps"],
+        })
+    return {k: float(np.mean([r[k] for r in rows])) for k in rows[0]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=4096)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval", type=int, default=32, help="held-out media (seeds 9000...)")
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    args = ap.parse_args()
+    net, info = train_network(args.train, args.epochs, args.batch, args.lr)
+    os.makedirs(os.path.dirname(args.out), exist_ok=True)
+    np.savez(args.out, **net.state())
+    info["heldout_rmse_mps"] = evaluate_init(net, range(9000, 9000 + args.eval))
+    print(json.dumps(info))
+
+
+if __name__ == "__main__":
+    main()
