@@ -52,6 +52,8 @@ def parse():
                     help="pixels of the bounded oracle sample (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (HBM counter scale)")
+    ap.add_argument("--no-autofocus", action="store_true",
+                    help="skip the plain-loop report and the learned-vs-plain s-to-target runs")
     return ap.parse_args()
 
 
@@ -76,15 +78,87 @@ def cpu_baseline(cfg, n_pix_sample: int):
     x0, z0, dx, dz, nx, nz = prob.grid
     s = np.full((nz, nx), 1.0 / 1.54)
     lp = problems.loss_params(cfg)
-    t0 = time.perf_counter()
-    model.loss_and_grad(prob, s, lp)
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        model.loss_and_grad(prob, s, lp)
+        dt = time.perf_counter() - t0
     samples = cfg.array.n_elem ** 2 * n_pix_sample * prob.n_patch
     return dict(value=samples / dt / 1e9, unit=UNIT, cores=1, kind="oracle",
                 sample=f"{n_pix_sample} of {cfg.img.n_depth * cfg.img.n_angle} pixels "
                        f"(x{prob.n_patch} points), full {cfg.array.n_elem}x{cfg.array.n_elem}"
                        f"x{cfg.acq.n_samples} channel data, one loss_and_grad in "
                        f"{dt:.1f} s (numpy single thread)")
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_clinical_hbm_traffic.txt")
+
+
+def measured_traffic(cfg_name: str, family: str):
+    """HBM bytes per launch of ``family`` from the committed rocprofv3 counter summary,
+    or None when there is none for this workload or the kernel's sources changed since."""
+    from paper_2608_06853_amd import profsummary
+    if cfg_name != "c2_clinical" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = profsummary.read_traffic(TRAFFIC_FILE).get(family)
+    if rec is None or rec[0] != profsummary.source_hash(family):
+        return None
+    return rec[1]
+
+
+def plain_loop_report():
+    """The full plain method (sweep + Adam with CMPE and speckle brightness) on the
+    two-layer medium with a cyst: speed errors and image quality before and after."""
+    import torch
+    import afsynth
+    from paper_2608_06853_amd import metrics, warmstart, workloads
+    cfg = afsynth.configs.C3
+    bf, iq, med = workloads.build(cfg)
+    base = bf.img
+    c_true = workloads.true_speed_nodes(cfg, med, bf.grid)
+    npx = base.centres.shape[0]
+    M = base.patch * base.patch
+
+    def image_quality(s):
+        bf.set_imaging(base)
+        img, _, _ = bf.beamform(iq, s=s, maps=False)
+        env = img.abs().view(npx, M)[:, M // 2].cpu().numpy()
+        return metrics.contrast_cnr(env, base.centres, med.cyst_xz[0], float(med.cyst_r[0]))
+
+    s_hom = torch.full(bf.grid.shape, 1.0 / cfg.img.c_ref, device=bf.device)
+    q0 = image_quality(s_hom)
+    torch.cuda.synchronize()
+    s, cm, times, t_sweep, best = warmstart.run_plain(bf, iq, cfg, cfg.method.n_iter)
+    q1 = image_quality(s)
+    e_hom = metrics.speed_errors(s_hom.cpu().numpy(), c_true)
+    e_swp = metrics.speed_errors(np.full(bf.grid.shape, 1.0 / best), c_true)
+    e_fin = metrics.speed_errors(s.cpu().numpy(), c_true)
+    return {"config": cfg.name, "iterations": len(cm), "seconds": round(times[-1], 3),
+            "sweep_seconds": round(t_sweep, 3), "sweep_best_speed": best,
+            "cmpe_first": cm[0], "cmpe_final": cm[-1],
+            "rmse_mps": {"homogeneous_1540": e_hom["rmse_mps"], "sweep": e_swp["rmse_mps"],
+                         "final": e_fin["rmse_mps"]},
+            "mae_mps": {"homogeneous_1540": e_hom["mae_mps"], "sweep": e_swp["mae_mps"],
+                        "final": e_fin["mae_mps"]},
+            "cyst_contrast_db": {"homogeneous_1540": q0["contrast_db"], "final": q1["contrast_db"]},
+            "cyst_cnr": {"homogeneous_1540": q0["cnr"], "final": q1["cnr"]}}
+
+
+def s_to_target_report(n_heldout: int = 3):
+    """Wall-clock to the plain method's final CMPE, learned warm start vs plain
+    initialisation: on the largest workload and on held-out media of the network's
+    training distribution."""
+    import afsynth
+    from paper_2608_06853_amd import warmstart
+    net = warmstart.load_network()
+    keep = ("target_cmpe", "plain_seconds", "plain_iters", "learned_seconds", "learned_iters",
+            "learned_reached", "learned_fallback", "speedup", "plain_rmse_mps", "learned_rmse_mps")
+    out = {}
+    r = warmstart.s_to_target(afsynth.configs.C5, net)
+    out["c5_largest"] = {k: r[k] for k in keep}
+    rows = [warmstart.s_to_target(afsynth.configs.C4, net, seed=9000 + k) for k in range(n_heldout)]
+    out["c4_heldout"] = [{k: r[k] for k in keep} for r in rows]
+    return out
 
 
 def main():
@@ -147,9 +221,11 @@ def main():
     roof = None
     if dom in FLOPS_PER_UNIT:
         ach = FLOPS_PER_UNIT[dom] * units[dom] / avg_s / 1e12
+        tr = measured_traffic(cfg.name, dom)
         roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
-                "traffic": None, "avg_launch_ms": round(avg_s * 1e3, 4)}
+                "traffic": tr, "traffic_unit": "bytes per launch",
+                "avg_launch_ms": round(avg_s * 1e3, 4)}
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": UNIT, "n_gpus": 1,
@@ -171,6 +247,13 @@ def main():
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in sorted(prof.items())},
         "loss_terms": [float(x) for x in tv[:7]],
     }
+    del bf, iq
+    torch.cuda.empty_cache()
+    if not args.no_autofocus:
+        t0 = time.perf_counter()
+        out["plain_loop"] = plain_loop_report()
+        out["s_to_target"] = s_to_target_report()
+        out["autofocus_report_seconds"] = round(time.perf_counter() - t0, 1)
     if args.cpu_pixels > 0:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_pixels)
     print(json.dumps(out))

@@ -90,7 +90,9 @@ af_status af_set_geometry(af_ctx* ctx, int n_elem, const double* elem_xz, int n_
 
 /* Lens of the bent-ray model (Eqs. 7-8): thickness d_lens (elements sit that far
  * behind the concentric lens arc), lens speed c_lens, time-to-peak t_ttp added
- * to every round trip.  Errors: AF_ERR_ARG for d_lens < 0 or c_lens <= 0. */
+ * to every round trip.  d_lens = 0 is the lens-free model: straight rays from the
+ * elements (the uncorrected baseline of the paper's comparisons).
+ * Errors: AF_ERR_ARG for d_lens < 0 or c_lens <= 0. */
 af_status af_set_lens(af_ctx* ctx, double d_lens, double c_lens, double t_ttp);
 
 /* Slowness grid s ~ 1/c (Section III-A): node (i, j) at (x0 + j dx, z0 + i dz),

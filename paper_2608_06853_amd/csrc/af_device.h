@@ -41,6 +41,18 @@ struct RayOut {
 // refined refraction point.
 __device__ inline RayOut trace_lens(double R, double sa, double ca, double rho, double sp,
                                     double cp, double dlens, double icl, double icm) {
+  if (dlens == 0.0) {
+    // no lens: the ray runs straight from the element, which is its own refraction point
+    const double ex = R * sa, ez = R * ca;
+    const double vx = rho * sp - ex, vz = rho * cp - ez;
+    const double L2 = sqrt(vx * vx + vz * vz);
+    RayOut o;
+    o.t_hom = L2 * icm;
+    o.refx = (float)ex;
+    o.refz = (float)ez;
+    o.l2 = (float)L2;
+    return o;
+  }
   const double RL = R + dlens;
   const double cT = cp * ca + sp * sa;   // cos(theta_p - theta_a)
   double sT = sp * ca - cp * sa;         // sin(theta_p - theta_a)

@@ -288,7 +288,62 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
   std::vector<int> ord(n_pix);
   std::iota(ord.begin(), ord.end(), 0);
   kd_partition(ord.data(), n_pix, ppt, pps, cu, cv);
-  const int n_tiles = (n_pix + ppt - 1) / ppt;
+  // Pack the pixels, in k-d order, into sub-tiles of pps and tiles of 4 sub-tiles.
+  // A tile is closed early (its remaining slots become padding) when the next
+  // pixel would widen its span of active blocks beyond what the CMPE kernel
+  // stages (MAX_NBA); with compact images this never happens and the packing
+  // follows the k-d units exactly.  slot[k] = tile * ppt + sub-tile * pps + s.
+  std::vector<long long> slot(n_pix);
+  int n_tiles = 0;
+  {
+    int t = -1, w = 0, sidx = pps, blo = 0, bhi = -1;
+    auto pix_blocks = [&](int q, int& lo, int& hi) {
+      lo = N;
+      hi = -1;
+      for (int m = 0; m < M; ++m) {
+        const long long pc = (long long)q * M + m;
+        if (lo_c[pc] <= hi_c[pc]) {
+          lo = std::min(lo, lo_c[pc] / block);
+          hi = std::max(hi, hi_c[pc] / block);
+        }
+      }
+    };
+    for (int k = 0; k < n_pix; ++k) {
+      const int q = ord[k];
+      int plo, phi;
+      pix_blocks(q, plo, phi);
+      if (plo <= phi && phi - plo + 1 > af::MAX_NBA)
+        return fail(c, AF_ERR_ARG, "af_set_geometry: a pixel spans more than 16 active blocks (aperture too wide for the block size)");
+      bool new_tile = t < 0;
+      if (!new_tile && plo <= phi) {
+        const int nlo = bhi < blo ? plo : std::min(blo, plo);
+        const int nhi = bhi < blo ? phi : std::max(bhi, phi);
+        new_tile = nhi - nlo + 1 > af::MAX_NBA;
+      }
+      if (!new_tile && sidx == pps) {  // current sub-tile full: next sub-tile or tile
+        if (w == 3) new_tile = true;
+        else {
+          ++w;
+          sidx = 0;
+        }
+      }
+      if (new_tile) {
+        ++t;
+        w = 0;
+        sidx = 0;
+        blo = 0;
+        bhi = -1;
+      }
+      if (plo <= phi) {
+        const bool empty = bhi < blo;
+        blo = empty ? plo : std::min(blo, plo);
+        bhi = empty ? phi : std::max(bhi, phi);
+      }
+      slot[k] = (long long)t * ppt + (long long)w * pps + sidx;
+      ++sidx;
+    }
+    n_tiles = t + 1;
+  }
   const long long P_int = (long long)n_tiles * TILE;
   c->n_tiles = n_tiles;
   c->P_int = P_int;
@@ -296,9 +351,10 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
   c->c2i.assign(P, -1);
   for (int k = 0; k < n_pix; ++k) {
     const int q = ord[k];
-    const int tile = k / ppt, w = (k % ppt) / pps, s = (k % ppt) % pps;
+    const long long tile = slot[k] / ppt;
+    const int w = (int)((slot[k] % ppt) / pps), s = (int)((slot[k] % ppt) % pps);
     for (int m = 0; m < M; ++m) {
-      const long long pi = (long long)tile * TILE + w * SUB + s * M + m;
+      const long long pi = tile * TILE + w * SUB + s * M + m;
       c->i2c[pi] = q * M + m;
       c->c2i[(long long)q * M + m] = (int)pi;
     }
@@ -353,10 +409,25 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
     return fail(c, AF_ERR_ARG, "af_set_geometry: a tile spans more than 16 active blocks (aperture too wide for the block size)");
   std::stable_sort(load.begin(), load.end(), [](auto& a, auto& b) { return a.first > b.first; });
   c->tile_order.clear();
-  for (auto& l : load) {
-    c->tile_order.push_back(l.second);
-    const int4 tr = tiles[l.second];
-    for (int jb = tr.z; jb <= tr.w; ++jb) daswork.push_back(make_int2(l.second, jb));
+  for (auto& l : load) c->tile_order.push_back(l.second);
+  // DAS work items (tile, receive block).  Workgroups are dealt to the XCDs
+  // round-robin (workgroup b runs on XCD b % 8), so every receive block is given
+  // to one XCD, and its tiles follow in k-d (spatial) order: the channel records
+  // of that block then stay in the XCD's L2 while neighbouring tiles reuse their
+  // time windows.  Shorter queues are padded with empty items (tile -1).
+  {
+    constexpr int NXCD = 8;
+    std::vector<std::vector<int2>> q(NXCD);
+    for (int t = 0; t < n_tiles; ++t) {
+      const int4 tr = tiles[t];
+      if (tr.x > tr.y) continue;
+      for (int jb = tr.z; jb <= tr.w; ++jb) q[jb % NXCD].push_back(make_int2(t, jb));
+    }
+    size_t L = 0;
+    for (auto& v : q) L = std::max(L, v.size());
+    for (size_t i = 0; i < L; ++i)
+      for (int x = 0; x < NXCD; ++x)
+        daswork.push_back(i < q[x].size() ? q[x][i] : make_int2(-1, 0));
   }
   c->n_tab_work = (int)tabwork.size();
   c->n_das_work = (int)daswork.size();

@@ -49,11 +49,15 @@ __device__ inline bool sample_pos(int ui_t, float uf_t, int ui_r, float uf_r, in
   return (unsigned)kk <= (unsigned)(ns - 2);
 }
 
+// The S gathers of one transmit element are issued together: a sample outside
+// the record reads the (always valid) first two samples of its channel and is
+// then zeroed, so no load sits behind a divergent branch.
 template <int S>
 __global__ __launch_bounds__(256) void k_das_fwd(DasArgs A) {
   const Geo& g = A.g;
   const int2 w = A.work[blockIdx.x];
   const int tile = w.x, jb = w.y;
+  if (tile < 0) return;  // padding item of a shorter XCD queue
   const int4 tr = A.tiles[tile];
   const long long P = g.P;
   const long long p = (long long)tile * TILE + threadIdx.x;
@@ -64,22 +68,29 @@ __global__ __launch_bounds__(256) void k_das_fwd(DasArgs A) {
   for (int k = 0; k < S; ++k) rx[k] = load_rx(A.tab, P, p, jb * S + k, tr.x, tr.y);
 
   float2 acc = make_float2(0.f, 0.f);
+  TabEntry et = A.tab[(long long)tr.x * P + p];
   for (int t = tr.x; t <= tr.y; ++t) {
-    const TabEntry et = A.tab[(long long)t * P + p];
+    const TabEntry en = A.tab[(long long)min(t + 1, tr.y) * P + p];
     const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
-    float ax = 0.f, ay = 0.f;
+    float2 a0[S], a1[S];
+    float fr[S];
+    bool ok[S];
 #pragma unroll
     for (int k = 0; k < S; ++k) {
       int kk;
-      float f;
-      if (sample_pos(et.ui, et.uf, rx[k].ui, rx[k].uf, ns, kk, f)) {
-        const float2* q = base + (long long)k * ns + kk;
-        const float2 a0 = q[0], a1 = q[1];
-        const float vx = fmaf(f, a1.x - a0.x, a0.x);
-        const float vy = fmaf(f, a1.y - a0.y, a0.y);
-        ax = fmaf(vx, rx[k].e.x, fmaf(-vy, rx[k].e.y, ax));
-        ay = fmaf(vx, rx[k].e.y, fmaf(vy, rx[k].e.x, ay));
-      }
+      ok[k] = sample_pos(et.ui, et.uf, rx[k].ui, rx[k].uf, ns, kk, fr[k]);
+      const float2* q = base + (unsigned)(k * ns + (ok[k] ? kk : 0));
+      a0[k] = q[0];
+      a1[k] = q[1];
+    }
+    float ax = 0.f, ay = 0.f;
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const float f = fr[k];
+      const float vx = ok[k] ? fmaf(f, a1[k].x - a0[k].x, a0[k].x) : 0.f;
+      const float vy = ok[k] ? fmaf(f, a1[k].y - a0[k].y, a0[k].y) : 0.f;
+      ax = fmaf(vx, rx[k].e.x, fmaf(-vy, rx[k].e.y, ax));
+      ay = fmaf(vx, rx[k].e.y, fmaf(vy, rx[k].e.x, ay));
     }
     acc.x = fmaf(ax, et.er, fmaf(-ay, et.ei, acc.x));
     acc.y = fmaf(ax, et.ei, fmaf(ay, et.er, acc.y));
@@ -88,6 +99,7 @@ __global__ __launch_bounds__(256) void k_das_fwd(DasArgs A) {
       A.bblk[((long long)ib * g.nblk + jb) * P + p] = acc;
       acc = make_float2(0.f, 0.f);
     }
+    et = en;
   }
 }
 
@@ -101,6 +113,7 @@ __global__ __launch_bounds__(256) void k_das_adj(DasArgs A) {
   const Geo& g = A.g;
   const int2 w = A.work[blockIdx.x];
   const int tile = w.x, jb = w.y;
+  if (tile < 0) return;  // padding item of a shorter XCD queue
   const int4 tr = A.tiles[tile];
   const long long P = g.P;
   const long long p = (long long)tile * TILE + threadIdx.x;
@@ -116,37 +129,45 @@ __global__ __launch_bounds__(256) void k_das_adj(DasArgs A) {
   for (int k = 0; k < S; ++k) grx[k] = 0.f;
   float2 G = make_float2(0.f, 0.f);
   int gib = -1;
+  TabEntry et = A.tab[(long long)tr.x * P + p];
   for (int t = tr.x; t <= tr.y; ++t) {
     const int ib = t / S;
     if (ib != gib) {
       G = A.gblk[((long long)ib * g.nblk + jb) * P + p];
       gib = ib;
     }
-    const TabEntry et = A.tab[(long long)t * P + p];
-    // Q = conj(G) * E_t
-    const float qx = G.x * et.er + G.y * et.ei;
-    const float qy = G.x * et.ei - G.y * et.er;
+    const TabEntry en = A.tab[(long long)min(t + 1, tr.y) * P + p];
     const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
-    float gtx = 0.f;
+    float2 a0[S], a1[S];
+    float fr[S];
+    bool ok[S];
 #pragma unroll
     for (int k = 0; k < S; ++k) {
       int kk;
-      float f;
-      if (sample_pos(et.ui, et.uf, rx[k].ui, rx[k].uf, ns, kk, f)) {
-        const float2* q = base + (long long)k * ns + kk;
-        const float2 a0 = q[0], a1 = q[1];
-        const float dx = a1.x - a0.x, dy = a1.y - a0.y;
-        const float vx = fmaf(f, dx, a0.x), vy = fmaf(f, dy, a0.y);
-        const float wx = fmaf(fsf, dx, -om * vy);
-        const float wy = fmaf(fsf, dy, om * vx);
-        const float zx = wx * rx[k].e.x - wy * rx[k].e.y;
-        const float zy = wx * rx[k].e.y + wy * rx[k].e.x;
-        const float D = qx * zx - qy * zy;
-        gtx += D;
-        grx[k] += D;
-      }
+      ok[k] = sample_pos(et.ui, et.uf, rx[k].ui, rx[k].uf, ns, kk, fr[k]);
+      const float2* q = base + (unsigned)(k * ns + (ok[k] ? kk : 0));
+      a0[k] = q[0];
+      a1[k] = q[1];
+    }
+    // Q = conj(G) * E_t
+    const float qx = G.x * et.er + G.y * et.ei;
+    const float qy = G.x * et.ei - G.y * et.er;
+    float gtx = 0.f;
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const float f = fr[k];
+      const float dx = a1[k].x - a0[k].x, dy = a1[k].y - a0[k].y;
+      const float vx = fmaf(f, dx, a0[k].x), vy = fmaf(f, dy, a0[k].y);
+      const float wx = fmaf(fsf, dx, -om * vy);
+      const float wy = fmaf(fsf, dy, om * vx);
+      const float zx = wx * rx[k].e.x - wy * rx[k].e.y;
+      const float zy = wx * rx[k].e.y + wy * rx[k].e.x;
+      const float D = ok[k] ? qx * zx - qy * zy : 0.f;
+      gtx += D;
+      grx[k] += D;
     }
     if (gtx != 0.f) atomicAdd(A.gT2 + (long long)t * P + p, gtx);
+    et = en;
   }
 #pragma unroll
   for (int k = 0; k < S; ++k) {

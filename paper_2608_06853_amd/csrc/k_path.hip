@@ -16,33 +16,57 @@
 namespace af {
 namespace {
 
-// Sum over the wavefront of v[i], i = 0..15; lane l (l % 4 == 0) returns the sum
-// of v[l / 4] (every lane returns the sum of v[(l >> 2) & 15]).
-__device__ inline float reduce_scatter16(const float v[16], int lane) {
-  float h8[8], h4[4], h2[2];
-  const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0, b3 = (lane & 8) != 0,
-             b2 = (lane & 4) != 0;
+// Cross-lane moves of the reduce-scatter, all on the VALU (no LDS round trip):
+// permlane32_swap exchanges the upper half-wave of its first operand with the
+// lower half-wave of its second; permlane16_swap does the same for odd rows of
+// the first and even rows of the second; the DPP moves read lane l ^ 8
+// (row_ror:8), l ^ 7 (row_half_mirror), l ^ 2 and l ^ 1 (quad_perm).
+__device__ inline void swap32(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
+}
+__device__ inline void swap16(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
+}
+template <int CTRL>
+__device__ inline float dpp(float x) {
+  return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), CTRL, 0xf, 0xf, false));
+}
+constexpr int DPP_ROR8 = 0x128, DPP_HALF_MIRROR = 0x141, DPP_XOR2 = 0x4e, DPP_XOR1 = 0xb1;
+
+// Sum over the wavefront of v[i], i = 0..15: every lane returns the sum of
+// v[(l >> 2) & 15] (bit 3 of the index is lane bit 5, bit 2 lane bit 4, bit 1
+// lane bit 3, bit 0 lane bit 2).  Each stage halves the values a lane holds:
+// the half-wave swaps pair lanes l, l ^ 32 and l, l ^ 16 with no selects; the
+// last two stages pair l, l ^ 8 and l, l ^ 7 inside rows; a quad all-reduce ends.
+__device__ inline float reduce_scatter16(float v[16], int lane) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const float send = b5 ? v[i] : v[8 + i];
-    const float keep = b5 ? v[8 + i] : v[i];
-    h8[i] = keep + __shfl_xor(send, 32, 64);
+    swap32(v[i], v[8 + i]);       // lower half: both halves of v[i]; upper: of v[8+i]
+    v[i] += v[8 + i];
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const float send = b4 ? h8[i] : h8[4 + i];
-    const float keep = b4 ? h8[4 + i] : h8[i];
-    h4[i] = keep + __shfl_xor(send, 16, 64);
+    swap16(v[i], v[4 + i]);       // rows 0, 2: both rows of v[i]; rows 1, 3: of v[4+i]
+    v[i] += v[4 + i];
   }
+  const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
+  float h2[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    const float send = b3 ? h4[i] : h4[2 + i];
-    const float keep = b3 ? h4[2 + i] : h4[i];
-    h2[i] = keep + __shfl_xor(send, 8, 64);
+    const float send = b3 ? v[i] : v[2 + i];
+    const float keep = b3 ? v[2 + i] : v[i];
+    h2[i] = keep + dpp<DPP_ROR8>(send);
   }
-  float h1 = (b2 ? h2[1] : h2[0]) + __shfl_xor(b2 ? h2[0] : h2[1], 4, 64);
-  h1 += __shfl_xor(h1, 2, 64);
-  h1 += __shfl_xor(h1, 1, 64);
+  const float send = b2 ? h2[0] : h2[1];
+  float h1 = (b2 ? h2[1] : h2[0]) + dpp<DPP_HALF_MIRROR>(send);
+  h1 += dpp<DPP_XOR2>(h1);
+  h1 += dpp<DPP_XOR1>(h1);
   return h1;
 }
 
@@ -96,11 +120,16 @@ __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) val[i] = ck * wz[i >> 2] * wx[i & 3];
       int cell = i0 * W + j0;
-      const int c0 = __shfl(cell, lead, 64);
+      const int c0 = __builtin_amdgcn_readlane(cell, lead);
       if (!live) cell = c0;  // idle lanes (zero weights) join the leader's cell
+      if (__ballot(cell != c0) == 0ull) {  // the usual case: one cell for the whole wavefront
+        const float sum = reduce_scatter16(val, lane);
+        if ((lane & 3) == 0) grid[c0 + my_off] += sum;
+        continue;
+      }
       bool done = false;
       int ccur = c0;
-      // one round per distinct cell among the wavefront's lanes (usually one)
+      // one round per distinct cell among the wavefront's lanes
       while (true) {
         const bool in = !done && cell == ccur;
         float vv[16];
@@ -111,7 +140,7 @@ __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
         done = done || in;
         const unsigned long long rest = __ballot(!done);
         if (rest == 0ull) break;
-        ccur = __shfl(cell, __ffsll((long long)rest) - 1, 64);
+        ccur = __builtin_amdgcn_readlane(cell, __ffsll((long long)rest) - 1);
       }
     }
   }

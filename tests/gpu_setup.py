@@ -44,11 +44,14 @@ MICRO = afsynth.configs.MICRO
 
 @functools.lru_cache(maxsize=8)
 def case(name: str, t0: float = 0.0, t_ttp: float = 0.0, patch: int = 3, block: int | None = None,
-         perturb: float = 0.01):
-    """(cfg, oracle problem, iq complex64, s [nz][nx] float32, loss params)."""
+         perturb: float = 0.01, d_lens: float | None = None):
+    """(cfg, oracle problem, iq complex64, s [nz][nx] float32, loss params).
+    d_lens = 0 gives the lens-free (straight-ray) model."""
     base = {"micro": MICRO, "c1_small": C1_SMALL}[name]
-    cfg = base.with_(array=replace(base.array, t_ttp=t_ttp), acq=replace(base.acq, t0=t0),
-                     img=replace(base.img, patch=patch))
+    arr = replace(base.array, t_ttp=t_ttp)
+    if d_lens is not None:
+        arr = replace(arr, d_lens=d_lens)
+    cfg = base.with_(array=arr, acq=replace(base.acq, t0=t0), img=replace(base.img, patch=patch))
     if block is not None:
         cfg = cfg.with_(method=replace(cfg.method, block=block))
     med = afsynth.medium_for(cfg)

@@ -1,0 +1,105 @@
+"""Edge cases and error behaviour of the C ABI on the GPU: invalid arguments are
+rejected with a status and a message, calls in the wrong order report a state
+error, and the degenerate inputs of the method (no echo data, every sample
+outside the record, a single pixel) give the oracle's results."""
+import numpy as np
+import pytest
+
+import gpu_setup as G
+from oracle import model
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    G.ensure_built()
+
+
+def _ctx():
+    from paper_2608_06853_amd import _lib
+    return _lib.Context(0)
+
+
+def test_invalid_geometry_is_rejected():
+    from paper_2608_06853_amd import _lib
+    cfg, prob, iq, s, lp = G.case("micro")
+    ctx = _ctx()
+    ctx.set_lens(prob.d_lens, prob.c_lens)
+    good = dict(elem_xz=prob.elem_xz, pix_xz=prob.centres, patch=3, patch_spacing=prob.spacing,
+                n_samples=iq.shape[2], fs=prob.fs, t0=prob.t0, fd=prob.fd, block=prob.block,
+                fnum=prob.fnum, n_seg=prob.n_seg)
+    bad = [dict(pix_xz=np.zeros((0, 2))),                 # no pixels
+           dict(block=3),                                  # block does not divide the array
+           dict(block=8),                                  # fewer than 3 blocks
+           dict(patch=2),
+           dict(n_samples=1),
+           dict(elem_xz=prob.elem_xz[::-1].copy())]        # elements out of order
+    for kw in bad:
+        with pytest.raises(_lib.AfError) as e:
+            ctx.set_geometry(**{**good, **kw})
+        assert e.value.status == _lib.AF_ERR_ARG, kw
+        print("rejected", list(kw), "->", e.value, flush=True)
+    with pytest.raises(_lib.AfError):
+        ctx.set_lens(-1.0, 1.0)
+
+
+def test_wrong_call_order_and_uncovered_grid():
+    import torch
+    from paper_2608_06853_amd import _lib
+    cfg, prob, iq, s, lp = G.case("micro")
+    bf = G.beamformer(cfg, prob)
+    iq_d = torch.from_numpy(iq).cuda()
+    with pytest.raises(_lib.AfError) as e:          # no slowness yet
+        bf.ctx.loss_and_grad(iq_d, G.lib_params(lp), bf.empty_terms(), None)
+    assert e.value.status == _lib.AF_ERR_STATE
+    x0, z0, dx, dz, nx, nz = prob.grid
+    with pytest.raises(_lib.AfError) as e:          # grid shifted off the image
+        bf.ctx.set_slowness(nx, nz, x0 + 50.0, z0, dx, dz, torch.from_numpy(s).cuda())
+    assert e.value.status == _lib.AF_ERR_ARG
+    with pytest.raises(_lib.AfError):               # sb_ref must be positive
+        bf.set_slowness(torch.from_numpy(s).cuda())
+        bad = G.lib_params(lp)
+        bad.sb_ref = 0.0
+        bf.ctx.loss_and_grad(iq_d, bad, bf.empty_terms(), None)
+
+
+@pytest.mark.parametrize("kind", ["zero_data", "outside_record"])
+def test_no_valid_pairs_leaves_only_the_regularisers(kind):
+    import torch
+    from dataclasses import replace
+    cfg, prob, iq, s, lp = G.case("micro")
+    if kind == "zero_data":
+        iq = np.zeros_like(iq)
+        p = prob
+    else:  # every delay falls before sample 0
+        p = replace(prob, t0=1.0e4, _cache={})
+    bf = G.beamformer(cfg, p)
+    lpw = model.LossParams(**{**lp.__dict__, "w_sb": 0.0})
+    terms, grad = bf.loss_and_grad(torch.from_numpy(iq).cuda(), G.lib_params(lpw),
+                                   torch.from_numpy(s).cuda())
+    t = terms.cpu().numpy()
+    po = replace(p, iq=iq.astype(np.complex128), _cache={})
+    fo, go = model.loss_and_grad(po, s.astype(np.float64), lpw)
+    print(kind, "gpu", t[:6], "oracle", fo["cmpe"], fo["total"], fo["n_valid"], flush=True)
+    assert fo["n_valid"] == 0 and t[5] == 0 and t[0] == 0.0
+    assert abs(t[4] - fo["total"]) <= 1e-4 * max(abs(fo["total"]), 1e-6)
+    assert G.rel(grad.cpu().numpy(), go) < 1e-4
+
+
+def test_single_pixel():
+    import torch
+    from dataclasses import replace
+    cfg, prob, iq, s, lp = G.case("c1_small")
+    k = prob.centres.shape[0] // 2
+    p = replace(prob, centres=prob.centres[k:k + 1], _cache={})
+    bf = G.beamformer(cfg, p)
+    lpw = model.LossParams(**{**lp.__dict__, "rho_thresh": 0.0})
+    terms, grad = bf.loss_and_grad(torch.from_numpy(iq).cuda(), G.lib_params(lpw),
+                                   torch.from_numpy(s).cuda())
+    t = terms.cpu().numpy()
+    fo, go = model.loss_and_grad(p, s.astype(np.float64), lpw)
+    print("single pixel gpu", t[:6], "oracle", fo["cmpe"], fo["total"], fo["n_valid"], flush=True)
+    assert t[5] == fo["n_valid"] > 0
+    assert abs(t[4] - fo["total"]) <= 1e-4 * abs(fo["total"])
+    assert G.rel(grad.cpu().numpy(), go) < 1e-3

@@ -1,0 +1,158 @@
+"""Parity at full size in the launch configuration the benchmark times: the whole
+clinical (128 elements, 2560 samples, 256 x 256 pixels x 3 x 3 points, 32 x 32
+grid) and largest (192 elements, 4096 samples, 512 x 512 pixels, 64 x 64 grid)
+geometries are set up exactly as in the benchmark, and sampled outputs are
+compared with the FP64 oracle computed for those pixels alone:
+
+* travel times of every element to every point of 40 random pixels (1e-6);
+* block images and the coherence-factor map at those pixels (1e-4);
+* loss and gradient of a context holding only the sampled pixels (same array,
+  channel data and grid) against the oracle (1e-4 / 1e-3);
+* at full size, the gradient along a smooth direction against a central
+  difference of the library's own loss (a property that holds at any size).
+
+The channel data are seeded circular Gaussian noise (afsynth.random_iq): oracle
+inputs never come from the library."""
+import numpy as np
+import pytest
+
+import afsynth
+import gpu_setup as G
+import problems
+from oracle import model
+
+pytestmark = pytest.mark.gpu
+
+N_SAMPLE_PIX = 40
+DEPTH_SCALE = 1.740 / 1.540     # the grid covers every speed of the dynamic-grid sweep
+
+
+def _slowness(grid, seed):
+    """Smooth seeded slowness around 1/1540 us/mm on the node grid."""
+    x0, z0, dx, dz, nx, nz = grid
+    rng = np.random.default_rng(seed)
+    X, Z = np.meshgrid(np.linspace(0, 1, nx), np.linspace(0, 1, nz))
+    s = np.full((nz, nx), 1.0 / 1.54)
+    for _ in range(3):
+        kx, kz, ph = rng.uniform(0.5, 2.0), rng.uniform(0.5, 2.0), rng.uniform(0, 2 * np.pi)
+        s += 0.01 / 1.54 * np.cos(2 * np.pi * (kx * X + kz * Z) + ph)
+    return s.astype(np.float32)
+
+
+def _lp(cfg):
+    lp = problems.loss_params(cfg)
+    return model.LossParams(**{**lp.__dict__, "rho_thresh": 0.5})
+
+
+@pytest.fixture(scope="module", params=["c2_clinical", "c5_largest"])
+def full(request):
+    import torch
+    from paper_2608_06853_amd import autofocus as af, workloads
+    G.ensure_built()
+    cfg = afsynth.config_by_name(request.param)
+    print("full-size case", cfg.name, flush=True)
+    acqd, imgd, grid, cover = workloads.geometry(cfg)
+    prob = problems.problem(cfg, depth_scale_max=DEPTH_SCALE)
+    assert np.allclose(prob.grid[:4], (grid.x0, grid.z0, grid.dx, grid.dz))
+    iq = afsynth.random_iq(cfg.array.n_elem, cfg.acq.n_samples, seed=cfg.seed)
+    s = _slowness(prob.grid, cfg.seed)
+    bf = af.Beamformer(acqd, imgd, grid)
+    iq_d = torch.from_numpy(iq).cuda().reshape(-1)
+    bf.set_slowness(torch.from_numpy(s).cuda())
+    rng = np.random.default_rng(cfg.seed + 101)
+    sel = np.sort(rng.choice(prob.centres.shape[0], N_SAMPLE_PIX, replace=False))
+    sub = model.Problem(**{**prob.__dict__, "centres": prob.centres[sel], "_cache": {},
+                           "iq": iq.astype(np.complex128)})
+    yield cfg, bf, iq_d, s, sel, sub, acqd, imgd, grid
+    del bf
+    torch.cuda.empty_cache()
+
+
+def _point_index(sel, M):
+    return (sel[:, None] * M + np.arange(M)[None, :]).reshape(-1)
+
+
+def test_travel_times_sampled(full):
+    import torch
+    cfg, bf, iq_d, s, sel, sub, *_ = full
+    M = sub.n_patch
+    idx = torch.from_numpy(_point_index(sel, M)).cuda()
+    T = bf.travel_times().index_select(1, idx).cpu().numpy().astype(np.float64)
+    To = model.travel_times(sub, s.astype(np.float64))
+    h = sub.apod()
+    assert np.array_equal(np.isfinite(T), h)
+    err = np.abs(T[h] - To[h]) / To[h]
+    print(cfg.name, "sampled T max rel err", err.max(), "rays", int(h.sum()), flush=True)
+    assert err.max() < 1e-6
+
+
+def test_block_images_sampled(full):
+    import torch
+    cfg, bf, iq_d, s, sel, sub, *_ = full
+    M = sub.n_patch
+    lp = _lp(cfg)
+    bf.ctx.loss_and_grad(iq_d, G.lib_params(lp), bf.empty_terms(), None)
+    img, maps, blk = bf.beamform(iq_d, blocks=True)
+    nb = bf.n_blk
+    idx = torch.from_numpy(_point_index(sel, M)).cuda()
+    bg = blk.view(nb * nb, -1).index_select(1, idx).cpu().numpy().reshape(nb, nb, -1)
+    del blk
+    f = model.forward(sub, s.astype(np.float64), lp, keep=True)
+    e_blk = G.rel(bg, f["bblk"])
+    cf = maps.view(2, -1)[1].cpu().numpy()[sel]
+    e_cf = G.rel(cf, f["cf"])
+    print(cfg.name, "sampled blocks rel", e_blk, "cf rel", e_cf, flush=True)
+    assert e_blk < 1e-4 and e_cf < 1e-4
+
+
+def test_loss_and_gradient_sampled_pixels(full):
+    import torch
+    from dataclasses import replace
+    from paper_2608_06853_amd import autofocus as af
+    cfg, bf, iq_d, s, sel, sub, acqd, imgd, grid = full
+    lp = _lp(cfg)
+    bs = af.Beamformer(acqd, replace(imgd, centres=imgd.centres[sel]), grid)
+    terms, grad = bs.loss_and_grad(iq_d, G.lib_params(lp), torch.from_numpy(s).cuda())
+    t = terms.cpu().numpy()
+    fo, go = model.loss_and_grad(sub, s.astype(np.float64), lp)
+    print(cfg.name, "sampled-pixel loss gpu", t[:6], "oracle", fo["cmpe"], fo["total"],
+          fo["n_valid"], flush=True)
+    assert fo["n_valid"] > 50
+    assert abs(t[5] - fo["n_valid"]) <= max(2, 1e-3 * fo["n_valid"])
+    tol = 1e-4 if t[5] == fo["n_valid"] else 2e-3
+    assert abs(t[4] - fo["total"]) <= tol * abs(fo["total"])
+    eg = G.rel(grad.cpu().numpy(), go)
+    print(cfg.name, "sampled-pixel grad rel err", eg, flush=True)
+    assert eg < (1e-3 if t[5] == fo["n_valid"] else 2e-2)
+
+
+def test_full_size_gradient_directional(full):
+    """Central difference of the library's own loss along a smooth direction that
+    keeps mean(1/s) (hence c_med and the refraction points, which the gradient
+    holds constant) fixed to first order.  rho_thresh = 0 keeps every pair valid,
+    so no validity mask flips inside the difference step."""
+    import torch
+    cfg, bf, iq_d, s, *_ = full
+    lp = G.lib_params(model.LossParams(**{**_lp(cfg).__dict__, "rho_thresh": 0.0}))
+    s_d = torch.from_numpy(s).cuda()
+    terms, grad = bf.loss_and_grad(iq_d, lp, s_d)
+    t = terms.cpu().numpy()
+    assert np.isfinite(t).all() and torch.isfinite(grad).all()
+    assert t[5] > 1000
+    nz, nx = s.shape
+    X, Z = np.meshgrid(np.linspace(-1, 1, nx), np.linspace(-1, 1, nz))
+    d = np.cos(1.3 * X + 0.4) * np.sin(0.9 * Z + 0.2)
+    w = 1.0 / s.astype(np.float64) ** 2
+    d -= (d * w).sum() / (w * w).sum() * w
+    d *= 2e-5 * float(s.mean()) / np.abs(d).max()
+    lv = []
+    for sgn in (1.0, -1.0):
+        tt, _ = bf.loss_and_grad(iq_d, lp, torch.from_numpy((s + sgn * d).astype(np.float32)).cuda(),
+                                 want_grad=False)
+        lv.append(float(tt[4].item()))
+    fd = (lv[0] - lv[1]) / 2.0
+    g = grad.cpu().numpy().astype(np.float64)
+    an = float((g * d).sum())
+    err = abs(fd - an) / (np.linalg.norm(g) * np.linalg.norm(d))
+    print(cfg.name, "directional derivative fd", fd, "adjoint", an, "normalised err", err, flush=True)
+    assert err < 2e-2

@@ -11,8 +11,11 @@ from oracle import model
 
 pytestmark = pytest.mark.gpu
 
+# (config, t0, t_ttp, patch, block, perturbation, lens thickness); the last case is
+# the lens-free straight-ray model.
 CASES = [("micro", 0.0, 0.0, 3, None), ("c1_small", 0.0, 0.0, 3, None),
-         ("micro", 0.7, 0.35, 3, None), ("micro", 0.0, 0.0, 1, 2)]
+         ("micro", 0.7, 0.35, 3, None), ("micro", 0.0, 0.0, 1, 2),
+         ("micro", 0.0, 0.0, 3, None, 0.01, 0.0)]
 
 
 @pytest.fixture(scope="module", autouse=True)
