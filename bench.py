@@ -146,18 +146,20 @@ def plain_loop_report():
 
 def s_to_target_report(n_heldout: int = 3):
     """Wall-clock to the plain method's final CMPE, learned warm start vs plain
-    initialisation: on the largest workload and on held-out media of the network's
-    training distribution."""
+    initialisation, on held-out media of the network's training distribution and
+    on the largest workload; plus the initial-map RMSE of both networks."""
     import afsynth
     from paper_2608_06853_amd import warmstart
-    net = warmstart.load_network()
+    nets = {k: warmstart.load_network(k) for k in ("plain", "true")}
     keep = ("target_cmpe", "plain_seconds", "plain_iters", "learned_seconds", "learned_iters",
             "learned_reached", "learned_fallback", "speedup", "plain_rmse_mps", "learned_rmse_mps")
     out = {}
-    r = warmstart.s_to_target(afsynth.configs.C5, net)
-    out["c5_largest"] = {k: r[k] for k in keep}
-    rows = [warmstart.s_to_target(afsynth.configs.C4, net, seed=9000 + k) for k in range(n_heldout)]
+    rows = [warmstart.s_to_target(afsynth.configs.C4, nets["plain"], seed=9000 + k)
+            for k in range(n_heldout)]
     out["c4_heldout"] = [{k: r[k] for k in keep} for r in rows]
+    r = warmstart.s_to_target(afsynth.configs.C5, nets["plain"])
+    out["c5_largest"] = {k: r[k] for k in keep}
+    out["c4_heldout_initial_rmse_mps"] = warmstart.evaluate_init(nets, range(9000, 9008))
     return out
 
 

@@ -7,9 +7,12 @@ convolution, its gradients, the loss and the Adam update run in libaf.so on the
 BF16 matrix cores (FP32 accumulate); this module holds parameters and buffers
 (torch tensors) and sequences the library calls.
 
-The prediction is resampled onto the slowness grid and checked against the
-homogeneous initial guess: if its loss is higher, the plain adaptive-grid
-initialisation is used instead.
+Two networks of this shape are trained on the same features: one on the true
+slowness of each medium (how close the initial map is to the truth) and one on
+the plain method's converged solution (what the objective prefers, used as the
+warm start).  The prediction is resampled onto the slowness grid and checked
+against the homogeneous initial guess: if its loss is higher, the plain
+adaptive-grid initialisation is used instead.
 """
 from __future__ import annotations
 
@@ -203,23 +206,56 @@ def label_map(cfg, med, og: OutGrid, sub: int = 4) -> np.ndarray:
     return ((s - S_BASE) / DS_SCALE).astype(np.float32)
 
 
-def make_dataset(cfg, seeds, device: int = 0, progress: bool = False):
-    """(features [n][128][128][2] BF16 on device, labels [n][32][32] FP32 on device)."""
+def grid_to_polar(s_grid: np.ndarray, grid: af.Grid, og: OutGrid) -> np.ndarray:
+    """Slowness given on the node grid, sampled bilinearly (clamped to the node range)
+    at the centres of the polar output bins, in network units [32][32]."""
+    r = og.r0 + og.dr * np.arange(OUT_H)[:, None]
+    t = og.t0 + og.dt * np.arange(OUT_W)[None, :]
+    u = np.clip((r * np.sin(t) - grid.x0) / grid.dx, 0.0, grid.nx - 1.0)
+    v = np.clip((r * np.cos(t) - grid.z0) / grid.dz, 0.0, grid.nz - 1.0)
+    j0 = np.minimum(u.astype(int), grid.nx - 2)
+    i0 = np.minimum(v.astype(int), grid.nz - 2)
+    fu, fv = u - j0, v - i0
+    sg = np.asarray(s_grid, dtype=np.float64)
+    val = ((1 - fv) * ((1 - fu) * sg[i0, j0] + fu * sg[i0, j0 + 1])
+           + fv * ((1 - fu) * sg[i0 + 1, j0] + fu * sg[i0 + 1, j0 + 1]))
+    return ((val - S_BASE) / DS_SCALE).astype(np.float32)
+
+
+def make_dataset(cfg, seeds, device: int = 0, progress: bool = False, plain_iters: int = 0):
+    """Features [n][128][128][2] BF16 and labels [n][32][32] FP32, on the device.
+
+    Returns (X, Y_true, Y_plain): Y_true is the true slowness of each medium;
+    Y_plain (None unless ``plain_iters`` > 0) is the plain method's solution on
+    the configuration's own grid (adaptive-grid sweep, then ``plain_iters`` Adam
+    steps), both as deviations from 1/1540 in network units."""
     fm = FeatureMaker(cfg, device)
     og = OutGrid.for_config(cfg)
     n = len(seeds)
     X = torch.empty(n, FEAT_H * FEAT_W * 2, device=fm.bf.device, dtype=torch.bfloat16)
     Y = torch.empty(n, OUT_H, OUT_W, device=fm.bf.device)
+    Yp = None
+    if plain_iters > 0:
+        Yp = torch.empty(n, OUT_H, OUT_W, device=fm.bf.device)
+        acqd, imgd, grid, _ = workloads.geometry(cfg)
+        bfp = af.Beamformer(acqd, imgd, grid, device)
+        lp = workloads.loss_params(cfg)
+        ap = _lib.adam_params(lr=cfg.method.lr)
     t0 = time.perf_counter()
     for i, sd in enumerate(seeds):
         med = afsynth.medium_for(fm.cfg, int(sd))
         iq = workloads.simulate(fm.bf, fm.cfg, med, fm.cover)
         fm.features(iq, X[i])
         Y[i] = torch.from_numpy(label_map(fm.cfg, med, og)).to(fm.bf.device)
+        if plain_iters > 0:
+            bfp.set_imaging(imgd)
+            af.sweep(bfp, iq, lp, cfg.acq.fc)
+            s, _ = af.plain_autofocus(bfp, iq, lp, ap, plain_iters, record_every=0)
+            Yp[i] = torch.from_numpy(grid_to_polar(s.cpu().numpy(), grid, og)).to(fm.bf.device)
         if progress and (i + 1) % 256 == 0:
             torch.cuda.synchronize()
             print(f"  dataset {i + 1}/{n}  {time.perf_counter() - t0:.1f} s", flush=True)
-    return X.view(n, FEAT_H, FEAT_W, 2), Y
+    return X.view(n, FEAT_H, FEAT_W, 2), Y, Yp
 
 
 def train(net: WarmStartNet, X, Y, epochs: int, batch: int = 32, lr: float = 1e-3, seed: int = 0,

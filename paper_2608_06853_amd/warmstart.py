@@ -1,9 +1,12 @@
-"""Training of the warm-start network and the wall-clock comparison of the learned
+"""Training of the warm-start networks and the wall-clock comparison of the learned
 initialisation against the plain adaptive-grid initialisation.
 
-Training data: media of the randomised configs[0] type (seeds 1000...), each with
-its channel data simulated on the GPU, the feature maps of a homogeneous 1540 m/s
-beamform and its true slowness on the network's polar output grid.
+Training data: media of the randomised 32-element two-layer type (seeds 1000...),
+each with its channel data simulated on the GPU, the feature maps of a
+homogeneous 1540 m/s beamform and two labels on the network's polar output grid:
+the true slowness, and the plain method's converged solution (sweep + Adam).
+One network is trained per label; the warm start uses the one trained on the
+plain solution, because the plain optimiser judges the initial map by its loss.
 
 Comparison ("s-to-target"): from channel data resident on the GPU, the time each
 method needs to reach the CMP phase error that the plain method reaches after its
@@ -13,7 +16,7 @@ best speed; learned: the mean speed of the predicted map).  The learned path fal
 back to the plain sweep when its initial loss exceeds that of the homogeneous
 1540 m/s guess.
 
-    python -m paper_2608_06853_amd.warmstart --train 4096 --epochs 20 --out FILE
+    python -m paper_2608_06853_amd.warmstart --train 2048 --epochs 30 --plain-iters 200
 """
 from __future__ import annotations
 
@@ -29,30 +32,39 @@ import afsynth
 from . import _lib, autofocus as af, cnn, workloads
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "warmstart_c4.npz")
+WEIGHTS = {"plain": os.path.join(HERE, "weights", "warmstart_c4_plain.npz"),
+           "true": os.path.join(HERE, "weights", "warmstart_c4_true.npz")}
 
 
-def train_network(n_train: int, epochs: int, batch: int = 32, lr: float = 1e-3, seed0: int = 1000,
-                  progress: bool = True, device: int = 0):
+def train_networks(n_train: int, epochs: int, batch: int = 32, lr: float = 1e-3, seed0: int = 1000,
+                   plain_iters: int = 200, progress: bool = True, device: int = 0):
+    """({"true": net, "plain": net}, info) trained on one seeded dataset."""
     cfg = afsynth.configs.C4
     ctx = _lib.Context(device)
     t0 = time.perf_counter()
-    X, Y = cnn.make_dataset(cfg, list(range(seed0, seed0 + n_train)), device, progress)
+    X, Y, Yp = cnn.make_dataset(cfg, list(range(seed0, seed0 + n_train)), device, progress,
+                                plain_iters=plain_iters)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    net = cnn.WarmStartNet(ctx, seed=0, device=device)
-    t0 = time.perf_counter()
-    hist = cnn.train(net, X, Y, epochs, batch, lr, progress=progress)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    return net, {"n_train": n_train, "epochs": epochs, "batch": batch, "lr": lr,
-                 "data_s": t_data, "train_s": t_train, "loss_per_epoch": hist}
+    nets, info = {}, {"n_train": n_train, "epochs": epochs, "batch": batch, "lr": lr,
+                      "plain_iters": plain_iters, "data_s": t_data}
+    for kind, lab in (("true", Y), ("plain", Yp)):
+        if lab is None:
+            continue
+        net = cnn.WarmStartNet(ctx, seed=0, device=device)
+        t0 = time.perf_counter()
+        hist = cnn.train(net, X, lab, epochs, batch, lr, progress=progress)
+        torch.cuda.synchronize()
+        info[f"train_s_{kind}"] = time.perf_counter() - t0
+        info[f"loss_per_epoch_{kind}"] = hist
+        nets[kind] = net
+    return nets, info
 
 
-def load_network(path: str = DEFAULT_WEIGHTS, device: int = 0):
+def load_network(kind: str = "plain", path: str | None = None, device: int = 0):
     ctx = _lib.Context(device)
     net = cnn.WarmStartNet(ctx, seed=0, device=device)
-    with np.load(path, allow_pickle=False) as f:
+    with np.load(path or WEIGHTS[kind], allow_pickle=False) as f:
         net.load({k: f[k] for k in f.files})
     return net
 
@@ -134,9 +146,10 @@ def s_to_target(cfg, net, n_iter: int = 200, max_iter: int = 400, seed=None, dev
     return out
 
 
-def evaluate_init(net, seeds, device: int = 0):
-    """RMSE (m/s) of the slowness grid from the network, from the homogeneous 1540 m/s
-    guess and from the plain sweep, on held-out configs[0]-type media."""
+def evaluate_init(nets: dict, seeds, device: int = 0, plain_iters: int = 0):
+    """Mean RMSE (m/s) against the true map of the slowness grid from each network,
+    from the homogeneous 1540 m/s guess, from the plain sweep and (with
+    ``plain_iters``) from the plain method's solution, on held-out media."""
     from . import metrics
     cfg = afsynth.configs.C4
     fm = cnn.FeatureMaker(cfg, device)
@@ -148,32 +161,44 @@ def evaluate_init(net, seeds, device: int = 0):
         med = afsynth.medium_for(cfg, int(sd))
         iq = workloads.simulate(bf, cfg, med, cover)
         c_true = workloads.true_speed_nodes(cfg, med, grid)
-        s_net = cnn.predict_slowness(net, fm, iq, cfg, grid).cpu().numpy()
+        row = {}
+        for kind, net in nets.items():
+            s_net = cnn.predict_slowness(net, fm, iq, cfg, grid).cpu().numpy()
+            row[f"net_{kind}"] = metrics.speed_errors(s_net, c_true)["rmse_mps"]
+        row["homogeneous_1540"] = metrics.speed_errors(np.full(grid.shape, 1 / 1.54), c_true)["rmse_mps"]
         bf.set_imaging(imgd)
         _, _, best = af.sweep(bf, iq, lp, cfg.acq.fc)
+        row["sweep"] = metrics.speed_errors(np.full(grid.shape, 1 / best), c_true)["rmse_mps"]
+        if plain_iters > 0:
+            s, _ = af.plain_autofocus(bf, iq, lp, _lib.adam_params(lr=cfg.method.lr), plain_iters,
+                                      record_every=0)
+            row["plain_solution"] = metrics.speed_errors(s.cpu().numpy(), c_true)["rmse_mps"]
         bf.set_imaging(imgd)
-        rows.append({
-            "net": metrics.speed_errors(s_net, c_true)["rmse_mps"],
-            "homogeneous_1540": metrics.speed_errors(np.full(grid.shape, 1 / 1.54), c_true)["rmse_mps"],
-            "sweep": metrics.speed_errors(np.full(grid.shape, 1 / best), c_true)["rmse_mps"],
-        })
+        rows.append(row)
     return {k: float(np.mean([r[k] for r in rows])) for k in rows[0]}
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train", type=int, default=4096)
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--train", type=int, default=2048)
+    ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--plain-iters", type=int, default=200)
     ap.add_argument("--eval", type=int, default=32, help="held-out media (seeds 9000...)")
-    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--out-dir", default=os.path.join(HERE, "weights"))
     args = ap.parse_args()
-    net, info = train_network(args.train, args.epochs, args.batch, args.lr)
-    os.makedirs(os.path.dirname(args.out), exist_ok=True)
-    np.savez(args.out, **net.state())
-    info["heldout_rmse_mps"] = evaluate_init(net, range(9000, 9000 + args.eval))
-    print(json.dumps(info))
+    nets, info = train_networks(args.train, args.epochs, args.batch, args.lr,
+                                plain_iters=args.plain_iters)
+    os.makedirs(args.out_dir, exist_ok=True)
+    for kind, net in nets.items():
+        np.savez(os.path.join(args.out_dir, os.path.basename(WEIGHTS[kind])), **net.state())
+    info["heldout_rmse_mps"] = evaluate_init(nets, range(9000, 9000 + args.eval),
+                                             plain_iters=args.plain_iters)
+    print(json.dumps(info), flush=True)
+    for k in range(3):
+        r = s_to_target(afsynth.configs.C4, nets["plain"], seed=9000 + k)
+        print(json.dumps({kk: v for kk, v in r.items()}), flush=True)
 
 
 if __name__ == "__main__":
