@@ -111,7 +111,10 @@ af_status af_set_slowness(af_ctx* ctx, int nx, int nz, double x0, double z0, dou
  *   maps_dev [2][n_pix] integrated CMPE (per-pixel mean phase error over valid
  *            pairs) and coherence factor at the patch centres.
  * Point order is the caller's (see af_set_geometry).  The CMPE map uses
- * rho_thresh from the most recent loss call (default 0.9). */
+ * rho_thresh from the most recent loss call (default 0.9).  The channel data
+ * must be finite: samples of apodised-out element pairs are read and weighted
+ * by zero, so a non-finite sample anywhere in a read window makes the result
+ * non-finite. */
 af_status af_beamform(af_ctx* ctx, const af_complex* iq_dev, af_complex* blk_dev,
                 af_complex* img_dev, float* maps_dev);
 

@@ -11,10 +11,10 @@ namespace af {
 constexpr int TILE = 256;           // points per tile = threads of a DAS workgroup
 constexpr int SUB = 64;             // points per CMPE sub-tile = one wavefront
 constexpr int MAX_NBA = 16;         // active blocks per tile the CMPE kernel supports
-constexpr int SENTINEL = -(1 << 29);  // sample index of a masked (element, point) entry
 
 // One travel-time table entry: sample position u = ui + uf of (T + t_ttp/2 - t0/2) * fs
-// and the apodised phasor h * exp(j 2 pi fd (T + t_ttp/2)).
+// and the apodised phasor h * exp(j 2 pi fd (T + t_ttp/2)).  A masked entry (h = 0)
+// has ui = 0, uf = 0 and a zero phasor, so its samples contribute nothing.
 struct alignas(16) TabEntry {
   int ui;
   float uf;

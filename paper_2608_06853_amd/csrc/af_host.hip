@@ -291,8 +291,9 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
   // Pack the pixels, in k-d order, into sub-tiles of pps and tiles of 4 sub-tiles.
   // A tile is closed early (its remaining slots become padding) when the next
   // pixel would widen its span of active blocks beyond what the CMPE kernel
-  // stages (MAX_NBA); with compact images this never happens and the packing
+  // stages in LDS; with compact images this never happens and the packing
   // follows the k-d units exactly.  slot[k] = tile * ppt + sub-tile * pps + s.
+  const int span_max = af::cmpe_span_limit(pps);
   std::vector<long long> slot(n_pix);
   int n_tiles = 0;
   {
@@ -312,13 +313,13 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
       const int q = ord[k];
       int plo, phi;
       pix_blocks(q, plo, phi);
-      if (plo <= phi && phi - plo + 1 > af::MAX_NBA)
-        return fail(c, AF_ERR_ARG, "af_set_geometry: a pixel spans more than 16 active blocks (aperture too wide for the block size)");
+      if (plo <= phi && phi - plo + 1 > span_max)
+        return fail(c, AF_ERR_ARG, "af_set_geometry: a pixel spans more active blocks than the CMPE stage holds (aperture too wide for the block size)");
       bool new_tile = t < 0;
       if (!new_tile && plo <= phi) {
         const int nlo = bhi < blo ? plo : std::min(blo, plo);
         const int nhi = bhi < blo ? phi : std::max(bhi, phi);
-        new_tile = nhi - nlo + 1 > af::MAX_NBA;
+        new_tile = nhi - nlo + 1 > span_max;
       }
       if (!new_tile && sidx == pps) {  // current sub-tile full: next sub-tile or tile
         if (w == 3) new_tile = true;
@@ -405,8 +406,8 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
     for (int a0 = LO; a0 <= HI; a0 += af::TAB_CHUNK) tabwork.push_back(make_int2(t, a0));
     load.push_back({(long long)(HI - LO + 1) * (HI - LO + 1), t});
   }
-  if (c->nba_max > af::MAX_NBA)
-    return fail(c, AF_ERR_ARG, "af_set_geometry: a tile spans more than 16 active blocks (aperture too wide for the block size)");
+  if (c->nba_max > span_max)
+    return fail(c, AF_ERR_ARG, "af_set_geometry: a tile spans more active blocks than the CMPE stage holds");
   std::stable_sort(load.begin(), load.end(), [](auto& a, auto& b) { return a.first > b.first; });
   c->tile_order.clear();
   for (auto& l : load) c->tile_order.push_back(l.second);

@@ -66,6 +66,7 @@ struct DasArgs {
   const TabEntry* tab;
   const float2* iq;       // [N][N][ns]
   const int4* tiles;
+  const int2* prange;     // active element range of every point
   const int2* work;       // (tile, rx block) for the forward
   const int* order;       // tile order for the adjoint
   float2* bblk;           // [nb][nb][P]  (forward output)
@@ -173,6 +174,7 @@ hipError_t launch_prepare_grid(af_ctx* c, const float* s, int nx, int nz, float*
                                int do_reg, const af_loss_params* lp, float* regg);
 hipError_t launch_table(af_ctx* c);
 hipError_t launch_das_fwd(af_ctx* c, const float2* iq, float2* bblk);
+int cmpe_span_limit(int pps);  // largest tile span in blocks whose CMPE stage fits in LDS
 hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g, float rho,
                        float sb_scale, float* map_cmpe, float* map_cf, float2* img);
 hipError_t launch_finalize(af_ctx* c, const af_loss_params* lp, float* terms);

@@ -9,9 +9,9 @@
 // C = sum X conj(Y); it is valid when both energies exceed 1e-30 and
 // rho = |C| / sqrt(sum|X|^2 sum|Y|^2) >= rho_thresh; its error is |arg C|.
 //
-// One wavefront owns one sub-tile of 64 points (whole patches plus padding) and
-// stages every active block image of the sub-tile in LDS.  Partial sums go to a
-// per-sub-tile slot and are reduced in fixed order afterwards (deterministic).
+// Four wavefronts own one sub-tile of 64 points (whole patches plus padding) and
+// stage its subaperture images in LDS.  Partial sums go to a per-sub-tile slot
+// and are reduced in fixed order afterwards (deterministic).
 #include "af_internal.h"
 
 namespace af {
@@ -25,10 +25,21 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(64) void k_cmpe(CmpeArgs A) {
-  extern __shared__ float2 Bs[];
+constexpr int CMPE_WAVES = 4;
+
+// One workgroup of 4 wavefronts per 64-point sub-tile.  Phase 1 forms, for this
+// sub-tile, the full image and block energy per point and every subaperture
+// image S(i, j) = sum of its 2 x 2 block images that a pair of the sub-tile can
+// use, in LDS.  Phase 2 evaluates the (pixel, pair) entries; phase 3 writes the
+// gradient of every active block image as the sum of dL/dS over the four
+// subapertures that contain it.  The block images are read only in phase 1, so
+// the gradient may overwrite them in place.
+__global__ __launch_bounds__(256) void k_cmpe(CmpeArgs A) {
+  extern __shared__ float2 sm[];
+  __shared__ float pimg[CMPE_WAVES][3][SUB];
+  __shared__ double red[CMPE_WAVES][3];
   const Geo& g = A.g;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & (SUB - 1), wv = tid / SUB;
   const long long st = blockIdx.x;
   const long long p0 = st * SUB;
   const long long tile = p0 / TILE;
@@ -36,59 +47,72 @@ __global__ __launch_bounds__(64) void k_cmpe(CmpeArgs A) {
   const int4 tr = A.tiles[tile];
   const int M = g.patch2, pps = g.pps;
   const long long P = g.P;
-  const int ppt = 4 * pps;
-  const long long slot0 = tile * ppt + (long long)w * pps;
+  const long long slot0 = tile * (4 * pps) + (long long)w * pps;
 
   if (tr.x > tr.y) {
+    if (tid < SUB) {
+      A.gsb[p0 + tid] = make_float2(0.f, 0.f);
+      if (A.img) A.img[p0 + tid] = make_float2(0.f, 0.f);
+      if (tid < pps) {
+        if (A.map_cmpe) A.map_cmpe[slot0 + tid] = 0.f;
+        if (A.map_cf) A.map_cf[slot0 + tid] = 0.f;
+      }
+    }
     if (tid == 0) {
       A.part[4 * st + 0] = 0.0;
       A.part[4 * st + 1] = 0.0;
       A.part[4 * st + 2] = 0.0;
       A.part[4 * st + 3] = 0.0;
     }
-    A.gsb[p0 + tid] = make_float2(0.f, 0.f);
-    if (A.img) A.img[p0 + tid] = make_float2(0.f, 0.f);
-    if (tid < pps) {
-      if (A.map_cmpe) A.map_cmpe[slot0 + tid] = 0.f;
-      if (A.map_cf) A.map_cf[slot0 + tid] = 0.f;
-    }
     return;
   }
-  const int bLO = tr.z, nbA = tr.w - tr.z + 1;
-  const int nbb = nbA * nbA;
-  for (int idx = tid; idx < nbb * SUB; idx += SUB) {
-    const int blk = idx / SUB, l = idx - blk * SUB;
-    const int bi = blk / nbA, bj = blk - bi * nbA;
-    Bs[idx] = A.bblk[((long long)(bLO + bi) * g.nblk + (bLO + bj)) * P + p0 + l];
+  const int bLO = tr.z, bHI = tr.w, nbA = bHI - bLO + 1, nbb = nbA * nbA;
+  // pairs (i, j) in [pLo, pHi]^2 use subapertures with indices in [pLo, pHi + 1]
+  const int pLo = max(0, bLO - 1);
+  const int pHi = min(g.nsub - 2, bHI - 1);
+  const int npr = max(0, pHi - pLo + 1);
+  const int np2 = npr * npr;
+  const int nS = npr > 0 ? npr + 1 : 0;
+  float2* Ss = sm;                                   // [nS * nS][SUB]
+  float2* gC = Ss + (size_t)nS * nS * SUB;           // [pps][np2]
+  float* er = reinterpret_cast<float*>(gC + (size_t)pps * np2);
+
+  auto bget = [&](int a, int b) -> float2 {
+    if (a < bLO || a > bHI || b < bLO || b > bHI) return make_float2(0.f, 0.f);
+    return A.bblk[((long long)a * g.nblk + b) * P + p0 + lane];
+  };
+
+  // phase 1: per-point image and energy (a quarter of the blocks per wavefront),
+  // subaperture images
+  {
+    float bx = 0.f, by = 0.f, e2 = 0.f;
+    for (int b = wv; b < nbb; b += CMPE_WAVES) {
+      const float2 v = A.bblk[((long long)(bLO + b / nbA) * g.nblk + (bLO + b % nbA)) * P + p0 + lane];
+      bx += v.x;
+      by += v.y;
+      e2 += v.x * v.x + v.y * v.y;
+    }
+    pimg[wv][0][lane] = bx;
+    pimg[wv][1][lane] = by;
+    pimg[wv][2][lane] = e2;
+  }
+  for (int idx = wv; idx < nS * nS; idx += CMPE_WAVES) {
+    const int si = pLo + idx / nS, sj = pLo + idx % nS;
+    const float2 a = bget(si, sj), b = bget(si + 1, sj), c = bget(si, sj + 1), d = bget(si + 1, sj + 1);
+    Ss[(size_t)idx * SUB + lane] = make_float2(a.x + b.x + c.x + d.x, a.y + b.y + c.y + d.y);
   }
   __syncthreads();
 
-  auto blk = [&](int i, int j, int l) -> float2 {
-    const int bi = i - bLO, bj = j - bLO;
-    if (bi < 0 || bj < 0 || bi >= nbA || bj >= nbA) return make_float2(0.f, 0.f);
-    return Bs[(bi * nbA + bj) * SUB + l];
-  };
-  auto sub = [&](int i, int j, int l) -> float2 {
-    const float2 a = blk(i, j, l), b = blk(i + 1, j, l), c = blk(i, j + 1, l), d = blk(i + 1, j + 1, l);
-    return make_float2(a.x + b.x + c.x + d.x, a.y + b.y + c.y + d.y);
-  };
-
-  const int pLo = max(0, bLO - 1);
-  const int pHi = min(g.nsub - 2, tr.w - 1);
-  const int npr = max(0, pHi - pLo + 1);
-  const int np2 = npr * npr;
-  float2* gC = Bs + nbb * SUB;
-  float* er = reinterpret_cast<float*>(gC + pps * np2);
-
+  // phase 2: (pixel, pair) entries
   double e_acc = 0.0, nv = 0.0;
-  for (int item = tid; item < pps * np2; item += SUB) {
+  for (int item = tid; item < pps * np2; item += CMPE_WAVES * SUB) {
     const int q = item / np2, pr = item - q * np2;
     const int i = pLo + pr / npr, j = pLo + pr % npr;
+    const float2* Xs = Ss + (size_t)((i - pLo) * nS + (j + 1 - pLo)) * SUB + q * M;
+    const float2* Ys = Ss + (size_t)((i + 1 - pLo) * nS + (j - pLo)) * SUB + q * M;
     float cx = 0.f, cy = 0.f, ex = 0.f, ey = 0.f;
     for (int m = 0; m < M; ++m) {
-      const int l = q * M + m;
-      const float2 X = sub(i, j + 1, l);
-      const float2 Y = sub(i + 1, j, l);
+      const float2 X = Xs[m], Y = Ys[m];
       cx += X.x * Y.x + X.y * Y.y;
       cy += X.y * Y.x - X.x * Y.y;
       ex += X.x * X.x + X.y * X.y;
@@ -128,65 +152,78 @@ __global__ __launch_bounds__(64) void k_cmpe(CmpeArgs A) {
     A.map_cmpe[slot0 + tid] = n > 0 ? s / (float)n : 0.f;
   }
 
+  // phase 3: dL/dB(i0, j0) = sum over the subapertures (i, j), i in {i0-1, i0},
+  // j in {j0-1, j0}, of dL/dS(i, j), where S(i, j) is X of pair (i, j-1) and Y of
+  // pair (i-1, j)
   if (A.write_g) {
-    for (int idx = tid; idx < nbb * SUB; idx += SUB) {
-      const int b = idx / SUB, l = idx - b * SUB;
+    for (int b = wv; b < nbb; b += CMPE_WAVES) {
       const int i0 = bLO + b / nbA, j0 = bLO + b % nbA;
       float2 G = make_float2(0.f, 0.f);
-      if (l < pps * M && npr > 0) {
-        const int q = l / M;
+      if (lane < pps * M && npr > 0) {
+        const int q = lane / M;
         const float2* gq = gC + q * np2;
         for (int di = -1; di <= 0; ++di)
           for (int dj = -1; dj <= 0; ++dj) {
             const int i = i0 + di, j = j0 + dj;
             if (i < 0 || j < 0 || i > g.nsub - 1 || j > g.nsub - 1) continue;
-            // B_{i,j} is X of pair (i, j-1): G += gC * Y, Y = B_{i+1, j-1}
             if (i >= pLo && i <= pHi && j - 1 >= pLo && j - 1 <= pHi) {
               const float2 c = gq[(i - pLo) * npr + (j - 1 - pLo)];
-              const float2 y = sub(i + 1, j - 1, l);
+              const float2 y = Ss[(size_t)((i + 1 - pLo) * nS + (j - 1 - pLo)) * SUB + lane];
               G.x += c.x * y.x - c.y * y.y;
               G.y += c.x * y.y + c.y * y.x;
             }
-            // B_{i,j} is Y of pair (i-1, j): G += conj(gC) * X, X = B_{i-1, j+1}
             if (i - 1 >= pLo && i - 1 <= pHi && j >= pLo && j <= pHi) {
               const float2 c = gq[(i - 1 - pLo) * npr + (j - pLo)];
-              const float2 x = sub(i - 1, j + 1, l);
+              const float2 x = Ss[(size_t)((i - 1 - pLo) * nS + (j + 1 - pLo)) * SUB + lane];
               G.x += c.x * x.x + c.y * x.y;
               G.y += c.x * x.y - c.y * x.x;
             }
           }
       }
-      A.gout[((long long)i0 * g.nblk + j0) * P + p0 + l] = G;
+      A.gout[((long long)i0 * g.nblk + j0) * P + p0 + lane] = G;
     }
   }
 
-  // full image, speckle brightness and coherence factor at this thread's point
-  float bx = 0.f, by = 0.f, e2 = 0.f;
-  for (int b = 0; b < nbb; ++b) {
-    const float2 v = Bs[b * SUB + tid];
-    bx += v.x;
-    by += v.y;
-    e2 += v.x * v.x + v.y * v.y;
-  }
-  if (A.img) A.img[p0 + tid] = make_float2(bx, by);
-  const bool centre = tid < pps * M && (tid % M) == M / 2;
+  // full image, speckle brightness and coherence factor at each point
   double sbp = 0.0;
-  if (centre) {
-    const float b2 = bx * bx + by * by;
-    sbp = (double)b2;
-    if (A.map_cf)
-      A.map_cf[slot0 + tid / M] = e2 > 0.f ? b2 / ((float)g.nblk * (float)g.nblk * e2) : 0.f;
-    A.gsb[p0 + tid] = make_float2(A.sb_scale * bx, A.sb_scale * by);
-  } else {
-    A.gsb[p0 + tid] = make_float2(0.f, 0.f);
+  if (wv == 0) {
+    float bx = 0.f, by = 0.f, e2 = 0.f;
+    for (int k = 0; k < CMPE_WAVES; ++k) {
+      bx += pimg[k][0][lane];
+      by += pimg[k][1][lane];
+      e2 += pimg[k][2][lane];
+    }
+    if (A.img) A.img[p0 + lane] = make_float2(bx, by);
+    const bool centre = lane < pps * M && (lane % M) == M / 2;
+    if (centre) {
+      const float b2 = bx * bx + by * by;
+      sbp = (double)b2;
+      if (A.map_cf)
+        A.map_cf[slot0 + lane / M] = e2 > 0.f ? b2 / ((float)g.nblk * (float)g.nblk * e2) : 0.f;
+      A.gsb[p0 + lane] = make_float2(A.sb_scale * bx, A.sb_scale * by);
+    } else {
+      A.gsb[p0 + lane] = make_float2(0.f, 0.f);
+    }
   }
   e_acc = wave_sum(e_acc);
   nv = wave_sum(nv);
   sbp = wave_sum(sbp);
+  if (lane == 0) {
+    red[wv][0] = e_acc;
+    red[wv][1] = nv;
+    red[wv][2] = sbp;
+  }
+  __syncthreads();
   if (tid == 0) {
-    A.part[4 * st + 0] = e_acc;
-    A.part[4 * st + 1] = nv;
-    A.part[4 * st + 2] = sbp;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int k = 0; k < CMPE_WAVES; ++k) {
+      a += red[k][0];
+      b += red[k][1];
+      c += red[k][2];
+    }
+    A.part[4 * st + 0] = a;
+    A.part[4 * st + 1] = b;
+    A.part[4 * st + 2] = c;
     A.part[4 * st + 3] = 0.0;
   }
 }
@@ -245,6 +282,19 @@ __global__ __launch_bounds__(256) void k_export_img(Geo g, const float2* __restr
 
 }  // namespace
 
+int cmpe_span_limit(int pps) {
+  // dynamic LDS of k_cmpe for a tile spanning n blocks: (n + 1)^2 subaperture
+  // images of SUB points plus pps * n^2 pair entries; the static arrays take the rest
+  const size_t budget = 160 * 1024 - sizeof(float) * CMPE_WAVES * 3 * SUB -
+                        sizeof(double) * CMPE_WAVES * 3 - 256;
+  for (int n = MAX_NBA; n >= 1; --n) {
+    const size_t need = sizeof(float2) * (size_t)(n + 1) * (n + 1) * SUB +
+                        (sizeof(float2) + sizeof(float)) * (size_t)pps * n * n;
+    if (need <= budget) return n;
+  }
+  return 0;
+}
+
 hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g, float rho,
                        float sb_scale, float* map_cmpe, float* map_cf, float2* img) {
   CmpeArgs A{};
@@ -261,10 +311,12 @@ hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g,
   A.sb_scale = sb_scale;
   A.write_g = write_g;
   const int nba = c->nba_max;
-  const int npr = nba;  // upper bound of pair rows
-  const size_t lds = sizeof(float2) * (size_t)nba * nba * SUB +
+  const int npr = nba;      // upper bound of pair rows (and columns)
+  const int nS = nba + 1;   // upper bound of subaperture rows
+  const size_t lds = sizeof(float2) * (size_t)nS * nS * SUB +
                      (sizeof(float2) + sizeof(float)) * (size_t)c->pps * npr * npr;
-  hipLaunchKernelGGL(k_cmpe, dim3((unsigned)(c->P_int / SUB)), dim3(SUB), lds, c->stream, A);
+  hipLaunchKernelGGL(k_cmpe, dim3((unsigned)(c->P_int / SUB)), dim3(CMPE_WAVES * SUB), lds,
+                     c->stream, A);
   return hipGetLastError();
 }
 

@@ -17,6 +17,8 @@ struct Rx {
   float2 e;
 };
 
+// Receive-role table entry; elements outside the tile's range act as masked
+// entries (sample 0, zero phasor), exactly like the masked entries of the table.
 __device__ inline Rx load_rx(const TabEntry* __restrict__ tab, long long P, long long p, int r,
                              int LO, int HI) {
   Rx x;
@@ -26,14 +28,15 @@ __device__ inline Rx load_rx(const TabEntry* __restrict__ tab, long long P, long
     x.uf = te.uf;
     x.e = make_float2(te.er, te.ei);
   } else {
-    x.ui = SENTINEL;
+    x.ui = 0;
     x.uf = 0.f;
     x.e = make_float2(0.f, 0.f);
   }
   return x;
 }
 
-// Sample index of channel (t, r): returns false when u lies outside [0, ns-1].
+// Sample index of channel (t, r) with its record check: returns false when u lies
+// outside [0, ns-1] (u = ns-1 exactly reads the last sample).
 __device__ inline bool sample_pos(int ui_t, float uf_t, int ui_r, float uf_r, int ns, int& k,
                                   float& f) {
   int kk = ui_t + ui_r;
@@ -49,9 +52,99 @@ __device__ inline bool sample_pos(int ui_t, float uf_t, int ui_r, float uf_r, in
   return (unsigned)kk <= (unsigned)(ns - 2);
 }
 
-// The S gathers of one transmit element are issued together: a sample outside
-// the record reads the (always valid) first two samples of its channel and is
-// then zeroed, so no load sits behind a divergent branch.
+__device__ inline int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// The S gathers of one transmit element t for this lane's point.  With CHECK
+// the record bounds are tested per sample (a sample outside the record reads
+// the first two samples of its channel and is zeroed); without, the caller has
+// shown for the whole wavefront that every sample lies strictly inside the
+// record.  Masked entries carry a zero phasor and contribute nothing either way.
+template <int S, bool CHECK>
+__device__ inline void gather(const float2* __restrict__ base, int ns, const TabEntry& et,
+                              const Rx (&rx)[S], float2 (&a0)[S], float2 (&a1)[S], float (&fr)[S],
+                              bool (&ok)[S]) {
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    int kk;
+    if (CHECK) {
+      ok[k] = sample_pos(et.ui, et.uf, rx[k].ui, rx[k].uf, ns, kk, fr[k]);
+      if (!ok[k]) kk = 0;
+    } else {
+      const float fsum = et.uf + rx[k].uf;
+      const int carry = fsum >= 1.f ? 1 : 0;
+      kk = et.ui + rx[k].ui + carry;
+      fr[k] = fsum - (float)carry;
+      ok[k] = true;
+    }
+    const float2* q = base + (unsigned)(k * ns + kk);
+    a0[k] = q[0];
+    a1[k] = q[1];
+  }
+}
+
+// Wavefront-uniform choice of the unchecked path for transmit element t: every
+// lane's samples u = u_t + u_r (r in the block) satisfy 0 <= u < ns - 1.
+__device__ inline bool interior(const TabEntry& et, int rmin, int rmax, int ns) {
+  const bool in = et.ui + rmin >= 0 && et.ui + rmax + 1 <= ns - 2;
+  return __ballot(!in) == 0ull;
+}
+
+template <int S>
+__device__ inline void das_fwd_t(const float2* __restrict__ base, int ns, const TabEntry& et,
+                                 const Rx (&rx)[S], bool check, float2& acc) {
+  float2 a0[S], a1[S];
+  float fr[S];
+  bool ok[S];
+  if (check) gather<S, true>(base, ns, et, rx, a0, a1, fr, ok);
+  else gather<S, false>(base, ns, et, rx, a0, a1, fr, ok);
+  float ax = 0.f, ay = 0.f;
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const float f = fr[k];
+    float vx = fmaf(f, a1[k].x - a0[k].x, a0[k].x);
+    float vy = fmaf(f, a1[k].y - a0[k].y, a0[k].y);
+    if (check) {
+      vx = ok[k] ? vx : 0.f;
+      vy = ok[k] ? vy : 0.f;
+    }
+    ax = fmaf(vx, rx[k].e.x, fmaf(-vy, rx[k].e.y, ax));
+    ay = fmaf(vx, rx[k].e.y, fmaf(vy, rx[k].e.x, ay));
+  }
+  acc.x = fmaf(ax, et.er, fmaf(-ay, et.ei, acc.x));
+  acc.y = fmaf(ax, et.ei, fmaf(ay, et.er, acc.y));
+}
+
+// Active transmit range of this wavefront's points within the tile range, and
+// whether any of them has an active element in receive block jb.
+struct WaveRange {
+  int lo, hi;
+  bool rx_active;
+};
+__device__ inline WaveRange wave_range(const int2* __restrict__ prange, long long p, int4 tr, int jb,
+                                       int S) {
+  const int2 pr = prange[p];
+  const bool act = pr.x <= pr.y;
+  WaveRange w;
+  w.lo = max(wave_min(act ? pr.x : 1 << 30), tr.x);
+  w.hi = min(wave_max(act ? pr.y : -1), tr.y);
+  const bool hit = act && pr.x <= jb * S + S - 1 && pr.y >= jb * S;
+  w.rx_active = __ballot(hit) != 0ull;
+  return w;
+}
+
+// One workgroup per (tile, receive block jb): the block images B^blk[ib][jb] of
+// the tile's points for every transmit block ib of the tile.  A wavefront skips
+// the transmit elements outside its points' active ranges (their samples are all
+// masked) and still writes its zero images.
 template <int S>
 __global__ __launch_bounds__(256) void k_das_fwd(DasArgs A) {
   const Geo& g = A.g;
@@ -64,42 +157,54 @@ __global__ __launch_bounds__(256) void k_das_fwd(DasArgs A) {
   const int N = g.n_elem, ns = g.ns;
 
   Rx rx[S];
+  int rmin = 0, rmax = 0;
 #pragma unroll
-  for (int k = 0; k < S; ++k) rx[k] = load_rx(A.tab, P, p, jb * S + k, tr.x, tr.y);
+  for (int k = 0; k < S; ++k) {
+    rx[k] = load_rx(A.tab, P, p, jb * S + k, tr.x, tr.y);
+    rmin = min(rmin, rx[k].ui);
+    rmax = max(rmax, rx[k].ui);
+  }
+  const WaveRange wr = wave_range(A.prange, p, tr, jb, S);
+  const int tlo = wr.rx_active ? wr.lo : tr.y + 1, thi = wr.rx_active ? wr.hi : tr.x - 1;
 
-  float2 acc = make_float2(0.f, 0.f);
-  TabEntry et = A.tab[(long long)tr.x * P + p];
-  for (int t = tr.x; t <= tr.y; ++t) {
-    const TabEntry en = A.tab[(long long)min(t + 1, tr.y) * P + p];
-    const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
-    float2 a0[S], a1[S];
-    float fr[S];
-    bool ok[S];
+  for (int ib = tr.z; ib <= tr.w; ++ib) {
+    float2 acc = make_float2(0.f, 0.f);
+    const int t0 = max(ib * S, tlo), t1 = min(ib * S + S - 1, thi);
+    if (t0 <= t1) {
+      TabEntry et = A.tab[(long long)t0 * P + p];
+      for (int t = t0; t <= t1; ++t) {
+        const TabEntry en = A.tab[(long long)min(t + 1, t1) * P + p];
+        const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
+        das_fwd_t<S>(base, ns, et, rx, !interior(et, rmin, rmax, ns), acc);
+        et = en;
+      }
+    }
+    A.bblk[((long long)ib * g.nblk + jb) * P + p] = acc;
+  }
+}
+
+template <int S>
+__device__ inline void das_adj_t(const float2* __restrict__ base, int ns, const TabEntry& et,
+                                 const Rx (&rx)[S], bool check, float qx, float qy, float fsf,
+                                 float om, float (&grx)[S], float& gtx) {
+  float2 a0[S], a1[S];
+  float fr[S];
+  bool ok[S];
+  if (check) gather<S, true>(base, ns, et, rx, a0, a1, fr, ok);
+  else gather<S, false>(base, ns, et, rx, a0, a1, fr, ok);
 #pragma unroll
-    for (int k = 0; k < S; ++k) {
-      int kk;
-      ok[k] = sample_pos(et.ui, et.uf, rx[k].ui, rx[k].uf, ns, kk, fr[k]);
-      const float2* q = base + (unsigned)(k * ns + (ok[k] ? kk : 0));
-      a0[k] = q[0];
-      a1[k] = q[1];
-    }
-    float ax = 0.f, ay = 0.f;
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-      const float f = fr[k];
-      const float vx = ok[k] ? fmaf(f, a1[k].x - a0[k].x, a0[k].x) : 0.f;
-      const float vy = ok[k] ? fmaf(f, a1[k].y - a0[k].y, a0[k].y) : 0.f;
-      ax = fmaf(vx, rx[k].e.x, fmaf(-vy, rx[k].e.y, ax));
-      ay = fmaf(vx, rx[k].e.y, fmaf(vy, rx[k].e.x, ay));
-    }
-    acc.x = fmaf(ax, et.er, fmaf(-ay, et.ei, acc.x));
-    acc.y = fmaf(ax, et.ei, fmaf(ay, et.er, acc.y));
-    if (((t + 1) % S) == 0 || t == tr.y) {
-      const int ib = t / S;
-      A.bblk[((long long)ib * g.nblk + jb) * P + p] = acc;
-      acc = make_float2(0.f, 0.f);
-    }
-    et = en;
+  for (int k = 0; k < S; ++k) {
+    const float f = fr[k];
+    const float dx = a1[k].x - a0[k].x, dy = a1[k].y - a0[k].y;
+    const float vx = fmaf(f, dx, a0[k].x), vy = fmaf(f, dy, a0[k].y);
+    const float wx = fmaf(fsf, dx, -om * vy);
+    const float wy = fmaf(fsf, dy, om * vx);
+    const float zx = wx * rx[k].e.x - wy * rx[k].e.y;
+    const float zy = wx * rx[k].e.y + wy * rx[k].e.x;
+    float D = qx * zx - qy * zy;
+    if (check) D = ok[k] ? D : 0.f;
+    gtx += D;
+    grx[k] += D;
   }
 }
 
@@ -122,52 +227,34 @@ __global__ __launch_bounds__(256) void k_das_adj(DasArgs A) {
   const float om = (float)(2.0 * 3.14159265358979323846 * g.fd);
 
   Rx rx[S];
+  int rmin = 0, rmax = 0;
 #pragma unroll
-  for (int k = 0; k < S; ++k) rx[k] = load_rx(A.tab, P, p, jb * S + k, tr.x, tr.y);
+  for (int k = 0; k < S; ++k) {
+    rx[k] = load_rx(A.tab, P, p, jb * S + k, tr.x, tr.y);
+    rmin = min(rmin, rx[k].ui);
+    rmax = max(rmax, rx[k].ui);
+  }
   float grx[S];
 #pragma unroll
   for (int k = 0; k < S; ++k) grx[k] = 0.f;
-  float2 G = make_float2(0.f, 0.f);
-  int gib = -1;
-  TabEntry et = A.tab[(long long)tr.x * P + p];
-  for (int t = tr.x; t <= tr.y; ++t) {
-    const int ib = t / S;
-    if (ib != gib) {
-      G = A.gblk[((long long)ib * g.nblk + jb) * P + p];
-      gib = ib;
+  const WaveRange wr = wave_range(A.prange, p, tr, jb, S);
+  if (wr.rx_active && wr.lo <= wr.hi) {
+    for (int ib = max(tr.z, wr.lo / S); ib <= min(tr.w, wr.hi / S); ++ib) {
+      const int t0 = max(ib * S, wr.lo), t1 = min(ib * S + S - 1, wr.hi);
+      const float2 G = A.gblk[((long long)ib * g.nblk + jb) * P + p];
+      TabEntry et = A.tab[(long long)t0 * P + p];
+      for (int t = t0; t <= t1; ++t) {
+        const TabEntry en = A.tab[(long long)min(t + 1, t1) * P + p];
+        // Q = conj(G) * E_t
+        const float qx = G.x * et.er + G.y * et.ei;
+        const float qy = G.x * et.ei - G.y * et.er;
+        const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
+        float gtx = 0.f;
+        das_adj_t<S>(base, ns, et, rx, !interior(et, rmin, rmax, ns), qx, qy, fsf, om, grx, gtx);
+        if (gtx != 0.f) atomicAdd(A.gT2 + (long long)t * P + p, gtx);
+        et = en;
+      }
     }
-    const TabEntry en = A.tab[(long long)min(t + 1, tr.y) * P + p];
-    const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
-    float2 a0[S], a1[S];
-    float fr[S];
-    bool ok[S];
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-      int kk;
-      ok[k] = sample_pos(et.ui, et.uf, rx[k].ui, rx[k].uf, ns, kk, fr[k]);
-      const float2* q = base + (unsigned)(k * ns + (ok[k] ? kk : 0));
-      a0[k] = q[0];
-      a1[k] = q[1];
-    }
-    // Q = conj(G) * E_t
-    const float qx = G.x * et.er + G.y * et.ei;
-    const float qy = G.x * et.ei - G.y * et.er;
-    float gtx = 0.f;
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-      const float f = fr[k];
-      const float dx = a1[k].x - a0[k].x, dy = a1[k].y - a0[k].y;
-      const float vx = fmaf(f, dx, a0[k].x), vy = fmaf(f, dy, a0[k].y);
-      const float wx = fmaf(fsf, dx, -om * vy);
-      const float wy = fmaf(fsf, dy, om * vx);
-      const float zx = wx * rx[k].e.x - wy * rx[k].e.y;
-      const float zy = wx * rx[k].e.y + wy * rx[k].e.x;
-      const float D = ok[k] ? qx * zx - qy * zy : 0.f;
-      gtx += D;
-      grx[k] += D;
-    }
-    if (gtx != 0.f) atomicAdd(A.gT2 + (long long)t * P + p, gtx);
-    et = en;
   }
 #pragma unroll
   for (int k = 0; k < S; ++k) {
@@ -206,6 +293,7 @@ DasArgs das_args(af_ctx* c, const float2* iq) {
   A.tab = c->d_tab.as<TabEntry>();
   A.iq = iq;
   A.tiles = c->d_tiles.as<int4>();
+  A.prange = c->d_prange.as<int2>();
   A.work = c->d_daswork.as<int2>();
   A.order = c->d_order.as<int>();
   return A;

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void k_table(TableArgs A) {
   for (int a = a0; a <= a1; ++a) {
     TabEntry e;
     if (a < pr.x || a > pr.y) {
-      e.ui = SENTINEL;
+      e.ui = 0;  // masked: zero phasor (and a sample index inside every record)
       e.uf = 0.f;
       e.er = 0.f;
       e.ei = 0.f;
