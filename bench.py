@@ -144,7 +144,7 @@ def plain_loop_report():
             "cyst_cnr": {"homogeneous_1540": q0["cnr"], "final": q1["cnr"]}}
 
 
-def s_to_target_report(n_heldout: int = 3):
+def s_to_target_report(n_heldout: int = 8):
     """Wall-clock to the plain method's final CMPE, learned warm start vs plain
     initialisation, on held-out media of the network's training distribution and
     on the largest workload; plus the initial-map RMSE of both networks."""
@@ -152,10 +152,17 @@ def s_to_target_report(n_heldout: int = 3):
     from paper_2608_06853_amd import warmstart
     nets = {k: warmstart.load_network(k) for k in ("plain", "true")}
     keep = ("target_cmpe", "plain_seconds", "plain_iters", "learned_seconds", "learned_iters",
-            "learned_reached", "learned_fallback", "speedup", "plain_rmse_mps", "learned_rmse_mps")
+            "learned_reached", "learned_start", "speedup", "plain_rmse_mps", "learned_rmse_mps")
     out = {}
     rows = [warmstart.s_to_target(afsynth.configs.C4, nets["plain"], seed=9000 + k)
             for k in range(n_heldout)]
+    tp = sum(r["plain_seconds"] for r in rows)
+    tl = sum(r["learned_seconds"] for r in rows)
+    out["c4_heldout_summary"] = {
+        "media": n_heldout, "plain_seconds_total": tp, "learned_seconds_total": tl,
+        "speedup_total": tp / tl if tl > 0 else None,
+        "reached": sum(bool(r["learned_reached"]) for r in rows),
+        "starts": {k: sum(r["learned_start"] == k for r in rows) for k in ("map", "speed", "sweep")}}
     out["c4_heldout"] = [{k: r[k] for k in keep} for r in rows]
     r = warmstart.s_to_target(afsynth.configs.C5, nets["plain"])
     out["c5_largest"] = {k: r[k] for k in keep}

@@ -547,8 +547,10 @@ af_status run_tables(af_ctx* c, const af_loss_params* lp) {
 }
 
 // forward: tables, DAS, CMPE (+G), terms; G goes to `gout` (or in place into the block images)
+// write_g: form dL/dB^blk; scale_now: apply its final scale (1/n_valid and the
+// speckle term) here, for a caller that receives it, instead of in the adjoint.
 af_status run_forward(af_ctx* c, const af_complex* iq, const af_loss_params* lp, float* terms,
-                      float2* gout, bool write_g) {
+                      float2* gout, bool write_g, bool scale_now) {
   af_status st = run_tables(c, lp);
   if (st != AF_OK) return st;
   const float2* iqf = reinterpret_cast<const float2*>(iq);
@@ -561,13 +563,14 @@ af_status run_forward(af_ctx* c, const af_complex* iq, const af_loss_params* lp,
                             c->d_maps.as<float>() + c->n_tiles * c->ppt, nullptr),
             "cmpe");
   AF_KERNEL(AF_K_FINALIZE, af::launch_finalize(c, lp, terms), "finalize");
-  if (write_g) AF_KERNEL(AF_K_GSCALE, af::launch_gscale(c, g), "gscale");
+  if (write_g && scale_now) AF_KERNEL(AF_K_GSCALE, af::launch_gscale(c, g), "gscale");
   c->rho_last = lp->rho_thresh;
   return AF_OK;
 }
 
-af_status run_backward(af_ctx* c, const af_complex* iq, const float2* gblk, float* grad) {
-  AF_KERNEL(AF_K_DAS_ADJ, af::launch_das_adj(c, reinterpret_cast<const float2*>(iq), gblk),
+af_status run_backward(af_ctx* c, const af_complex* iq, const float2* gblk, bool scaled,
+                       float* grad) {
+  AF_KERNEL(AF_K_DAS_ADJ, af::launch_das_adj(c, reinterpret_cast<const float2*>(iq), gblk, scaled),
             "das_adj");
   AF_KERNEL(AF_K_PATH_ADJ, af::launch_path_adj(c), "path_adj");
   AF_KERNEL(AF_K_FOLD, af::launch_grad_fold(c, grad), "grad_fold");
@@ -608,10 +611,10 @@ af_status af_loss_and_grad(af_ctx* c, const af_complex* iq, const af_loss_params
   if (st != AF_OK) return st;
   if ((st = check_lp(c, lp)) != AF_OK) return st;
   if (!terms) return fail(c, AF_ERR_ARG, "af_loss_and_grad: null terms");
-  if ((st = run_forward(c, iq, lp, terms, nullptr, grad != nullptr)) != AF_OK) return st;
+  if ((st = run_forward(c, iq, lp, terms, nullptr, grad != nullptr, false)) != AF_OK) return st;
   if (!grad) return AF_OK;
   // the table of this call is still current: the adjoint uses it directly
-  return run_backward(c, iq, c->d_bblk.as<float2>(), grad);
+  return run_backward(c, iq, c->d_bblk.as<float2>(), false, grad);
 }
 
 af_status af_forward(af_ctx* c, const af_complex* iq, const af_loss_params* lp, float* terms,
@@ -620,7 +623,7 @@ af_status af_forward(af_ctx* c, const af_complex* iq, const af_loss_params* lp, 
   if (st != AF_OK) return st;
   if ((st = check_lp(c, lp)) != AF_OK) return st;
   if (!terms || !gblk) return fail(c, AF_ERR_ARG, "af_forward: null output");
-  return run_forward(c, iq, lp, terms, reinterpret_cast<float2*>(gblk), true);
+  return run_forward(c, iq, lp, terms, reinterpret_cast<float2*>(gblk), true, true);
 }
 
 af_status af_backward(af_ctx* c, const af_complex* iq, const af_loss_params* lp,
@@ -630,7 +633,7 @@ af_status af_backward(af_ctx* c, const af_complex* iq, const af_loss_params* lp,
   if ((st = check_lp(c, lp)) != AF_OK) return st;
   if (!gblk || !grad) return fail(c, AF_ERR_ARG, "af_backward: null buffer");
   if ((st = run_tables(c, lp)) != AF_OK) return st;  // recompute: no table is stored between calls
-  return run_backward(c, iq, reinterpret_cast<const float2*>(gblk), grad);
+  return run_backward(c, iq, reinterpret_cast<const float2*>(gblk), true, grad);
 }
 
 af_status af_autofocus_step(af_ctx* c, const af_complex* iq, const af_loss_params* lp,
@@ -645,9 +648,10 @@ af_status af_autofocus_step(af_ctx* c, const af_complex* iq, const af_loss_param
   AF_HIP(hipMemcpyAsync(c->d_s.p, s, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream), "copy s");
   // forward, then a backward that rebuilds the travel-time table (no table is
   // kept from the forward pass)
-  if ((st = run_forward(c, iq, lp, terms, nullptr, true)) != AF_OK) return st;
+  if ((st = run_forward(c, iq, lp, terms, nullptr, true, false)) != AF_OK) return st;
   if ((st = run_tables(c, lp)) != AF_OK) return st;
-  if ((st = run_backward(c, iq, c->d_bblk.as<float2>(), c->d_grad.as<float>())) != AF_OK) return st;
+  if ((st = run_backward(c, iq, c->d_bblk.as<float2>(), false, c->d_grad.as<float>())) != AF_OK)
+    return st;
   AF_KERNEL(AF_K_ADAM, af::launch_adam(c, ap, step, s, m, v, c->d_grad.as<float>()), "adam");
   return AF_OK;
 }

@@ -70,7 +70,9 @@ struct DasArgs {
   const int2* work;       // (tile, rx block) for the forward
   const int* order;       // tile order for the adjoint
   float2* bblk;           // [nb][nb][P]  (forward output)
-  const float2* gblk;     // [nb][nb][P]  (adjoint input, final scale applied)
+  const float2* gblk;     // [nb][nb][P]  (adjoint input)
+  const double* gscal;    // null: gblk is final; else dL/dB = gblk * gscal[5] + gsb[p]
+  const float2* gsb;      // [P] speckle-brightness gradient per point
   float* gT;              // [n_elem][P]  dL/dT, receive role (adjoint output)
   float* gT2;             // [n_elem][P]  dL/dT, transmit role (atomic adds)
 };
@@ -179,7 +181,8 @@ hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g,
                        float sb_scale, float* map_cmpe, float* map_cf, float2* img);
 hipError_t launch_finalize(af_ctx* c, const af_loss_params* lp, float* terms);
 hipError_t launch_gscale(af_ctx* c, float2* gblk);
-hipError_t launch_das_adj(af_ctx* c, const float2* iq, const float2* gblk);
+// scaled = false: gblk still lacks its final scale, which the adjoint applies
+hipError_t launch_das_adj(af_ctx* c, const float2* iq, const float2* gblk, bool scaled);
 hipError_t launch_path_adj(af_ctx* c);
 hipError_t launch_grad_fold(af_ctx* c, float* grad);
 hipError_t launch_adam(af_ctx* c, const af_adam_params* ap, int step, float* s, float* m,

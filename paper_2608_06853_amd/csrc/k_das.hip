@@ -213,8 +213,10 @@ __device__ inline void das_adj_t(const float2* __restrict__ base, int ns, const 
 // receive block) as in the forward: the receive-role sums of its S elements are
 // complete and written directly; the transmit-role sums of every t are partial
 // (one per receive block) and are added with global atomics.
+// The register budget is capped at 128 so that 4 wavefronts fit per SIMD; without
+// the cap the compiler lands at 131 registers and loses one wavefront per SIMD.
 template <int S>
-__global__ __launch_bounds__(256) void k_das_adj(DasArgs A) {
+__global__ __launch_bounds__(256, 4) void k_das_adj(DasArgs A) {
   const Geo& g = A.g;
   const int2 w = A.work[blockIdx.x];
   const int tile = w.x, jb = w.y;
@@ -238,10 +240,16 @@ __global__ __launch_bounds__(256) void k_das_adj(DasArgs A) {
 #pragma unroll
   for (int k = 0; k < S; ++k) grx[k] = 0.f;
   const WaveRange wr = wave_range(A.prange, p, tr, jb, S);
+  const float gi = A.gscal ? (float)A.gscal[5] : 0.f;
   if (wr.rx_active && wr.lo <= wr.hi) {
     for (int ib = max(tr.z, wr.lo / S); ib <= min(tr.w, wr.hi / S); ++ib) {
       const int t0 = max(ib * S, wr.lo), t1 = min(ib * S + S - 1, wr.hi);
-      const float2 G = A.gblk[((long long)ib * g.nblk + jb) * P + p];
+      float2 G = A.gblk[((long long)ib * g.nblk + jb) * P + p];
+      if (A.gscal) {  // final scale of the block gradient, as k_gscale forms it
+        const float2 sb = A.gsb[p];
+        G.x = fmaf(G.x, gi, sb.x);
+        G.y = fmaf(G.y, gi, sb.y);
+      }
       TabEntry et = A.tab[(long long)t0 * P + p];
       for (int t = t0; t <= t1; ++t) {
         const TabEntry en = A.tab[(long long)min(t + 1, t1) * P + p];
@@ -315,10 +323,12 @@ hipError_t launch_das_fwd(af_ctx* c, const float2* iq, float2* bblk) {
   }
 }
 
-hipError_t launch_das_adj(af_ctx* c, const float2* iq, const float2* gblk) {
+hipError_t launch_das_adj(af_ctx* c, const float2* iq, const float2* gblk, bool scaled) {
   if (c->n_das_work == 0) return hipSuccess;
   DasArgs A = das_args(c, iq);
   A.gblk = gblk;
+  A.gscal = scaled ? nullptr : c->d_scal.as<double>();
+  A.gsb = c->d_gsb.as<float2>();
   A.gT = c->d_gT.as<float>();
   A.gT2 = c->d_gT.as<float>() + (size_t)c->N * c->P_int;
   switch (c->S) {

@@ -151,15 +151,35 @@ __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
     part[n] = (sg[n] + sg[nodes + n]) + (sg[2 * nodes + n] + sg[3 * nodes + n]);
 }
 
-// gpad[n] = sum over workgroups of their partial grids (fixed order: deterministic).
+// gpad[n] = sum over workgroups of their partial grids, in a fixed order
+// (deterministic), in two passes: k_path_chunk sums each chunk of PCHUNK
+// consecutive partial grids into the first grid of the chunk (every element is
+// read and then overwritten by the same thread), k_path_reduce sums the chunks.
+constexpr int PCHUNK = 32;
+
+__global__ __launch_bounds__(256) void k_path_chunk(float* __restrict__ gpart, int n_wg, int nodes) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  const int w0 = blockIdx.y * PCHUNK;
+  if (n >= nodes) return;
+  const int w1 = min(w0 + PCHUNK, n_wg);
+  float v[PCHUNK];
+#pragma unroll
+  for (int k = 0; k < PCHUNK; ++k) v[k] = (w0 + k < w1) ? gpart[(long long)(w0 + k) * nodes + n] : 0.f;
+  float s = 0.f;
+#pragma unroll
+  for (int k = 0; k < PCHUNK; ++k) s += v[k];
+  gpart[(long long)w0 * nodes + n] = s;
+}
+
 __global__ __launch_bounds__(256) void k_path_reduce(const float* __restrict__ gpart, int n_wg,
                                                      int nodes, float* __restrict__ gpad) {
   const int n = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int lane_grp = threadIdx.x >> 6;  // 4 groups stride over the workgroups
+  const int lane_grp = threadIdx.x >> 6;  // 4 groups stride over the chunks
+  const int n_chunk = (n_wg + PCHUNK - 1) / PCHUNK;
   __shared__ float red[4][64];
   float s = 0.f;
   if (n < nodes)
-    for (int w = lane_grp; w < n_wg; w += 4) s += gpart[(long long)w * nodes + n];
+    for (int c = lane_grp; c < n_chunk; c += 4) s += gpart[(long long)c * PCHUNK * nodes + n];
   red[lane_grp][threadIdx.x & 63] = s;
   __syncthreads();
   if (lane_grp == 0 && n < nodes)
@@ -195,6 +215,11 @@ hipError_t launch_path_adj(af_ctx* c) {
   const size_t lds = sizeof(float) * (size_t)nodes * 4;
   hipLaunchKernelGGL(k_path_adj, dim3(c->n_order), dim3(256), lds, c->stream, A);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int n_chunk = (c->n_order + PCHUNK - 1) / PCHUNK;
+  hipLaunchKernelGGL(k_path_chunk, dim3((nodes + 255) / 256, n_chunk), dim3(256), 0, c->stream,
+                     c->d_gpart.as<float>(), c->n_order, nodes);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_path_reduce, dim3((nodes + 63) / 64), dim3(256), 0, c->stream,
                      c->d_gpart.as<float>(), c->n_order, nodes, c->d_gpad.as<float>());

@@ -6,7 +6,10 @@ each with its channel data simulated on the GPU, the feature maps of a
 homogeneous 1540 m/s beamform and two labels on the network's polar output grid:
 the true slowness, and the plain method's converged solution (sweep + Adam).
 One network is trained per label; the warm start uses the one trained on the
-plain solution, because the plain optimiser judges the initial map by its loss.
+plain solution, because the plain optimiser judges the initial map by its loss:
+the predicted map if it does not raise the loss over the homogeneous 1540 m/s
+guess, else the uniform map at its mean speed if that passes the same test,
+else the plain adaptive-grid sweep.
 
 Comparison ("s-to-target"): from channel data resident on the GPU, the time each
 method needs to reach the CMP phase error that the plain method reaches after its
@@ -85,30 +88,42 @@ def run_plain(bf: af.Beamformer, iq, cfg, n_iter: int, lp=None):
 
 def run_learned(bf: af.Beamformer, iq, cfg, net, fm: cnn.FeatureMaker, target: float,
                 max_iter: int, lp=None):
-    """Warm start + Adam until CMPE <= target.  Returns a dict of timings and results."""
+    """Warm start + Adam until CMPE <= target.  Returns a dict of timings and results.
+
+    The network's map is judged by the plain objective: it is used if its loss is
+    not above that of the homogeneous 1540 m/s guess.  Otherwise the uniform map
+    at the network's mean speed (rounded to the sweep's 10 m/s lattice) on its
+    dynamic grid is tried the same way, and only if that fails too does the plain
+    adaptive-grid sweep run."""
     lp = lp or workloads.loss_params(cfg)
     base = bf.img
+    terms = bf.empty_terms()
+
+    def loss_on(c_grid, s):
+        bf.set_imaging(af.scaled_imaging(base, bf.acq, c_grid, cfg.img.c_ref, cfg.acq.fc))
+        bf.set_slowness(s)
+        bf.ctx.loss_and_grad(iq, lp, terms, None)
+        return float(terms[_lib.TERM_TOTAL].item())
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s0 = cnn.predict_slowness(net, fm, iq, cfg, bf.grid)
     c_mean = float((1.0 / s0).mean().item())
     c_mean = min(max(c_mean, 1.340), 1.740)
-    bf.set_imaging(af.scaled_imaging(base, bf.acq, c_mean, cfg.img.c_ref, cfg.acq.fc))
-    terms = bf.empty_terms()
-    bf.set_slowness(s0)
-    bf.ctx.loss_and_grad(iq, lp, terms, None)
-    l_net = float(terms[_lib.TERM_TOTAL].item())
-    bf.set_imaging(base)
-    bf.set_slowness(torch.full(bf.grid.shape, 1.0 / cfg.img.c_ref, device=bf.device))
-    bf.ctx.loss_and_grad(iq, lp, terms, None)
-    l_hom = float(terms[_lib.TERM_TOTAL].item())
-    fallback = not (l_net <= l_hom)
-    if fallback:
-        _, _, best = af.sweep(bf, iq, lp, cfg.acq.fc)
-        s_init = bf.s
-    else:
-        bf.set_imaging(af.scaled_imaging(base, bf.acq, c_mean, cfg.img.c_ref, cfg.acq.fc))
-        s_init = s0
+    l_hom = loss_on(cfg.img.c_ref, torch.full(bf.grid.shape, 1.0 / cfg.img.c_ref, device=bf.device))
+    l_net = loss_on(c_mean, s0)
+    start, s_init, c_grid = "map", s0, c_mean
+    if not l_net <= l_hom:
+        c_r = round(c_mean * 100.0) / 100.0
+        s_u = torch.full(bf.grid.shape, 1.0 / c_r, device=bf.device)
+        l_u = loss_on(c_r, s_u)
+        if l_u <= l_hom:
+            start, s_init, c_grid = "speed", s_u, c_r
+        else:
+            bf.set_imaging(base)
+            _, _, c_grid = af.sweep(bf, iq, lp, cfg.acq.fc)
+            start, s_init = "sweep", bf.s
+    bf.set_imaging(af.scaled_imaging(base, bf.acq, c_grid, cfg.img.c_ref, cfg.acq.fc))
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
     s, hist = af.plain_autofocus(bf, iq, lp, _lib.adam_params(lr=cfg.method.lr), max_iter,
@@ -117,9 +132,9 @@ def run_learned(bf: af.Beamformer, iq, cfg, net, fm: cnn.FeatureMaker, target: f
     reached = bool(cm and cm[-1] <= target)
     t_total = t_init + (hist.times[-1] if hist.times else 0.0)
     bf.set_imaging(base)
-    return {"fallback": fallback, "loss_net": l_net, "loss_homogeneous": l_hom, "init_s": t_init,
-            "iters": len(cm), "reached": reached, "seconds": t_total, "final_cmpe": cm[-1] if cm else None,
-            "s": s}
+    return {"start": start, "fallback": start == "sweep", "loss_net": l_net,
+            "loss_homogeneous": l_hom, "init_s": t_init, "iters": len(cm), "reached": reached,
+            "seconds": t_total, "final_cmpe": cm[-1] if cm else None, "s": s}
 
 
 def s_to_target(cfg, net, n_iter: int = 200, max_iter: int = 400, seed=None, device: int = 0):
@@ -139,6 +154,7 @@ def s_to_target(cfg, net, n_iter: int = 200, max_iter: int = 400, seed=None, dev
            "plain_sweep_seconds": t_sweep, "plain_best_speed": best, "plain_iters": k + 1,
            "learned_seconds": res["seconds"], "learned_iters": res["iters"],
            "learned_reached": res["reached"], "learned_fallback": res["fallback"],
+           "learned_start": res["start"],
            "learned_init_seconds": res["init_s"],
            "speedup": t_plain / res["seconds"] if res["reached"] else None,
            "plain_rmse_mps": metrics.speed_errors(s_plain.cpu().numpy(), c_true)["rmse_mps"],
