@@ -97,6 +97,7 @@ af_status af_set_lens(af_ctx* ctx, double d_lens, double c_lens, double t_ttp);
 
 /* Slowness grid s ~ 1/c (Section III-A): node (i, j) at (x0 + j dx, z0 + i dz),
  * values [nz][nx] float32 at `s_dev` (device), copied on the context stream.
+ * At most (nx+3)(nz+3) = 9600 padded nodes (e.g. 95 x 95).
  * The grid box must contain every evaluation point and the lens arc over the
  * angles of the elements and points (AF_ERR_ARG otherwise); needs geometry and
  * lens first (AF_ERR_STATE).  Non-finite or non-positive values are reported as

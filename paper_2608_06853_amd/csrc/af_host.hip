@@ -475,8 +475,10 @@ af_status af_set_slowness(af_ctx* c, int nx, int nz, double x0, double z0, doubl
     return fail(c, AF_ERR_STATE, "af_set_slowness: set geometry and lens first");
   if (nx < 2 || nz < 2 || !(dx > 0) || !(dz > 0) || !s_dev)
     return fail(c, AF_ERR_ARG, "af_set_slowness: bad grid");
-  if ((size_t)(nx + 3) * (nz + 3) > 16384)
-    return fail(c, AF_ERR_ARG, "af_set_slowness: grid larger than (nx+3)(nz+3) <= 16384 nodes");
+  // the path adjoint keeps four copies of the padded grid in LDS (160 KB per
+  // workgroup)
+  if ((size_t)(nx + 3) * (nz + 3) > 9600)
+    return fail(c, AF_ERR_ARG, "af_set_slowness: grid larger than (nx+3)(nz+3) <= 9600 nodes");
   const double x1 = x0 + (nx - 1) * dx, z1 = z0 + (nz - 1) * dz, tol = 1e-9;
   auto inside = [&](double x, double z) {
     return x >= x0 - tol && x <= x1 + tol && z >= z0 - tol && z <= z1 + tol;
