@@ -81,7 +81,7 @@ class Config:
         return replace(self, **kw)
 
 
-# configs[0]: tiny plain-method case.
+# Tiny plain-method case (32 elements, 64 x 64 pixels, 8 x 8 grid).
 C1 = Config(
     name="c1_tiny",
     array=ArrayCfg(n_elem=32, radius=40.0, pitch=0.4, d_lens=1.0, c_lens=1.000),
@@ -91,7 +91,7 @@ C1 = Config(
     medium="c1_two_layer", seed=0, n_scat_random=2000,
 )
 
-# configs[1]: clinical-size forward + adjoint (the benchmarked workload).
+# Clinical-size forward + adjoint (128 elements, 256 x 256 pixels): the benchmarked workload.
 C2 = Config(
     name="c2_clinical",
     array=ArrayCfg(n_elem=128, radius=60.0, pitch=0.37, d_lens=1.2, c_lens=1.000),
@@ -102,18 +102,18 @@ C2 = Config(
     medium="liver_wall", seed=2, sim_spacing=1.0,
 )
 
-# configs[2]: full plain autofocus loop on configs[0] media (+ one cyst), CMPE + SB.
+# Full plain autofocus loop on the tiny case's medium plus one cyst, CMPE + SB.
 C3 = C1.with_(
     name="c3_plain_loop",
     method=replace(C1.method, n_iter=200, w_sb=0.1),
     medium="c1_two_layer_cyst",
 )
 
-# configs[3]: learned warm-start training media (configs[0]-type, randomised).
+# Learned warm-start training media: randomised two-layer media on the tiny case's array.
 C4 = C1.with_(name="c4_train", medium="c1_random", seed=1000,
               method=replace(C1.method, n_iter=200))
 
-# configs[4]: largest.
+# Largest: 192 elements, 4096 samples, 512 x 512 pixels, 64 x 64 grid.
 C5 = Config(
     name="c5_largest",
     array=ArrayCfg(n_elem=192, radius=60.0, pitch=0.37, d_lens=1.2, c_lens=1.000),

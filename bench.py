@@ -33,7 +33,8 @@ UNIT = "Gsamples/s"
 PEAK_FP32_TFLOPS = 157.3        # 256 CU x 2.4 GHz x 256 FP32 flop/clk/CU
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic FP32 operations per unit (Measurement).
+# Algorithmic FP32 operations per unit of each kernel (counted from the arithmetic
+# the step needs, not from the compiled code).
 FLOPS_PER_UNIT = {
     "das_fwd": 14.0,     # per active (t, r, point) sample: interpolate (6) + rotate-accumulate (8)
     "das_adj": 22.0,     # per active sample: interpolate + derivative (12) + rotate (6) + Re/acc (4)
@@ -174,7 +175,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build is single-GPU by design "
-              f"(--gpus {args.gpus} requested; see DESIGN.md for how the path shards)",
+              f"(--gpus {args.gpus} requested; the path would shard by points)",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -31,7 +31,7 @@ def gpu_available() -> bool:
         return False
 
 
-# A configs[0]-geometry case small enough for the oracle: 32 elements (8 blocks),
+# A case on the tiny 32-element array small enough for the oracle: 8 blocks,
 # 24 x 20 pixels (480 patches -> 18 tiles, ragged tail), 8 x 8 slowness grid.
 C1_SMALL = afsynth.configs.C1.with_(
     name="c1_small",

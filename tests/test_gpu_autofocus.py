@@ -1,5 +1,5 @@
 """Plain autofocus method on the GPU against the oracle: Adam trajectory on the
-configs[0] workload, dynamic-grid sweep values, and descent of the objective."""
+tiny 32-element workload, dynamic-grid sweep values, and descent of the objective."""
 import numpy as np
 import pytest
 
@@ -17,7 +17,7 @@ def _built():
 
 
 def test_five_adam_steps_tiny_config():
-    """configs[0]: 32 elements, 64x64 pixels, 8x8 grid, 5 Adam steps, FP32 GPU vs FP64 oracle."""
+    """Tiny case: 32 elements, 64x64 pixels, 8x8 grid, 5 Adam steps, FP32 GPU vs FP64 oracle."""
     import torch
     from paper_2608_06853_amd import _lib
     cfg = afsynth.configs.C1

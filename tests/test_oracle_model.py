@@ -53,7 +53,7 @@ def test_gradient_matches_finite_differences(small_problem):
 
 @pytest.mark.parametrize("c_true", [1.500, 1.560])
 def test_sweep_minimum_at_true_speed(c_true):
-    # a configs[0]-sized aperture (32 elements, 8 blocks -> 36 pairs per patch) in a
+    # the tiny case's aperture (32 elements, 8 blocks -> 36 pairs per patch) in a
     # homogeneous medium: the dynamic-grid sweep minimum is within one 10 m/s step
     cfg = afsynth.configs.C1.with_(
         img=afsynth.ImgCfg(n_depth=10, n_angle=8, depth_min=10.0, depth_max=50.0),
