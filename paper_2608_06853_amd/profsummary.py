@@ -32,6 +32,7 @@ FAMILIES = {
     "cmpe": (r"k_cmpe\(", "k_cmpe.hip"),
     "gscale": (r"k_gscale\(", "k_misc.hip"),
     "path_adj": (r"k_path_adj\(", "k_path.hip"),
+    "path_chunk": (r"k_path_chunk\(", "k_path.hip"),
     "path_reduce": (r"k_path_reduce\(", "k_path.hip"),
     "prepare_grid": (r"k_prepare_grid\(", "k_misc.hip"),
     "finalize": (r"k_finalize\(", "k_misc.hip"),
