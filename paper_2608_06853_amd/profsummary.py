@@ -5,6 +5,7 @@ WRITE_SIZE scaled by a plain copy of known size).
     python -m paper_2608_06853_amd.profsummary stats --dir OUT --cmd "..." > FILE
     python -m paper_2608_06853_amd.profsummary traffic --fetch D1 --write D2 \
         --copy-fetch D3 --copy-write D4 --copy-bytes B --cmd "..." > FILE
+    python -m paper_2608_06853_amd.profsummary counters --dir OUT --cmd "..." > FILE
 
 The traffic summary records, per kernel family, the SHA-256 of the sources the
 kernel is compiled from, so a reader can tell whether the counters still describe
@@ -130,6 +131,36 @@ def traffic(args):
               f"{w_k[0]:12.1f} {b:16.0f}")
 
 
+def counters(args):
+    """Per kernel family: mean SQ counters per dispatch, the dispatch duration from
+    the counter run's timestamps, VALU instructions per CU per ns and the share of
+    active lanes in VALU instructions."""
+    rows = _csv(_find(args.dir, "counter_collection.csv"))
+    per, dur = {}, {}
+    for r in rows:
+        fam = family_of(r["Kernel_Name"])
+        if fam is None:
+            continue
+        d = per.setdefault(fam, {}).setdefault(r["Counter_Name"], {})
+        d[r["Dispatch_Id"]] = d.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+        dur.setdefault(fam, {})[r["Dispatch_Id"]] = (float(r["End_Timestamp"]) -
+                                                     float(r["Start_Timestamp"]))
+    print(f"# rocprofv3 --pmc SQ counters per dispatch: {args.title}")
+    print(f"# command: {args.cmd}")
+    print(f"# valu_per_cu_ns = SQ_INSTS_VALU / dispatch duration / {args.cus} CUs; "
+          "lane_util = SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)")
+    names = sorted({c for f in per.values() for c in f})
+    print("# family        duration_us  valu_per_cu_ns  lane_util  " + "  ".join(names))
+    for fam in sorted(per):
+        m = {c: sum(v.values()) / len(v) for c, v in per[fam].items()}
+        t = sum(dur[fam].values()) / len(dur[fam])
+        rate = m.get("SQ_INSTS_VALU", 0.0) / t / args.cus if t > 0 else 0.0
+        util = (m.get("SQ_THREAD_CYCLES_VALU", 0.0) / (64.0 * m["SQ_ACTIVE_INST_VALU"])
+                if m.get("SQ_ACTIVE_INST_VALU") else 0.0)
+        print(f"{fam:14s} {t / 1e3:11.1f} {rate:15.2f} {util:10.3f}  " +
+              "  ".join(f"{m.get(c, 0.0):.4g}" for c in names))
+
+
 def read_traffic(path: str) -> dict:
     """{family: (source hash, bytes per dispatch)} from a traffic summary."""
     out = {}
@@ -156,8 +187,13 @@ def main(argv=None):
     b.add_argument("--copy-bytes", type=float, required=True)
     b.add_argument("--cmd", required=True)
     b.add_argument("--title", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("--dir", required=True)
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--title", default="")
+    c.add_argument("--cus", type=int, default=256)
     args = ap.parse_args(argv)
-    (stats if args.mode == "stats" else traffic)(args)
+    {"stats": stats, "traffic": traffic, "counters": counters}[args.mode](args)
 
 
 if __name__ == "__main__":
