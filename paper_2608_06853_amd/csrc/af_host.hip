@@ -54,11 +54,30 @@ af_status hip_fail(af_ctx* c, hipError_t e, const char* where) {
       return fail(c, AF_ERR_OOM, std::string("af: cannot allocate ") + (what));       \
   } while (0)
 
+// Host worker threads for the per-point loops of the geometry set-up.
+int host_threads(long long work) {
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  return (int)std::max<long long>(1, std::min<long long>(hw, work / 65536));
+}
+
+// Runs fn(t, nthr) on nthr threads (thread 0 is the caller).  Workers keep
+// their running results in locals and write them once (no shared cache lines
+// are updated inside the loops).
+template <class F>
+void parallel(int nthr, F&& fn) {
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nthr; ++t) pool.emplace_back(fn, t, nthr);
+  fn(0, nthr);
+  for (auto& t : pool) t.join();
+}
+
 // Orders idx[0..n) so that consecutive runs of `unit` items (and of `sub` items
 // inside them) are spatially compact: recursive median split along the longer
-// extent of (u, v), with the left part always a whole number of units.
+// extent of (u, v), with the left part always a whole number of units.  The two
+// halves of the top `par_depth` levels are split on separate threads (the
+// result does not depend on it).
 void kd_partition(int* idx, int n, int unit, int sub, const std::vector<double>& u,
-                  const std::vector<double>& v) {
+                  const std::vector<double>& v, int par_depth = 0) {
   if (n <= sub) return;
   const int q = n > unit ? unit : sub;
   const int n_left = q * ((n + 2 * q - 1) / (2 * q));
@@ -74,8 +93,15 @@ void kd_partition(int* idx, int n, int unit, int sub, const std::vector<double>&
   std::nth_element(idx, idx + n_left, idx + n, [&](int a, int b) {
     return key[a] < key[b] || (key[a] == key[b] && a < b);
   });
-  kd_partition(idx, n_left, unit, sub, u, v);
-  kd_partition(idx + n_left, n - n_left, unit, sub, u, v);
+  if (par_depth > 0 && n > 20000) {
+    std::thread left(kd_partition, idx, n_left, unit, sub, std::cref(u), std::cref(v),
+                     par_depth - 1);
+    kd_partition(idx + n_left, n - n_left, unit, sub, u, v, par_depth - 1);
+    left.join();
+  } else {
+    kd_partition(idx, n_left, unit, sub, u, v, 0);
+    kd_partition(idx + n_left, n - n_left, unit, sub, u, v, 0);
+  }
 }
 
 template <class T>
@@ -228,9 +254,10 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
     return std::fabs(xp) <= half_f * zp;
   };
   const bool full_scan = (double)P * N <= 2e7;
-  std::vector<char> bad_flag(64, 0);
+  std::vector<char> bad_flag(64 * 64, 0);  // one cache line per thread
   auto work = [&](int tid, int nthr) {
-    for (long long p = tid; p < P; p += nthr) {
+    const long long p0 = P * tid / nthr, p1 = P * (tid + 1) / nthr;  // contiguous run
+    for (long long p = p0; p < p1; ++p) {
       int lo = N, hi = -1, cnt = 0;
       if (full_scan) {
         for (int a = 0; a < N; ++a)
@@ -239,7 +266,7 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
             hi = std::max(hi, a);
             ++cnt;
           }
-        if (cnt > 0 && cnt != hi - lo + 1) bad_flag[tid] = 1;
+        if (cnt > 0 && cnt != hi - lo + 1) bad_flag[64 * tid] = 1;
       } else {
         const double ang = std::atan2(c->pts_xz[2 * p], c->pts_xz[2 * p + 1]);
         int a0 = (int)(std::upper_bound(c->elem_pol.begin(), c->elem_pol.end(), ang) - c->elem_pol.begin());
@@ -257,14 +284,7 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
       hi_c[p] = cnt > 0 ? hi : 0;
     }
   };
-  {
-    const int nthr = (int)std::min<long long>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())),
-                                             std::max<long long>(1, P / 4096));
-    std::vector<std::thread> th_pool;
-    for (int t = 1; t < nthr; ++t) th_pool.emplace_back(work, t, nthr);
-    work(0, nthr);
-    for (auto& t : th_pool) t.join();
-  }
+  parallel(std::min(host_threads(P * (full_scan ? N : 8)), 64), work);
   for (char b : bad_flag)
     if (b) return fail(c, AF_ERR_ARG, "af_set_geometry: active elements of a point are not contiguous");
 
@@ -287,7 +307,7 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
   }
   std::vector<int> ord(n_pix);
   std::iota(ord.begin(), ord.end(), 0);
-  kd_partition(ord.data(), n_pix, ppt, pps, cu, cv);
+  kd_partition(ord.data(), n_pix, ppt, pps, cu, cv, 4);
   // Pack the pixels, in k-d order, into sub-tiles of pps and tiles of 4 sub-tiles.
   // A tile is closed early (its remaining slots become padding) when the next
   // pixel would widen its span of active blocks beyond what the CMPE kernel
@@ -365,27 +385,46 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
   std::vector<int2> prange(P_int);
   c->tile_lo.assign(n_tiles, N);
   c->tile_hi.assign(n_tiles, -1);
-  c->active_pairs = 0;
-  c->active_samples = 0;
-  for (long long pi = 0; pi < P_int; ++pi) {
-    const int pc = c->i2c[pi];
-    const long long src = pc >= 0 ? pc : c->i2c[(pi / TILE) * TILE];
-    const double x = c->pts_xz[2 * src], z = c->pts_xz[2 * src + 1];
-    const double rho = std::sqrt(x * x + z * z);
-    ptpol[pi] = make_double4(rho, x / rho, z / rho, 0.0);
-    ptxy[pi] = make_float2((float)x, (float)z);
-    int lo = 1, hi = 0;
-    if (pc >= 0) {
-      lo = lo_c[pc];
-      hi = hi_c[pc];
-    }
-    prange[pi] = make_int2(lo, hi);
-    if (lo <= hi) {
-      const int t = (int)(pi / TILE);
-      c->tile_lo[t] = std::min(c->tile_lo[t], lo);
-      c->tile_hi[t] = std::max(c->tile_hi[t], hi);
-      c->active_pairs += hi - lo + 1;
-      c->active_samples += (long long)(hi - lo + 1) * (hi - lo + 1);
+  {
+    // contiguous runs of whole tiles per thread
+    const int nthr = host_threads(P_int);
+    std::vector<long long> pairs(nthr * 8, 0), samples(nthr * 8, 0);  // one cache line apart
+    parallel(nthr, [&](int tid, int nt) {
+      const int t0 = (int)((long long)n_tiles * tid / nt), t1 = (int)((long long)n_tiles * (tid + 1) / nt);
+      long long np = 0, ns = 0;
+      for (int t = t0; t < t1; ++t) {
+        int tlo = N, thi = -1;
+        for (long long pi = (long long)t * TILE; pi < (long long)(t + 1) * TILE; ++pi) {
+          const int pc = c->i2c[pi];
+          const long long src = pc >= 0 ? pc : c->i2c[(long long)t * TILE];
+          const double x = c->pts_xz[2 * src], z = c->pts_xz[2 * src + 1];
+          const double rho = std::sqrt(x * x + z * z);
+          ptpol[pi] = make_double4(rho, x / rho, z / rho, 0.0);
+          ptxy[pi] = make_float2((float)x, (float)z);
+          int lo = 1, hi = 0;
+          if (pc >= 0) {
+            lo = lo_c[pc];
+            hi = hi_c[pc];
+          }
+          prange[pi] = make_int2(lo, hi);
+          if (lo <= hi) {
+            tlo = std::min(tlo, lo);
+            thi = std::max(thi, hi);
+            np += hi - lo + 1;
+            ns += (long long)(hi - lo + 1) * (hi - lo + 1);
+          }
+        }
+        c->tile_lo[t] = tlo;
+        c->tile_hi[t] = thi;
+      }
+      pairs[tid * 8] = np;
+      samples[tid * 8] = ns;
+    });
+    c->active_pairs = 0;
+    c->active_samples = 0;
+    for (int t = 0; t < nthr; ++t) {
+      c->active_pairs += pairs[t * 8];
+      c->active_samples += samples[t * 8];
     }
   }
   std::vector<int4> tiles(n_tiles);
@@ -488,12 +527,30 @@ af_status af_set_slowness(af_ctx* c, int nx, int nz, double x0, double z0, doubl
     amin = std::min(amin, c->elem_pol[a]);
     amax = std::max(amax, c->elem_pol[a]);
   }
-  for (long long p = 0; p < c->P; ++p) {
-    const double x = c->pts_xz[2 * p], z = c->pts_xz[2 * p + 1];
-    if (!inside(x, z)) return fail(c, AF_ERR_ARG, "af_set_slowness: grid does not cover every point");
-    const double ang = std::atan2(x, z);
-    amin = std::min(amin, ang);
-    amax = std::max(amax, ang);
+  {
+    const int nthr = host_threads(c->P);
+    std::vector<double> tmin(nthr * 8, 1e300), tmax(nthr * 8, -1e300);  // one cache line apart
+    std::vector<long long> out(nthr * 8, 0);
+    parallel(nthr, [&](int tid, int nt) {
+      const long long p0 = c->P * tid / nt, p1 = c->P * (tid + 1) / nt;
+      double lo = 1e300, hi = -1e300;
+      long long bad = 0;
+      for (long long p = p0; p < p1; ++p) {
+        const double x = c->pts_xz[2 * p], z = c->pts_xz[2 * p + 1];
+        bad += inside(x, z) ? 0 : 1;
+        const double ang = std::atan2(x, z);
+        lo = std::min(lo, ang);
+        hi = std::max(hi, ang);
+      }
+      tmin[tid * 8] = lo;
+      tmax[tid * 8] = hi;
+      out[tid * 8] = bad;
+    });
+    for (int t = 0; t < nthr; ++t) {
+      if (out[t * 8]) return fail(c, AF_ERR_ARG, "af_set_slowness: grid does not cover every point");
+      amin = std::min(amin, tmin[t * 8]);
+      amax = std::max(amax, tmax[t * 8]);
+    }
   }
   // lens arc over [amin, amax] (both ends and the apex if it is inside)
   for (int a = 0; a < c->N; ++a) {
