@@ -234,18 +234,24 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
   c->P = P;
   c->pts_xz.resize(2 * P);
   const int h = patch / 2;
-  for (int q = 0; q < n_pix; ++q)
-    for (int m = 0; m < M; ++m) {
-      const double ox = (double)(m % patch - h) * spacing, oz = (double)(m / patch - h) * spacing;
-      c->pts_xz[2 * (q * M + m)] = pix_xz[2 * q] + ox;
-      c->pts_xz[2 * (q * M + m) + 1] = pix_xz[2 * q + 1] + oz;
-    }
+  parallel(host_threads(P), [&](int tid, int nt) {
+    const int q0 = (int)((long long)n_pix * tid / nt), q1 = (int)((long long)n_pix * (tid + 1) / nt);
+    for (int q = q0; q < q1; ++q)
+      for (int m = 0; m < M; ++m) {
+        const double ox = (double)(m % patch - h) * spacing, oz = (double)(m / patch - h) * spacing;
+        c->pts_xz[2 * ((long long)q * M + m)] = pix_xz[2 * q] + ox;
+        c->pts_xz[2 * ((long long)q * M + m) + 1] = pix_xz[2 * q + 1] + oz;
+      }
+  });
 
   // active element range of every caller point (Eqs. 2 and 4, FP64).  Small
   // problems scan every element and check that the active set is contiguous;
   // large ones expand from the element nearest in polar angle (on a convex arc
   // the active set is the contiguous run around it).  Split over host threads.
-  std::vector<int> lo_c(P), hi_c(P);
+  std::vector<int>& lo_c = c->h_lo;
+  std::vector<int>& hi_c = c->h_hi;
+  lo_c.resize(P);
+  hi_c.resize(P);
   const double half_f = fnum / 2.0;
   auto active = [&](long long p, int a) {
     const double dx = c->pts_xz[2 * p] - elem_xz[2 * a], dz = c->pts_xz[2 * p + 1] - elem_xz[2 * a + 1];
@@ -300,10 +306,13 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
     double rsum = 0;
     for (int q = 0; q < n_pix; ++q) rsum += std::hypot(pix_xz[2 * q], pix_xz[2 * q + 1]);
     const double rref = rsum / n_pix;
-    for (int q = 0; q < n_pix; ++q) {
-      cu[q] = std::hypot(pix_xz[2 * q], pix_xz[2 * q + 1]);
-      cv[q] = std::atan2(pix_xz[2 * q], pix_xz[2 * q + 1]) * rref;
-    }
+    parallel(host_threads(n_pix * 8LL), [&](int tid, int nt) {
+      const int q0 = (int)((long long)n_pix * tid / nt), q1 = (int)((long long)n_pix * (tid + 1) / nt);
+      for (int q = q0; q < q1; ++q) {
+        cu[q] = std::hypot(pix_xz[2 * q], pix_xz[2 * q + 1]);
+        cv[q] = std::atan2(pix_xz[2 * q], pix_xz[2 * q + 1]) * rref;
+      }
+    });
   }
   std::vector<int> ord(n_pix);
   std::iota(ord.begin(), ord.end(), 0);
@@ -317,22 +326,26 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
   std::vector<long long> slot(n_pix);
   int n_tiles = 0;
   {
-    int t = -1, w = 0, sidx = pps, blo = 0, bhi = -1;
-    auto pix_blocks = [&](int q, int& lo, int& hi) {
-      lo = N;
-      hi = -1;
-      for (int m = 0; m < M; ++m) {
-        const long long pc = (long long)q * M + m;
-        if (lo_c[pc] <= hi_c[pc]) {
-          lo = std::min(lo, lo_c[pc] / block);
-          hi = std::max(hi, hi_c[pc] / block);
+    // active block span of every pixel (in parallel), then the greedy packing
+    std::vector<int2> pspan(n_pix);
+    parallel(host_threads(P), [&](int tid, int nt) {
+      const int q0 = (int)((long long)n_pix * tid / nt), q1 = (int)((long long)n_pix * (tid + 1) / nt);
+      for (int q = q0; q < q1; ++q) {
+        int lo = N, hi = -1;
+        for (int m = 0; m < M; ++m) {
+          const long long pc = (long long)q * M + m;
+          if (lo_c[pc] <= hi_c[pc]) {
+            lo = std::min(lo, lo_c[pc] / block);
+            hi = std::max(hi, hi_c[pc] / block);
+          }
         }
+        pspan[q] = make_int2(lo, hi);
       }
-    };
+    });
+    int t = -1, w = 0, sidx = pps, blo = 0, bhi = -1;
     for (int k = 0; k < n_pix; ++k) {
       const int q = ord[k];
-      int plo, phi;
-      pix_blocks(q, plo, phi);
+      const int plo = pspan[q].x, phi = pspan[q].y;
       if (plo <= phi && phi - plo + 1 > span_max)
         return fail(c, AF_ERR_ARG, "af_set_geometry: a pixel spans more active blocks than the CMPE stage holds (aperture too wide for the block size)");
       bool new_tile = t < 0;
@@ -380,9 +393,14 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
       c->c2i[(long long)q * M + m] = (int)pi;
     }
   }
-  std::vector<double4> ptpol(P_int);
-  std::vector<float2> ptxy(P_int);
-  std::vector<int2> prange(P_int);
+  // host staging kept in the context: repeated calls (the dynamic-grid sweep)
+  // reuse the pages instead of faulting in fresh ones
+  std::vector<double4>& ptpol = c->h_ptpol;
+  std::vector<float2>& ptxy = c->h_ptxy;
+  std::vector<int2>& prange = c->h_prange;
+  ptpol.resize(P_int);
+  ptxy.resize(P_int);
+  prange.resize(P_int);
   c->tile_lo.assign(n_tiles, N);
   c->tile_hi.assign(n_tiles, -1);
   {

@@ -123,6 +123,10 @@ struct af_ctx {
   int pps = 0, ppt = 0, n_tiles = 0;
   long long P = 0, P_int = 0;
   std::vector<int> i2c;                     // internal point -> caller point (-1 pad)
+  std::vector<int> h_lo, h_hi;              // host staging of the geometry set-up
+  std::vector<double4> h_ptpol;
+  std::vector<float2> h_ptxy;
+  std::vector<int2> h_prange;
   std::vector<int> c2i;                     // caller point -> internal point
   std::vector<int> prange_lo, prange_hi;    // per internal point
   std::vector<int> tile_lo, tile_hi;
