@@ -107,6 +107,22 @@ def measured_traffic(cfg_name: str, family: str):
     return rec[1]
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "c2_clinical_valu_counters.txt")
+
+
+def measured_issue(cfg_name: str, family: str):
+    """VALU instructions per CU per ns and active-lane share of ``family`` from the
+    committed SQ counter summary, or None when there is none for this workload or
+    the kernel's sources changed since."""
+    from paper_2608_06853_amd import profsummary
+    if cfg_name != "c2_clinical" or not os.path.exists(COUNTERS_FILE):
+        return None
+    rec = profsummary.read_counters(COUNTERS_FILE).get(family)
+    if rec is None or rec[0] != profsummary.source_hash(family):
+        return None
+    return {"valu_instr_per_cu_per_ns": rec[1], "active_lane_share": rec[2]}
+
+
 def plain_loop_report():
     """The full plain method (sweep + Adam with CMPE and speckle brightness) on the
     two-layer medium with a cyst: speed errors and image quality before and after."""
@@ -163,7 +179,7 @@ def s_to_target_report(n_heldout: int = 8):
         "media": n_heldout, "plain_seconds_total": tp, "learned_seconds_total": tl,
         "speedup_total": tp / tl if tl > 0 else None,
         "reached": sum(bool(r["learned_reached"]) for r in rows),
-        "starts": {k: sum(r["learned_start"] == k for r in rows) for k in ("map", "speed", "sweep")}}
+        "starts": {k: sum(r["learned_start"] == k for r in rows) for k in ("map", "local_sweep", "sweep")}}
     out["c4_heldout"] = [{k: r[k] for k in keep} for r in rows]
     r = warmstart.s_to_target(afsynth.configs.C5, nets["plain"])
     out["c5_largest"] = {k: r[k] for k in keep}
@@ -235,7 +251,8 @@ def main():
         roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
                 "traffic": tr, "traffic_unit": "bytes per launch",
-                "avg_launch_ms": round(avg_s * 1e3, 4)}
+                "avg_launch_ms": round(avg_s * 1e3, 4),
+                "valu_issue": measured_issue(cfg.name, dom)}
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": UNIT, "n_gpus": 1,

@@ -64,16 +64,29 @@ def lens_radius(acq: Acquisition) -> float:
     return float(np.hypot(acq.elem_xz[0, 0], acq.elem_xz[0, 1])) + acq.d_lens
 
 
+class DynamicGrid:
+    """Dynamic CMPE grid of a base pixel layout: at speed c_g every pixel's depth
+    below the lens surface is stretched by c_g/c_ref along its polar angle and the
+    kernel spacing becomes lambda_g/2 = c_g/(2 fc), so the same time samples are
+    observed.  The polar decomposition of the base layout is taken once."""
+
+    def __init__(self, img: Imaging, acq: Acquisition, c_ref: float, fc: float):
+        self.img, self.c_ref, self.fc = img, c_ref, fc
+        self.rl = lens_radius(acq)
+        rho = np.hypot(img.centres[:, 0], img.centres[:, 1])
+        th = np.arctan2(img.centres[:, 0], img.centres[:, 1])
+        self.depth = rho - self.rl
+        self.dirs = np.stack([np.sin(th), np.cos(th)], axis=1)
+
+    def at(self, c_g: float) -> Imaging:
+        rho_g = self.rl + self.depth * (c_g / self.c_ref)
+        return replace(self.img, centres=rho_g[:, None] * self.dirs,
+                       spacing=c_g / (2.0 * self.fc))
+
+
 def scaled_imaging(img: Imaging, acq: Acquisition, c_g: float, c_ref: float, fc: float) -> Imaging:
-    """Dynamic CMPE grid at speed c_g: every pixel's depth below the lens surface is
-    stretched by c_g/c_ref along its polar angle and the kernel spacing becomes
-    lambda_g/2 = c_g/(2 fc), so the same time samples are observed."""
-    rl = lens_radius(acq)
-    rho = np.hypot(img.centres[:, 0], img.centres[:, 1])
-    th = np.arctan2(img.centres[:, 0], img.centres[:, 1])
-    rho_g = rl + (rho - rl) * (c_g / c_ref)
-    cen = np.stack([rho_g * np.sin(th), rho_g * np.cos(th)], axis=1)
-    return replace(img, centres=cen, spacing=c_g / (2.0 * fc))
+    """The dynamic CMPE grid of ``img`` at speed c_g (see DynamicGrid)."""
+    return DynamicGrid(img, acq, c_ref, fc).at(c_g)
 
 
 class Beamformer:
@@ -88,12 +101,14 @@ class Beamformer:
         self.set_imaging(img)
         self.s = None
 
-    def set_imaging(self, img: Imaging):
+    def set_imaging(self, img: Imaging, keep_slowness: bool = True):
+        """New evaluation grid.  The slowness is set again unless the caller sets a
+        new one next (keep_slowness=False)."""
         a = self.acq
         self.ctx.set_geometry(a.elem_xz, img.centres, img.patch, img.spacing, a.n_samples, a.fs,
                               a.t0, a.fd, img.block, img.fnum, img.n_seg)
         self.img = img
-        if getattr(self, "s", None) is not None:
+        if keep_slowness and getattr(self, "s", None) is not None:
             self.set_slowness(self.s)
 
     def set_slowness(self, s: torch.Tensor):
@@ -182,17 +197,17 @@ def sweep(bf: Beamformer, iq, lp, fc: float, c_ref: float = 1.540, speeds=None, 
     of the best speed with a uniform slowness.  Returns (speeds, values, best)."""
     speeds = sweep_speeds() if speeds is None else np.asarray(speeds)
     base = bf.img
-    vals = []
+    dyn = DynamicGrid(base, bf.acq, c_ref, fc)
     terms = bf.empty_terms()
-    for c_g in speeds:
-        img = scaled_imaging(base, bf.acq, float(c_g), c_ref, fc) if dynamic else base
-        bf.set_imaging(img)
+    vals = torch.empty(len(speeds), device=bf.device)
+    for k, c_g in enumerate(speeds):
+        bf.set_imaging(dyn.at(float(c_g)) if dynamic else base, keep_slowness=False)
         bf.set_slowness(torch.full(bf.grid.shape, 1.0 / float(c_g), device=bf.device))
         bf.ctx.loss_and_grad(iq, lp, terms, None)
-        vals.append(float(terms[_lib.TERM_CMPE].item()))
-    vals = np.array(vals)
+        vals[k] = terms[_lib.TERM_CMPE]
+    vals = vals.cpu().numpy().astype(np.float64)
     best = float(speeds[int(np.argmin(vals))])
-    bf.set_imaging(scaled_imaging(base, bf.acq, best, c_ref, fc) if dynamic else base)
+    bf.set_imaging(dyn.at(best) if dynamic else base, keep_slowness=False)
     bf.set_slowness(torch.full(bf.grid.shape, 1.0 / best, device=bf.device))
     return speeds, vals, best
 

@@ -150,15 +150,28 @@ def counters(args):
     print(f"# valu_per_cu_ns = SQ_INSTS_VALU / dispatch duration / {args.cus} CUs; "
           "lane_util = SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)")
     names = sorted({c for f in per.values() for c in f})
-    print("# family        duration_us  valu_per_cu_ns  lane_util  " + "  ".join(names))
+    print("# family        source            duration_us  valu_per_cu_ns  lane_util  " + "  ".join(names))
     for fam in sorted(per):
         m = {c: sum(v.values()) / len(v) for c, v in per[fam].items()}
         t = sum(dur[fam].values()) / len(dur[fam])
         rate = m.get("SQ_INSTS_VALU", 0.0) / t / args.cus if t > 0 else 0.0
         util = (m.get("SQ_THREAD_CYCLES_VALU", 0.0) / (64.0 * m["SQ_ACTIVE_INST_VALU"])
                 if m.get("SQ_ACTIVE_INST_VALU") else 0.0)
-        print(f"{fam:14s} {t / 1e3:11.1f} {rate:15.2f} {util:10.3f}  " +
+        print(f"{fam:14s} {source_hash(fam):17s} {t / 1e3:11.1f} {rate:15.2f} {util:10.3f}  " +
               "  ".join(f"{m.get(c, 0.0):.4g}" for c in names))
+
+
+def read_counters(path: str) -> dict:
+    """{family: (source hash, VALU instructions per CU per ns, lane utilisation)}
+    from a counter summary."""
+    out = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            p = line.split()
+            out[p[0]] = (p[1], float(p[3]), float(p[4]))
+    return out
 
 
 def read_traffic(path: str) -> dict:

@@ -26,3 +26,18 @@ def test_network_initial_map_beats_homogeneous_and_sweep(net):
     print("held-out initial-map RMSE (m/s):", r, flush=True)
     assert r["net_true"] < 0.75 * r["homogeneous_1540"]
     assert r["net_true"] < 0.75 * r["sweep"]
+
+
+def test_learned_start_runs_end_to_end():
+    """The learned warm start (network map, else a sweep narrowed around the
+    network's speed, else the full sweep) runs through to the plain method's
+    target on a held-out medium."""
+    import afsynth
+    from paper_2608_06853_amd import warmstart
+    net = warmstart.load_network("plain")
+    r = warmstart.s_to_target(afsynth.configs.C4, net, seed=9001)
+    print({k: r[k] for k in ("learned_start", "learned_iters", "learned_reached", "learned_seconds",
+                             "learned_init_seconds", "plain_seconds", "plain_sweep_seconds")},
+          flush=True)
+    assert r["learned_start"] in ("map", "local_sweep", "sweep")
+    assert r["learned_iters"] >= 1 and np.isfinite(r["learned_seconds"])
