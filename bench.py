@@ -136,17 +136,20 @@ def plain_loop_report():
     npx = base.centres.shape[0]
     M = base.patch * base.patch
 
+    depth = np.linspace(cfg.img.depth_min, cfg.img.depth_max, cfg.img.n_depth)
+
     def image_quality(s):
         bf.set_imaging(base)
         img, _, _ = bf.beamform(iq, s=s, maps=False)
         env = img.abs().view(npx, M)[:, M // 2].cpu().numpy()
-        return metrics.contrast_cnr(env, base.centres, med.cyst_xz[0], float(med.cyst_r[0]))
+        q = metrics.contrast_cnr(env, base.centres, med.cyst_xz[0], float(med.cyst_r[0]))
+        return q, env.reshape(cfg.img.n_depth, cfg.img.n_angle)
 
     s_hom = torch.full(bf.grid.shape, 1.0 / cfg.img.c_ref, device=bf.device)
-    q0 = image_quality(s_hom)
+    q0, env0 = image_quality(s_hom)
     torch.cuda.synchronize()
     s, cm, times, t_sweep, best = warmstart.run_plain(bf, iq, cfg, cfg.method.n_iter)
-    q1 = image_quality(s)
+    q1, env1 = image_quality(s)
     e_hom = metrics.speed_errors(s_hom.cpu().numpy(), c_true)
     e_swp = metrics.speed_errors(np.full(bf.grid.shape, 1.0 / best), c_true)
     e_fin = metrics.speed_errors(s.cpu().numpy(), c_true)
@@ -158,7 +161,29 @@ def plain_loop_report():
             "mae_mps": {"homogeneous_1540": e_hom["mae_mps"], "sweep": e_swp["mae_mps"],
                         "final": e_fin["mae_mps"]},
             "cyst_contrast_db": {"homogeneous_1540": q0["contrast_db"], "final": q1["contrast_db"]},
-            "cyst_cnr": {"homogeneous_1540": q0["cnr"], "final": q1["cnr"]}}
+            "cyst_cnr": {"homogeneous_1540": q0["cnr"], "final": q1["cnr"]},
+            "tenengrad_change_pct": metrics.tenengrad_change(env0, env1, depth)}
+
+
+def lens_model_report():
+    """The paper's lens ablation on the plain loop's medium: channel data simulated
+    through the lens (bent rays), then the plain method (sweep + Adam) run with
+    each lens model of the beamformer; global speed and map errors against the
+    true medium."""
+    import afsynth
+    from paper_2608_06853_amd import metrics, warmstart, workloads
+    cfg = afsynth.configs.C3
+    out = {}
+    for model in workloads.LENS_MODELS:
+        bf, iq, med = workloads.build(cfg, lens_model=model)
+        s, cm, times, t_sweep, best = warmstart.run_plain(bf, iq, cfg, cfg.method.n_iter)
+        c_true = workloads.true_speed_nodes(cfg, med, bf.grid)
+        e = metrics.speed_errors(s.cpu().numpy(), c_true)
+        e_sweep = metrics.speed_errors(np.full(bf.grid.shape, 1.0 / best), c_true)
+        out[model] = {"sweep_best_speed": best, "sweep_mae_mps": e_sweep["mae_mps"],
+                      "final_mae_mps": e["mae_mps"], "final_rmse_mps": e["rmse_mps"],
+                      "cmpe_final": cm[-1]}
+    return out
 
 
 def s_to_target_report(n_heldout: int = 8):
@@ -279,6 +304,7 @@ def main():
     if not args.no_autofocus:
         t0 = time.perf_counter()
         out["plain_loop"] = plain_loop_report()
+        out["lens_models"] = lens_model_report()
         out["s_to_target"] = s_to_target_report()
         out["autofocus_report_seconds"] = round(time.perf_counter() - t0, 1)
     if args.cpu_pixels > 0:

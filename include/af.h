@@ -95,6 +95,19 @@ af_status af_set_geometry(af_ctx* ctx, int n_elem, const double* elem_xz, int n_
  * Errors: AF_ERR_ARG for d_lens < 0 or c_lens <= 0. */
 af_status af_set_lens(af_ctx* ctx, double d_lens, double c_lens, double t_ttp);
 
+/* Refraction-point rule of the lens model (Section III-A, model implementation):
+ * n_search = 0 (the default) takes the exact Fermat stationary point (continuous
+ * root, Eq. 8); n_search in [2, AF_MAX_SEARCH] takes the best of n_search lens
+ * points evenly spaced in polar angle over the interval that holds the root:
+ * from the element's polar angle to the crossing of the straight element-point
+ * segment with the lens arc when c_lens <= c_med, else from that crossing to the
+ * point's polar angle; least L1/c_lens + L2/c_med at the global mean speed wins
+ * (the first on ties).  Applies to the table, the beamformer and the gradient
+ * from the next call on; no effect with d_lens = 0.
+ * Errors: AF_ERR_ARG for other values of n_search. */
+#define AF_MAX_SEARCH 4096
+af_status af_set_refraction_search(af_ctx* ctx, int n_search);
+
 /* Slowness grid s ~ 1/c (Section III-A): node (i, j) at (x0 + j dx, z0 + i dz),
  * values [nz][nx] float32 at `s_dev` (device), copied on the context stream.
  * At most (nx+3)(nz+3) = 9600 padded nodes (e.g. 95 x 95).
@@ -109,8 +122,11 @@ af_status af_set_slowness(af_ctx* ctx, int nx, int nz, double x0, double z0, dou
  * demodulated FSA data (device), transmit-major.  Optional outputs (NULL = skip):
  *   blk_dev  [Nb][Nb][P] block-pair images B^blk[i][j](p), Nb = n_elem / block;
  *   img_dev  [P] full-aperture image (sum over all block pairs);
- *   maps_dev [2][n_pix] integrated CMPE (per-pixel mean phase error over valid
- *            pairs) and coherence factor at the patch centres.
+ *   maps_dev [3][n_pix] integrated CMPE (per-pixel mean phase error over valid
+ *            pairs), coherence factor at the patch centres, and common-midpoint
+ *            correlation coefficient (per-pixel mean rho over the pairs with
+ *            energy, before the rho threshold) - global image-quality metrics
+ *            of the Model Evaluation subsection.
  * Point order is the caller's (see af_set_geometry).  The CMPE map uses
  * rho_thresh from the most recent loss call (default 0.9).  The channel data
  * must be finite: samples of apodised-out element pairs are read and weighted

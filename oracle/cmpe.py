@@ -132,6 +132,20 @@ def speckle_brightness_grad(bblk: np.ndarray, n_patch: int) -> np.ndarray:
     return np.broadcast_to(g, bblk.shape).copy()
 
 
+def cmcc_map(bsub: np.ndarray, n_patch: int) -> np.ndarray:
+    """Per-pixel common-midpoint correlation coefficient: the mean of rho over the
+    pixel's common-midpoint pairs whose two energies exceed MIN_ENERGY, before any
+    rho threshold (0 when there is none).  One of the global image-quality
+    metrics of the Model Evaluation subsection; its exact formula is in the cited
+    work, which is not at hand, so this is the reading that matches the CMPE
+    reading above."""
+    d = cmpe(bsub, n_patch, 0.0)
+    pos = (d["ex"] > MIN_ENERGY) & (d["ey"] > MIN_ENERGY)
+    n = np.sum(pos, axis=(0, 1))
+    tot = np.sum(np.where(pos, d["rho"], 0.0), axis=(0, 1))
+    return np.where(n > 0, tot / np.maximum(n, 1), 0.0)
+
+
 def coherence_factor(bblk: np.ndarray, n_patch: int) -> np.ndarray:
     """Per-pixel coherence factor at the patch centre:
     |sum_ij B^blk_ij|^2 / (Nb^2 sum_ij |B^blk_ij|^2) (0 when there is no energy)."""

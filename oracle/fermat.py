@@ -12,10 +12,18 @@ lens point L(phi) = R_L (sin phi, cos phi) is
     T(phi) = |L(phi) - e_a| / c_lens + |p - L(phi)| / c_med .
 
 Reading: the paper searches a finite set of N_search candidate points; the
-oracle returns the continuous minimiser instead (the discrete search converges
-to it).  It scans phi over [min(theta_a, theta_p), max(theta_a, theta_p)] --
-outside that interval both legs get longer -- and then bisects the sign of
-dT/dphi inside the bracket around the best scanned point.
+oracle's ``refract`` returns the continuous minimiser (the discrete search
+converges to it).  It scans phi over [min(theta_a, theta_p), max(theta_a,
+theta_p)] -- outside that interval both legs get longer -- and then bisects the
+sign of dT/dphi inside the bracket around the best scanned point.
+
+``discrete_refract`` is the paper's search itself.  The paper gives neither
+N_search nor where the candidates lie; the reading here: N_search lens points
+evenly spaced in polar angle over the interval that holds the minimiser -- from
+the element's own polar angle theta_a to the polar angle theta_x where the
+straight element-to-point segment crosses the lens arc when c_lens <= c_med
+(Snell bends the lens leg towards the normal), else from theta_x to theta_p --
+and the candidate of least T, the first one on ties.
 """
 from __future__ import annotations
 
@@ -126,3 +134,55 @@ def brute_refract(elem_xz, d_lens, c_lens, c_med, pts, n_points=200001):
             res[a, p] = tt[i]
             arg[a, p] = phis[i]
     return res, arg
+
+
+def _ray_arrays(elem_xz, pts, pairs):
+    """Flattened element and point coordinates of every ray, and the output shape."""
+    ex_all = np.asarray(elem_xz[:, 0], dtype=np.float64)
+    ez_all = np.asarray(elem_xz[:, 1], dtype=np.float64)
+    if pairs is None:
+        n, p = elem_xz.shape[0], pts.shape[0]
+        ex, ez = np.repeat(ex_all, p), np.repeat(ez_all, p)
+        px, pz = np.tile(pts[:, 0], n), np.tile(pts[:, 1], n)
+        shape = (n, p)
+    else:
+        ai, pi = pairs
+        ex, ez, px, pz = ex_all[ai], ez_all[ai], pts[pi, 0], pts[pi, 1]
+        shape = np.shape(ai)
+    return [np.asarray(v, dtype=np.float64).ravel() for v in (ex, ez, px, pz)], shape
+
+
+def discrete_refract(elem_xz: np.ndarray, d_lens: float, c_lens: float, c_med: float,
+                     pts: np.ndarray, n_search: int,
+                     pairs: tuple[np.ndarray, np.ndarray] | None = None):
+    """The N_search refraction search (Model Implementation subsection): the best
+    of ``n_search`` >= 2 candidate lens points per ray, candidates as read in the
+    module docstring.  Same arguments (plus ``n_search``) and outputs as
+    ``refract``."""
+    assert n_search >= 2
+    (ex, ez, px, pz), shape = _ray_arrays(elem_xz, pts, pairs)
+    rl = np.hypot(ex, ez) + d_lens
+    th_a = np.arctan2(ex, ez)
+    th_p = np.arctan2(px, pz)
+    # where the straight segment e + t (p - e), t in [0, 1], meets |x| = rl
+    dx, dz = px - ex, pz - ez
+    qa = dx * dx + dz * dz
+    qb = 2.0 * (ex * dx + ez * dz)
+    qc = ex * ex + ez * ez - rl * rl
+    t = np.where(qa > 0, (-qb + np.sqrt(np.maximum(qb * qb - 4.0 * qa * qc, 0.0)))
+                 / (2.0 * np.where(qa > 0, qa, 1.0)), 0.0)
+    t = np.clip(t, 0.0, 1.0)
+    th_x = np.arctan2(ex + t * dx, ez + t * dz)
+    if c_lens <= c_med:
+        lo, hi = th_a, th_x
+    else:
+        lo, hi = th_x, th_p
+    k = np.arange(n_search) / (n_search - 1)
+    phis = lo[:, None] + (hi - lo)[:, None] * k[None, :]
+    tt = travel_time_via(phis, ex[:, None], ez[:, None], px[:, None], pz[:, None], rl[:, None],
+                         c_lens, c_med)
+    best = np.argmin(tt, axis=1)          # first minimum on ties
+    phi = phis[np.arange(phis.shape[0]), best]
+    lx, lz, l1, l2 = _legs(phi, ex, ez, px, pz, rl)
+    out = dict(phi=phi, l1=l1, l2=l2, t_hom=l1 / c_lens + l2 / c_med, ref_x=lx, ref_z=lz)
+    return {k_: v.reshape(shape) for k_, v in out.items()}

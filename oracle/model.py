@@ -50,6 +50,7 @@ class Problem:
     n_seg: int                   # ray segments
     grid: tuple                  # (x0, z0, dx, dz, nx, nz)
     iq: np.ndarray | None = None  # [N][N][Ns] complex
+    n_search: int = 0            # discrete refraction candidates (0: continuous root)
     _cache: dict = field(default_factory=dict, repr=False)
 
     @property
@@ -89,7 +90,11 @@ def rays(prob: Problem, s: np.ndarray, mask: np.ndarray | None = None,
         mask = prob.apod()
     ai, pi = np.nonzero(mask)
     cm = c_mean(s) if c_med is None else c_med
-    r = fermat.refract(prob.elem_xz, prob.d_lens, prob.c_lens, cm, pts, pairs=(ai, pi))
+    if prob.n_search >= 2 and prob.d_lens > 0:
+        r = fermat.discrete_refract(prob.elem_xz, prob.d_lens, prob.c_lens, cm, pts,
+                                    prob.n_search, pairs=(ai, pi))
+    else:
+        r = fermat.refract(prob.elem_xz, prob.d_lens, prob.c_lens, cm, pts, pairs=(ai, pi))
     return ai, pi, r
 
 
@@ -124,7 +129,8 @@ def forward(prob: Problem, s: np.ndarray, lp: LossParams, keep: bool = False,
     tv, sv = reg.reg_terms(s.astype(np.float64), dx, dz, lp.kx1, lp.kz1, lp.kx2, lp.kz2)
     total = l_cmpe + lp.w1 * tv + lp.w2 * sv - lp.w_sb * sb
     out = dict(cmpe=l_cmpe, tv=tv, sv=sv, sb=sb, total=total, n_valid=nv, cmpe_map=cmap,
-               cf=cmpe.coherence_factor(bblk, prob.n_patch))
+               cf=cmpe.coherence_factor(bblk, prob.n_patch),
+               cmcc=cmpe.cmcc_map(bsub, prob.n_patch))
     if keep:
         out.update(T=T, bblk=bblk, bsub=bsub)
     return out

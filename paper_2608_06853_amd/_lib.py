@@ -29,7 +29,7 @@ N_TERMS = 8
 
 EXPORTS = [
     "af_create", "af_destroy", "af_last_error", "af_set_geometry", "af_set_lens",
-    "af_set_slowness", "af_beamform", "af_loss_and_grad", "af_forward", "af_backward",
+    "af_set_refraction_search", "af_set_slowness", "af_beamform", "af_loss_and_grad", "af_forward", "af_backward",
     "af_autofocus_step", "af_travel_times", "af_simulate", "af_query", "af_set_profiling",
     "af_profile_read", "af_conv3x3_pack", "af_conv3x3_fwd", "af_conv3x3_bwd_data",
     "af_conv3x3_bwd_weight", "af_mse_loss", "af_adam_update", "af_features", "af_polar_to_grid",
@@ -56,6 +56,7 @@ _sig = {
     "af_last_error": (C.c_char_p, [_vp]),
     "af_set_geometry": (C.c_int, [_vp, _i, _vp, _i, _vp, _i, _d, _i, _d, _d, _d, _i, _d, _i]),
     "af_set_lens": (C.c_int, [_vp, _d, _d, _d]),
+    "af_set_refraction_search": (C.c_int, [_vp, _i]),
     "af_set_slowness": (C.c_int, [_vp, _i, _i, _d, _d, _d, _d, _vp]),
     "af_beamform": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "af_loss_and_grad": (C.c_int, [_vp, _vp, C.POINTER(LossParams), _vp, _vp]),
@@ -169,6 +170,9 @@ class Context:
     def set_lens(self, d_lens, c_lens, t_ttp=0.0):
         self._chk(_lib.af_set_lens(self._h, float(d_lens), float(c_lens), float(t_ttp)))
 
+    def set_refraction_search(self, n_search: int):
+        self._chk(_lib.af_set_refraction_search(self._h, int(n_search)))
+
     def set_slowness(self, nx, nz, x0, z0, dx, dz, s):
         import torch
         self.nx, self.nz = int(nx), int(nz)
@@ -187,7 +191,7 @@ class Context:
         self._chk(_lib.af_beamform(self._h, self._iq(iq),
                                    _dev(blk, torch.complex64, nb * nb * P, "blk"),
                                    _dev(img, torch.complex64, P, "img"),
-                                   _dev(maps, torch.float32, 2 * self.n_pix, "maps")))
+                                   _dev(maps, torch.float32, 3 * self.n_pix, "maps")))
 
     def loss_and_grad(self, iq, lp: LossParams, terms, grad=None):
         import torch

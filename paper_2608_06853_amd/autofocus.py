@@ -92,11 +92,15 @@ def scaled_imaging(img: Imaging, acq: Acquisition, c_g: float, c_ref: float, fc:
 class Beamformer:
     """Library context bound to one acquisition, evaluation grid and slowness grid."""
 
-    def __init__(self, acq: Acquisition, img: Imaging, grid: Grid, device: int = 0):
+    def __init__(self, acq: Acquisition, img: Imaging, grid: Grid, device: int = 0,
+                 n_search: int = 0):
+        """``n_search`` = 0 refracts at the exact Fermat root, >= 2 by the discrete
+        search over that many lens points."""
         self.acq, self.grid = acq, grid
         self.device = torch.device("cuda", device)
         self.ctx = _lib.Context(device)
         self.ctx.set_lens(acq.d_lens, acq.c_lens, acq.t_ttp)
+        self.ctx.set_refraction_search(n_search)
         self.img = None
         self.set_imaging(img)
         self.s = None
@@ -142,7 +146,7 @@ class Beamformer:
         P = self.n_points
         nb = self.n_blk
         img = torch.empty(P, device=self.device, dtype=torch.complex64)
-        mp = torch.empty(2 * self.img.centres.shape[0], device=self.device) if maps else None
+        mp = torch.empty(3 * self.img.centres.shape[0], device=self.device) if maps else None
         blk = torch.empty(nb * nb * P, device=self.device, dtype=torch.complex64) if blocks else None
         self.ctx.beamform(iq, blk, img, mp)
         return img, mp, blk

@@ -189,7 +189,8 @@ class FeatureMaker:
     def features(self, iq: torch.Tensor, out: torch.Tensor):
         """out: [128 * 128 * 2] BF16 (NHWC of one sample)."""
         _, maps, _ = self.bf.beamform(iq, blocks=False, maps=True)
-        self.bf.ctx.features(maps, self.shift, self.scale, out)
+        n = maps.numel() // 3  # channels: CMPE map, coherence factor (CMCC unused)
+        self.bf.ctx.features(maps[:2 * n], self.shift, self.scale, out)
 
 
 def label_map(cfg, med, og: OutGrid, sub: int = 4) -> np.ndarray:

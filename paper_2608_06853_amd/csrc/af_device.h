@@ -139,6 +139,67 @@ __device__ inline RayOut trace_lens(double R, double sa, double ca, double rho, 
   return o;
 }
 
+// Discrete refraction search (Section III-A: the refraction point is the best of
+// a finite set of N_search lens points, taken at the homogeneous mean speed).
+// The candidates are n >= 2 lens points evenly spaced in polar angle over the
+// interval that holds the minimiser of T: from the element's own polar angle to
+// the point where the straight element-point segment crosses the lens arc when
+// the lens is the slower layer (Snell bends the lens leg towards the normal),
+// else from that crossing to the point's polar angle.  The candidate of least
+// L1/c_lens + L2/c_med is taken, the first one on ties.  Same arguments and
+// outputs as trace_lens; FP64 throughout.
+__device__ inline RayOut trace_lens_search(double R, double sa, double ca, double rho, double sp,
+                                           double cp, double dlens, double icl, double icm,
+                                           int n) {
+  const double RL = R + dlens;
+  const double cT = cp * ca + sp * sa;
+  double sT = sp * ca - cp * sa;
+  const double sgn = sT < 0.0 ? -1.0 : 1.0;
+  sT = fabs(sT);
+  const double px = rho * sT, pz = rho * cT;  // point in the element's frame, element at (0, R)
+  // crossing of the segment (0, R) -> (px, pz) with the arc of radius RL
+  const double dz = pz - R;
+  const double dd = px * px + dz * dz;
+  const double ed = R * dz;
+  double t = dd > 0.0 ? (-ed + sqrt(fmax(ed * ed + dd * (RL * RL - R * R), 0.0))) / dd : 0.0;
+  t = fmin(fmax(t, 0.0), 1.0);
+  const double phx = atan2(t * px, R + t * dz);
+  const double lo = icl >= icm ? 0.0 : phx;
+  const double hi = icl >= icm ? phx : atan2(px, pz);
+  const double step = (hi - lo) / (double)(n - 1);
+  double best = 1e300, bs = 0.0, bc = 1.0, bl2 = 0.0;
+  for (int k = 0; k < n; ++k) {
+    double s, c;
+    sincos(lo + step * (double)k, &s, &c);
+    const double lx = RL * s, lz = RL * c;
+    const double l1 = sqrt(lx * lx + (lz - R) * (lz - R));
+    const double l2 = sqrt((px - lx) * (px - lx) + (pz - lz) * (pz - lz));
+    const double T = l1 * icl + l2 * icm;
+    if (T < best) {
+      best = T;
+      bs = s;
+      bc = c;
+      bl2 = l2;
+    }
+  }
+  RayOut o;
+  o.t_hom = best;
+  const double ss = bs * sgn;
+  o.refx = (float)(RL * (sa * bc + ca * ss));
+  o.refz = (float)(RL * (ca * bc - sa * ss));
+  o.l2 = (float)bl2;
+  return o;
+}
+
+// Refraction by the context's rule: straight rays without a lens, the discrete
+// search with nsearch >= 2 candidates, else the continuous Fermat root.
+__device__ inline RayOut refract(double R, double sa, double ca, double rho, double sp, double cp,
+                                 double dlens, double icl, double icm, int nsearch) {
+  if (nsearch >= 2 && dlens > 0.0)
+    return trace_lens_search(R, sa, ca, rho, sp, cp, dlens, icl, icm, nsearch);
+  return trace_lens(R, sa, ca, rho, sp, cp, dlens, icl, icm);
+}
+
 // Keys cubic-convolution weights (a = -0.5) of the taps at offsets -1, 0, 1, 2
 // for fractional position f in [0, 1].
 __device__ inline void keys_weights(float f, float& w0, float& w1, float& w2, float& w3) {

@@ -133,6 +133,7 @@ af::Geo af_ctx::geo() const {
   g.t_ttp = t_ttp;
   g.dlens = d_lens;
   g.icl = 1.0 / c_lens;
+  g.nsearch = n_search;
   g.nx = nx;
   g.nz = nz;
   g.W = nx + 3;
@@ -508,7 +509,7 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
   AF_ALLOC(c->d_gT, sizeof(float) * 2 * (size_t)N * P_int, "time gradient");
   AF_ALLOC(c->d_gsb, sizeof(float2) * (size_t)P_int, "brightness gradient");
   AF_ALLOC(c->d_part, sizeof(double) * 4 * (size_t)(P_int / SUB), "partials");
-  AF_ALLOC(c->d_maps, sizeof(float) * 2 * (size_t)n_tiles * ppt, "maps");
+  AF_ALLOC(c->d_maps, sizeof(float) * 3 * (size_t)n_tiles * ppt, "maps");
   c->has_geom = true;
   return AF_OK;
 }
@@ -522,6 +523,14 @@ af_status af_set_lens(af_ctx* c, double d_lens, double c_lens, double t_ttp) {
   c->t_ttp = t_ttp;
   c->has_lens = true;
   c->has_grid = false;
+  return AF_OK;
+}
+
+af_status af_set_refraction_search(af_ctx* c, int n_search) {
+  if (!c) return AF_ERR_ARG;
+  if (n_search != 0 && (n_search < 2 || n_search > AF_MAX_SEARCH))
+    return fail(c, AF_ERR_ARG, "af_set_refraction_search: n_search must be 0 or in [2, 4096]");
+  c->n_search = n_search;
   return AF_OK;
 }
 
@@ -637,7 +646,8 @@ af_status run_forward(af_ctx* c, const af_complex* iq, const af_loss_params* lp,
   AF_KERNEL(AF_K_CMPE,
             af::launch_cmpe(c, c->d_bblk.as<float2>(), g, write_g ? 1 : 0, lp->rho_thresh,
                             sb_scale, c->d_maps.as<float>(),
-                            c->d_maps.as<float>() + c->n_tiles * c->ppt, nullptr),
+                            c->d_maps.as<float>() + c->n_tiles * c->ppt,
+                            c->d_maps.as<float>() + 2 * (size_t)c->n_tiles * c->ppt, nullptr),
             "cmpe");
   AF_KERNEL(AF_K_FINALIZE, af::launch_finalize(c, lp, terms), "finalize");
   if (write_g && scale_now) AF_KERNEL(AF_K_GSCALE, af::launch_gscale(c, g), "gscale");
@@ -673,7 +683,7 @@ af_status af_beamform(af_ctx* c, const af_complex* iq, af_complex* blk, af_compl
   if (maps)
     AF_HIP(af::launch_cmpe(c, c->d_bblk.as<float2>(), nullptr, 0, c->rho_last, 0.f,
                            c->d_maps.as<float>(), c->d_maps.as<float>() + c->n_tiles * c->ppt,
-                           nullptr),
+                           c->d_maps.as<float>() + 2 * (size_t)c->n_tiles * c->ppt, nullptr),
            "cmpe maps");
   if (blk || img || maps)
     AF_HIP(af::launch_export_images(c, c->d_bblk.as<float2>(), reinterpret_cast<float2*>(blk),

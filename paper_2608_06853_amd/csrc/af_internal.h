@@ -42,6 +42,7 @@ struct Geo {
   long long P;            // internal points (multiple of TILE)
   double fs, fd, t0, t_ttp;
   double dlens, icl;      // lens thickness, 1/c_lens
+  int nsearch;            // discrete refraction candidates (0: continuous root)
   // slowness grid
   int nx, nz, W;          // W = nx + 3 (padded row stride)
   float x0, z0, idx, idz;
@@ -86,6 +87,7 @@ struct CmpeArgs {
   double* part;           // [n_sub_tiles][4] (sum err, n_valid, sum |B|^2, 0)
   float* map_cmpe;        // [P/patch2 internal pixel slots] or null
   float* map_cf;          // same, or null
+  float* map_cmcc;        // same, or null
   float2* img;            // [P] full image or null
   float rho_thresh;
   float sb_scale;         // -2 w_sb / (sb_ref n_pix)
@@ -137,6 +139,7 @@ struct af_ctx {
 
   // lens
   double d_lens = 0, c_lens = 1, t_ttp = 0;
+  int n_search = 0;
   // grid
   int nx = 0, nz = 0;
   double x0 = 0, z0 = 0, dx = 1, dz = 1;
@@ -182,7 +185,8 @@ hipError_t launch_table(af_ctx* c);
 hipError_t launch_das_fwd(af_ctx* c, const float2* iq, float2* bblk);
 int cmpe_span_limit(int pps);  // largest tile span in blocks whose CMPE stage fits in LDS
 hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g, float rho,
-                       float sb_scale, float* map_cmpe, float* map_cf, float2* img);
+                       float sb_scale, float* map_cmpe, float* map_cf, float* map_cmcc,
+                       float2* img);
 hipError_t launch_finalize(af_ctx* c, const af_loss_params* lp, float* terms);
 hipError_t launch_gscale(af_ctx* c, float2* gblk);
 // scaled = false: gblk still lacks its final scale, which the adjoint applies

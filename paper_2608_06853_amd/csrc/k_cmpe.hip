@@ -56,6 +56,7 @@ __global__ __launch_bounds__(256) void k_cmpe(CmpeArgs A) {
       if (tid < pps) {
         if (A.map_cmpe) A.map_cmpe[slot0 + tid] = 0.f;
         if (A.map_cf) A.map_cf[slot0 + tid] = 0.f;
+        if (A.map_cmcc) A.map_cmcc[slot0 + tid] = 0.f;
       }
     }
     if (tid == 0) {
@@ -76,6 +77,7 @@ __global__ __launch_bounds__(256) void k_cmpe(CmpeArgs A) {
   float2* Ss = sm;                                   // [nS * nS][SUB]
   float2* gC = Ss + (size_t)nS * nS * SUB;           // [pps][np2]
   float* er = reinterpret_cast<float*>(gC + (size_t)pps * np2);
+  float* rh = er + (size_t)pps * np2;                // rho of each entry, -1 if no energy
 
   auto bget = [&](int a, int b) -> float2 {
     if (a < bLO || a > bHI || b < bLO || b > bHI) return make_float2(0.f, 0.f);
@@ -120,7 +122,9 @@ __global__ __launch_bounds__(256) void k_cmpe(CmpeArgs A) {
     }
     const float mag = sqrtf(cx * cx + cy * cy);
     bool valid = ex > kMinEnergy && ey > kMinEnergy;
-    if (valid) valid = mag / (sqrtf(ex) * sqrtf(ey)) >= A.rho_thresh;
+    const float rho = valid ? mag / (sqrtf(ex) * sqrtf(ey)) : -1.f;
+    rh[item] = rho;
+    if (valid) valid = rho >= A.rho_thresh;
     const float ang = atan2f(cy, cx);
     float2 gc = make_float2(0.f, 0.f);
     if (valid) {
@@ -150,6 +154,18 @@ __global__ __launch_bounds__(256) void k_cmpe(CmpeArgs A) {
       }
     }
     A.map_cmpe[slot0 + tid] = n > 0 ? s / (float)n : 0.f;
+  }
+  if (tid < pps && A.map_cmcc) {  // common-midpoint correlation coefficient
+    float s = 0.f;
+    int n = 0;
+    for (int k = 0; k < np2; ++k) {
+      const float r = rh[tid * np2 + k];
+      if (r >= 0.f) {
+        s += r;
+        ++n;
+      }
+    }
+    A.map_cmcc[slot0 + tid] = n > 0 ? s / (float)n : 0.f;
   }
 
   // phase 3: dL/dB(i0, j0) = sum over the subapertures (i, j), i in {i0-1, i0},
@@ -253,6 +269,7 @@ __global__ __launch_bounds__(256) void k_export_img(Geo g, const float2* __restr
                                                     const int* __restrict__ c2i, long long Pc,
                                                     int n_pix, const float* __restrict__ mc,
                                                     const float* __restrict__ mcf,
+                                                    const float* __restrict__ mcc,
                                                     float2* __restrict__ blk_out,
                                                     float2* __restrict__ img_out,
                                                     float* __restrict__ maps_out) {
@@ -277,6 +294,7 @@ __global__ __launch_bounds__(256) void k_export_img(Geo g, const float2* __restr
     const long long q = pc / g.patch2;
     maps_out[q] = mc[slot];
     maps_out[n_pix + q] = mcf[slot];
+    maps_out[2 * (long long)n_pix + q] = mcc[slot];
   }
 }
 
@@ -289,14 +307,15 @@ int cmpe_span_limit(int pps) {
                         sizeof(double) * CMPE_WAVES * 3 - 256;
   for (int n = MAX_NBA; n >= 1; --n) {
     const size_t need = sizeof(float2) * (size_t)(n + 1) * (n + 1) * SUB +
-                        (sizeof(float2) + sizeof(float)) * (size_t)pps * n * n;
+                        (sizeof(float2) + 2 * sizeof(float)) * (size_t)pps * n * n;
     if (need <= budget) return n;
   }
   return 0;
 }
 
 hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g, float rho,
-                       float sb_scale, float* map_cmpe, float* map_cf, float2* img) {
+                       float sb_scale, float* map_cmpe, float* map_cf, float* map_cmcc,
+                       float2* img) {
   CmpeArgs A{};
   A.g = c->geo();
   A.tiles = c->d_tiles.as<int4>();
@@ -306,6 +325,7 @@ hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g,
   A.part = c->d_part.as<double>();
   A.map_cmpe = map_cmpe;
   A.map_cf = map_cf;
+  A.map_cmcc = map_cmcc;
   A.img = img;
   A.rho_thresh = rho;
   A.sb_scale = sb_scale;
@@ -314,7 +334,7 @@ hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g,
   const int npr = nba;      // upper bound of pair rows (and columns)
   const int nS = nba + 1;   // upper bound of subaperture rows
   const size_t lds = sizeof(float2) * (size_t)nS * nS * SUB +
-                     (sizeof(float2) + sizeof(float)) * (size_t)c->pps * npr * npr;
+                     (sizeof(float2) + 2 * sizeof(float)) * (size_t)c->pps * npr * npr;
   hipLaunchKernelGGL(k_cmpe, dim3((unsigned)(c->P_int / SUB)), dim3(CMPE_WAVES * SUB), lds,
                      c->stream, A);
   return hipGetLastError();
@@ -333,8 +353,9 @@ hipError_t launch_export_images(af_ctx* c, const float2* bblk, float2* blk_out, 
   const long long Pc = c->P;
   hipLaunchKernelGGL(k_export_img, dim3((unsigned)((Pc + 255) / 256)), dim3(256), 0, c->stream,
                      c->geo(), bblk, c->d_tiles.as<int4>(), c->d_c2i.as<int>(), Pc, c->n_pix,
-                     c->d_maps.as<float>(), c->d_maps.as<float>() + c->n_tiles * c->ppt, blk_out,
-                     img_out, maps_out);
+                     c->d_maps.as<float>(), c->d_maps.as<float>() + c->n_tiles * c->ppt,
+                     c->d_maps.as<float>() + 2 * (size_t)c->n_tiles * c->ppt, blk_out, img_out,
+                     maps_out);
   return hipGetLastError();
 }
 

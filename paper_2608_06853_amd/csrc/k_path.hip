@@ -70,6 +70,8 @@ __device__ inline float reduce_scatter16(float v[16], int lane) {
   return h1;
 }
 
+// SEARCH selects the discrete refraction search (see k_table).
+template <bool SEARCH>
 __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
   extern __shared__ float sg[];  // [4 wavefronts][nodes]
   const Geo& g = A.g;
@@ -103,7 +105,8 @@ __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
     const unsigned long long lmask = __ballot(live);
     if (lmask == 0ull) continue;
     const double4 el = A.elem[a];
-    const RayOut r = trace_lens(el.x, el.y, el.z, pp.x, pp.y, pp.z, g.dlens, g.icl, icm);
+    const RayOut r = refract(el.x, el.y, el.z, pp.x, pp.y, pp.z, g.dlens, g.icl, icm,
+                                 SEARCH ? g.nsearch : 0);
     const float coef = live ? gbar * r.l2 * inv_n : 0.f;
     const float u0 = (r.refx - g.x0) * g.idx, v0 = (r.refz - g.z0) * g.idz;
     const float du = (up - u0) * inv_n, dv = (vp - v0) * inv_n;
@@ -213,7 +216,10 @@ hipError_t launch_path_adj(af_ctx* c) {
   A.scal = c->d_scal.as<double>();
   A.gpart = c->d_gpart.as<float>();
   const size_t lds = sizeof(float) * (size_t)nodes * 4;
-  hipLaunchKernelGGL(k_path_adj, dim3(c->n_order), dim3(256), lds, c->stream, A);
+  if (A.g.nsearch >= 2 && A.g.dlens > 0.0)
+    hipLaunchKernelGGL(k_path_adj<true>, dim3(c->n_order), dim3(256), lds, c->stream, A);
+  else
+    hipLaunchKernelGGL(k_path_adj<false>, dim3(c->n_order), dim3(256), lds, c->stream, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n_chunk = (c->n_order + PCHUNK - 1) / PCHUNK;

@@ -12,6 +12,9 @@
 namespace af {
 namespace {
 
+// SEARCH selects the discrete refraction search; the continuous root is the
+// other instantiation, so each keeps its own register allocation.
+template <bool SEARCH>
 __global__ __launch_bounds__(256) void k_table(TableArgs A) {
   extern __shared__ float G[];
   const Geo& g = A.g;
@@ -43,7 +46,8 @@ __global__ __launch_bounds__(256) void k_table(TableArgs A) {
       e.ei = 0.f;
     } else {
       const double4 el = A.elem[a];
-      const RayOut r = trace_lens(el.x, el.y, el.z, pp.x, pp.y, pp.z, g.dlens, g.icl, icm);
+      const RayOut r = refract(el.x, el.y, el.z, pp.x, pp.y, pp.z, g.dlens, g.icl, icm,
+                                 SEARCH ? g.nsearch : 0);
       const float u0 = (r.refx - g.x0) * g.idx, v0 = (r.refz - g.z0) * g.idz;
       const float acc = path_sum(G, g.W, u0, v0, (up - u0) * inv_n, (vp - v0) * inv_n, g.n_seg,
                                  umax, vmax);
@@ -82,7 +86,10 @@ hipError_t launch_table(af_ctx* c) {
   A.tab = c->d_tab.as<TabEntry>();
   if (c->n_tab_work == 0) return hipSuccess;
   const size_t lds = sizeof(float) * (size_t)(c->nx + 3) * (c->nz + 3);
-  hipLaunchKernelGGL(k_table, dim3(c->n_tab_work), dim3(256), lds, c->stream, A);
+  if (A.g.nsearch >= 2 && A.g.dlens > 0.0)
+    hipLaunchKernelGGL(k_table<true>, dim3(c->n_tab_work), dim3(256), lds, c->stream, A);
+  else
+    hipLaunchKernelGGL(k_table<false>, dim3(c->n_tab_work), dim3(256), lds, c->stream, A);
   return hipGetLastError();
 }
 

@@ -8,7 +8,12 @@ slowness maps they take come from the library.
   contrast = 20 log10(mu_in / mu_out) and CNR = |mu_in - mu_out| /
   sqrt(var_in + var_out) on the envelope (Rodriguez-Molares et al.); the regions
   are the disc r < 0.7 R inside the cyst and the annulus 1.3 R < r < 2 R around
-  it (the paper drew its regions by hand).
+  it (the paper drew its regions by hand);
+* the Tenengrad sharpness change eta between an aberrated and a corrected image:
+  both envelopes are log-compressed to a 60 dB display range, the corrected
+  image is scaled so that its 80th-percentile amplitude equals the aberrated
+  one's, a lateral Sobel filter is applied, the filtered amplitudes are summed
+  from 10 mm depth down, and eta = 100 (S_corrected / S_aberrated - 1).
 """
 from __future__ import annotations
 
@@ -33,3 +38,31 @@ def contrast_cnr(env: np.ndarray, xz: np.ndarray, centre, radius: float) -> dict
     vi, vo = env[inside].var(), env[outside].var()
     return {"contrast_db": float(20.0 * np.log10(max(mi, 1e-30) / max(mo, 1e-30))),
             "cnr": float(abs(mi - mo) / np.sqrt(vi + vo + 1e-30))}
+
+
+def log_compress(env: np.ndarray, dyn_range_db: float = 60.0) -> np.ndarray:
+    """Envelope [depth][angle] -> display amplitude in [0, 1] over dyn_range_db."""
+    env = np.asarray(env, dtype=np.float64)
+    db = 20.0 * np.log10(np.maximum(env, 1e-30) / max(float(env.max()), 1e-30))
+    return np.clip(db + dyn_range_db, 0.0, dyn_range_db) / dyn_range_db
+
+
+def lateral_sobel(img: np.ndarray) -> np.ndarray:
+    """3x3 Sobel derivative along the lateral (last) axis, edge rows/columns replicated."""
+    p = np.pad(img, 1, mode="edge")
+    d = p[:, 2:] - p[:, :-2]                       # central difference across columns
+    return d[:-2] + 2.0 * d[1:-1] + d[2:]          # [1, 2, 1] smoothing along depth
+
+
+def tenengrad_change(env_aberrated: np.ndarray, env_corrected: np.ndarray, depth_mm: np.ndarray,
+                     min_depth_mm: float = 10.0) -> float:
+    """eta (%) for envelopes [depth][angle] with row depths ``depth_mm``."""
+    a = log_compress(env_aberrated)
+    c = log_compress(env_corrected)
+    pa, pc = np.percentile(a, 80.0), np.percentile(c, 80.0)
+    if pc > 0:
+        c = c * (pa / pc)
+    rows = np.asarray(depth_mm) >= min_depth_mm
+    sa = float(np.abs(lateral_sobel(a))[rows].sum())
+    sc = float(np.abs(lateral_sobel(c))[rows].sum())
+    return 100.0 * (sc / sa - 1.0) if sa > 0 else float("nan")

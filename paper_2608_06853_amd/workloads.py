@@ -6,6 +6,8 @@ sweep (depths stretched up to 1740/1540).
 """
 from __future__ import annotations
 
+from dataclasses import replace
+
 import numpy as np
 import torch
 
@@ -15,15 +17,36 @@ from . import autofocus as af
 SWEEP_MAX = 1.740
 
 
-def geometry(cfg):
+LENS_MODELS = ("bent", "conventional", "none")
+
+
+def geometry(cfg, lens_model: str = "bent"):
+    """(acquisition, imaging, slowness grid, cover points) of ``cfg`` for one lens
+    model of the beamformer:
+
+    * ``bent``: the two-layer Fermat ray through the lens (Eqs. 7-8);
+    * ``conventional``: straight rays from the elements plus the scalar round-trip
+      lens offset of Eq. 6 (``afsynth.lens_correction``);
+    * ``none``: straight rays from the elements, no lens term.
+
+    Pixels are the same physical points in every model; the slowness grid of the
+    straight-ray models also covers the element arc, where their rays start."""
+    if lens_model not in LENS_MODELS:
+        raise ValueError(f"lens model must be one of {LENS_MODELS}")
     arr, acq, img, met = cfg.array, cfg.acq, cfg.img, cfg.method
     elem = afsynth.element_positions(arr)
     centres = afsynth.pixel_centres(arr, img)
     sp = afsynth.patch_spacing(img, acq)
     smax = SWEEP_MAX / img.c_ref
     cover = np.concatenate([centres, afsynth.pixel_centres(arr, img, depth_scale=smax)])
-    x0, z0, dx, dz = afsynth.slowness_box(arr, cover, sp * smax, met.nx, met.nz)
-    acqd = af.Acquisition(elem_xz=elem, d_lens=arr.d_lens, c_lens=arr.c_lens, t_ttp=arr.t_ttp,
+    arr_box = arr if lens_model == "bent" else replace(arr, d_lens=0.0)
+    x0, z0, dx, dz = afsynth.slowness_box(arr_box, cover, sp * smax, met.nx, met.nz)
+    d_lens, t_ttp = arr.d_lens, arr.t_ttp
+    if lens_model != "bent":
+        d_lens = 0.0
+        if lens_model == "conventional":
+            t_ttp = t_ttp + afsynth.lens_correction(arr, img.c_ref)
+    acqd = af.Acquisition(elem_xz=elem, d_lens=d_lens, c_lens=arr.c_lens, t_ttp=t_ttp,
                           fs=acq.fs, t0=acq.t0, fd=acq.fc, n_samples=acq.n_samples)
     imgd = af.Imaging(centres=centres, patch=img.patch, spacing=sp, block=met.block,
                       fnum=met.fnum, n_seg=met.n_seg)
@@ -47,12 +70,17 @@ def simulate(bf: af.Beamformer, cfg, med, cover) -> torch.Tensor:
     return iq
 
 
-def build(cfg, seed=None, device: int = 0):
-    """(Beamformer at a uniform 1/c_ref slowness, channel data, medium)."""
+def build(cfg, seed=None, device: int = 0, lens_model: str = "bent"):
+    """(Beamformer of ``lens_model`` at a uniform 1/c_ref slowness, channel data,
+    medium).  The channel data always come from the bent-ray physics of the lens."""
     acqd, imgd, grid, cover = geometry(cfg)
     bf = af.Beamformer(acqd, imgd, grid, device)
     med = afsynth.medium_for(cfg, seed)
     iq = simulate(bf, cfg, med, cover)
+    if lens_model != "bent":
+        acqm, imgm, gridm, _ = geometry(cfg, lens_model)
+        bf = af.Beamformer(acqm, imgm, gridm, device)
+        grid = gridm
     bf.set_slowness(torch.full(grid.shape, 1.0 / cfg.img.c_ref, device=bf.device))
     return bf, iq, med
 

@@ -44,9 +44,10 @@ MICRO = afsynth.configs.MICRO
 
 @functools.lru_cache(maxsize=8)
 def case(name: str, t0: float = 0.0, t_ttp: float = 0.0, patch: int = 3, block: int | None = None,
-         perturb: float = 0.01, d_lens: float | None = None):
+         perturb: float = 0.01, d_lens: float | None = None, n_search: int = 0):
     """(cfg, oracle problem, iq complex64, s [nz][nx] float32, loss params).
-    d_lens = 0 gives the lens-free (straight-ray) model."""
+    d_lens = 0 gives the lens-free (straight-ray) model; n_search >= 2 the discrete
+    refraction search."""
     base = {"micro": MICRO, "c1_small": C1_SMALL}[name]
     arr = replace(base.array, t_ttp=t_ttp)
     if d_lens is not None:
@@ -57,6 +58,7 @@ def case(name: str, t0: float = 0.0, t_ttp: float = 0.0, patch: int = 3, block: 
     med = afsynth.medium_for(cfg)
     iq = problems.simulate_iq(cfg, med, n_seg=64).astype(np.complex64)
     prob = problems.problem(cfg, iq.astype(np.complex128))
+    prob.n_search = n_search
     s_true = problems.true_slowness(cfg, med, prob)
     rng = np.random.default_rng(cfg.seed + 11)
     s = (s_true * (1.0 + perturb * rng.standard_normal(s_true.shape))).astype(np.float32)
@@ -80,7 +82,7 @@ def beamformer(cfg, prob, device=0):
                      block=prob.block, fnum=prob.fnum, n_seg=prob.n_seg)
     x0, z0, dx, dz, nx, nz = prob.grid
     grid = af.Grid(nx=nx, nz=nz, x0=x0, z0=z0, dx=dx, dz=dz)
-    return af.Beamformer(acq, img, grid, device)
+    return af.Beamformer(acq, img, grid, device, n_search=prob.n_search)
 
 
 def rel(a, b):

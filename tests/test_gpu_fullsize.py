@@ -99,10 +99,12 @@ def test_block_images_sampled(full):
     del blk
     f = model.forward(sub, s.astype(np.float64), lp, keep=True)
     e_blk = G.rel(bg, f["bblk"])
-    cf = maps.view(2, -1)[1].cpu().numpy()[sel]
+    cf = maps.view(3, -1)[1].cpu().numpy()[sel]
+    cmcc = maps.view(3, -1)[2].cpu().numpy()[sel]
     e_cf = G.rel(cf, f["cf"])
-    print(cfg.name, "sampled blocks rel", e_blk, "cf rel", e_cf, flush=True)
-    assert e_blk < 1e-4 and e_cf < 1e-4
+    e_cc = G.rel(cmcc, f["cmcc"])
+    print(cfg.name, "sampled blocks rel", e_blk, "cf rel", e_cf, "cmcc rel", e_cc, flush=True)
+    assert e_blk < 1e-4 and e_cf < 1e-4 and e_cc < 1e-4
 
 
 def test_loss_and_gradient_sampled_pixels(full):

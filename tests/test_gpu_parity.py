@@ -11,11 +11,14 @@ from oracle import model
 
 pytestmark = pytest.mark.gpu
 
-# (config, t0, t_ttp, patch, block, perturbation, lens thickness); the last case is
-# the lens-free straight-ray model.
+# (config, t0, t_ttp, patch, block, perturbation, lens thickness, refraction
+# candidates); after the first four come the lens-free straight-ray model, the
+# conventional model (straight rays plus a scalar round-trip lens offset in the
+# time-to-peak constant) and the bent-ray model with the discrete refraction search.
 CASES = [("micro", 0.0, 0.0, 3, None), ("c1_small", 0.0, 0.0, 3, None),
          ("micro", 0.7, 0.35, 3, None), ("micro", 0.0, 0.0, 1, 2),
-         ("micro", 0.0, 0.0, 3, None, 0.01, 0.0)]
+         ("micro", 0.0, 0.0, 3, None, 0.01, 0.0), ("micro", 0.0, 0.5, 3, None, 0.01, 0.0),
+         ("micro", 0.0, 0.0, 3, None, 0.01, None, 24)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -57,10 +60,11 @@ def test_block_images_and_maps(key):
     bg = blk.cpu().numpy().reshape(nb, nb, -1)
     e_blk = G.rel(bg, bo)
     e_img = G.rel(img.cpu().numpy(), ocmpe.full_image(bo))
-    mp = maps.cpu().numpy().reshape(2, -1)
+    mp = maps.cpu().numpy().reshape(3, -1)
     e_cf = G.rel(mp[1], f["cf"])
-    print("blk", e_blk, "img", e_img, "cf", e_cf, flush=True)
-    assert e_blk < 1e-4 and e_img < 1e-4 and e_cf < 1e-4
+    e_cc = G.rel(mp[2], f["cmcc"])
+    print("blk", e_blk, "img", e_img, "cf", e_cf, "cmcc", e_cc, flush=True)
+    assert e_blk < 1e-4 and e_img < 1e-4 and e_cf < 1e-4 and e_cc < 1e-4
     # integrated CMPE map: per-pixel means agree except where a pair sits on rho_thresh
     d = np.abs(mp[0] - f["cmpe_map"])
     assert np.mean(d < 1e-3) > 0.98
@@ -124,6 +128,32 @@ def test_gradient_finite_differences_gpu(key):
         errs.append(abs(fd - an) / (np.linalg.norm(g) * np.linalg.norm(d)))
     print("fd errs", errs, flush=True)
     assert np.median(errs) < 1e-2
+
+
+@pytest.mark.parametrize("n_search", [2, 8, 64])
+def test_discrete_refraction_search_travel_times(n_search):
+    """Travel times of the discrete refraction search against the oracle's search,
+    entry by entry; and the search converges to the continuous root as the
+    candidates get denser."""
+    import torch
+    print("discrete search, c1_small, n_search", n_search, flush=True)
+    cfg, prob, iq, s, lp = G.case("c1_small")
+    bf = G.beamformer(cfg, prob)
+    bf.set_slowness(torch.from_numpy(s).cuda())
+    T_cont = bf.travel_times().cpu().numpy().astype(np.float64)
+    bf.ctx.set_refraction_search(n_search)
+    T = bf.travel_times().cpu().numpy().astype(np.float64)
+    h = prob.apod()
+    from dataclasses import replace
+    To = model.travel_times(replace(prob, n_search=n_search, _cache={}), s.astype(np.float64))
+    assert np.array_equal(np.isfinite(T), h)
+    err = np.abs(T[h] - To[h]) / To[h]
+    gap = np.abs(T[h] - T_cont[h]) / T_cont[h]
+    print("n_search", n_search, "T max rel err vs oracle", err.max(),
+          "median rel gap to the continuous root", np.median(gap), flush=True)
+    assert err.max() < 1e-6
+    if n_search == 64:
+        assert np.median(gap) < 1e-6
 
 
 def test_adam_step_matches_oracle():

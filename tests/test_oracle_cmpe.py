@@ -89,3 +89,24 @@ def test_speckle_brightness_and_cf():
     assert np.all((cf >= 0) & (cf <= 1 + 1e-12))
     same = np.broadcast_to(bblk[:1, :1], bblk.shape).copy()
     assert np.allclose(cmpe.coherence_factor(same, M), 1.0)
+
+
+def test_cmcc_map_closed_forms():
+    """rho = 1 for pairs that differ by a complex factor, rho = |<u, v>| / (|u||v|)
+    for an explicit pair, pixels with no energy give 0 and the threshold plays no
+    part."""
+    rng = np.random.default_rng(5)
+    ns, n_pix, M = 4, 3, 9
+    u = rng.standard_normal((n_pix, M)) + 1j * rng.standard_normal((n_pix, M))
+    gains = rng.uniform(0.5, 2.0, (ns, ns, 1, 1)) * np.exp(1j * rng.uniform(-3, 3, (ns, ns, 1, 1)))
+    bsub = (gains * u[None, None]).reshape(ns, ns, n_pix * M)
+    assert np.allclose(cmpe.cmcc_map(bsub, M), 1.0)
+    # one explicit pair: ns = 2 has the single pair X = B_{0,1}, Y = B_{1,0}
+    x = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    y = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    b2 = np.zeros((2, 2, M), dtype=complex)
+    b2[0, 1], b2[1, 0] = x, y
+    exp = abs(np.sum(x * np.conj(y))) / (np.linalg.norm(x) * np.linalg.norm(y))
+    assert abs(cmpe.cmcc_map(b2, M)[0] - exp) < 1e-12
+    b2[1, 0] = 0.0
+    assert cmpe.cmcc_map(b2, M)[0] == 0.0

@@ -75,3 +75,82 @@ def test_brute_force_tiny():
     # the discretisation error (quadratic in the lens-point spacing)
     assert np.all(r["t_hom"] <= tb + 1e-13)
     assert np.max(tb - r["t_hom"]) < 1e-9
+
+
+def test_discrete_search_equal_speeds_is_straight_ray():
+    # the straight crossing is the last candidate, and the straight line is the fastest path
+    elem, pts = _setup(n=5, n_pts=20, seed=4)
+    for n in (2, 7, 64):
+        r = fermat.discrete_refract(elem, 0.9, 1.54, 1.54, pts, n)
+        d = np.hypot(pts[None, :, 0] - elem[:, None, 0], pts[None, :, 1] - elem[:, None, 1])
+        assert np.allclose(r["t_hom"], d / 1.54, rtol=1e-13, atol=0)
+
+
+def test_discrete_search_radial_closed_form():
+    elem, _ = _setup(n=5, d=0.9)
+    R = float(np.hypot(*elem[0]))
+    th = np.arctan2(elem[:, 0], elem[:, 1])
+    dd = 25.0
+    pts = np.stack([(R + 0.9 + dd) * np.sin(th), (R + 0.9 + dd) * np.cos(th)], 1)
+    r = fermat.discrete_refract(elem, 0.9, 0.9994, 1.54, pts, 16)
+    for a in range(5):
+        assert abs(r["t_hom"][a, a] - (0.9 / 0.9994 + dd / 1.54)) < 1e-12
+
+
+def _discrete_errors(c_lens, c_med, ns):
+    elem, pts = _setup(n=8, n_pts=60, seed=5)
+    rc = fermat.refract(elem, 0.9, c_lens, c_med, pts)
+    out = []
+    for n in ns:
+        rd = fermat.discrete_refract(elem, 0.9, c_lens, c_med, pts, n)
+        gap = rd["t_hom"] - rc["t_hom"]
+        # no lens point beats the exact stationary point (a minimum over the arc)
+        assert gap.min() > -1e-13
+        out.append(gap)
+    return out
+
+
+def test_discrete_search_converges_quadratically_to_the_root():
+    # slow lens (c_lens < c_med): candidates from the element's apex to the straight
+    # crossing; the error of a ray shrinks with the square of the candidate spacing
+    g16, g64 = _discrete_errors(0.9994, 1.54, (16, 64))
+    assert np.median(g64) < 1.3 * (15.0 / 63.0) ** 2 * np.median(g16)
+    assert np.median(g64) < 1e-5 and g64.max() < 5e-3
+
+
+def test_discrete_search_fast_lens_interval():
+    # fast lens (c_lens > c_med): candidates from the straight crossing to the point's angle
+    g16, g64 = _discrete_errors(2.2, 1.54, (16, 64))
+    assert np.median(g64) < 1.3 * (15.0 / 63.0) ** 2 * np.median(g16)
+
+
+def _crossing(e, p, rl):
+    """Where the segment e -> p leaves the circle of radius rl (bisection on t)."""
+    lo, hi = 0.0, 1.0
+    for _ in range(200):
+        m = 0.5 * (lo + hi)
+        if np.hypot(*(e + m * (p - e))) < rl:
+            lo = m
+        else:
+            hi = m
+    return e + 0.5 * (lo + hi) * (p - e)
+
+
+def test_discrete_search_two_candidates_are_the_interval_ends():
+    # slow lens: the candidates run from the lens apex above the element (lens leg
+    # = d_lens, radial) to the straight crossing; with two candidates the better end wins
+    elem, pts = _setup(n=6, n_pts=30, seed=6)
+    d, cl, cm = 0.9, 0.9994, 1.54
+    r2 = fermat.discrete_refract(elem, d, cl, cm, pts, 2)
+    r64 = fermat.discrete_refract(elem, d, cl, cm, pts, 64)
+    for a in range(elem.shape[0]):
+        e = elem[a]
+        rl = np.hypot(*e) + d
+        apex = e * rl / np.hypot(*e)
+        for p in range(pts.shape[0]):
+            q = pts[p]
+            t_apex = d / cl + np.hypot(*(q - apex)) / cm
+            x = _crossing(e, q, rl)
+            t_x = np.hypot(*(x - e)) / cl + np.hypot(*(q - x)) / cm
+            assert abs(r2["t_hom"][a, p] - min(t_apex, t_x)) < 1e-11
+            assert r64["t_hom"][a, p] <= min(t_apex, t_x) + 1e-11
