@@ -6,6 +6,10 @@ pitch is the arc length at the element radius.  The paper's simulated C5-2v
 array (Simulations subsection: 49.6 mm radius, 0.5872 degree angular pitch,
 508 um linear pitch) is consistent with that reading.  The lens outer surface
 is the concentric arc of radius ``R + d_lens``.
+
+A linear array (``radius = inf``) has its elements on the line z = 0 at
+x = (a - (N-1)/2) * pitch, and a flat lens: the layer 0 <= z <= d_lens, whose
+outer surface is the plane z = d_lens.
 """
 from __future__ import annotations
 
@@ -16,7 +20,13 @@ import numpy as np
 from .configs import ArrayCfg, ImgCfg, AcqCfg
 
 
+def is_linear(arr: ArrayCfg) -> bool:
+    return math.isinf(arr.radius)
+
+
 def lens_radius(arr: ArrayCfg) -> float:
+    if is_linear(arr):
+        raise ValueError("a linear array has a flat lens")
     return arr.radius + arr.d_lens
 
 
@@ -32,8 +42,16 @@ def element_polar_angles(arr: ArrayCfg) -> np.ndarray:
     return (a - (arr.n_elem - 1) / 2.0) * (arr.pitch / arr.radius)
 
 
+def element_x(arr: ArrayCfg) -> np.ndarray:
+    """Lateral positions of a linear array's elements."""
+    a = np.arange(arr.n_elem, dtype=np.float64)
+    return (a - (arr.n_elem - 1) / 2.0) * arr.pitch
+
+
 def element_positions(arr: ArrayCfg) -> np.ndarray:
     """[N][2] float64 element centres (x, z) in mm."""
+    if is_linear(arr):
+        return np.stack([element_x(arr), np.zeros(arr.n_elem)], axis=1)
     th = element_polar_angles(arr)
     return np.stack([arr.radius * np.sin(th), arr.radius * np.cos(th)], axis=1)
 
@@ -49,8 +67,13 @@ def pixel_centres(arr: ArrayCfg, img: ImgCfg, depth_scale: float = 1.0) -> np.nd
     Depth is measured below the lens surface; ``depth_scale`` stretches every
     depth by the same factor (the caller decides what the factor means).
     """
-    th0, th1 = element_span(arr)
     depth = np.linspace(img.depth_min, img.depth_max, img.n_depth) * depth_scale
+    if is_linear(arr):
+        xe = element_x(arr)
+        x = np.linspace(xe[0], xe[-1], img.n_angle)
+        X, Z = np.meshgrid(x, arr.d_lens + depth)
+        return np.stack([X.ravel(), Z.ravel()], axis=1)
+    th0, th1 = element_span(arr)
     ang = np.linspace(th0, th1, img.n_angle)
     rho = lens_radius(arr) + depth[:, None]
     x = rho * np.sin(ang)[None, :]
@@ -65,9 +88,17 @@ def patch_spacing(img: ImgCfg, acq: AcqCfg, c: float | None = None) -> float:
 
 
 def _cover(arr: ArrayCfg, centres: np.ndarray, spacing: float, margin: float):
-    """Axis-aligned box holding the lens arc over the imaged angles and every point."""
+    """Axis-aligned box holding the lens arc over the imaged angles and every point
+    (for a linear array: the lens plane over the element span and every point)."""
     pts_x = centres[:, 0]
     pts_z = centres[:, 1]
+    if is_linear(arr):
+        xe = element_x(arr)
+        x_lo = min(float(pts_x.min()) - spacing, float(xe[0]))
+        x_hi = max(float(pts_x.max()) + spacing, float(xe[-1]))
+        z_lo = min(arr.d_lens, float(pts_z.min()) - spacing)
+        z_hi = float(pts_z.max()) + spacing
+        return x_lo - margin, x_hi + margin, z_lo - margin, z_hi + margin
     th0, th1 = element_span(arr)
     ang_pts = np.arctan2(pts_x, pts_z)
     th_abs = max(abs(th0), abs(th1), float(np.max(np.abs(ang_pts))))

@@ -1,8 +1,9 @@
 """Seeded random media: sound-speed maps and scatterer lists.
 
 A medium is a set of concentric layers (radii measured from the centre of
-curvature, so every layer follows the lens surface), optional Gaussian speed
-blobs, optional anechoic cysts (no scatterers, same speed) and a list of point
+curvature, so every layer follows the lens surface) or, for a linear array,
+horizontal layers (bounded by depths z), optional Gaussian speed blobs,
+optional anechoic cysts (no scatterers, same speed) and a list of point
 scatterers with real amplitudes.  Speeds are in mm/us.
 """
 from __future__ import annotations
@@ -13,7 +14,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .configs import Config
-from .geometry import element_span, lens_radius
+from .geometry import element_span, element_x, is_linear, lens_radius
 
 
 @dataclass
@@ -27,6 +28,7 @@ class Medium:
     cyst_r: np.ndarray = field(default_factory=lambda: np.zeros(0))
     scat_xz: np.ndarray = field(default_factory=lambda: np.zeros((0, 2)))
     scat_amp: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    layer_axis: str = "radial"     # "radial": layer_r are radii; "depth": they are depths z
 
     @property
     def n_scat(self) -> int:
@@ -37,7 +39,7 @@ def sample_speed(med: Medium, x: np.ndarray, z: np.ndarray) -> np.ndarray:
     """Speed (mm/us) of ``med`` at points (x, z)."""
     x = np.asarray(x, dtype=np.float64)
     z = np.asarray(z, dtype=np.float64)
-    rho = np.hypot(x, z)
+    rho = np.hypot(x, z) if med.layer_axis == "radial" else z
     idx = np.searchsorted(med.layer_r, rho, side="right")
     c = med.layer_c[idx].astype(np.float64)
     for (bx, bz), sg, am in zip(med.blob_xz, med.blob_sigma, med.blob_amp):
@@ -71,10 +73,40 @@ def _polar(rho, th):
     return np.array([rho * math.sin(th), rho * math.cos(th)])
 
 
+def _linear_medium(cfg: Config, rng) -> Medium:
+    """Bi-layer phantom under a linear array: a layer at 1575 m/s (the paper's chicken
+    breast) of thickness U(6, 12) mm on the lens over a phantom at 1490, 1516 or
+    1540 m/s, one anechoic cyst, nine point targets and random scatterers."""
+    arr, img = cfg.array, cfg.img
+    xe = element_x(arr)
+    x0, x1 = float(xe[0]), float(xe[-1])
+    z_lo, z_hi = arr.d_lens + img.depth_min, arr.d_lens + img.depth_max
+    top = arr.d_lens + rng.uniform(6.0, 12.0)
+    layer_r = np.array([top])
+    layer_c = np.array([1.575, float(rng.choice([1.490, 1.516, 1.540]))])
+    span = x1 - x0
+    cyst_xz = np.array([[x0 + rng.uniform(0.35, 0.65) * span,
+                         rng.uniform(top + 6.0, max(top + 7.0, z_hi - 8.0))]])
+    cyst_r = np.array([rng.uniform(2.0, 3.5)])
+    area = (x1 - x0) * (z_hi - z_lo)
+    n_rand = cfg.n_scat_random if cfg.n_scat_random > 0 else int(round(cfg.scat_density * area))
+    rand_xz = np.stack([rng.uniform(x0, x1, n_rand), rng.uniform(z_lo, z_hi, n_rand)], axis=1)
+    rand_amp = rng.standard_normal(n_rand)
+    dep = (z_lo + 0.25 * (z_hi - z_lo), z_lo + 0.5 * (z_hi - z_lo), z_lo + 0.75 * (z_hi - z_lo))
+    tg = np.array([[x0 + f * span, d] for d in dep for f in (0.25, 0.5, 0.75)])
+    scat_xz = np.concatenate([tg, rand_xz])
+    scat_amp = np.concatenate([np.full(9, 10.0), rand_amp])
+    scat_xz, scat_amp = _drop_in_cysts(scat_xz, scat_amp, cyst_xz, cyst_r)
+    return Medium(layer_r=layer_r, layer_c=layer_c, cyst_xz=cyst_xz, cyst_r=cyst_r,
+                  scat_xz=scat_xz, scat_amp=scat_amp, layer_axis="depth")
+
+
 def medium_for(cfg: Config, seed: int | None = None) -> Medium:
     """Draw the medium named by ``cfg.medium`` from ``seed`` (default ``cfg.seed``)."""
     seed = cfg.seed if seed is None else seed
     rng = np.random.Generator(np.random.PCG64(seed))
+    if cfg.medium == "linear_bilayer":
+        return _linear_medium(cfg, rng)
     arr, img = cfg.array, cfg.img
     rl = lens_radius(arr)
     th0, th1 = element_span(arr)

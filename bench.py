@@ -140,16 +140,21 @@ def plain_loop_report():
 
     def image_quality(s):
         bf.set_imaging(base)
-        img, _, _ = bf.beamform(iq, s=s, maps=False)
+        img, maps, _ = bf.beamform(iq, s=s)
         env = img.abs().view(npx, M)[:, M // 2].cpu().numpy()
         q = metrics.contrast_cnr(env, base.centres, med.cyst_xz[0], float(med.cyst_r[0]))
-        return q, env.reshape(cfg.img.n_depth, cfg.img.n_angle)
+        mp = maps.view(3, -1).cpu().numpy()
+        g = {"speckle_brightness": float((img.abs() ** 2).mean().item()),
+             "coherence_factor": float(mp[1].mean()), "cmcc": float(mp[2].mean()),
+             "cmpe_map_mean": float(mp[0].mean()),
+             "lag_one_coherence": float(bf.lag_one_coherence(iq).mean().item())}
+        return q, g, env.reshape(cfg.img.n_depth, cfg.img.n_angle)
 
     s_hom = torch.full(bf.grid.shape, 1.0 / cfg.img.c_ref, device=bf.device)
-    q0, env0 = image_quality(s_hom)
+    q0, g0, env0 = image_quality(s_hom)
     torch.cuda.synchronize()
     s, cm, times, t_sweep, best = warmstart.run_plain(bf, iq, cfg, cfg.method.n_iter)
-    q1, env1 = image_quality(s)
+    q1, g1, env1 = image_quality(s)
     e_hom = metrics.speed_errors(s_hom.cpu().numpy(), c_true)
     e_swp = metrics.speed_errors(np.full(bf.grid.shape, 1.0 / best), c_true)
     e_fin = metrics.speed_errors(s.cpu().numpy(), c_true)
@@ -162,6 +167,10 @@ def plain_loop_report():
                         "final": e_fin["mae_mps"]},
             "cyst_contrast_db": {"homogeneous_1540": q0["contrast_db"], "final": q1["contrast_db"]},
             "cyst_cnr": {"homogeneous_1540": q0["cnr"], "final": q1["cnr"]},
+            "cyst_gcnr": {"homogeneous_1540": q0["gcnr"], "final": q1["gcnr"]},
+            "global_metrics": {"homogeneous_1540": g0, "final": g1,
+                               "change_pct": {k: 100.0 * (g1[k] / g0[k] - 1.0) for k in g0
+                                              if g0[k] != 0}},
             "tenengrad_change_pct": metrics.tenengrad_change(env0, env1, depth)}
 
 
@@ -183,6 +192,80 @@ def lens_model_report():
         out[model] = {"sweep_best_speed": best, "sweep_mae_mps": e_sweep["mae_mps"],
                       "final_mae_mps": e["mae_mps"], "final_rmse_mps": e["rmse_mps"],
                       "cmpe_final": cm[-1]}
+    return out
+
+
+def grid_init_report(seeds=range(9000, 9008)):
+    """Model initialisation on the static grid (laid out once for 1500 m/s) against
+    the dynamic grid (moved with every swept speed): the speed each selects against
+    the mean true speed of the grid nodes, on held-out random two-layer media of
+    the tiny array and on the clinical medium, and how often a choice falls on an
+    end of the sweep range.  The sweep curves of the clinical medium are kept."""
+    import afsynth
+    from paper_2608_06853_amd import autofocus as af, workloads
+    speeds = af.sweep_speeds()
+    ends = (float(speeds[0]), float(speeds[-1]))
+    rows, curves = [], {}
+    cases = [(afsynth.configs.C4, int(sd)) for sd in seeds] + [(afsynth.configs.C2, None)]
+    for cfg, sd in cases:
+        bf, iq, med = workloads.build(cfg, seed=sd)
+        base = bf.img
+        lp = workloads.loss_params(cfg)
+        c_true = float(workloads.true_speed_nodes(cfg, med, bf.grid).mean())
+        row = {"config": cfg.name, "seed": sd, "c_mean_true": round(c_true, 5)}
+        for mode in ("dynamic", "static"):
+            bf.set_imaging(base, keep_slowness=False)
+            _, vals, best = af.sweep(bf, iq, lp, cfg.acq.fc, dynamic=(mode == "dynamic"))
+            row[f"{mode}_best"] = best
+            row[f"{mode}_err_mps"] = round(1000.0 * abs(best - c_true), 2)
+            row[f"{mode}_at_range_end"] = best in ends
+            if sd is None:
+                curves[mode] = [round(float(v), 5) for v in vals]
+        rows.append(row)
+        del bf, iq
+    summ = {}
+    for mode in ("dynamic", "static"):
+        summ[f"{mode}_mean_err_mps"] = round(float(np.mean([r[f"{mode}_err_mps"] for r in rows])), 2)
+        summ[f"{mode}_range_end_picks"] = int(sum(r[f"{mode}_at_range_end"] for r in rows))
+    return {"summary": summ, "media": rows, "speeds": [round(float(c), 3) for c in speeds],
+            "clinical_curves": curves}
+
+
+def refraction_search_report(ns=(8, 32, 128), reps: int = 5):
+    """The discrete N_search refraction search against the continuous root on the
+    clinical geometry: deviation of the travel times, of the loss, and the time of
+    one loss_and_grad."""
+    import torch
+    import afsynth
+    from paper_2608_06853_amd import _lib, workloads
+    cfg = afsynth.configs.C2
+    bf, iq, med = workloads.build(cfg)
+    lp = workloads.loss_params(cfg)
+    terms = bf.empty_terms()
+    grad = torch.empty(bf.grid.shape, device=bf.device)
+
+    def run(n):
+        bf.ctx.set_refraction_search(n)
+        bf.ctx.loss_and_grad(iq, lp, terms, grad)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            bf.ctx.loss_and_grad(iq, lp, terms, grad)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        return ms, float(terms[_lib.TERM_CMPE].item()), bf.travel_times()
+
+    ms0, cm0, T0 = run(0)
+    ok = torch.isfinite(T0)
+    out = {"continuous": {"ms_per_loss_and_grad": round(ms0, 3), "cmpe": cm0}}
+    for n in ns:
+        ms, cm, T = run(n)
+        rel = ((T - T0).abs() / T0)[ok]
+        out[f"n_search_{n}"] = {"ms_per_loss_and_grad": round(ms, 3), "cmpe": cm,
+                                "T_rel_dev_median": float(rel.median().item()),
+                                "T_rel_dev_max": float(rel.max().item())}
+        del T, rel
+    bf.ctx.set_refraction_search(0)
     return out
 
 
@@ -303,9 +386,12 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_autofocus:
         t0 = time.perf_counter()
-        out["plain_loop"] = plain_loop_report()
-        out["lens_models"] = lens_model_report()
-        out["s_to_target"] = s_to_target_report()
+        for key, fn in (("plain_loop", plain_loop_report), ("lens_models", lens_model_report),
+                        ("grid_init", grid_init_report),
+                        ("refraction_search", refraction_search_report),
+                        ("s_to_target", s_to_target_report)):
+            print(f"report {key}", file=sys.stderr, flush=True)
+            out[key] = fn()
         out["autofocus_report_seconds"] = round(time.perf_counter() - t0, 1)
     if args.cpu_pixels > 0:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_pixels)

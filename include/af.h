@@ -135,6 +135,25 @@ af_status af_set_slowness(af_ctx* ctx, int nx, int nz, double x0, double z0, dou
 af_status af_beamform(af_ctx* ctx, const af_complex* iq_dev, af_complex* blk_dev,
                 af_complex* img_dev, float* maps_dev);
 
+/* Receive-channel images (Eq. 5 with the transmit aperture the whole array and
+ * the receive aperture one element): x_dev[r][p] = sum_t h_t h_r
+ * Psi_{t,r}(tau) exp(j 2 pi f_d tau), complex64 [n_elem][n_points] in caller
+ * point order, device memory owned by the caller, at the current slowness.  The
+ * focused per-channel signals of the coherence metrics of the Model Evaluation
+ * subsection.  The library keeps an internal buffer of n_elem x points x 8 bytes
+ * from the first call on.
+ * Errors: AF_ERR_STATE before geometry, lens and slowness; AF_ERR_ARG for null
+ * pointers; AF_ERR_OOM if the buffer cannot be allocated. */
+af_status af_channel_images(af_ctx* ctx, const af_complex* iq_dev, af_complex* x_dev);
+
+/* Lag-one coherence of every pixel (global image-quality metric of the Model
+ * Evaluation subsection): over the pixel's patch points m and every pair of
+ * adjacent receive elements (r, r+1) whose channel images both have energy
+ * E = sum_m |x|^2 > 1e-30, the mean of Re(sum_m x_r conj(x_{r+1})) / sqrt(E_r
+ * E_{r+1}); 0 if no pair qualifies.  loc_dev: float32 [n_pix] (device, caller
+ * pixel order).  Same state, buffer and errors as af_channel_images. */
+af_status af_lag_one_coherence(af_ctx* ctx, const af_complex* iq_dev, float* loc_dev);
+
 /* Loss (Eq. 12, CMPE + regularisers - speckle term) and, if grad_dev != NULL,
  * its gradient dL/ds [nz][nx] (device, overwritten).  terms_dev: float[8]
  * (device), see AF_TERM_*.  Refraction points, c_med, apodisation and validity

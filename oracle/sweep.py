@@ -11,6 +11,10 @@ c_ref = 1.540 mm/us, and at speed c_g every pixel's depth below the lens
 surface is scaled by c_g/c_ref along its polar angle while the kernel spacing
 becomes c_g/(2 f_c).  For radial rays through the concentric lens this keeps
 the round-trip time exactly fixed.
+
+The static grid of the earlier method (the comparison of the model-initialisation
+results) is laid out once for 1500 m/s: every speed of the sweep is evaluated on
+the pixels and kernel spacing of c_g = 1.500 mm/us.
 """
 from __future__ import annotations
 
@@ -34,7 +38,7 @@ def scaled_centres(centres: np.ndarray, elem_xz: np.ndarray, d_lens: float, c_g:
 
 
 def sweep(prob: Problem, lp: LossParams, fc: float, c_ref: float = 1.540,
-          speeds: np.ndarray | None = None, dynamic: bool = True):
+          speeds: np.ndarray | None = None, dynamic: bool = True, static_c: float = 1.500):
     """CMPE for each homogeneous speed.  Returns (speeds, cmpe values, best speed)."""
     speeds = sweep_speeds() if speeds is None else speeds
     x0, z0, dx, dz, nx, nz = prob.grid
@@ -44,7 +48,8 @@ def sweep(prob: Problem, lp: LossParams, fc: float, c_ref: float = 1.540,
             cen = scaled_centres(prob.centres, prob.elem_xz, prob.d_lens, c_g, c_ref)
             sp = c_g / (2.0 * fc)
         else:
-            cen, sp = prob.centres, prob.spacing
+            cen = scaled_centres(prob.centres, prob.elem_xz, prob.d_lens, static_c, c_ref)
+            sp = static_c / (2.0 * fc)
         p = Problem(**{**prob.__dict__, "centres": cen, "spacing": sp, "_cache": {}})
         s = np.full((nz, nx), 1.0 / c_g)
         vals.append(forward(p, s, lp)["cmpe"])

@@ -59,6 +59,8 @@ _sig = {
     "af_set_refraction_search": (C.c_int, [_vp, _i]),
     "af_set_slowness": (C.c_int, [_vp, _i, _i, _d, _d, _d, _d, _vp]),
     "af_beamform": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "af_channel_images": (C.c_int, [_vp, _vp, _vp]),
+    "af_lag_one_coherence": (C.c_int, [_vp, _vp, _vp]),
     "af_loss_and_grad": (C.c_int, [_vp, _vp, C.POINTER(LossParams), _vp, _vp]),
     "af_forward": (C.c_int, [_vp, _vp, C.POINTER(LossParams), _vp, _vp]),
     "af_backward": (C.c_int, [_vp, _vp, C.POINTER(LossParams), _vp, _vp]),
@@ -192,6 +194,17 @@ class Context:
                                    _dev(blk, torch.complex64, nb * nb * P, "blk"),
                                    _dev(img, torch.complex64, P, "img"),
                                    _dev(maps, torch.float32, 3 * self.n_pix, "maps")))
+
+    def channel_images(self, iq, out):
+        import torch
+        P = self.n_pix * self.patch ** 2
+        self._chk(_lib.af_channel_images(self._h, self._iq(iq),
+                                         _dev(out, torch.complex64, self.n_elem * P, "out")))
+
+    def lag_one_coherence(self, iq, out):
+        import torch
+        self._chk(_lib.af_lag_one_coherence(self._h, self._iq(iq),
+                                            _dev(out, torch.float32, self.n_pix, "out")))
 
     def loss_and_grad(self, iq, lp: LossParams, terms, grad=None):
         import torch

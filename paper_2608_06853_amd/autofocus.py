@@ -151,6 +151,23 @@ class Beamformer:
         self.ctx.beamform(iq, blk, img, mp)
         return img, mp, blk
 
+    def channel_images(self, iq, s=None):
+        """Receive-channel images [n_elem][points] (complex64) at the slowness."""
+        if s is not None:
+            self.set_slowness(s)
+        n = self.acq.elem_xz.shape[0]
+        out = torch.empty(n * self.n_points, device=self.device, dtype=torch.complex64)
+        self.ctx.channel_images(iq, out)
+        return out.view(n, self.n_points)
+
+    def lag_one_coherence(self, iq, s=None):
+        """Per-pixel lag-one coherence [n_pix] at the slowness."""
+        if s is not None:
+            self.set_slowness(s)
+        out = torch.empty(self.img.centres.shape[0], device=self.device)
+        self.ctx.lag_one_coherence(iq, out)
+        return out
+
     def travel_times(self, s=None):
         if s is not None:
             self.set_slowness(s)
@@ -196,22 +213,30 @@ def sweep_speeds(lo=1.340, hi=1.740, step=0.010) -> np.ndarray:
     return lo + step * np.arange(n)
 
 
-def sweep(bf: Beamformer, iq, lp, fc: float, c_ref: float = 1.540, speeds=None, dynamic=True):
-    """CMPE of homogeneous speeds over the (dynamic) grid.  Leaves ``bf`` on the grid
-    of the best speed with a uniform slowness.  Returns (speeds, values, best)."""
+def sweep(bf: Beamformer, iq, lp, fc: float, c_ref: float = 1.540, speeds=None, dynamic=True,
+          static_c: float = 1.500):
+    """CMPE of homogeneous speeds (Section II-C, model initialisation).  With
+    ``dynamic`` every speed c_g is evaluated on the grid laid out for c_g; without,
+    every speed is evaluated on the one grid laid out for ``static_c`` (the static
+    grid the dynamic one replaces).  Leaves ``bf`` on the grid of the best speed
+    (dynamic) or the static grid, with a uniform slowness.  Returns
+    (speeds, values, best)."""
     speeds = sweep_speeds() if speeds is None else np.asarray(speeds)
-    base = bf.img
-    dyn = DynamicGrid(base, bf.acq, c_ref, fc)
+    dyn = DynamicGrid(bf.img, bf.acq, c_ref, fc)
+    static = None if dynamic else dyn.at(static_c)
     terms = bf.empty_terms()
     vals = torch.empty(len(speeds), device=bf.device)
+    if static is not None:
+        bf.set_imaging(static, keep_slowness=False)
     for k, c_g in enumerate(speeds):
-        bf.set_imaging(dyn.at(float(c_g)) if dynamic else base, keep_slowness=False)
+        if static is None:
+            bf.set_imaging(dyn.at(float(c_g)), keep_slowness=False)
         bf.set_slowness(torch.full(bf.grid.shape, 1.0 / float(c_g), device=bf.device))
         bf.ctx.loss_and_grad(iq, lp, terms, None)
         vals[k] = terms[_lib.TERM_CMPE]
     vals = vals.cpu().numpy().astype(np.float64)
     best = float(speeds[int(np.argmin(vals))])
-    bf.set_imaging(dyn.at(best) if dynamic else base, keep_slowness=False)
+    bf.set_imaging(dyn.at(best) if static is None else static, keep_slowness=False)
     bf.set_slowness(torch.full(bf.grid.shape, 1.0 / best, device=bf.device))
     return speeds, vals, best
 

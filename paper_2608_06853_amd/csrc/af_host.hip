@@ -692,6 +692,33 @@ af_status af_beamform(af_ctx* c, const af_complex* iq, af_complex* blk, af_compl
   return AF_OK;
 }
 
+static af_status channel_images(af_ctx* c, const af_complex* iq) {
+  af_status st = ready(c, iq);
+  if (st != AF_OK) return st;
+  if ((st = run_tables(c, nullptr)) != AF_OK) return st;
+  AF_ALLOC(c->d_chan, sizeof(float2) * (size_t)c->N * c->P_int, "channel images");
+  AF_HIP(af::launch_channel_images(c, reinterpret_cast<const float2*>(iq), c->d_chan.as<float2>()),
+         "channel images");
+  return AF_OK;
+}
+
+af_status af_channel_images(af_ctx* c, const af_complex* iq, af_complex* x) {
+  if (c && !x) return fail(c, AF_ERR_ARG, "af_channel_images: null output");
+  af_status st = channel_images(c, iq);
+  if (st != AF_OK) return st;
+  AF_HIP(af::launch_export_rx(c, c->d_chan.as<float2>(), reinterpret_cast<float2*>(x)),
+         "export channel images");
+  return AF_OK;
+}
+
+af_status af_lag_one_coherence(af_ctx* c, const af_complex* iq, float* loc) {
+  if (c && !loc) return fail(c, AF_ERR_ARG, "af_lag_one_coherence: null output");
+  af_status st = channel_images(c, iq);
+  if (st != AF_OK) return st;
+  AF_HIP(af::launch_loc(c, c->d_chan.as<float2>(), loc), "lag-one coherence");
+  return AF_OK;
+}
+
 af_status af_loss_and_grad(af_ctx* c, const af_complex* iq, const af_loss_params* lp, float* terms,
                            float* grad) {
   af_status st = ready(c, iq);

@@ -149,6 +149,7 @@ struct af_ctx {
   af::DBuf d_elem, d_ptpol, d_ptxy, d_prange, d_tiles, d_tabwork, d_daswork, d_order, d_i2c,
       d_c2i;
   af::DBuf d_cnn_part;
+  af::DBuf d_chan;  // receive-channel images, allocated by the coherence calls only
   af::DBuf d_s, d_gdev, d_regg, d_scal, d_tab, d_bblk, d_g, d_gT, d_gsb, d_part, d_gpad, d_gpart,
       d_grad, d_terms, d_maps, d_img;
 
@@ -191,6 +192,11 @@ hipError_t launch_finalize(af_ctx* c, const af_loss_params* lp, float* terms);
 hipError_t launch_gscale(af_ctx* c, float2* gblk);
 // scaled = false: gblk still lacks its final scale, which the adjoint applies
 hipError_t launch_das_adj(af_ctx* c, const float2* iq, const float2* gblk, bool scaled);
+// receive-channel images X[N][P_int] (internal order), their caller-order export,
+// and the per-pixel lag-one coherence from them
+hipError_t launch_channel_images(af_ctx* c, const float2* iq, float2* X);
+hipError_t launch_export_rx(af_ctx* c, const float2* X, float2* out);
+hipError_t launch_loc(af_ctx* c, const float2* X, float* loc);
 hipError_t launch_path_adj(af_ctx* c);
 hipError_t launch_grad_fold(af_ctx* c, float* grad);
 hipError_t launch_adam(af_ctx* c, const af_adam_params* ap, int step, float* s, float* m,

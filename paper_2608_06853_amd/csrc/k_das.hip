@@ -271,6 +271,119 @@ __global__ __launch_bounds__(256, 4) void k_das_adj(DasArgs A) {
   }
 }
 
+// Receive-channel images X_r(p) = h_r E_r sum_t h_t E_t Psi_{t,r}(u_t + u_r): Eq. 5
+// with the transmit aperture the whole array and the receive aperture one element
+// (the focused per-channel signals of the coherence metrics).  Same work split
+// as k_das_fwd; each lane keeps one accumulator per receive element of its block
+// and applies the receive phasor once at the end.
+template <int S>
+__global__ __launch_bounds__(256) void k_das_rx(DasArgs A, float2* __restrict__ X) {
+  const Geo& g = A.g;
+  const int2 w = A.work[blockIdx.x];
+  const int tile = w.x, jb = w.y;
+  if (tile < 0) return;  // padding item of a shorter XCD queue
+  const int4 tr = A.tiles[tile];
+  const long long P = g.P;
+  const long long p = (long long)tile * TILE + threadIdx.x;
+  const int N = g.n_elem, ns = g.ns;
+
+  Rx rx[S];
+  int rmin = 0, rmax = 0;
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    rx[k] = load_rx(A.tab, P, p, jb * S + k, tr.x, tr.y);
+    rmin = min(rmin, rx[k].ui);
+    rmax = max(rmax, rx[k].ui);
+  }
+  const WaveRange wr = wave_range(A.prange, p, tr, jb, S);
+  const int tlo = wr.rx_active ? wr.lo : tr.y + 1, thi = wr.rx_active ? wr.hi : tr.x - 1;
+  float2 acc[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) acc[k] = make_float2(0.f, 0.f);
+  for (int t = tlo; t <= thi; ++t) {
+    const TabEntry et = A.tab[(long long)t * P + p];
+    const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
+    float2 a0[S], a1[S];
+    float fr[S];
+    bool ok[S];
+    const bool check = !interior(et, rmin, rmax, ns);
+    if (check) gather<S, true>(base, ns, et, rx, a0, a1, fr, ok);
+    else gather<S, false>(base, ns, et, rx, a0, a1, fr, ok);
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      float vx = fmaf(fr[k], a1[k].x - a0[k].x, a0[k].x);
+      float vy = fmaf(fr[k], a1[k].y - a0[k].y, a0[k].y);
+      if (check) {
+        vx = ok[k] ? vx : 0.f;
+        vy = ok[k] ? vy : 0.f;
+      }
+      acc[k].x = fmaf(vx, et.er, fmaf(-vy, et.ei, acc[k].x));
+      acc[k].y = fmaf(vx, et.ei, fmaf(vy, et.er, acc[k].y));
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const float2 e = rx[k].e;
+    X[(long long)(jb * S + k) * P + p] =
+        make_float2(acc[k].x * e.x - acc[k].y * e.y, acc[k].x * e.y + acc[k].y * e.x);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero2(float2* __restrict__ x, long long n) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    x[i] = make_float2(0.f, 0.f);
+}
+
+// Internal -> caller point order of the channel images, one row per element.
+__global__ __launch_bounds__(256) void k_export_rx(long long P, long long Pc,
+                                                   const int* __restrict__ c2i,
+                                                   const float2* __restrict__ X,
+                                                   float2* __restrict__ out) {
+  const long long pc = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (pc >= Pc) return;
+  const long long r = blockIdx.y;
+  out[r * Pc + pc] = X[r * P + c2i[pc]];
+}
+
+// Lag-one coherence of pixel q over its M <= 9 patch points: the mean over
+// adjacent receive elements (r, r+1) with energy of
+// Re(sum_m X_r conj X_{r+1}) / sqrt(E_r E_{r+1}), E_r = sum_m |X_r|^2; 0 if none.
+constexpr float LOC_MIN_ENERGY = 1e-30f;
+__global__ __launch_bounds__(256) void k_loc(int N, long long P, int M, int n_pix,
+                                             const int* __restrict__ c2i,
+                                             const float2* __restrict__ X,
+                                             float* __restrict__ loc) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= n_pix) return;
+  long long pi[9];
+  float2 xp[9];
+  float ep = 0.f;
+#pragma unroll
+  for (int m = 0; m < 9; ++m) {
+    pi[m] = m < M ? (long long)c2i[(long long)q * M + m] : 0;
+    xp[m] = m < M ? X[pi[m]] : make_float2(0.f, 0.f);
+    ep = fmaf(xp[m].x, xp[m].x, fmaf(xp[m].y, xp[m].y, ep));
+  }
+  float sum = 0.f;
+  int n = 0;
+  for (int r = 1; r < N; ++r) {
+    float ec = 0.f, cr = 0.f;
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+      const float2 xc = m < M ? X[(long long)r * P + pi[m]] : make_float2(0.f, 0.f);
+      ec = fmaf(xc.x, xc.x, fmaf(xc.y, xc.y, ec));
+      cr = fmaf(xp[m].x, xc.x, fmaf(xp[m].y, xc.y, cr));
+      xp[m] = xc;
+    }
+    if (ep > LOC_MIN_ENERGY && ec > LOC_MIN_ENERGY) {
+      sum += cr / (sqrtf(ep) * sqrtf(ec));
+      ++n;
+    }
+    ep = ec;
+  }
+  loc[q] = n > 0 ? sum / (float)n : 0.f;
+}
+
 // Zero the transmit-role sums over the active elements of every tile.
 __global__ __launch_bounds__(256) void k_zero_tx(Geo g, const int4* __restrict__ tiles,
                                                  float* __restrict__ gT2) {
@@ -321,6 +434,42 @@ hipError_t launch_das_fwd(af_ctx* c, const float2* iq, float2* bblk) {
     case 16: return das_fwd_s<16>(c, A);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int S>
+hipError_t das_rx_s(af_ctx* c, const DasArgs& A, float2* X) {
+  hipLaunchKernelGGL(k_das_rx<S>, dim3(c->n_das_work), dim3(256), 0, c->stream, A, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_channel_images(af_ctx* c, const float2* iq, float2* X) {
+  const long long n = (long long)c->N * c->P_int;
+  const unsigned nblk = (unsigned)std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_fill_zero2, dim3(std::max(nblk, 1u)), dim3(256), 0, c->stream, X, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || c->n_das_work == 0) return e;
+  DasArgs A = das_args(c, iq);
+  switch (c->S) {
+    case 1: return das_rx_s<1>(c, A, X);
+    case 2: return das_rx_s<2>(c, A, X);
+    case 4: return das_rx_s<4>(c, A, X);
+    case 8: return das_rx_s<8>(c, A, X);
+    case 16: return das_rx_s<16>(c, A, X);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_export_rx(af_ctx* c, const float2* X, float2* out) {
+  const long long Pc = c->P;
+  hipLaunchKernelGGL(k_export_rx, dim3((unsigned)((Pc + 255) / 256), (unsigned)c->N), dim3(256), 0,
+                     c->stream, (long long)c->P_int, Pc, c->d_c2i.as<int>(), X, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_loc(af_ctx* c, const float2* X, float* loc) {
+  hipLaunchKernelGGL(k_loc, dim3((unsigned)((c->n_pix + 255) / 256)), dim3(256), 0, c->stream, c->N,
+                     (long long)c->P_int, c->M, c->n_pix, c->d_c2i.as<int>(), X, loc);
+  return hipGetLastError();
 }
 
 hipError_t launch_das_adj(af_ctx* c, const float2* iq, const float2* gblk, bool scaled) {

@@ -51,7 +51,8 @@ def test_five_adam_steps_tiny_config():
     assert dev < 1e-2
 
 
-def test_dynamic_grid_sweep_matches_oracle():
+@pytest.mark.parametrize("dynamic", [True, False])
+def test_dynamic_grid_sweep_matches_oracle(dynamic):
     import torch
     from paper_2608_06853_amd import autofocus as af
     cfg = G.C1_SMALL
@@ -60,11 +61,11 @@ def test_dynamic_grid_sweep_matches_oracle():
     speeds = np.array([1.46, 1.49, 1.52, 1.55, 1.58])
     prob = problems.problem(cfg, iq.astype(np.complex128), depth_scale_max=1.60 / 1.54)
     lp = problems.loss_params(cfg)
-    _, vo, best_o = osweep.sweep(prob, lp, cfg.acq.fc, speeds=speeds)
+    _, vo, best_o = osweep.sweep(prob, lp, cfg.acq.fc, speeds=speeds, dynamic=dynamic)
     bf = G.beamformer(cfg, prob)
     _, vg, best_g = af.sweep(bf, torch.from_numpy(iq).cuda(), G.lib_params(lp), cfg.acq.fc,
-                             speeds=speeds)
-    print("oracle", vo, "gpu", vg, flush=True)
+                             speeds=speeds, dynamic=dynamic)
+    print("dynamic" if dynamic else "static", "oracle", vo, "gpu", vg, flush=True)
     assert np.max(np.abs(vg - vo) / vo) < 2e-3
     assert best_g == best_o
 

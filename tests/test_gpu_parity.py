@@ -6,6 +6,7 @@ import pytest
 
 import gpu_setup as G
 from oracle import cmpe as ocmpe
+from oracle import coherence as ocoh
 from oracle import das as odas
 from oracle import model
 
@@ -154,6 +155,23 @@ def test_discrete_refraction_search_travel_times(n_search):
     assert err.max() < 1e-6
     if n_search == 64:
         assert np.median(gap) < 1e-6
+
+
+@pytest.mark.parametrize("key", [CASES[0], CASES[1], CASES[3], CASES[4]])
+def test_channel_images_and_lag_one_coherence(key):
+    """Receive-channel images element by element and the per-pixel lag-one
+    coherence against the oracle."""
+    cfg, prob, iq, s, lp, bf, iq_d, s_d = _setup(key)
+    print("case", key, flush=True)
+    X = bf.channel_images(iq_d).cpu().numpy()
+    loc = bf.lag_one_coherence(iq_d).cpu().numpy()
+    Xo = ocoh.channel_images(prob, s.astype(np.float64))
+    loco = ocoh.lag_one_coherence(Xo, prob.n_patch)
+    e_x = G.rel(X, Xo)
+    e_l = float(np.abs(loc - loco).max())
+    print("channel images rel", e_x, "LOC max abs err", e_l, "mean LOC", loco.mean(), flush=True)
+    assert np.array_equal(X == 0, Xo == 0)
+    assert e_x < 1e-4 and e_l < 1e-4
 
 
 def test_adam_step_matches_oracle():

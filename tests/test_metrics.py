@@ -40,3 +40,18 @@ def test_contrast_cnr_of_an_empty_disc():
     env[r < 3.0] *= 0.01
     q = metrics.contrast_cnr(env, xz, (0.0, 0.0), 3.0)
     assert q["contrast_db"] < -30.0 and q["cnr"] > 0.5
+
+
+def test_gcnr_limits():
+    rng = np.random.default_rng(2)
+    a = rng.rayleigh(1.0, 50000)
+    assert metrics.gcnr(a, a) == 0.0
+    assert metrics.gcnr(a, a + 100.0) == 1.0                  # disjoint supports
+    b = rng.rayleigh(1.0, 50000)
+    assert metrics.gcnr(a, b) < 0.05                           # same distribution
+    # two unit-variance Gaussians d apart overlap by 2 Phi(-d/2): gCNR = 1 - that
+    from math import erf, sqrt
+    x = rng.standard_normal(400000)
+    y = rng.standard_normal(400000) + 2.0
+    ov = 1.0 + erf(-1.0 / sqrt(2.0))
+    assert abs(metrics.gcnr(x, y) - (1.0 - ov)) < 0.02

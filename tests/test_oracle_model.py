@@ -68,6 +68,18 @@ def test_sweep_minimum_at_true_speed(c_true):
     assert abs(best - c_true) <= 0.010 + 1e-9
 
 
+def test_static_grid_is_the_dynamic_grid_of_its_own_speed(small_problem):
+    # the static grid is laid out once for 1500 m/s: at that speed both sweeps see the
+    # same pixels and kernel spacing, at any other speed the static one does not move
+    prob, _ = small_problem
+    lp = problems.loss_params(SMALL)
+    speeds = np.array([1.47, 1.50])
+    _, vd, _ = sweep.sweep(prob, lp, SMALL.acq.fc, speeds=speeds)
+    _, vs, _ = sweep.sweep(prob, lp, SMALL.acq.fc, speeds=speeds, dynamic=False)
+    assert vd[1] == vs[1]
+    assert vd[0] != vs[0]
+
+
 def test_adam_matches_torch():
     torch = pytest.importorskip("torch")
     rng = np.random.default_rng(1)
