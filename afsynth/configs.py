@@ -11,13 +11,14 @@ ones (0.05, the in-vivo value read in these units, diverges).
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field, replace
 
 
 @dataclass(frozen=True)
 class ArrayCfg:
     n_elem: int          # number of elements (= transmits = receives, FSA)
-    radius: float        # mm, radius of curvature of the element arc
+    radius: float        # mm, radius of curvature of the element arc (inf: linear array)
     pitch: float         # mm, arc length between neighbouring elements
     d_lens: float        # mm, lens thickness (elements sit this far behind the lens arc)
     c_lens: float        # mm/us, lens sound speed
@@ -135,11 +136,38 @@ MICRO = Config(
     medium="c1_two_layer", seed=7, n_scat_random=300,
 )
 
-CONFIGS = [C1, C2, C3, C4, C5]
+# Linear array with a flat lens: the paper's L12-3v (0.2 mm pitch, Table I lens
+# 1049.4 m/s, 0.67 mm, t_ttp 578.3 ns; 128 captured elements, 7.35 MHz) and its
+# phantom hyperparameters (Table II: F 0.75, 32 segments, w1 7, no second-order
+# term), on a bi-layer phantom (1575 m/s layer over 1490/1516/1540 m/s), imaged
+# to 25 mm (deeper pixels see all 16 blocks, one more than the CMPE stage holds).
+L1 = Config(
+    name="l1_linear",
+    array=ArrayCfg(n_elem=128, radius=math.inf, pitch=0.2, d_lens=0.67, c_lens=1.0494,
+                   t_ttp=0.5783),
+    acq=AcqCfg(fc=7.35, fs=29.4, n_samples=1536),
+    img=ImgCfg(n_depth=128, n_angle=128, depth_min=2.0, depth_max=25.0),
+    method=MethodCfg(block=8, fnum=0.75, n_seg=32, nx=16, nz=16, lr=0.003, w1=7.0,
+                     kx1=0.001, kz1=0.02, w2=0.0, kx2=0.0, kz2=0.0, n_iter=200),
+    medium="linear_bilayer", seed=31, scat_density=6.0, sim_spacing=0.25,
+)
+
+# Small linear-array case for the oracle (16 elements, 12 x 10 pixels).
+MICRO_LINEAR = Config(
+    name="micro_linear",
+    array=ArrayCfg(n_elem=16, radius=math.inf, pitch=0.3, d_lens=0.67, c_lens=1.0494,
+                   t_ttp=0.0),
+    acq=AcqCfg(fc=5.0, fs=20.0, n_samples=512),
+    img=ImgCfg(n_depth=12, n_angle=10, depth_min=2.0, depth_max=14.0),
+    method=MethodCfg(block=4, fnum=0.75, n_seg=16, nx=6, nz=7, n_iter=3),
+    medium="linear_bilayer", seed=5, n_scat_random=300,
+)
+
+CONFIGS = [C1, C2, C3, C4, C5, L1]
 
 
 def config_by_name(name: str) -> Config:
-    for c in CONFIGS + [MICRO]:
+    for c in CONFIGS + [MICRO, MICRO_LINEAR]:
         if c.name == name:
             return c
     raise KeyError(name)

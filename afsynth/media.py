@@ -73,17 +73,18 @@ def _polar(rho, th):
     return np.array([rho * math.sin(th), rho * math.cos(th)])
 
 
-def _linear_medium(cfg: Config, rng) -> Medium:
+def _linear_medium(cfg: Config, rng, seed: int) -> Medium:
     """Bi-layer phantom under a linear array: a layer at 1575 m/s (the paper's chicken
     breast) of thickness U(6, 12) mm on the lens over a phantom at 1490, 1516 or
-    1540 m/s, one anechoic cyst, nine point targets and random scatterers."""
+    1540 m/s (seed mod 3), one anechoic cyst, nine point targets and random
+    scatterers."""
     arr, img = cfg.array, cfg.img
     xe = element_x(arr)
     x0, x1 = float(xe[0]), float(xe[-1])
     z_lo, z_hi = arr.d_lens + img.depth_min, arr.d_lens + img.depth_max
     top = arr.d_lens + rng.uniform(6.0, 12.0)
     layer_r = np.array([top])
-    layer_c = np.array([1.575, float(rng.choice([1.490, 1.516, 1.540]))])
+    layer_c = np.array([1.575, (1.490, 1.516, 1.540)[seed % 3]])
     span = x1 - x0
     cyst_xz = np.array([[x0 + rng.uniform(0.35, 0.65) * span,
                          rng.uniform(top + 6.0, max(top + 7.0, z_hi - 8.0))]])
@@ -106,7 +107,7 @@ def medium_for(cfg: Config, seed: int | None = None) -> Medium:
     seed = cfg.seed if seed is None else seed
     rng = np.random.Generator(np.random.PCG64(seed))
     if cfg.medium == "linear_bilayer":
-        return _linear_medium(cfg, rng)
+        return _linear_medium(cfg, rng, seed)
     arr, img = cfg.array, cfg.img
     rl = lens_radius(arr)
     th0, th1 = element_span(arr)

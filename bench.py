@@ -195,6 +195,55 @@ def lens_model_report():
     return out
 
 
+def linear_array_report(seeds=(30, 31, 32)):
+    """Linear array with a flat lens (128 elements at 0.2 mm, the Table I lens) on
+    seeded bi-layer phantoms (1575 m/s over 1490/1516/1540 m/s): the plain method
+    (sweep + Adam) with each lens model of the beamformer, sound-speed MAE over the
+    imaged depths against the true medium, and the time of one loss_and_grad."""
+    import torch
+    import afsynth
+    from paper_2608_06853_amd import _lib, metrics, warmstart, workloads
+    cfg = afsynth.configs.L1
+    z_lo = cfg.array.d_lens + cfg.img.depth_min
+    z_hi = cfg.array.d_lens + cfg.img.depth_max
+    rows, timing = [], None
+    for sd in seeds:
+        row = {"seed": sd}
+        for model in workloads.LENS_MODELS:
+            bf, iq, med = workloads.build(cfg, seed=sd, lens_model=model)
+            row["phantom_speed"] = float(med.layer_c[-1])
+            if timing is None:
+                lp = workloads.loss_params(cfg)
+                terms = bf.empty_terms()
+                grad = torch.empty(bf.grid.shape, device=bf.device)
+                bf.ctx.loss_and_grad(iq, lp, terms, grad)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(10):
+                    bf.ctx.loss_and_grad(iq, lp, terms, grad)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) / 10 * 1e3
+                n, P = cfg.array.n_elem, bf.n_points
+                timing = {"ms_per_loss_and_grad": round(ms, 3),
+                          "nominal_Gsamples_per_s": round(n * n * P / ms / 1e6, 1)}
+            s, cm, times, t_sweep, best = warmstart.run_plain(bf, iq, cfg, cfg.method.n_iter)
+            c_true = workloads.true_speed_nodes(cfg, med, bf.grid)
+            zs = bf.grid.z0 + bf.grid.dz * np.arange(bf.grid.nz)
+            keep = (zs >= z_lo) & (zs <= z_hi)
+            e = metrics.speed_errors(s.cpu().numpy()[keep], c_true[keep])
+            e_sw = metrics.speed_errors(np.full((int(keep.sum()), bf.grid.nx), 1.0 / best),
+                                        c_true[keep])
+            row[model] = {"sweep_best_speed": best, "sweep_mae_mps": round(e_sw["mae_mps"], 2),
+                          "final_mae_mps": round(e["mae_mps"], 2), "cmpe_final": cm[-1],
+                          "seconds": round(times[-1], 3)}
+            del bf, iq
+        rows.append(row)
+    summ = {m: {"sweep_mae_mps": round(float(np.mean([r[m]["sweep_mae_mps"] for r in rows])), 2),
+                "final_mae_mps": round(float(np.mean([r[m]["final_mae_mps"] for r in rows])), 2)}
+            for m in workloads.LENS_MODELS}
+    return {"timing": timing, "summary": summ, "media": rows}
+
+
 def grid_init_report(seeds=range(9000, 9008)):
     """Model initialisation on the static grid (laid out once for 1500 m/s) against
     the dynamic grid (moved with every swept speed): the speed each selects against
@@ -387,6 +436,7 @@ def main():
     if not args.no_autofocus:
         t0 = time.perf_counter()
         for key, fn in (("plain_loop", plain_loop_report), ("lens_models", lens_model_report),
+                        ("linear_array", linear_array_report),
                         ("grid_init", grid_init_report),
                         ("refraction_search", refraction_search_report),
                         ("s_to_target", s_to_target_report)):

@@ -24,6 +24,17 @@ the element's own polar angle theta_a to the polar angle theta_x where the
 straight element-to-point segment crosses the lens arc when c_lens <= c_med
 (Snell bends the lens leg towards the normal), else from theta_x to theta_p --
 and the candidate of least T, the first one on ties.
+
+A linear array (every element on one line z = z_e) has a flat lens: the layer
+z_e <= z <= z_e + d_lens, refracting at the plane z_L = z_e + d_lens.  The lens
+point is L(x) = (x, z_L) and
+
+    T(x) = |L(x) - e_a| / c_lens + |p - L(x)| / c_med ;
+
+``refract`` scans x over [min(x_a, x_p), max(x_a, x_p)] and bisects dT/dx;
+``discrete_refract`` spaces its candidates in x over the same kind of interval
+as on the arc (element to straight crossing for a slower lens, crossing to the
+point otherwise).  d_lens = 0 means no lens: the straight ray from the element.
 """
 from __future__ import annotations
 
@@ -67,6 +78,8 @@ def refract(elem_xz: np.ndarray, d_lens: float, c_lens: float, c_med: float,
     lens arc, lens leg, medium leg, homogeneous travel time l1/c_lens + l2/c_med
     and the refraction point.
     """
+    if is_linear(elem_xz):
+        return _refract_flat(elem_xz, d_lens, c_lens, c_med, pts, pairs, n_scan, n_bisect)
     ex_all = np.asarray(elem_xz[:, 0], dtype=np.float64)
     ez_all = np.asarray(elem_xz[:, 1], dtype=np.float64)
     if pairs is None:
@@ -160,6 +173,8 @@ def discrete_refract(elem_xz: np.ndarray, d_lens: float, c_lens: float, c_med: f
     module docstring.  Same arguments (plus ``n_search``) and outputs as
     ``refract``."""
     assert n_search >= 2
+    if is_linear(elem_xz):
+        return _discrete_refract_flat(elem_xz, d_lens, c_lens, c_med, pts, n_search, pairs)
     (ex, ez, px, pz), shape = _ray_arrays(elem_xz, pts, pairs)
     rl = np.hypot(ex, ez) + d_lens
     th_a = np.arctan2(ex, ez)
@@ -186,3 +201,75 @@ def discrete_refract(elem_xz: np.ndarray, d_lens: float, c_lens: float, c_med: f
     lx, lz, l1, l2 = _legs(phi, ex, ez, px, pz, rl)
     out = dict(phi=phi, l1=l1, l2=l2, t_hom=l1 / c_lens + l2 / c_med, ref_x=lx, ref_z=lz)
     return {k_: v.reshape(shape) for k_, v in out.items()}
+
+
+def is_linear(elem_xz: np.ndarray) -> bool:
+    """Every element on one line z = const (within 1e-9 of the array's size)."""
+    z = np.asarray(elem_xz[:, 1], dtype=np.float64)
+    return bool(np.max(np.abs(z - z[0])) <= 1e-9 * (1.0 + np.max(np.abs(elem_xz[:, 0]))))
+
+
+def _flat_out(x, ex, ez, px, pz, d_lens, c_lens, c_med, shape):
+    zl = ez + d_lens
+    l1 = np.hypot(x - ex, zl - ez)
+    l2 = np.hypot(px - x, pz - zl)
+    out = dict(phi=x, l1=l1, l2=l2, t_hom=l1 / c_lens + l2 / c_med, ref_x=x, ref_z=zl)
+    return {k_: v.reshape(shape) for k_, v in out.items()}
+
+
+def _straight(ex, ez, px, pz, c_med, shape):
+    l2 = np.hypot(px - ex, pz - ez)
+    out = dict(phi=ex.copy(), l1=np.zeros_like(l2), l2=l2, t_hom=l2 / c_med, ref_x=ex.copy(),
+               ref_z=ez.copy())
+    return {k_: v.reshape(shape) for k_, v in out.items()}
+
+
+def _refract_flat(elem_xz, d_lens, c_lens, c_med, pts, pairs, n_scan, n_bisect):
+    (ex, ez, px, pz), shape = _ray_arrays(elem_xz, pts, pairs)
+    if d_lens == 0.0:
+        return _straight(ex, ez, px, pz, c_med, shape)
+    zl = ez + d_lens
+
+    def T(x):
+        return np.hypot(x - ex_, d_lens) / c_lens + np.hypot(px_ - x, pz_ - zl_) / c_med
+
+    def dT(x):
+        l1 = np.hypot(x - ex, d_lens)
+        l2 = np.hypot(px - x, pz - zl)
+        return (x - ex) / l1 / c_lens - (px - x) / np.where(l2 > 0, l2, 1.0) / c_med
+
+    lo = np.minimum(ex, px)
+    hi = np.maximum(ex, px)
+    k = np.arange(n_scan) / (n_scan - 1)
+    xs = lo[:, None] + (hi - lo)[:, None] * k[None, :]
+    ex_, px_, pz_, zl_ = ex[:, None], px[:, None], pz[:, None], zl[:, None]
+    best = np.argmin(T(xs), axis=1)
+    rows = np.arange(xs.shape[0])
+    a_ = xs[rows, np.maximum(best - 1, 0)]
+    b_ = xs[rows, np.minimum(best + 1, n_scan - 1)]
+    interior = (dT(a_) < 0) & (dT(b_) > 0)
+    for _ in range(n_bisect):
+        m = 0.5 * (a_ + b_)
+        right = dT(m) < 0
+        a_ = np.where(interior & right, m, a_)
+        b_ = np.where(interior & ~right, m, b_)
+    x = np.where(interior, 0.5 * (a_ + b_), xs[rows, best])
+    return _flat_out(x, ex, ez, px, pz, d_lens, c_lens, c_med, shape)
+
+
+def _discrete_refract_flat(elem_xz, d_lens, c_lens, c_med, pts, n_search, pairs):
+    (ex, ez, px, pz), shape = _ray_arrays(elem_xz, pts, pairs)
+    if d_lens == 0.0:
+        return _straight(ex, ez, px, pz, c_med, shape)
+    zl = ez + d_lens
+    # straight crossing of the segment e -> p with the plane z = zl
+    frac = np.where(pz - ez > 0, d_lens / np.where(pz - ez > 0, pz - ez, 1.0), 0.0)
+    xc = ex + (px - ex) * frac
+    lo, hi = (ex, xc) if c_lens <= c_med else (xc, px)
+    k = np.arange(n_search) / (n_search - 1)
+    xs = lo[:, None] + (hi - lo)[:, None] * k[None, :]
+    tt = (np.hypot(xs - ex[:, None], d_lens) / c_lens
+          + np.hypot(px[:, None] - xs, pz[:, None] - zl[:, None]) / c_med)
+    best = np.argmin(tt, axis=1)
+    x = xs[np.arange(xs.shape[0]), best]
+    return _flat_out(x, ex, ez, px, pz, d_lens, c_lens, c_med, shape)

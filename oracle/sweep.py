@@ -10,7 +10,9 @@ Readings: the sweep step is 10 m/s; the reference grid is laid out for
 c_ref = 1.540 mm/us, and at speed c_g every pixel's depth below the lens
 surface is scaled by c_g/c_ref along its polar angle while the kernel spacing
 becomes c_g/(2 f_c).  For radial rays through the concentric lens this keeps
-the round-trip time exactly fixed.
+the round-trip time exactly fixed.  For a linear array with a flat lens the
+depth below the lens plane is scaled straight down, which keeps it fixed for
+rays normal to the lens.
 
 The static grid of the earlier method (the comparison of the model-initialisation
 results) is laid out once for 1500 m/s: every speed of the sweep is evaluated on
@@ -20,6 +22,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from .fermat import is_linear
 from .model import Problem, LossParams, forward
 
 
@@ -30,6 +33,10 @@ def sweep_speeds(lo: float = 1.340, hi: float = 1.740, step: float = 0.010) -> n
 
 def scaled_centres(centres: np.ndarray, elem_xz: np.ndarray, d_lens: float, c_g: float,
                    c_ref: float) -> np.ndarray:
+    if is_linear(elem_xz):
+        # flat lens: depth below the lens plane scaled straight down
+        zl = float(elem_xz[0, 1]) + d_lens
+        return np.stack([centres[:, 0], zl + (centres[:, 1] - zl) * (c_g / c_ref)], axis=1)
     rl = float(np.hypot(elem_xz[0, 0], elem_xz[0, 1])) + d_lens
     rho = np.hypot(centres[:, 0], centres[:, 1])
     th = np.arctan2(centres[:, 0], centres[:, 1])

@@ -60,28 +60,44 @@ class Grid:
         return (self.nz, self.nx)
 
 
+def is_linear(acq: Acquisition) -> bool:
+    """Every element on one line z = const: a linear array with a flat lens (the
+    library's own test of the array shape)."""
+    z = acq.elem_xz[:, 1]
+    return bool(np.max(np.abs(z - z[0])) <= 1e-9 * (1.0 + np.max(np.abs(acq.elem_xz[:, 0]))))
+
+
 def lens_radius(acq: Acquisition) -> float:
     return float(np.hypot(acq.elem_xz[0, 0], acq.elem_xz[0, 1])) + acq.d_lens
 
 
 class DynamicGrid:
     """Dynamic CMPE grid of a base pixel layout: at speed c_g every pixel's depth
-    below the lens surface is stretched by c_g/c_ref along its polar angle and the
-    kernel spacing becomes lambda_g/2 = c_g/(2 fc), so the same time samples are
-    observed.  The polar decomposition of the base layout is taken once."""
+    below the lens surface is stretched by c_g/c_ref -- along its polar angle for a
+    curvilinear array, straight down for a linear one -- and the kernel spacing
+    becomes lambda_g/2 = c_g/(2 fc), so the same time samples are observed.  The
+    decomposition of the base layout is taken once."""
 
     def __init__(self, img: Imaging, acq: Acquisition, c_ref: float, fc: float):
         self.img, self.c_ref, self.fc = img, c_ref, fc
-        self.rl = lens_radius(acq)
-        rho = np.hypot(img.centres[:, 0], img.centres[:, 1])
-        th = np.arctan2(img.centres[:, 0], img.centres[:, 1])
-        self.depth = rho - self.rl
-        self.dirs = np.stack([np.sin(th), np.cos(th)], axis=1)
+        if is_linear(acq):
+            self.rl = float(acq.elem_xz[0, 1]) + acq.d_lens       # lens surface plane
+            self.depth = img.centres[:, 1] - self.rl
+            self.dirs = None
+        else:
+            self.rl = lens_radius(acq)
+            rho = np.hypot(img.centres[:, 0], img.centres[:, 1])
+            th = np.arctan2(img.centres[:, 0], img.centres[:, 1])
+            self.depth = rho - self.rl
+            self.dirs = np.stack([np.sin(th), np.cos(th)], axis=1)
 
     def at(self, c_g: float) -> Imaging:
-        rho_g = self.rl + self.depth * (c_g / self.c_ref)
-        return replace(self.img, centres=rho_g[:, None] * self.dirs,
-                       spacing=c_g / (2.0 * self.fc))
+        d_g = self.depth * (c_g / self.c_ref)
+        if self.dirs is None:
+            centres = np.stack([self.img.centres[:, 0], self.rl + d_g], axis=1)
+        else:
+            centres = (self.rl + d_g)[:, None] * self.dirs
+        return replace(self.img, centres=centres, spacing=c_g / (2.0 * self.fc))
 
 
 def scaled_imaging(img: Imaging, acq: Acquisition, c_g: float, c_ref: float, fc: float) -> Imaging:

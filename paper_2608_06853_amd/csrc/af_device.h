@@ -36,6 +36,8 @@ struct RayOut {
 // on the z axis) by safeguarded FP32 Newton on the Snell residual
 //   G(alpha) = sin(i1)/c_lens - sin(i2)/c_med,
 // where alpha is the direction of the lens leg; G is close to linear in alpha.
+// The iterations only place the start of the FP64 step, so they divide with the
+// hardware reciprocal (1 ulp) instead of correctly rounded divisions.
 // The lens point is then projected onto the arc in FP64 and one FP64 second-order
 // step on T(phi) gives T at the stationary point (error O(dphi^3)) and the
 // refined refraction point.
@@ -85,8 +87,8 @@ __device__ inline RayOut trace_lens(double R, double sa, double ca, double rho, 
       sincosf(x, &s, &c);
     }
     const float Q = sqrtf(Rf * Rf * c * c + d2f);
-    const float iQ = 1.f / Q;
-    const float L1 = d2f / (Rf * c + Q);
+    const float iQ = __builtin_amdgcn_rcpf(Q);
+    const float L1 = d2f * __builtin_amdgcn_rcpf(Rf * c + Q);
     const float dL1 = Rf * s * L1 * iQ;
     lx = L1 * s;
     lz = Rf + L1 * c;
@@ -106,7 +108,7 @@ __device__ inline RayOut trace_lens(double R, double sa, double ca, double rho, 
     const float dg = dsi1 * iclf - dsi2 * icmf;
     if (it == 3) break;  // (lx, lz) is the lens point at the converged alpha
     if (g < 0.f) lo = x; else hi = x;
-    const float nw = x - g / dg;
+    const float nw = x - g * __builtin_amdgcn_rcpf(dg);
     x = (nw >= lo && nw <= hi) ? nw : 0.5f * (lo + hi);
   }
 
@@ -191,13 +193,85 @@ __device__ inline RayOut trace_lens_search(double R, double sa, double ca, doubl
   return o;
 }
 
-// Refraction by the context's rule: straight rays without a lens, the discrete
-// search with nsearch >= 2 candidates, else the continuous Fermat root.
-__device__ inline RayOut refract(double R, double sa, double ca, double rho, double sp, double cp,
-                                 double dlens, double icl, double icm, int nsearch) {
-  if (nsearch >= 2 && dlens > 0.0)
-    return trace_lens_search(R, sa, ca, rho, sp, cp, dlens, icl, icm, nsearch);
-  return trace_lens(R, sa, ca, rho, sp, cp, dlens, icl, icm);
+// Fermat ray through a flat lens (linear array; Eqs. 7-8 with a plane interface).
+// Element at (xe, ze); the lens is the layer ze <= z <= ze + dlens; point at
+// (xp, zp) below it.  The lens point is (xe +- xi, ze + dlens) with lateral
+// offset xi >= 0 towards the point.  T(xi) is convex; its minimiser lies between
+// 0 and the straight crossing uc = u dlens / (zp - ze) when the lens is the slower
+// layer, between uc and u otherwise.  FP64 Newton on dT/dxi from the thin-lens
+// guess, safeguarded by bisection inside that bracket; with nsearch >= 2 the best
+// of nsearch evenly spaced candidates over the same interval (the first on ties).
+// dlens = 0 is the straight ray from the element.
+__device__ inline RayOut trace_flat(double xe, double ze, double xp, double zp, double dlens,
+                                    double icl, double icm, int nsearch) {
+  const double dx = xp - xe;
+  const double sgn = dx < 0.0 ? -1.0 : 1.0;
+  const double u = fabs(dx);
+  const double H = zp - ze;
+  RayOut o;
+  if (dlens == 0.0) {
+    const double L2 = sqrt(u * u + H * H);
+    o.t_hom = L2 * icm;
+    o.refx = (float)xe;
+    o.refz = (float)ze;
+    o.l2 = (float)L2;
+    return o;
+  }
+  const double h = H - dlens;  // depth of the point below the lens surface
+  const double uc = H > 0.0 ? u * dlens / H : 0.0;
+  const double lo = icl >= icm ? 0.0 : uc, hi = icl >= icm ? uc : u;
+  const double d2 = dlens * dlens, h2 = h * h;
+  double xi;
+  if (nsearch >= 2) {
+    const double step = (hi - lo) / (double)(nsearch - 1);
+    double best = 1e300;
+    xi = lo;
+    for (int k = 0; k < nsearch; ++k) {
+      const double x = lo + step * (double)k;
+      const double T = sqrt(x * x + d2) * icl + sqrt((u - x) * (u - x) + h2) * icm;
+      if (T < best) {
+        best = T;
+        xi = x;
+      }
+    }
+  } else {
+    double a = lo, b = hi;
+    xi = icl >= icm ? uc * (icm / icl) : uc;
+    for (int it = 0; it < 6; ++it) {
+      const double L1 = sqrt(xi * xi + d2), L2 = sqrt((u - xi) * (u - xi) + h2);
+      const double g = xi / L1 * icl - (u - xi) / L2 * icm;
+      const double gp = d2 / (L1 * L1 * L1) * icl + h2 / (L2 * L2 * L2) * icm;
+      if (g < 0.0) a = xi; else b = xi;
+      const double nw = xi - g / gp;
+      xi = (nw >= a && nw <= b) ? nw : 0.5 * (a + b);
+    }
+  }
+  const double L1 = sqrt(xi * xi + d2), L2 = sqrt((u - xi) * (u - xi) + h2);
+  o.t_hom = L1 * icl + L2 * icm;
+  o.refx = (float)(xe + sgn * xi);
+  o.refz = (float)(ze + dlens);
+  o.l2 = (float)L2;
+  return o;
+}
+
+// Refraction modes: the lens surface is the concentric arc (curvilinear array)
+// or a plane (linear array), and the refraction point the continuous root or the
+// discrete search.  Element descriptor: (R, sin, cos) of the element on the arc,
+// or (x, z) on the line; point descriptor: (rho, sin, cos), or (x, z).
+enum RefractMode { ARC_ROOT = 0, ARC_SEARCH = 1, FLAT_ROOT = 2, FLAT_SEARCH = 3 };
+
+inline int refract_mode(bool flat, int nsearch, double dlens) {
+  return (flat ? FLAT_ROOT : ARC_ROOT) + (nsearch >= 2 && dlens > 0.0 ? 1 : 0);
+}
+
+template <int MODE>
+__device__ inline RayOut refract(const double4& el, const double4& pp, double dlens, double icl,
+                                 double icm, int nsearch) {
+  if (MODE == FLAT_ROOT || MODE == FLAT_SEARCH)
+    return trace_flat(el.x, el.y, pp.x, pp.y, dlens, icl, icm, MODE == FLAT_SEARCH ? nsearch : 0);
+  if (MODE == ARC_SEARCH)
+    return trace_lens_search(el.x, el.y, el.z, pp.x, pp.y, pp.z, dlens, icl, icm, nsearch);
+  return trace_lens(el.x, el.y, el.z, pp.x, pp.y, pp.z, dlens, icl, icm);
 }
 
 // Keys cubic-convolution weights (a = -0.5) of the taps at offsets -1, 0, 1, 2
@@ -215,13 +289,14 @@ __device__ inline void keys_weights(float f, float& w0, float& w1, float& w2, fl
 // grid has row stride W = nx + 3 and holds node (i, j) at (i + 1) * W + (j + 1)
 // for i in [-1, nz + 1], j in [-1, nx + 1] (edge values replicated).  Returns
 // sum_k w_k value_k with w = 1/2 at both ends and 1 inside (caller divides by nseg).
+// The clamp is one median-of-three (umax, vmax >= 0; positions are finite).
 template <class GridPtr>
 __device__ inline float path_sum(GridPtr G, int W, float u0, float v0, float du, float dv,
                                  int nseg, float umax, float vmax) {
   float acc = 0.f, first = 0.f, last = 0.f;
   for (int k = 0; k <= nseg; ++k) {
-    const float u = fminf(fmaxf(fmaf((float)k, du, u0), 0.f), umax);
-    const float v = fminf(fmaxf(fmaf((float)k, dv, v0), 0.f), vmax);
+    const float u = __builtin_amdgcn_fmed3f(fmaf((float)k, du, u0), 0.f, umax);
+    const float v = __builtin_amdgcn_fmed3f(fmaf((float)k, dv, v0), 0.f, vmax);
     const int j0 = (int)u, i0 = (int)v;
     float wx0, wx1, wx2, wx3, wz0, wz1, wz2, wz3;
     keys_weights(u - (float)j0, wx0, wx1, wx2, wx3);

@@ -134,6 +134,7 @@ af::Geo af_ctx::geo() const {
   g.dlens = d_lens;
   g.icl = 1.0 / c_lens;
   g.nsearch = n_search;
+  g.flat = flat ? 1 : 0;
   g.nx = nx;
   g.nz = nz;
   g.W = nx + 3;
@@ -207,7 +208,16 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
   const int N = n_elem, M = c->M;
   c->elem_xz.assign(elem_xz, elem_xz + 2 * N);
 
-  // element polar geometry (centre of curvature at the origin)
+  // A linear array has every element on one line z = const and a flat lens;
+  // otherwise the elements lie on an arc about the origin with a concentric lens.
+  double xmax = 0.0, zdev = 0.0;
+  for (int a = 0; a < N; ++a) {
+    xmax = std::max(xmax, std::fabs(elem_xz[2 * a]));
+    zdev = std::max(zdev, std::fabs(elem_xz[2 * a + 1] - elem_xz[1]));
+  }
+  c->flat = zdev <= 1e-9 * (1.0 + xmax);
+  // element geometry: polar (R, sin, cos) on the arc, or (x, z) on the line;
+  // elem_pol is the ordering key (polar angle, or x)
   c->elem_R.resize(N);
   c->elem_pol.resize(N);
   std::vector<double4> el(N);
@@ -215,12 +225,13 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
     const double x = elem_xz[2 * a], z = elem_xz[2 * a + 1];
     const double R = std::sqrt(x * x + z * z);
     c->elem_R[a] = R;
-    c->elem_pol[a] = std::atan2(x, z);
-    el[a] = make_double4(R, x / R, z / R, 0.0);
+    c->elem_pol[a] = c->flat ? x : std::atan2(x, z);
+    el[a] = c->flat ? make_double4(x, z, 0.0, 0.0) : make_double4(R, x / R, z / R, 0.0);
   }
   for (int a = 1; a < N; ++a)
     if (!(c->elem_pol[a] > c->elem_pol[a - 1]))
-      return fail(c, AF_ERR_ARG, "af_set_geometry: elements must be ordered by increasing polar angle");
+      return fail(c, AF_ERR_ARG, c->flat ? "af_set_geometry: elements must be ordered by increasing x"
+                                         : "af_set_geometry: elements must be ordered by increasing polar angle");
   // element orientation, Eq. 3 (one-sided differences at the two ends)
   std::vector<double> th(N), cth(N), sth(N);
   for (int a = 0; a < N; ++a) {
@@ -275,7 +286,7 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
           }
         if (cnt > 0 && cnt != hi - lo + 1) bad_flag[64 * tid] = 1;
       } else {
-        const double ang = std::atan2(c->pts_xz[2 * p], c->pts_xz[2 * p + 1]);
+        const double ang = c->flat ? c->pts_xz[2 * p] : std::atan2(c->pts_xz[2 * p], c->pts_xz[2 * p + 1]);
         int a0 = (int)(std::upper_bound(c->elem_pol.begin(), c->elem_pol.end(), ang) - c->elem_pol.begin());
         int best = -1;
         for (int a = std::max(a0 - 1, 0); a <= std::min(a0, N - 1); ++a)
@@ -295,7 +306,8 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
   for (char b : bad_flag)
     if (b) return fail(c, AF_ERR_ARG, "af_set_geometry: active elements of a point are not contiguous");
 
-  // spatial tiling of the pixels: k-d partition in (depth, arc length) whose
+  // spatial tiling of the pixels: k-d partition in (depth, arc length) -- (z, x)
+  // for a linear array -- whose
   // splits are multiples of the tile (ppt pixels) and sub-tile (pps pixels)
   // sizes, so every tile and sub-tile is a compact blob
   const int pps = SUB / M;          // whole patches per 64-point sub-tile
@@ -310,8 +322,13 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
     parallel(host_threads(n_pix * 8LL), [&](int tid, int nt) {
       const int q0 = (int)((long long)n_pix * tid / nt), q1 = (int)((long long)n_pix * (tid + 1) / nt);
       for (int q = q0; q < q1; ++q) {
-        cu[q] = std::hypot(pix_xz[2 * q], pix_xz[2 * q + 1]);
-        cv[q] = std::atan2(pix_xz[2 * q], pix_xz[2 * q + 1]) * rref;
+        if (c->flat) {
+          cu[q] = pix_xz[2 * q + 1];
+          cv[q] = pix_xz[2 * q];
+        } else {
+          cu[q] = std::hypot(pix_xz[2 * q], pix_xz[2 * q + 1]);
+          cv[q] = std::atan2(pix_xz[2 * q], pix_xz[2 * q + 1]) * rref;
+        }
       }
     });
   }
@@ -418,7 +435,7 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
           const long long src = pc >= 0 ? pc : c->i2c[(long long)t * TILE];
           const double x = c->pts_xz[2 * src], z = c->pts_xz[2 * src + 1];
           const double rho = std::sqrt(x * x + z * z);
-          ptpol[pi] = make_double4(rho, x / rho, z / rho, 0.0);
+          ptpol[pi] = c->flat ? make_double4(x, z, 0.0, 0.0) : make_double4(rho, x / rho, z / rho, 0.0);
           ptxy[pi] = make_float2((float)x, (float)z);
           int lo = 1, hi = 0;
           if (pc >= 0) {
@@ -505,6 +522,8 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
   if ((st = upload(c, c->d_i2c, c->i2c, "point map")) != AF_OK) return st;
 
   AF_ALLOC(c->d_tab, sizeof(af::TabEntry) * (size_t)N * P_int, "travel-time table");
+  AF_ALLOC(c->d_ray_uv, sizeof(float2) * (size_t)N * P_int, "ray starts");
+  AF_ALLOC(c->d_ray_l2, sizeof(float) * (size_t)N * P_int, "ray medium legs");
   AF_ALLOC(c->d_bblk, sizeof(float2) * (size_t)c->nb * c->nb * P_int, "block images");
   AF_ALLOC(c->d_gT, sizeof(float) * 2 * (size_t)N * P_int, "time gradient");
   AF_ALLOC(c->d_gsb, sizeof(float2) * (size_t)P_int, "brightness gradient");
@@ -565,7 +584,7 @@ af_status af_set_slowness(af_ctx* c, int nx, int nz, double x0, double z0, doubl
       for (long long p = p0; p < p1; ++p) {
         const double x = c->pts_xz[2 * p], z = c->pts_xz[2 * p + 1];
         bad += inside(x, z) ? 0 : 1;
-        const double ang = std::atan2(x, z);
+        const double ang = c->flat ? x : std::atan2(x, z);
         lo = std::min(lo, ang);
         hi = std::max(hi, ang);
       }
@@ -579,8 +598,14 @@ af_status af_set_slowness(af_ctx* c, int nx, int nz, double x0, double z0, doubl
       amax = std::max(amax, tmax[t * 8]);
     }
   }
+  // flat lens: the plane segment over [amin, amax] in x (its two ends)
+  for (int a = 0; c->flat && a < c->N; ++a) {
+    const double zl = c->elem_xz[2 * a + 1] + c->d_lens;
+    if (!inside(amin, zl) || !inside(amax, zl))
+      return fail(c, AF_ERR_ARG, "af_set_slowness: grid does not cover the lens surface");
+  }
   // lens arc over [amin, amax] (both ends and the apex if it is inside)
-  for (int a = 0; a < c->N; ++a) {
+  for (int a = 0; !c->flat && a < c->N; ++a) {
     const double RL = c->elem_R[a] + c->d_lens;
     const double cand[3] = {amin, amax, 0.0};
     for (int k = 0; k < 3; ++k) {

@@ -43,6 +43,7 @@ struct Geo {
   double fs, fd, t0, t_ttp;
   double dlens, icl;      // lens thickness, 1/c_lens
   int nsearch;            // discrete refraction candidates (0: continuous root)
+  int flat;               // linear array with a flat lens (else the concentric arc)
   // slowness grid
   int nx, nz, W;          // W = nx + 3 (padded row stride)
   float x0, z0, idx, idz;
@@ -59,6 +60,8 @@ struct TableArgs {
   const float* gdev;      // padded deviation grid s - s_med
   const double* scal;     // scal[0] = c_med, scal[1] = s_med
   TabEntry* tab;          // [n_elem][P]
+  float2* ray_uv;         // [n_elem][P] ray start (refraction point) in grid coordinates
+  float* ray_l2;          // [n_elem][P] medium leg length
 };
 constexpr int TAB_CHUNK = 8;
 
@@ -96,8 +99,8 @@ struct CmpeArgs {
 
 struct PathArgs {
   Geo g;
-  const double4* elem;
-  const double4* ptpol;
+  const float2* ray_uv;   // ray start and medium leg of every table entry (k_table)
+  const float* ray_l2;
   const float2* ptxy;
   const int2* prange;
   const int4* tiles;
@@ -140,6 +143,7 @@ struct af_ctx {
   // lens
   double d_lens = 0, c_lens = 1, t_ttp = 0;
   int n_search = 0;
+  bool flat = false;      // linear array: every element on one line z = const
   // grid
   int nx = 0, nz = 0;
   double x0 = 0, z0 = 0, dx = 1, dz = 1;
@@ -149,6 +153,7 @@ struct af_ctx {
   af::DBuf d_elem, d_ptpol, d_ptxy, d_prange, d_tiles, d_tabwork, d_daswork, d_order, d_i2c,
       d_c2i;
   af::DBuf d_cnn_part;
+  af::DBuf d_ray_uv, d_ray_l2;  // per table entry: ray start (grid coordinates), medium leg
   af::DBuf d_chan;  // receive-channel images, allocated by the coherence calls only
   af::DBuf d_s, d_gdev, d_regg, d_scal, d_tab, d_bblk, d_g, d_gT, d_gsb, d_part, d_gpad, d_gpart,
       d_grad, d_terms, d_maps, d_img;

@@ -1,6 +1,7 @@
 // Adjoint of the path integral: dL/ds[node] += sum over rays and ray points of
 // dL/dT * L2 * w_k * (bicubic weight of the node at r_k) / N.  Refraction points
-// and c_med are held constant (they follow the global mean speed).
+// and c_med are held constant (they follow the global mean speed); each ray's
+// start and medium leg L2 are read from the table kernel of the same slowness.
 //
 // A workgroup takes one tile of points and every active element of it; a
 // wavefront walks the rays from one element to its 64 points in lock step.  The
@@ -70,8 +71,6 @@ __device__ inline float reduce_scatter16(float v[16], int lane) {
   return h1;
 }
 
-// SEARCH selects the discrete refraction search (see k_table).
-template <bool SEARCH>
 __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
   extern __shared__ float sg[];  // [4 wavefronts][nodes]
   const Geo& g = A.g;
@@ -87,9 +86,7 @@ __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
 
   const long long p = (long long)tile * TILE + tid;
   const int2 pr = A.prange[p];
-  const double4 pp = A.ptpol[p];
   const float2 pxy = A.ptxy[p];
-  const double icm = A.scal[1];
   const float inv_n = 1.f / (float)g.n_seg;
   const float up = (pxy.x - g.x0) * g.idx, vp = (pxy.y - g.z0) * g.idz;
   const float umax = (float)(g.nx - 1), vmax = (float)(g.nz - 1);
@@ -104,16 +101,14 @@ __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
     const bool live = act && gbar != 0.f;
     const unsigned long long lmask = __ballot(live);
     if (lmask == 0ull) continue;
-    const double4 el = A.elem[a];
-    const RayOut r = refract(el.x, el.y, el.z, pp.x, pp.y, pp.z, g.dlens, g.icl, icm,
-                                 SEARCH ? g.nsearch : 0);
-    const float coef = live ? gbar * r.l2 * inv_n : 0.f;
-    const float u0 = (r.refx - g.x0) * g.idx, v0 = (r.refz - g.z0) * g.idz;
+    const float2 ruv = A.ray_uv[(long long)a * g.P + p];
+    const float coef = live ? gbar * A.ray_l2[(long long)a * g.P + p] * inv_n : 0.f;
+    const float u0 = ruv.x, v0 = ruv.y;
     const float du = (up - u0) * inv_n, dv = (vp - v0) * inv_n;
     const int lead = __ffsll((long long)lmask) - 1;
     for (int k = 0; k <= g.n_seg; ++k) {
-      const float u = fminf(fmaxf(fmaf((float)k, du, u0), 0.f), umax);
-      const float v = fminf(fmaxf(fmaf((float)k, dv, v0), 0.f), vmax);
+      const float u = __builtin_amdgcn_fmed3f(fmaf((float)k, du, u0), 0.f, umax);
+      const float v = __builtin_amdgcn_fmed3f(fmaf((float)k, dv, v0), 0.f, vmax);
       const int j0 = (int)u, i0 = (int)v;
       float wx[4], wz[4];
       keys_weights(u - (float)j0, wx[0], wx[1], wx[2], wx[3]);
@@ -205,8 +200,8 @@ hipError_t launch_path_adj(af_ctx* c) {
   }
   PathArgs A{};
   A.g = c->geo();
-  A.elem = c->d_elem.as<double4>();
-  A.ptpol = c->d_ptpol.as<double4>();
+  A.ray_uv = c->d_ray_uv.as<float2>();
+  A.ray_l2 = c->d_ray_l2.as<float>();
   A.ptxy = c->d_ptxy.as<float2>();
   A.prange = c->d_prange.as<int2>();
   A.tiles = c->d_tiles.as<int4>();
@@ -216,10 +211,7 @@ hipError_t launch_path_adj(af_ctx* c) {
   A.scal = c->d_scal.as<double>();
   A.gpart = c->d_gpart.as<float>();
   const size_t lds = sizeof(float) * (size_t)nodes * 4;
-  if (A.g.nsearch >= 2 && A.g.dlens > 0.0)
-    hipLaunchKernelGGL(k_path_adj<true>, dim3(c->n_order), dim3(256), lds, c->stream, A);
-  else
-    hipLaunchKernelGGL(k_path_adj<false>, dim3(c->n_order), dim3(256), lds, c->stream, A);
+  hipLaunchKernelGGL(k_path_adj, dim3(c->n_order), dim3(256), lds, c->stream, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n_chunk = (c->n_order + PCHUNK - 1) / PCHUNK;

@@ -24,7 +24,8 @@ __global__ __launch_bounds__(256) void k_sim_times(Geo g, SimGeo sgeo, const dou
   if (k >= n_scat) return;
   const double4 el = elem[a];
   const double4 pp = spol[k];
-  const RayOut r = trace_lens(el.x, el.y, el.z, pp.x, pp.y, pp.z, g.dlens, g.icl, scal[1]);
+  const RayOut r = g.flat ? trace_flat(el.x, el.y, pp.x, pp.y, g.dlens, g.icl, scal[1], 0)
+                         : trace_lens(el.x, el.y, el.z, pp.x, pp.y, pp.z, g.dlens, g.icl, scal[1]);
   const float inv_n = 1.f / (float)sgeo.n_seg;
   const float u0 = (r.refx - sgeo.x0) * sgeo.idx, v0 = (r.refz - sgeo.z0) * sgeo.idz;
   const float up = (sxy[k].x - sgeo.x0) * sgeo.idx, vp = (sxy[k].y - sgeo.z0) * sgeo.idz;
@@ -73,13 +74,14 @@ __global__ __launch_bounds__(256) void k_sim_synth(Geo g, const double* __restri
 hipError_t launch_simulate(af_ctx* c, int n_scat, const double* scat_xz, const float* amp, int nx,
                            int nz, double x0, double z0, double dx, double dz, const float* s_true,
                            int n_seg, double fc, double frac_bw, float2* iq) {
-  // host-side polar geometry of the scatterers
+  // host-side geometry of the scatterers: polar (rho, sin, cos) for the arc lens,
+  // (x, z) for the flat one
   std::vector<double4> spol(n_scat);
   std::vector<float2> sxy(n_scat);
   for (int k = 0; k < n_scat; ++k) {
     const double x = scat_xz[2 * k], z = scat_xz[2 * k + 1];
     const double rho = std::sqrt(x * x + z * z);
-    spol[k] = make_double4(rho, x / rho, z / rho, 0.0);
+    spol[k] = c->flat ? make_double4(x, z, 0.0, 0.0) : make_double4(rho, x / rho, z / rho, 0.0);
     sxy[k] = make_float2((float)x, (float)z);
   }
   DBuf d_spol, d_sxy, d_amp, d_T, d_gd, d_sc;

@@ -12,9 +12,9 @@
 namespace af {
 namespace {
 
-// SEARCH selects the discrete refraction search; the continuous root is the
-// other instantiation, so each keeps its own register allocation.
-template <bool SEARCH>
+// One instantiation per refraction mode (arc or flat lens, root or discrete
+// search), so the default mode keeps its own register allocation.
+template <int MODE>
 __global__ __launch_bounds__(256) void k_table(TableArgs A) {
   extern __shared__ float G[];
   const Geo& g = A.g;
@@ -39,6 +39,8 @@ __global__ __launch_bounds__(256) void k_table(TableArgs A) {
   const int a1 = min(a0 + TAB_CHUNK - 1, tr.y);
   for (int a = a0; a <= a1; ++a) {
     TabEntry e;
+    float2 ruv = make_float2(0.f, 0.f);
+    float rl2 = 0.f;
     if (a < pr.x || a > pr.y) {
       e.ui = 0;  // masked: zero phasor (and a sample index inside every record)
       e.uf = 0.f;
@@ -46,12 +48,13 @@ __global__ __launch_bounds__(256) void k_table(TableArgs A) {
       e.ei = 0.f;
     } else {
       const double4 el = A.elem[a];
-      const RayOut r = refract(el.x, el.y, el.z, pp.x, pp.y, pp.z, g.dlens, g.icl, icm,
-                                 SEARCH ? g.nsearch : 0);
+      const RayOut r = refract<MODE>(el, pp, g.dlens, g.icl, icm, g.nsearch);
       const float u0 = (r.refx - g.x0) * g.idx, v0 = (r.refz - g.z0) * g.idz;
       const float acc = path_sum(G, g.W, u0, v0, (up - u0) * inv_n, (vp - v0) * inv_n, g.n_seg,
                                  umax, vmax);
       const float dT = r.l2 * acc * inv_n;
+      ruv = make_float2(u0, v0);
+      rl2 = r.l2;
       const double uh = (r.t_hom + u_off) * g.fs;
       const double kh = floor(uh);
       float uf = (float)(uh - kh) + dT * fsf;
@@ -67,6 +70,8 @@ __global__ __launch_bounds__(256) void k_table(TableArgs A) {
       e.ei = sn;
     }
     A.tab[(size_t)a * g.P + p] = e;
+    A.ray_uv[(size_t)a * g.P + p] = ruv;
+    A.ray_l2[(size_t)a * g.P + p] = rl2;
   }
 }
 
@@ -84,12 +89,23 @@ hipError_t launch_table(af_ctx* c) {
   A.gdev = c->d_gdev.as<float>();
   A.scal = c->d_scal.as<double>();
   A.tab = c->d_tab.as<TabEntry>();
+  A.ray_uv = c->d_ray_uv.as<float2>();
+  A.ray_l2 = c->d_ray_l2.as<float>();
   if (c->n_tab_work == 0) return hipSuccess;
   const size_t lds = sizeof(float) * (size_t)(c->nx + 3) * (c->nz + 3);
-  if (A.g.nsearch >= 2 && A.g.dlens > 0.0)
-    hipLaunchKernelGGL(k_table<true>, dim3(c->n_tab_work), dim3(256), lds, c->stream, A);
-  else
-    hipLaunchKernelGGL(k_table<false>, dim3(c->n_tab_work), dim3(256), lds, c->stream, A);
+  switch (refract_mode(A.g.flat != 0, A.g.nsearch, A.g.dlens)) {
+    case ARC_ROOT:
+      hipLaunchKernelGGL(k_table<ARC_ROOT>, dim3(c->n_tab_work), dim3(256), lds, c->stream, A);
+      break;
+    case ARC_SEARCH:
+      hipLaunchKernelGGL(k_table<ARC_SEARCH>, dim3(c->n_tab_work), dim3(256), lds, c->stream, A);
+      break;
+    case FLAT_ROOT:
+      hipLaunchKernelGGL(k_table<FLAT_ROOT>, dim3(c->n_tab_work), dim3(256), lds, c->stream, A);
+      break;
+    default:
+      hipLaunchKernelGGL(k_table<FLAT_SEARCH>, dim3(c->n_tab_work), dim3(256), lds, c->stream, A);
+  }
   return hipGetLastError();
 }
 

@@ -48,7 +48,7 @@ def case(name: str, t0: float = 0.0, t_ttp: float = 0.0, patch: int = 3, block: 
     """(cfg, oracle problem, iq complex64, s [nz][nx] float32, loss params).
     d_lens = 0 gives the lens-free (straight-ray) model; n_search >= 2 the discrete
     refraction search."""
-    base = {"micro": MICRO, "c1_small": C1_SMALL}[name]
+    base = {"micro": MICRO, "c1_small": C1_SMALL, "micro_linear": afsynth.configs.MICRO_LINEAR}[name]
     arr = replace(base.array, t_ttp=t_ttp)
     if d_lens is not None:
         arr = replace(arr, d_lens=d_lens)

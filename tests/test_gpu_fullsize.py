@@ -1,7 +1,8 @@
 """Parity at full size in the launch configuration the benchmark times: the whole
 clinical (128 elements, 2560 samples, 256 x 256 pixels x 3 x 3 points, 32 x 32
-grid) and largest (192 elements, 4096 samples, 512 x 512 pixels, 64 x 64 grid)
-geometries are set up exactly as in the benchmark, and sampled outputs are
+grid), largest (192 elements, 4096 samples, 512 x 512 pixels, 64 x 64 grid) and
+linear-array (128 elements at 0.2 mm, flat lens, 1536 samples, 128 x 128 pixels,
+16 x 16 grid) geometries are set up exactly as in the benchmark, and sampled outputs are
 compared with the FP64 oracle computed for those pixels alone:
 
 * travel times of every element to every point of 40 random pixels (1e-6);
@@ -44,7 +45,7 @@ def _lp(cfg):
     return model.LossParams(**{**lp.__dict__, "rho_thresh": 0.5})
 
 
-@pytest.fixture(scope="module", params=["c2_clinical", "c5_largest"])
+@pytest.fixture(scope="module", params=["c2_clinical", "c5_largest", "l1_linear"])
 def full(request):
     import torch
     from paper_2608_06853_amd import autofocus as af, workloads
@@ -132,7 +133,10 @@ def test_full_size_gradient_directional(full):
     """Central difference of the library's own loss along a smooth direction that
     keeps mean(1/s) (hence c_med and the refraction points, which the gradient
     holds constant) fixed to first order.  rho_thresh = 0 keeps every pair valid,
-    so no validity mask flips inside the difference step."""
+    so no validity mask flips inside the difference step.  |arg C| has kinks at 0
+    and +-pi that a step crosses for a share of pairs proportional to the phase
+    excursion, so the step is scaled by 1/f_c: every sample's phase moves by about
+    0.008 rad at any centre frequency."""
     import torch
     cfg, bf, iq_d, s, *_ = full
     lp = G.lib_params(model.LossParams(**{**_lp(cfg).__dict__, "rho_thresh": 0.0}))
@@ -146,7 +150,7 @@ def test_full_size_gradient_directional(full):
     d = np.cos(1.3 * X + 0.4) * np.sin(0.9 * Z + 0.2)
     w = 1.0 / s.astype(np.float64) ** 2
     d -= (d * w).sum() / (w * w).sum() * w
-    d *= 2e-5 * float(s.mean()) / np.abs(d).max()
+    d *= 1e-5 * (3.5 / cfg.acq.fc) * float(s.mean()) / np.abs(d).max()
     lv = []
     for sgn in (1.0, -1.0):
         tt, _ = bf.loss_and_grad(iq_d, lp, torch.from_numpy((s + sgn * d).astype(np.float32)).cuda(),

@@ -15,11 +15,16 @@ pytestmark = pytest.mark.gpu
 # (config, t0, t_ttp, patch, block, perturbation, lens thickness, refraction
 # candidates); after the first four come the lens-free straight-ray model, the
 # conventional model (straight rays plus a scalar round-trip lens offset in the
-# time-to-peak constant) and the bent-ray model with the discrete refraction search.
+# time-to-peak constant) and the bent-ray model with the discrete refraction search;
+# the last four are a linear array with a flat lens (plain, timing offsets,
+# lens-free, discrete search).
 CASES = [("micro", 0.0, 0.0, 3, None), ("c1_small", 0.0, 0.0, 3, None),
          ("micro", 0.7, 0.35, 3, None), ("micro", 0.0, 0.0, 1, 2),
          ("micro", 0.0, 0.0, 3, None, 0.01, 0.0), ("micro", 0.0, 0.5, 3, None, 0.01, 0.0),
-         ("micro", 0.0, 0.0, 3, None, 0.01, None, 24)]
+         ("micro", 0.0, 0.0, 3, None, 0.01, None, 24),
+         ("micro_linear", 0.0, 0.0, 3, None), ("micro_linear", 0.4, 0.58, 3, None),
+         ("micro_linear", 0.0, 0.0, 3, None, 0.01, 0.0),
+         ("micro_linear", 0.0, 0.0, 3, None, 0.01, None, 24)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -103,7 +108,7 @@ def test_autograd_function_matches_fused(key):
     assert G.rel(x.grad.cpu().numpy(), g_fused.cpu().numpy()) < 1e-5
 
 
-@pytest.mark.parametrize("key", CASES[:2])
+@pytest.mark.parametrize("key", [CASES[0], CASES[1], CASES[7]])
 def test_gradient_finite_differences_gpu(key):
     """Directional derivatives of the GPU loss along directions that keep mean(1/s)
     (hence c_med and the refraction points) fixed to first order."""
@@ -157,7 +162,7 @@ def test_discrete_refraction_search_travel_times(n_search):
         assert np.median(gap) < 1e-6
 
 
-@pytest.mark.parametrize("key", [CASES[0], CASES[1], CASES[3], CASES[4]])
+@pytest.mark.parametrize("key", [CASES[0], CASES[1], CASES[3], CASES[4], CASES[7]])
 def test_channel_images_and_lag_one_coherence(key):
     """Receive-channel images element by element and the per-pixel lag-one
     coherence against the oracle."""
@@ -199,15 +204,16 @@ def test_adam_step_matches_oracle():
     assert np.max(np.abs(got - so)[big]) < 1e-5
 
 
-def test_simulator_matches_oracle():
+@pytest.mark.parametrize("name", ["micro", "micro_linear"])
+def test_simulator_matches_oracle(name):
     import torch
     import afsynth
     import problems
-    from paper_2608_06853_amd import _lib
-    cfg = G.MICRO
+    print("simulator", name, flush=True)
+    cfg = afsynth.config_by_name(name)
     med = afsynth.medium_for(cfg)
     iq_o = problems.simulate_iq(cfg, med, n_seg=64)
-    cfg_, prob, iq, s, lp = G.case("micro")
+    cfg_, prob, iq, s, lp = G.case(name)
     bf = G.beamformer(cfg_, prob)
     arr, acq = cfg.array, cfg.acq
     centres = afsynth.pixel_centres(arr, cfg.img)

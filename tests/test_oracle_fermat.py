@@ -154,3 +154,88 @@ def test_discrete_search_two_candidates_are_the_interval_ends():
             t_x = np.hypot(*(x - e)) / cl + np.hypot(*(q - x)) / cm
             assert abs(r2["t_hom"][a, p] - min(t_apex, t_x)) < 1e-11
             assert r64["t_hom"][a, p] <= min(t_apex, t_x) + 1e-11
+
+
+# ---- linear array, flat lens (the L12-3v lens of Table I) ----
+
+def _linear(n=6, pitch=0.3, n_pts=24, seed=7):
+    elem = np.stack([(np.arange(n) - (n - 1) / 2) * pitch, np.zeros(n)], axis=1)
+    rng = np.random.default_rng(seed)
+    pts = np.stack([rng.uniform(-8.0, 8.0, n_pts), rng.uniform(1.5, 40.0, n_pts)], axis=1)
+    return elem, pts
+
+
+def _table1_l12():
+    c_lens, d_lens = [GOLD["table1_lens_calibration"]["L12-3v"][i] for i in (0, 1)]
+    return c_lens / 1000.0, d_lens
+
+
+def test_flat_lens_equal_speeds_and_no_lens_are_straight():
+    elem, pts = _linear()
+    d = np.hypot(pts[None, :, 0] - elem[:, None, 0], pts[None, :, 1] - elem[:, None, 1])
+    r = fermat.refract(elem, 0.67, 1.54, 1.54, pts)
+    assert np.allclose(r["t_hom"], d / 1.54, rtol=1e-12, atol=0)
+    r0 = fermat.refract(elem, 0.0, 1.0494, 1.54, pts)
+    assert np.allclose(r0["t_hom"], d / 1.54, rtol=1e-14, atol=0)
+    for n in (2, 9):
+        rd = fermat.discrete_refract(elem, 0.67, 1.54, 1.54, pts, n)
+        assert np.allclose(rd["t_hom"], d / 1.54, rtol=1e-13, atol=0)
+
+
+def test_flat_lens_normal_incidence_closed_form():
+    c_lens, d_lens = _table1_l12()
+    elem, _ = _linear(n=5)
+    depth = 20.0
+    pts = np.stack([elem[:, 0], np.full(5, d_lens + depth)], axis=1)
+    r = fermat.refract(elem, d_lens, c_lens, 1.54, pts)
+    for a in range(5):
+        assert abs(r["t_hom"][a, a] - (d_lens / c_lens + depth / 1.54)) < 1e-12
+        assert abs(r["ref_x"][a, a] - elem[a, 0]) < 1e-12
+
+
+def test_flat_lens_snell_law_with_angles():
+    c_lens, d_lens = _table1_l12()
+    elem, pts = _linear(n=6, n_pts=40, seed=8)
+    c_med = 1.50
+    r = fermat.refract(elem, d_lens, c_lens, c_med, pts)
+    for a in range(elem.shape[0]):
+        for p in range(pts.shape[0]):
+            lx, lz = r["ref_x"][a, p], r["ref_z"][a, p]
+            assert abs(lz - d_lens) < 1e-15
+            inc = math.atan2(lx - elem[a, 0], lz - elem[a, 1])   # angle to the plane's normal
+            out = math.atan2(pts[p, 0] - lx, pts[p, 1] - lz)
+            assert abs(math.sin(inc) / c_lens - math.sin(out) / c_med) < 1e-9
+
+
+def test_flat_lens_brute_force():
+    c_lens, d_lens = _table1_l12()
+    elem, pts = _linear(n=4, n_pts=12, seed=9)
+    r = fermat.refract(elem, d_lens, c_lens, 1.48, pts)
+    for a in range(4):
+        for p in range(12):
+            xs = np.linspace(min(elem[a, 0], pts[p, 0]), max(elem[a, 0], pts[p, 0]), 400001)
+            tt = (np.hypot(xs - elem[a, 0], d_lens) / c_lens
+                  + np.hypot(pts[p, 0] - xs, pts[p, 1] - d_lens) / 1.48)
+            assert r["t_hom"][a, p] <= tt.min() + 1e-13
+            assert tt.min() - r["t_hom"][a, p] < 1e-9
+
+
+def test_flat_lens_discrete_search():
+    c_lens, d_lens = _table1_l12()
+    elem, pts = _linear(n=6, n_pts=30, seed=10)
+    cm = 1.54
+    rc = fermat.refract(elem, d_lens, c_lens, cm, pts)
+    r2 = fermat.discrete_refract(elem, d_lens, c_lens, cm, pts, 2)
+    g16 = fermat.discrete_refract(elem, d_lens, c_lens, cm, pts, 16)["t_hom"] - rc["t_hom"]
+    g64 = fermat.discrete_refract(elem, d_lens, c_lens, cm, pts, 64)["t_hom"] - rc["t_hom"]
+    assert g16.min() > -1e-13 and g64.min() > -1e-13
+    assert np.median(g64) < 1.3 * (15.0 / 63.0) ** 2 * np.median(g16)
+    for a in range(elem.shape[0]):
+        xe = elem[a, 0]
+        for p in range(pts.shape[0]):
+            xp, zp = pts[p]
+            # two candidates: above the element, and where the straight ray meets the plane
+            t_up = d_lens / c_lens + math.hypot(xp - xe, zp - d_lens) / cm
+            xc = xe + (xp - xe) * d_lens / zp
+            t_x = math.hypot(xc - xe, d_lens) / c_lens + math.hypot(xp - xc, zp - d_lens) / cm
+            assert abs(r2["t_hom"][a, p] - min(t_up, t_x)) < 1e-11

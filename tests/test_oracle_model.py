@@ -16,17 +16,29 @@ SMALL = afsynth.configs.MICRO.with_(
 )
 
 
-@pytest.fixture(scope="module")
-def small_problem():
-    med = afsynth.medium_for(SMALL)
-    iq = problems.simulate_iq(SMALL, med, n_seg=64)
-    prob = problems.problem(SMALL, iq)
-    s_true = problems.true_slowness(SMALL, med, prob)
+# the same on a linear array with a flat lens
+SMALL_LINEAR = afsynth.configs.MICRO_LINEAR.with_(
+    img=afsynth.ImgCfg(n_depth=5, n_angle=5, depth_min=3.0, depth_max=12.0),
+    method=SMALL.method,
+)
+
+
+def _small(cfg):
+    med = afsynth.medium_for(cfg)
+    iq = problems.simulate_iq(cfg, med, n_seg=64)
+    prob = problems.problem(cfg, iq)
+    s_true = problems.true_slowness(cfg, med, prob)
     return prob, s_true
 
 
-def test_gradient_matches_finite_differences(small_problem):
-    prob, s_true = small_problem
+@pytest.fixture(scope="module")
+def small_problem():
+    return _small(SMALL)
+
+
+@pytest.mark.parametrize("which", ["arc", "linear"])
+def test_gradient_matches_finite_differences(small_problem, which):
+    prob, s_true = small_problem if which == "arc" else _small(SMALL_LINEAR)
     rng = np.random.default_rng(0)
     s = s_true * (1.0 + 0.01 * rng.standard_normal(s_true.shape))
     lp = problems.loss_params(SMALL, sb_ref=50.0)
