@@ -150,6 +150,18 @@ def plain_loop_report():
              "lag_one_coherence": float(bf.lag_one_coherence(iq).mean().item())}
         return q, g, env.reshape(cfg.img.n_depth, cfg.img.n_angle)
 
+    # the nine point targets of the medium: 15/30/45 mm deep at -1/3, 0, +1/3 of the
+    # half-span; lateral -6 dB width along the image row (arc length)
+    th0, th1 = afsynth.element_span(cfg.array)
+    ang = np.linspace(th0, th1, cfg.img.n_angle)
+    arc = (afsynth.lens_radius(cfg.array) + depth)[:, None] * ang[None, :]
+
+    def target_width(env2):
+        w = [metrics.point_width(env2, arc, int(np.argmin(np.abs(depth - dp))),
+                                 int(np.argmin(np.abs(ang - f * 0.5 * (th1 - th0)))))
+             for dp in (15.0, 30.0, 45.0) for f in (-1.0 / 3.0, 0.0, 1.0 / 3.0)]
+        return float(np.nanmean(w))
+
     s_hom = torch.full(bf.grid.shape, 1.0 / cfg.img.c_ref, device=bf.device)
     q0, g0, env0 = image_quality(s_hom)
     torch.cuda.synchronize()
@@ -171,7 +183,9 @@ def plain_loop_report():
             "global_metrics": {"homogeneous_1540": g0, "final": g1,
                                "change_pct": {k: 100.0 * (g1[k] / g0[k] - 1.0) for k in g0
                                               if g0[k] != 0}},
-            "tenengrad_change_pct": metrics.tenengrad_change(env0, env1, depth)}
+            "tenengrad_change_pct": metrics.tenengrad_change(env0, env1, depth),
+            "point_target_width_mm": {"homogeneous_1540": target_width(env0),
+                                      "final": target_width(env1)}}
 
 
 def lens_model_report():

@@ -11,6 +11,9 @@ slowness maps they take come from the library.
   it (the paper drew its regions by hand);
 * the generalised CNR of the same regions (Rodriguez-Molares et al.): one minus
   the overlap of the two envelope histograms, over 100 common bins;
+* the lateral -6 dB width of a point target: along the image row of the
+  envelope peak near the target, the distance between the two half-amplitude
+  crossings (linear interpolation between columns);
 * the Tenengrad sharpness change eta between an aberrated and a corrected image:
   both envelopes are log-compressed to a 60 dB display range, the corrected
   image is scaled so that its 80th-percentile amplitude equals the aberrated
@@ -82,3 +85,36 @@ def tenengrad_change(env_aberrated: np.ndarray, env_corrected: np.ndarray, depth
     sa = float(np.abs(lateral_sobel(a))[rows].sum())
     sc = float(np.abs(lateral_sobel(c))[rows].sum())
     return 100.0 * (sc / sa - 1.0) if sa > 0 else float("nan")
+
+
+def point_width(env: np.ndarray, col_mm: np.ndarray, row: int, col: int, search: int = 3) -> float:
+    """Lateral -6 dB width (mm) of the peak of envelope ``env`` [rows][cols] nearest
+    (row, col); ``col_mm`` gives the lateral position of every column, for all
+    rows ([cols]) or per row ([rows][cols]).  NaN if the half-amplitude level is
+    not crossed on both sides."""
+    env = np.asarray(env, dtype=np.float64)
+    r0, r1 = max(row - search, 0), min(row + search + 1, env.shape[0])
+    c0, c1 = max(col - search, 0), min(col + search + 1, env.shape[1])
+    win = env[r0:r1, c0:c1]
+    pr, pc = np.unravel_index(np.argmax(win), win.shape)
+    pr, pc = pr + r0, pc + c0
+    line = env[pr]
+    col_mm = np.asarray(col_mm, dtype=np.float64)
+    if col_mm.ndim == 2:
+        col_mm = col_mm[pr]
+    while pc > 0 and line[pc - 1] > line[pc]:          # climb to the row's local maximum
+        pc -= 1
+    while pc < line.size - 1 and line[pc + 1] > line[pc]:
+        pc += 1
+    half = 0.5 * line[pc]
+    pos = []
+    for step in (-1, 1):
+        k = pc
+        while 0 <= k + step < line.size and line[k + step] > half:
+            k += step
+        if not 0 <= k + step < line.size:
+            return float("nan")
+        a, b = line[k], line[k + step]          # a > half >= b
+        t = (a - half) / (a - b)
+        pos.append(col_mm[k] + t * (col_mm[k + step] - col_mm[k]))
+    return float(abs(pos[1] - pos[0]))

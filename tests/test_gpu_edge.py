@@ -103,3 +103,30 @@ def test_single_pixel():
     assert t[5] == fo["n_valid"] > 0
     assert abs(t[4] - fo["total"]) <= 1e-4 * abs(fo["total"])
     assert G.rel(grad.cpu().numpy(), go) < 1e-3
+
+
+def test_linear_array_errors():
+    """A linear array whose elements are not in increasing x, a grid that misses
+    the lens plane, and refraction-search counts outside [2, 4096] are rejected."""
+    import torch
+    from paper_2608_06853_amd import _lib
+    cfg, prob, iq, s, lp = G.case("micro_linear")
+    ctx = _ctx()
+    ctx.set_lens(prob.d_lens, prob.c_lens)
+    good = dict(elem_xz=prob.elem_xz, pix_xz=prob.centres, patch=3, patch_spacing=prob.spacing,
+                n_samples=iq.shape[2], fs=prob.fs, t0=prob.t0, fd=prob.fd, block=prob.block,
+                fnum=prob.fnum, n_seg=prob.n_seg)
+    with pytest.raises(_lib.AfError) as e:
+        ctx.set_geometry(**{**good, "elem_xz": prob.elem_xz[::-1].copy()})
+    assert e.value.status == _lib.AF_ERR_ARG and "increasing x" in str(e.value)
+    ctx.set_geometry(**good)
+    x0, z0, dx, dz, nx, nz = prob.grid
+    with pytest.raises(_lib.AfError) as e:     # grid starts below the lens plane
+        ctx.set_slowness(nx, nz, x0, prob.d_lens + 0.1, dx, dz, torch.from_numpy(s).cuda())
+    assert e.value.status == _lib.AF_ERR_ARG
+    for n in (1, -3, 4097):
+        with pytest.raises(_lib.AfError) as e:
+            ctx.set_refraction_search(n)
+        assert e.value.status == _lib.AF_ERR_ARG
+    ctx.set_refraction_search(0)
+    ctx.set_refraction_search(4096)

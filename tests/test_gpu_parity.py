@@ -124,14 +124,16 @@ def test_gradient_finite_differences_gpu(key):
         d = rng.standard_normal(s.shape)
         d -= (d * w).sum() / (w * w).sum() * w
         d *= 2e-5 * s.mean() / np.abs(d).max()
-        lv = []
+        lv, sides = [], []
         for sgn in (1.0, -1.0):
-            t, _ = bf.loss_and_grad(iq_d, lpl, torch.from_numpy((s + sgn * d).astype(np.float32)).cuda(),
-                                    want_grad=False)
+            side = (s + sgn * d).astype(np.float32)
+            sides.append(side.astype(np.float64))
+            t, _ = bf.loss_and_grad(iq_d, lpl, torch.from_numpy(side).cuda(), want_grad=False)
             lv.append(float(t[4].item()))
         fd = (lv[0] - lv[1]) / 2.0
-        an = float((g * d).sum())
-        errs.append(abs(fd - an) / (np.linalg.norm(g) * np.linalg.norm(d)))
+        d_real = (sides[0] - sides[1]) / 2.0        # the step realised in float32
+        an = float((g * d_real).sum())
+        errs.append(abs(fd - an) / (np.linalg.norm(g) * np.linalg.norm(d_real)))
     print("fd errs", errs, flush=True)
     assert np.median(errs) < 1e-2
 

@@ -55,3 +55,13 @@ def test_gcnr_limits():
     y = rng.standard_normal(400000) + 2.0
     ov = 1.0 + erf(-1.0 / sqrt(2.0))
     assert abs(metrics.gcnr(x, y) - (1.0 - ov)) < 0.02
+
+
+def test_point_width_of_a_gaussian():
+    # exp(-x^2 / (2 sig^2)) halves at x = sig sqrt(2 ln 2): width 2.3548 sig
+    x = np.linspace(-5.0, 5.0, 401)
+    sig = 0.6
+    env = np.outer(np.exp(-np.linspace(-1, 1, 9) ** 2), np.exp(-x ** 2 / (2 * sig * sig)))
+    w = metrics.point_width(env, x, 4, 205)
+    assert abs(w - 2.0 * sig * np.sqrt(2.0 * np.log(2.0))) < 1e-3
+    assert np.isnan(metrics.point_width(np.ones((3, 10)), np.arange(10.0), 1, 5))
