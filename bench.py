@@ -361,7 +361,7 @@ def s_to_target_report(n_heldout: int = 8):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: this build is single-GPU by design "
+        print(f"bench.py runs on one GPU only: the library drives a single GPU "
               f"(--gpus {args.gpus} requested; the path would shard by points)",
               file=sys.stderr)
         sys.exit(2)
