@@ -431,7 +431,11 @@ def main():
         "ms_per_step": round(dt / args.steps * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (GPU-simulated FSA data of a seeded random liver-like medium)",
-        "config": {"workload": f"{cfg.name}: {n} el curvilinear R {cfg.array.radius} mm, {n} tx, "
+        "config": {"workload": f"{cfg.name}: {n} el "
+                               + (f"linear pitch {cfg.array.pitch} mm, flat lens, "
+                                  if afsynth.is_linear(cfg.array)
+                                  else f"curvilinear R {cfg.array.radius} mm, ")
+                               + f"{n} tx, "
                                f"{cfg.acq.n_samples} IQ samples, {cfg.img.n_depth}x{cfg.img.n_angle} px "
                                f"x 3x3 patch to {cfg.img.depth_max} mm, {met.nx}x{met.nz} slowness grid, "
                                f"one loss_and_grad per step",

@@ -9,7 +9,8 @@
 // cell: the 16 tap weights are then summed across the wavefront with a
 // reduce-scatter (17 lane shuffles) and 16 lanes add the sums to the
 // wavefront's private copy of the padded grid with plain LDS read-add-writes
-// (no LDS atomics).  Lanes spread over several cells are handled one cell at a
+// (no LDS atomics).  Lanes spread over two neighbouring cells are summed as one
+// window of 4 x 5 or 5 x 4 nodes; lanes spread wider are handled one cell at a
 // time.  The copies are summed into one partial grid per workgroup, and a
 // second kernel adds the partial grids node by node in a fixed order.
 #include "af_internal.h"
@@ -39,6 +40,7 @@ __device__ inline float dpp(float x) {
   return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), CTRL, 0xf, 0xf, false));
 }
 constexpr int DPP_ROR8 = 0x128, DPP_HALF_MIRROR = 0x141, DPP_XOR2 = 0x4e, DPP_XOR1 = 0xb1;
+constexpr int DPP_ROR4 = 0x124, DPP_ROR2 = 0x122, DPP_ROR1 = 0x121;
 
 // Sum over the wavefront of v[i], i = 0..15: every lane returns the sum of
 // v[(l >> 2) & 15] (bit 3 of the index is lane bit 5, bit 2 lane bit 4, bit 1
@@ -69,6 +71,62 @@ __device__ inline float reduce_scatter16(float v[16], int lane) {
   h1 += dpp<DPP_XOR2>(h1);
   h1 += dpp<DPP_XOR1>(h1);
   return h1;
+}
+
+// Sum over the wavefront of v[r], r = 0..3: every lane returns the sum of
+// v[l >> 4].  The half-wave swaps leave row r (16 lanes) holding value r summed
+// over four lanes; rotations by 8, 4, 2 and 1 inside the row finish the sum.
+__device__ inline float reduce_scatter4(float v[4]) {
+  swap32(v[0], v[2]);  // lower half: value 0; upper half: value 2
+  v[0] += v[2];
+  swap32(v[1], v[3]);  // lower half: value 1; upper half: value 3
+  v[1] += v[3];
+  swap16(v[0], v[1]);  // rows 0, 2: v[0] of both rows; rows 1, 3: v[1] of both rows
+  float h = v[0] + v[1];
+  h += dpp<DPP_ROR8>(h);
+  h += dpp<DPP_ROR4>(h);
+  h += dpp<DPP_ROR2>(h);
+  h += dpp<DPP_ROR1>(h);
+  return h;
+}
+
+// A wavefront whose lanes sit in two neighbouring cells, cb and cb + 1
+// (horizontal) or cb and cb + W (vertical): every lane shifts its four weights
+// along that axis into a window of five nodes (by one place if it is in the
+// second cell), so the union of the taps is a 4 x 5 (or 5 x 4) block at cb.  Its
+// first 16 nodes are summed by the 16-value reduce-scatter, the last row or
+// column of four by the 4-value one.  a[r] = ck wz[r]; b[c] = wx[c].
+template <bool HORIZONTAL>
+__device__ inline void scatter_window(float* grid, int cb, int W, const float a[4], const float b[4],
+                                      bool shift, int lane, int my_off) {
+  float v16[16], v4[4];
+  if (HORIZONTAL) {
+    float bs[5];
+    bs[0] = shift ? 0.f : b[0];
+#pragma unroll
+    for (int c = 1; c < 4; ++c) bs[c] = shift ? b[c - 1] : b[c];
+    bs[4] = shift ? b[3] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v16[i] = a[i >> 2] * bs[i & 3];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v4[r] = a[r] * bs[4];
+  } else {
+    float as[5];
+    as[0] = shift ? 0.f : a[0];
+#pragma unroll
+    for (int r = 1; r < 4; ++r) as[r] = shift ? a[r - 1] : a[r];
+    as[4] = shift ? a[3] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v16[i] = as[i >> 2] * b[i & 3];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v4[c] = as[4] * b[c];
+  }
+  const float sum16 = reduce_scatter16(v16, lane);
+  if ((lane & 3) == 0) grid[cb + my_off] += sum16;
+  const float sum4 = reduce_scatter4(v4);
+  // node 4 of row (lane >> 4), or node (lane >> 4) of row 4
+  const int off4 = HORIZONTAL ? (lane >> 4) * W + 4 : 4 * W + (lane >> 4);
+  if ((lane & 15) == 0) grid[cb + off4] += sum4;
 }
 
 __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
@@ -114,15 +172,36 @@ __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
       keys_weights(u - (float)j0, wx[0], wx[1], wx[2], wx[3]);
       keys_weights(v - (float)i0, wz[0], wz[1], wz[2], wz[3]);
       const float ck = (k == 0 || k == g.n_seg) ? 0.5f * coef : coef;
+      float az[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) az[r] = ck * wz[r];
       float val[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) val[i] = ck * wz[i >> 2] * wx[i & 3];
+      for (int i = 0; i < 16; ++i) val[i] = az[i >> 2] * wx[i & 3];
       int cell = i0 * W + j0;
       const int c0 = __builtin_amdgcn_readlane(cell, lead);
       if (!live) cell = c0;  // idle lanes (zero weights) join the leader's cell
       if (__ballot(cell != c0) == 0ull) {  // the usual case: one cell for the whole wavefront
         const float sum = reduce_scatter16(val, lane);
         if ((lane & 3) == 0) grid[c0 + my_off] += sum;
+        continue;
+      }
+      // two neighbouring cells: one window reduce (cells never exceed node nx - 1 or
+      // nz - 1, so the window's fifth column or row stays inside the padded grid)
+      if (__ballot(cell != c0 && cell != c0 + 1) == 0ull) {
+        scatter_window<true>(grid, c0, W, az, wx, cell != c0, lane, my_off);
+        continue;
+      }
+      if (__ballot(cell != c0 && cell != c0 - 1) == 0ull) {
+        scatter_window<true>(grid, c0 - 1, W, az, wx, cell == c0, lane, my_off);
+        continue;
+      }
+      if (__ballot(cell != c0 && cell != c0 + W) == 0ull) {
+        scatter_window<false>(grid, c0, W, az, wx, cell != c0, lane, my_off);
+        continue;
+      }
+      if (__ballot(cell != c0 && cell != c0 - W) == 0ull) {
+        scatter_window<false>(grid, c0 - W, W, az, wx, cell == c0, lane, my_off);
         continue;
       }
       bool done = false;
