@@ -430,7 +430,8 @@ def main():
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(dt / args.steps * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (GPU-simulated FSA data of a seeded random liver-like medium)",
+        "data": "synthetic (GPU-simulated FSA data of a seeded random "
+                + ("bi-layer phantom)" if afsynth.is_linear(cfg.array) else "liver-like medium)"),
         "config": {"workload": f"{cfg.name}: {n} el "
                                + (f"linear pitch {cfg.array.pitch} mm, flat lens, "
                                   if afsynth.is_linear(cfg.array)

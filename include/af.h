@@ -12,8 +12,9 @@
  *
  * Conventions
  *   Units: mm, microseconds, MHz; speed in mm/us, slowness in us/mm.
- *   Coordinates: origin at the array's centre of curvature, x lateral, z into
- *   the body.  Host arrays are read during the call and never retained; device
+ *   Coordinates: x lateral, z into the body; the origin is the centre of
+ *   curvature of a curvilinear array (any point of the element line for a
+ *   linear array).  Host arrays are read during the call and never retained; device
  *   pointers are caller-owned and must stay valid until the work enqueued on
  *   the context's stream has finished.  Every call that takes device pointers
  *   only enqueues work on that stream (no host synchronisation); results are
@@ -69,8 +70,11 @@ void af_destroy(af_ctx* ctx);
 const char* af_last_error(const af_ctx* ctx);
 
 /* Static acquisition and imaging geometry (Section II-A, Eqs. 2-5; Section III-A).
- *   elem_xz   [n_elem][2] element centres (host, float64), on a circular arc
- *             centred at the origin; element orientation follows Eq. 3.
+ *   elem_xz   [n_elem][2] element centres (host, float64): on a circular arc
+ *             centred at the origin, in increasing polar angle (curvilinear
+ *             array, concentric lens); or on one line z = const, in increasing x
+ *             (linear array, flat lens: taken when every z agrees to 1e-9 of the
+ *             array's size).  Element orientation follows Eq. 3.
  *   pix_xz    [n_pix][2] patch centres (host, float64); each patch is a
  *             patch x patch kernel of points at patch_spacing (lambda/2), point m
  *             offset by ((m % patch - patch/2), (m / patch - patch/2)) * spacing.
@@ -81,16 +85,19 @@ const char* af_last_error(const af_ctx* ctx);
  *   n_seg     ray segments after the lens (N_segments).
  * Caller order of points: p = q * patch^2 + m for pixel q, patch point m.
  * Errors: AF_ERR_ARG if n_elem < 3, block does not divide n_elem, patch is not
- * 1 or 3, sizes are not positive, the active element set of a point is not
- * contiguous, or a tile spans more than 17 active blocks. */
+ * 1 or 3, sizes are not positive, the elements are out of order, the active
+ * element set of a point is not contiguous, or a pixel spans more active blocks
+ * than the CMPE stage holds in LDS (15 at 3 x 3 patches: the aperture is too
+ * wide for the block size). */
 af_status af_set_geometry(af_ctx* ctx, int n_elem, const double* elem_xz, int n_pix,
                     const double* pix_xz, int patch, double patch_spacing,
                     int n_samples, double fs, double t0, double fd, int block,
                     double fnum, int n_seg);
 
 /* Lens of the bent-ray model (Eqs. 7-8): thickness d_lens (elements sit that far
- * behind the concentric lens arc), lens speed c_lens, time-to-peak t_ttp added
- * to every round trip.  d_lens = 0 is the lens-free model: straight rays from the
+ * behind the concentric lens arc, or below the flat lens surface z_elem + d_lens
+ * of a linear array), lens speed c_lens, time-to-peak t_ttp added to every round
+ * trip.  d_lens = 0 is the lens-free model: straight rays from the
  * elements (the uncorrected baseline of the paper's comparisons).
  * Errors: AF_ERR_ARG for d_lens < 0 or c_lens <= 0. */
 af_status af_set_lens(af_ctx* ctx, double d_lens, double c_lens, double t_ttp);

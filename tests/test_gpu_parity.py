@@ -16,15 +16,18 @@ pytestmark = pytest.mark.gpu
 # candidates); after the first four come the lens-free straight-ray model, the
 # conventional model (straight rays plus a scalar round-trip lens offset in the
 # time-to-peak constant) and the bent-ray model with the discrete refraction search;
-# the last four are a linear array with a flat lens (plain, timing offsets,
-# lens-free, discrete search).
+# then four cases of a linear array with a flat lens (plain, timing offsets,
+# lens-free, discrete search), the linear array with 1 x 1 patches and blocks of 2,
+# and the small curvilinear case with timing offsets.
 CASES = [("micro", 0.0, 0.0, 3, None), ("c1_small", 0.0, 0.0, 3, None),
          ("micro", 0.7, 0.35, 3, None), ("micro", 0.0, 0.0, 1, 2),
          ("micro", 0.0, 0.0, 3, None, 0.01, 0.0), ("micro", 0.0, 0.5, 3, None, 0.01, 0.0),
          ("micro", 0.0, 0.0, 3, None, 0.01, None, 24),
          ("micro_linear", 0.0, 0.0, 3, None), ("micro_linear", 0.4, 0.58, 3, None),
          ("micro_linear", 0.0, 0.0, 3, None, 0.01, 0.0),
-         ("micro_linear", 0.0, 0.0, 3, None, 0.01, None, 24)]
+         ("micro_linear", 0.0, 0.0, 3, None, 0.01, None, 24),
+         ("micro_linear", 0.0, 0.0, 1, 2), ("c1_small", 0.5, 0.6, 3, None)]
+IDS = ["-".join(str(v) for v in k) for k in CASES]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -42,7 +45,7 @@ def _setup(key):
     return cfg, prob, iq, s, lp, bf, iq_d, s_d
 
 
-@pytest.mark.parametrize("key", CASES)
+@pytest.mark.parametrize("key", CASES, ids=IDS)
 def test_travel_times(key):
     cfg, prob, iq, s, lp, bf, iq_d, s_d = _setup(key)
     print("case", key, flush=True)
@@ -55,7 +58,7 @@ def test_travel_times(key):
     assert err.max() < 1e-6
 
 
-@pytest.mark.parametrize("key", CASES)
+@pytest.mark.parametrize("key", CASES, ids=IDS)
 def test_block_images_and_maps(key):
     cfg, prob, iq, s, lp, bf, iq_d, s_d = _setup(key)
     bf.ctx.loss_and_grad(iq_d, G.lib_params(lp), bf.empty_terms(), None)  # sets rho for maps
@@ -76,7 +79,7 @@ def test_block_images_and_maps(key):
     assert np.mean(d < 1e-3) > 0.98
 
 
-@pytest.mark.parametrize("key", CASES)
+@pytest.mark.parametrize("key", CASES, ids=IDS)
 def test_loss_and_gradient(key):
     import torch
     cfg, prob, iq, s, lp, bf, iq_d, s_d = _setup(key)
@@ -94,7 +97,7 @@ def test_loss_and_gradient(key):
     assert eg < 1e-3
 
 
-@pytest.mark.parametrize("key", CASES[:2])
+@pytest.mark.parametrize("key", CASES[:2], ids=IDS[:2])
 def test_autograd_function_matches_fused(key):
     import torch
     from paper_2608_06853_amd import autofocus as af
@@ -108,7 +111,8 @@ def test_autograd_function_matches_fused(key):
     assert G.rel(x.grad.cpu().numpy(), g_fused.cpu().numpy()) < 1e-5
 
 
-@pytest.mark.parametrize("key", [CASES[0], CASES[1], CASES[7]])
+@pytest.mark.parametrize("key", [CASES[0], CASES[1], CASES[7]],
+                         ids=[IDS[0], IDS[1], IDS[7]])
 def test_gradient_finite_differences_gpu(key):
     """Directional derivatives of the GPU loss along directions that keep mean(1/s)
     (hence c_med and the refraction points) fixed to first order."""
@@ -164,7 +168,8 @@ def test_discrete_refraction_search_travel_times(n_search):
         assert np.median(gap) < 1e-6
 
 
-@pytest.mark.parametrize("key", [CASES[0], CASES[1], CASES[3], CASES[4], CASES[7]])
+@pytest.mark.parametrize("key", [CASES[i] for i in (0, 1, 3, 4, 7)],
+                         ids=[IDS[i] for i in (0, 1, 3, 4, 7)])
 def test_channel_images_and_lag_one_coherence(key):
     """Receive-channel images element by element and the per-pixel lag-one
     coherence against the oracle."""
