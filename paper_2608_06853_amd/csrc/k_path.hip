@@ -11,7 +11,8 @@
 // wavefront's private copy of the padded grid with plain LDS read-add-writes
 // (no LDS atomics).  Lanes spread over two neighbouring cells are summed as one
 // window of 4 x 5 or 5 x 4 nodes; lanes spread wider are handled one cell at a
-// time.  The copies are summed into one partial grid per workgroup, and a
+// time.  The rays of two neighbouring elements are walked together and summed
+// by the same reduce whenever their cells allow it.  The copies are summed into one partial grid per workgroup, and a
 // second kernel adds the partial grids node by node in a fixed order.
 #include "af_internal.h"
 
@@ -90,36 +91,69 @@ __device__ inline float reduce_scatter4(float v[4]) {
   return h;
 }
 
-// A wavefront whose lanes sit in two neighbouring cells, cb and cb + 1
-// (horizontal) or cb and cb + W (vertical): every lane shifts its four weights
-// along that axis into a window of five nodes (by one place if it is in the
-// second cell), so the union of the taps is a 4 x 5 (or 5 x 4) block at cb.  Its
-// first 16 nodes are summed by the 16-value reduce-scatter, the last row or
-// column of four by the 4-value one.  a[r] = ck wz[r]; b[c] = wx[c].
-template <bool HORIZONTAL>
-__device__ inline void scatter_window(float* grid, int cb, int W, const float a[4], const float b[4],
-                                      bool shift, int lane, int my_off) {
+// One element's rays from the wavefront's points: start in grid coordinates, step
+// per segment, and the adjoint weight dL/dT * L2 / N of the lane's ray.
+struct Ray {
+  float u0, v0, du, dv, coef;
+  bool live;
+};
+
+// Ray point k of every lane: returns its cell and the two weight vectors whose
+// outer product az x wx gives the 16 tap weights (trapezoid end weights folded
+// into az).
+__device__ inline int ray_point(const Ray& r, int k, int nseg, float umax, float vmax, int W,
+                                float az[4], float wx[4]) {
+  const float u = __builtin_amdgcn_fmed3f(fmaf((float)k, r.du, r.u0), 0.f, umax);
+  const float v = __builtin_amdgcn_fmed3f(fmaf((float)k, r.dv, r.v0), 0.f, vmax);
+  const int j0 = (int)u, i0 = (int)v;
+  float wz[4];
+  keys_weights(u - (float)j0, wx[0], wx[1], wx[2], wx[3]);
+  keys_weights(v - (float)i0, wz[0], wz[1], wz[2], wz[3]);
+  const float ck = (k == 0 || k == nseg) ? 0.5f * r.coef : r.coef;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) az[q] = ck * wz[q];
+  return i0 * W + j0;
+}
+
+// NR ray points per lane whose cells lie in two neighbouring cells, cb and cb + 1
+// (horizontal) or cb and cb + W (vertical): every ray point shifts its four weights
+// along that axis into a window of five nodes (by one place if it is in the second
+// cell), so the union of the taps is a 4 x 5 (or 5 x 4) block at cb.  Its first 16
+// nodes are summed by the 16-value reduce-scatter, the last row or column of four by
+// the 4-value one.  (Cells never exceed node nx - 1 or nz - 1, so the window's
+// fifth column or row stays inside the padded grid.)
+template <bool HORIZONTAL, int NR>
+__device__ inline void scatter_window(float* grid, int cb, int W, const float (&a)[NR][4],
+                                      const float (&b)[NR][4], const bool (&shift)[NR], int lane,
+                                      int my_off) {
   float v16[16], v4[4];
-  if (HORIZONTAL) {
-    float bs[5];
-    bs[0] = shift ? 0.f : b[0];
 #pragma unroll
-    for (int c = 1; c < 4; ++c) bs[c] = shift ? b[c - 1] : b[c];
-    bs[4] = shift ? b[3] : 0.f;
+  for (int i = 0; i < 16; ++i) v16[i] = 0.f;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v16[i] = a[i >> 2] * bs[i & 3];
+  for (int q = 0; q < 4; ++q) v4[q] = 0.f;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) v4[r] = a[r] * bs[4];
-  } else {
-    float as[5];
-    as[0] = shift ? 0.f : a[0];
+  for (int n = 0; n < NR; ++n) {
+    if (HORIZONTAL) {
+      float bs[5];
+      bs[0] = shift[n] ? 0.f : b[n][0];
 #pragma unroll
-    for (int r = 1; r < 4; ++r) as[r] = shift ? a[r - 1] : a[r];
-    as[4] = shift ? a[3] : 0.f;
+      for (int c = 1; c < 4; ++c) bs[c] = shift[n] ? b[n][c - 1] : b[n][c];
+      bs[4] = shift[n] ? b[n][3] : 0.f;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v16[i] = as[i >> 2] * b[i & 3];
+      for (int i = 0; i < 16; ++i) v16[i] = fmaf(a[n][i >> 2], bs[i & 3], v16[i]);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) v4[c] = as[4] * b[c];
+      for (int r = 0; r < 4; ++r) v4[r] = fmaf(a[n][r], bs[4], v4[r]);
+    } else {
+      float as[5];
+      as[0] = shift[n] ? 0.f : a[n][0];
+#pragma unroll
+      for (int r = 1; r < 4; ++r) as[r] = shift[n] ? a[n][r - 1] : a[n][r];
+      as[4] = shift[n] ? a[n][3] : 0.f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v16[i] = fmaf(as[i >> 2], b[n][i & 3], v16[i]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v4[c] = fmaf(as[4], b[n][c], v4[c]);
+    }
   }
   const float sum16 = reduce_scatter16(v16, lane);
   if ((lane & 3) == 0) grid[cb + my_off] += sum16;
@@ -127,6 +161,98 @@ __device__ inline void scatter_window(float* grid, int cb, int W, const float a[
   // node 4 of row (lane >> 4), or node (lane >> 4) of row 4
   const int off4 = HORIZONTAL ? (lane >> 4) * W + 4 : 4 * W + (lane >> 4);
   if ((lane & 15) == 0) grid[cb + off4] += sum4;
+}
+
+// Adds the tap weights of NR ray points per lane (cells in `cell`, idle lanes
+// already moved to c0 with zero weights) when the union of their cells is the one
+// cell c0 or two neighbouring cells; returns false, writing nothing, otherwise.
+template <int NR>
+__device__ inline bool scatter_union(float* grid, int c0, int W, const int (&cell)[NR],
+                                     const float (&az)[NR][4], const float (&wx)[NR][4], int lane,
+                                     int my_off) {
+  bool one = true;
+#pragma unroll
+  for (int n = 0; n < NR; ++n) one = one && cell[n] == c0;
+  if (__ballot(!one) == 0ull) {  // the usual case: one cell for the whole wavefront
+    float val[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      val[i] = az[0][i >> 2] * wx[0][i & 3];
+#pragma unroll
+      for (int n = 1; n < NR; ++n) val[i] = fmaf(az[n][i >> 2], wx[n][i & 3], val[i]);
+    }
+    const float sum = reduce_scatter16(val, lane);
+    if ((lane & 3) == 0) grid[c0 + my_off] += sum;
+    return true;
+  }
+  // the other cell, relative to c0: +1, -1, +W or -W for every lane (0 if none)
+  int d = 0;
+#pragma unroll
+  for (int n = 0; n < NR; ++n) d = cell[n] != c0 ? cell[n] - c0 : d;
+  const int dd = __builtin_amdgcn_readlane(d, __ffsll((long long)__ballot(d != 0)) - 1);
+  bool same = true;
+#pragma unroll
+  for (int n = 0; n < NR; ++n) same = same && (cell[n] == c0 || cell[n] - c0 == dd);
+  if (__ballot(!same) != 0ull || (dd != 1 && dd != -1 && dd != W && dd != -W)) return false;
+  bool shift[NR];
+  const bool h = dd == 1, hl = dd == -1, v = dd == W;
+  if (h) {
+#pragma unroll
+    for (int n = 0; n < NR; ++n) shift[n] = cell[n] != c0;
+    scatter_window<true, NR>(grid, c0, W, az, wx, shift, lane, my_off);
+    return true;
+  }
+  if (hl) {
+#pragma unroll
+    for (int n = 0; n < NR; ++n) shift[n] = cell[n] == c0;
+    scatter_window<true, NR>(grid, c0 - 1, W, az, wx, shift, lane, my_off);
+    return true;
+  }
+  if (v) {
+#pragma unroll
+    for (int n = 0; n < NR; ++n) shift[n] = cell[n] != c0;
+    scatter_window<false, NR>(grid, c0, W, az, wx, shift, lane, my_off);
+    return true;
+  }
+#pragma unroll
+  for (int n = 0; n < NR; ++n) shift[n] = cell[n] == c0;
+  scatter_window<false, NR>(grid, c0 - W, W, az, wx, shift, lane, my_off);
+  return true;
+}
+
+// One ray point per lane spread over more cells: one masked reduce round per
+// distinct cell (idle lanes already moved to c0 with zero weights).
+__device__ inline void scatter_rounds(float* grid, int c0, int cell, const float (&az)[4],
+                                      const float (&wx)[4], int lane, int my_off) {
+  float val[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) val[i] = az[i >> 2] * wx[i & 3];
+  bool done = false;
+  int ccur = c0;
+  while (true) {
+    const bool in = !done && cell == ccur;
+    float vv[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) vv[i] = in ? val[i] : 0.f;
+    const float sum = reduce_scatter16(vv, lane);
+    if ((lane & 3) == 0) grid[ccur + my_off] += sum;
+    done = done || in;
+    const unsigned long long rest = __ballot(!done);
+    if (rest == 0ull) break;
+    ccur = __builtin_amdgcn_readlane(cell, __ffsll((long long)rest) - 1);
+  }
+}
+
+// One ray point per lane, any spread.
+__device__ inline void scatter_one(float* grid, int cell, bool live, int lead, int W,
+                                   const float (&az)[4], const float (&wx)[4], int lane,
+                                   int my_off) {
+  const int c0 = __builtin_amdgcn_readlane(cell, lead);
+  const int c[1] = {live ? cell : c0};  // idle lanes (zero weights) join the leader's cell
+  const float a1[1][4] = {{az[0], az[1], az[2], az[3]}};
+  const float b1[1][4] = {{wx[0], wx[1], wx[2], wx[3]}};
+  if (!scatter_union<1>(grid, c0, W, c, a1, b1, lane, my_off))
+    scatter_rounds(grid, c0, c[0], az, wx, lane, my_off);
 }
 
 __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
@@ -152,73 +278,55 @@ __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
   const int my_tap = (lane >> 2) & 15;
   const int my_off = (my_tap >> 2) * W + (my_tap & 3);
 
-  for (int a = tr.x; a <= tr.y; ++a) {  // wavefront-uniform loop
-    const bool act = a >= pr.x && a <= pr.y;
-    float gbar = 0.f;
-    if (act) gbar = A.gT[(long long)a * g.P + p] + A.gT2[(long long)a * g.P + p];
-    const bool live = act && gbar != 0.f;
-    const unsigned long long lmask = __ballot(live);
-    if (lmask == 0ull) continue;
-    const float2 ruv = A.ray_uv[(long long)a * g.P + p];
-    const float coef = live ? gbar * A.ray_l2[(long long)a * g.P + p] * inv_n : 0.f;
-    const float u0 = ruv.x, v0 = ruv.y;
-    const float du = (up - u0) * inv_n, dv = (vp - v0) * inv_n;
-    const int lead = __ffsll((long long)lmask) - 1;
+  // Elements two at a time: the rays of neighbouring elements to the same points
+  // run side by side, so at a step their ray points usually share one cell (or two
+  // neighbouring cells) and one reduce covers both.
+  for (int a = tr.x; a <= tr.y; a += 2) {  // wavefront-uniform loop
+    Ray R[2];
+    unsigned long long lm[2];
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      const int e = a + n;
+      const bool act = e <= tr.y && e >= pr.x && e <= pr.y;
+      float gbar = 0.f;
+      if (act) gbar = A.gT[(long long)e * g.P + p] + A.gT2[(long long)e * g.P + p];
+      R[n].live = act && gbar != 0.f;
+      lm[n] = __ballot(R[n].live);
+      R[n].coef = 0.f;
+      R[n].u0 = R[n].v0 = R[n].du = R[n].dv = 0.f;
+      if (lm[n] != 0ull) {
+        const float2 ruv = A.ray_uv[(long long)e * g.P + p];
+        if (R[n].live) R[n].coef = gbar * A.ray_l2[(long long)e * g.P + p] * inv_n;
+        R[n].u0 = ruv.x;
+        R[n].v0 = ruv.y;
+        R[n].du = (up - ruv.x) * inv_n;
+        R[n].dv = (vp - ruv.y) * inv_n;
+      }
+    }
+    if ((lm[0] | lm[1]) == 0ull) continue;
+    if (lm[0] == 0ull || lm[1] == 0ull) {  // one element with work
+      const Ray& r = lm[0] != 0ull ? R[0] : R[1];
+      const int lead = __ffsll((long long)(lm[0] | lm[1])) - 1;
+      for (int k = 0; k <= g.n_seg; ++k) {
+        float az[4], wx[4];
+        const int cell = ray_point(r, k, g.n_seg, umax, vmax, W, az, wx);
+        scatter_one(grid, cell, r.live, lead, W, az, wx, lane, my_off);
+      }
+      continue;
+    }
+    const int lead = __ffsll((long long)(lm[0] | lm[1])) - 1;
+    const int lead0 = __ffsll((long long)lm[0]) - 1, lead1 = __ffsll((long long)lm[1]) - 1;
     for (int k = 0; k <= g.n_seg; ++k) {
-      const float u = __builtin_amdgcn_fmed3f(fmaf((float)k, du, u0), 0.f, umax);
-      const float v = __builtin_amdgcn_fmed3f(fmaf((float)k, dv, v0), 0.f, vmax);
-      const int j0 = (int)u, i0 = (int)v;
-      float wx[4], wz[4];
-      keys_weights(u - (float)j0, wx[0], wx[1], wx[2], wx[3]);
-      keys_weights(v - (float)i0, wz[0], wz[1], wz[2], wz[3]);
-      const float ck = (k == 0 || k == g.n_seg) ? 0.5f * coef : coef;
-      float az[4];
+      float az[2][4], wx[2][4];
+      int cell[2];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) az[r] = ck * wz[r];
-      float val[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) val[i] = az[i >> 2] * wx[i & 3];
-      int cell = i0 * W + j0;
-      const int c0 = __builtin_amdgcn_readlane(cell, lead);
-      if (!live) cell = c0;  // idle lanes (zero weights) join the leader's cell
-      if (__ballot(cell != c0) == 0ull) {  // the usual case: one cell for the whole wavefront
-        const float sum = reduce_scatter16(val, lane);
-        if ((lane & 3) == 0) grid[c0 + my_off] += sum;
-        continue;
-      }
-      // two neighbouring cells: one window reduce (cells never exceed node nx - 1 or
-      // nz - 1, so the window's fifth column or row stays inside the padded grid)
-      if (__ballot(cell != c0 && cell != c0 + 1) == 0ull) {
-        scatter_window<true>(grid, c0, W, az, wx, cell != c0, lane, my_off);
-        continue;
-      }
-      if (__ballot(cell != c0 && cell != c0 - 1) == 0ull) {
-        scatter_window<true>(grid, c0 - 1, W, az, wx, cell == c0, lane, my_off);
-        continue;
-      }
-      if (__ballot(cell != c0 && cell != c0 + W) == 0ull) {
-        scatter_window<false>(grid, c0, W, az, wx, cell != c0, lane, my_off);
-        continue;
-      }
-      if (__ballot(cell != c0 && cell != c0 - W) == 0ull) {
-        scatter_window<false>(grid, c0 - W, W, az, wx, cell == c0, lane, my_off);
-        continue;
-      }
-      bool done = false;
-      int ccur = c0;
-      // one round per distinct cell among the wavefront's lanes
-      while (true) {
-        const bool in = !done && cell == ccur;
-        float vv[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) vv[i] = in ? val[i] : 0.f;
-        const float sum = reduce_scatter16(vv, lane);
-        if ((lane & 3) == 0) grid[ccur + my_off] += sum;
-        done = done || in;
-        const unsigned long long rest = __ballot(!done);
-        if (rest == 0ull) break;
-        ccur = __builtin_amdgcn_readlane(cell, __ffsll((long long)rest) - 1);
-      }
+      for (int n = 0; n < 2; ++n) cell[n] = ray_point(R[n], k, g.n_seg, umax, vmax, W, az[n], wx[n]);
+      const int c0 = __builtin_amdgcn_readlane(R[0].live ? cell[0] : cell[1], lead);
+      const int cu[2] = {R[0].live ? cell[0] : c0, R[1].live ? cell[1] : c0};
+      if (scatter_union<2>(grid, c0, W, cu, az, wx, lane, my_off)) continue;
+      // the two ray points of a lane lie wider apart: each element on its own
+      scatter_one(grid, cell[0], R[0].live, lead0, W, az[0], wx[0], lane, my_off);
+      scatter_one(grid, cell[1], R[1].live, lead1, W, az[1], wx[1], lane, my_off);
     }
   }
   __syncthreads();
