@@ -98,6 +98,40 @@ __device__ inline bool interior(const TabEntry& et, int rmin, int rmax, int ns) 
   return __ballot(!in) == 0ull;
 }
 
+// Span of the sample index sums of this lane's active receive entries (nonzero
+// phasor); lo > hi when none is active.
+struct RxSpan {
+  int lo, hi;
+};
+template <int S>
+__device__ inline RxSpan rx_span(const Rx (&rx)[S]) {
+  RxSpan sp{1 << 29, -(1 << 29)};
+#pragma unroll
+  for (int k = 0; k < S; ++k)
+    if (rx[k].e.x != 0.f || rx[k].e.y != 0.f) {
+      sp.lo = min(sp.lo, rx[k].ui);
+      sp.hi = max(sp.hi, rx[k].ui);
+    }
+  return sp;
+}
+
+// Wavefront-uniform: no lane has a sample of transmit element t inside the
+// record.  A sample reads index ui_t + ui_r + carry (carry 0 or 1) and counts
+// only for an index in [0, ns - 1], so a lane contributes nothing when its
+// transmit entry is masked or every ui_t + ui_r lies above ns - 1 or below -1.
+// (Taken only for wavefronts that are not entirely inside the record.)
+__device__ inline bool wave_silent(const TabEntry& et, RxSpan sp, int ns) {
+  const bool live = (et.er != 0.f || et.ei != 0.f) && et.ui + sp.hi + 1 >= 0 &&
+                    et.ui + sp.lo <= ns - 1;
+  return __ballot(live) == 0ull;
+}
+// The same test with the span formed on the spot (for kernels at their register
+// limit, where keeping the span across the transmit loop would spill).
+template <int S>
+__device__ inline bool wave_silent(const TabEntry& et, const Rx (&rx)[S], int ns) {
+  return wave_silent(et, rx_span<S>(rx), ns);
+}
+
 template <int S>
 __device__ inline void das_fwd_t(const float2* __restrict__ base, int ns, const TabEntry& et,
                                  const Rx (&rx)[S], bool check, float2& acc) {
@@ -166,6 +200,7 @@ __global__ __launch_bounds__(256) void k_das_fwd(DasArgs A) {
   }
   const WaveRange wr = wave_range(A.prange, p, tr, jb, S);
   const int tlo = wr.rx_active ? wr.lo : tr.y + 1, thi = wr.rx_active ? wr.hi : tr.x - 1;
+  const RxSpan sp = rx_span<S>(rx);
 
   for (int ib = tr.z; ib <= tr.w; ++ib) {
     float2 acc = make_float2(0.f, 0.f);
@@ -174,8 +209,11 @@ __global__ __launch_bounds__(256) void k_das_fwd(DasArgs A) {
       TabEntry et = A.tab[(long long)t0 * P + p];
       for (int t = t0; t <= t1; ++t) {
         const TabEntry en = A.tab[(long long)min(t + 1, t1) * P + p];
-        const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
-        das_fwd_t<S>(base, ns, et, rx, !interior(et, rmin, rmax, ns), acc);
+        const bool inside = interior(et, rmin, rmax, ns);
+        if (inside || !wave_silent(et, sp, ns)) {
+          const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
+          das_fwd_t<S>(base, ns, et, rx, !inside, acc);
+        }
         et = en;
       }
     }
@@ -253,13 +291,16 @@ __global__ __launch_bounds__(256, 4) void k_das_adj(DasArgs A) {
       TabEntry et = A.tab[(long long)t0 * P + p];
       for (int t = t0; t <= t1; ++t) {
         const TabEntry en = A.tab[(long long)min(t + 1, t1) * P + p];
-        // Q = conj(G) * E_t
-        const float qx = G.x * et.er + G.y * et.ei;
-        const float qy = G.x * et.ei - G.y * et.er;
-        const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
-        float gtx = 0.f;
-        das_adj_t<S>(base, ns, et, rx, !interior(et, rmin, rmax, ns), qx, qy, fsf, om, grx, gtx);
-        if (gtx != 0.f) atomicAdd(A.gT2 + (long long)t * P + p, gtx);
+        const bool inside = interior(et, rmin, rmax, ns);
+        if (inside || !wave_silent<S>(et, rx, ns)) {
+          // Q = conj(G) * E_t
+          const float qx = G.x * et.er + G.y * et.ei;
+          const float qy = G.x * et.ei - G.y * et.er;
+          const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
+          float gtx = 0.f;
+          das_adj_t<S>(base, ns, et, rx, !inside, qx, qy, fsf, om, grx, gtx);
+          if (gtx != 0.f) atomicAdd(A.gT2 + (long long)t * P + p, gtx);
+        }
         et = en;
       }
     }
@@ -300,13 +341,15 @@ __global__ __launch_bounds__(256) void k_das_rx(DasArgs A, float2* __restrict__ 
   float2 acc[S];
 #pragma unroll
   for (int k = 0; k < S; ++k) acc[k] = make_float2(0.f, 0.f);
+  const RxSpan sp = rx_span<S>(rx);
   for (int t = tlo; t <= thi; ++t) {
     const TabEntry et = A.tab[(long long)t * P + p];
+    const bool check = !interior(et, rmin, rmax, ns);
+    if (check && wave_silent(et, sp, ns)) continue;
     const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
     float2 a0[S], a1[S];
     float fr[S];
     bool ok[S];
-    const bool check = !interior(et, rmin, rmax, ns);
     if (check) gather<S, true>(base, ns, et, rx, a0, a1, fr, ok);
     else gather<S, false>(base, ns, et, rx, a0, a1, fr, ok);
 #pragma unroll
