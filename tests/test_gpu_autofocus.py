@@ -51,11 +51,16 @@ def test_five_adam_steps_tiny_config():
     assert dev < 1e-2
 
 
+@pytest.mark.parametrize("name", ["c1_small", "micro_linear"])
 @pytest.mark.parametrize("dynamic", [True, False])
-def test_dynamic_grid_sweep_matches_oracle(dynamic):
+def test_dynamic_grid_sweep_matches_oracle(dynamic, name):
+    """CMPE of each swept speed on the dynamic (or static) grid against the oracle's
+    sweep: on the curvilinear array (depths stretched along the polar angle) and
+    on the linear array (depths stretched straight down)."""
     import torch
     from paper_2608_06853_amd import autofocus as af
-    cfg = G.C1_SMALL
+    print("sweep", name, "dynamic" if dynamic else "static", flush=True)
+    cfg = G.C1_SMALL if name == "c1_small" else afsynth.configs.MICRO_LINEAR
     med = afsynth.medium_for(cfg)
     iq = problems.simulate_iq(cfg, med, n_seg=64).astype(np.complex64)
     speeds = np.array([1.46, 1.49, 1.52, 1.55, 1.58])
@@ -70,10 +75,12 @@ def test_dynamic_grid_sweep_matches_oracle(dynamic):
     assert best_g == best_o
 
 
-def test_plain_loop_descends():
+@pytest.mark.parametrize("name", ["c3_plain_loop", "l1_linear"])
+def test_plain_loop_descends(name):
     import torch
     from paper_2608_06853_amd import _lib, autofocus as af, workloads
-    cfg = afsynth.configs.C3
+    print("plain loop", name, flush=True)
+    cfg = afsynth.config_by_name(name)
     bf, iq, med = workloads.build(cfg)
     _, vals, best = af.sweep(bf, iq, workloads.loss_params(cfg), cfg.acq.fc)
     s, hist = af.plain_autofocus(bf, iq, workloads.loss_params(cfg),
