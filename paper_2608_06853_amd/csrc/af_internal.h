@@ -107,7 +107,6 @@ struct PathArgs {
   const int* order;
   const float* gT;        // dL/dT [n_elem][P], receive role
   const float* gT2;       // dL/dT [n_elem][P], transmit role
-  const double* scal;
   float* gpart;           // [n_wg][padded nodes] per-workgroup partial grids
 };
 

@@ -4,16 +4,17 @@
 // start and medium leg L2 are read from the table kernel of the same slowness.
 //
 // A workgroup takes one tile of points and every active element of it; a
-// wavefront walks the rays from one element to its 64 points in lock step.  The
+// wavefront walks the rays from the elements to its 64 points in lock step.  The
 // rays are nearly parallel, so at a given step the lanes usually sit in one grid
 // cell: the 16 tap weights are then summed across the wavefront with a
 // reduce-scatter (17 lane shuffles) and 16 lanes add the sums to the
 // wavefront's private copy of the padded grid with plain LDS read-add-writes
 // (no LDS atomics).  Lanes spread over two neighbouring cells are summed as one
 // window of 4 x 5 or 5 x 4 nodes; lanes spread wider are handled one cell at a
-// time.  The rays of two neighbouring elements are walked together and summed
-// by the same reduce whenever their cells allow it.  The copies are summed into one partial grid per workgroup, and a
-// second kernel adds the partial grids node by node in a fixed order.
+// time.  The rays of two neighbouring elements are walked together and summed by
+// the same reduce whenever their cells allow it.  The copies are summed into one
+// partial grid per workgroup, and a second kernel adds the partial grids node by
+// node in a fixed order.
 #include "af_internal.h"
 
 namespace af {
@@ -395,7 +396,6 @@ hipError_t launch_path_adj(af_ctx* c) {
   A.order = c->d_order.as<int>();
   A.gT = c->d_gT.as<float>();
   A.gT2 = c->d_gT.as<float>() + (size_t)c->N * c->P_int;
-  A.scal = c->d_scal.as<double>();
   A.gpart = c->d_gpart.as<float>();
   const size_t lds = sizeof(float) * (size_t)nodes * 4;
   hipLaunchKernelGGL(k_path_adj, dim3(c->n_order), dim3(256), lds, c->stream, A);
