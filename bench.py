@@ -32,6 +32,7 @@ UNIT = "Gsamples/s"
 # MI355X published peaks
 PEAK_FP32_TFLOPS = 157.3        # 256 CU x 2.4 GHz x 256 FP32 flop/clk/CU
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0       # dense MFMA, no sparsity
 
 # Algorithmic FP32 operations per unit of each kernel (counted from the arithmetic
 # the step needs, not from the compiled code).
@@ -55,6 +56,8 @@ def parse():
                     help="only run a plain device copy of known size (HBM counter scale)")
     ap.add_argument("--no-autofocus", action="store_true",
                     help="skip the plain-loop report and the learned-vs-plain s-to-target runs")
+    ap.add_argument("--reports", default="all",
+                    help="comma-separated report names to run after the timed steps (default all)")
     return ap.parse_args()
 
 
@@ -358,6 +361,78 @@ def s_to_target_report(n_heldout: int = 8):
     return out
 
 
+def conv_counts(B: int):
+    """Algorithmic FLOPs and compulsory HBM bytes per call family of one forward
+    and one backward over a batch of B feature maps, from the layer shapes
+    (unpadded K = 9 Cin; BF16 activations, FP32 network output)."""
+    from paper_2608_06853_amd import cnn
+    fl = {"conv_fwd": 0.0, "conv_bwd_data": 0.0, "conv_bwd_weight": 0.0}
+    by = dict(fl)
+    h, w = cnn.FEAT_H, cnn.FEAT_W
+    for li, (ci, co, st, relu) in enumerate(cnn.LAYERS):
+        ho, wo = cnn.out_size(h, st), cnn.out_size(w, st)
+        mac = 2.0 * B * ho * wo * co * 9 * ci
+        x_b, y_b = 2.0 * B * h * w * ci, (2.0 if relu else 4.0) * B * ho * wo * co
+        g_b = 2.0 * B * ho * wo * co
+        fl["conv_fwd"] += mac
+        by["conv_fwd"] += x_b + y_b
+        fl["conv_bwd_weight"] += mac
+        by["conv_bwd_weight"] += x_b + g_b
+        if li > 0:       # input gradient: read dout and the ReLU mask, write din
+            fl["conv_bwd_data"] += mac
+            by["conv_bwd_data"] += g_b + 2 * x_b
+        h, w = ho, wo
+    return fl, by
+
+
+def cnn_report(reps: int = 20):
+    """The learned warm start's BF16 MFMA convolutions on random inputs of the
+    feature shape: inference (forward) at batch 256 and a training step (forward,
+    loss, backward, Adam) at the training batch of 32 and at 256.  Per call family:
+    time per pass from HIP events, achieved TFLOP/s and GB/s, and the fraction of
+    the bound that applies (HBM: the layers carry 40 FLOP per compulsory byte,
+    below the BF16 ridge of 312)."""
+    import torch
+    from paper_2608_06853_amd import _lib, cnn
+    ctx = _lib.Context(0)
+    net = cnn.WarmStartNet(ctx, seed=0)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    out = {}
+    for mode, B in (("forward", 256), ("train_step", 32), ("train_step", 256)):
+        x = torch.randn((B, cnn.FEAT_H, cnn.FEAT_W, 2), device="cuda",
+                        generator=g).to(torch.bfloat16)
+        lab = 0.1 * torch.randn((B, cnn.OUT_H, cnn.OUT_W), device="cuda", generator=g)
+        step = (lambda: net.forward(x, B)) if mode == "forward" else \
+            (lambda: net.train_step(x, lab, B, 1e-4))
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        ctx.set_profiling(True)
+        ctx.profile_read()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        prof = ctx.profile_read()
+        ctx.set_profiling(False)
+        fl, by = conv_counts(B)
+        fam = {}
+        for k in fl:
+            if k not in prof:
+                continue
+            t = prof[k][0] / reps / 1e3
+            tf, gb = fl[k] / t / 1e12, by[k] / t / 1e9
+            fam[k] = {"ms": round(t * 1e3, 4), "launches": prof[k][1] // reps,
+                      "TFLOP_per_s": round(tf, 2), "GB_per_s": round(gb, 1),
+                      "hbm_frac": round(gb / PEAK_HBM_GBS, 3),
+                      "bf16_mfma_frac": round(tf / PEAK_BF16_TFLOPS, 4)}
+        out[f"{mode}_b{B}"] = {"ms_per_pass": round(wall * 1e3, 4),
+                               "samples_per_s": round(B / wall, 1), "families": fam}
+        del x, lab
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -458,7 +533,10 @@ def main():
                         ("linear_array", linear_array_report),
                         ("grid_init", grid_init_report),
                         ("refraction_search", refraction_search_report),
+                        ("cnn_kernels", cnn_report),
                         ("s_to_target", s_to_target_report)):
+            if args.reports != "all" and key not in args.reports.split(","):
+                continue
             print(f"report {key}", file=sys.stderr, flush=True)
             out[key] = fn()
         out["autofocus_report_seconds"] = round(time.perf_counter() - t0, 1)

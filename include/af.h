@@ -214,8 +214,11 @@ af_status af_simulate(af_ctx* ctx, int n_scat, const double* scat_xz, const floa
  * FP32.  Ho = (H - 1) / stride + 1, likewise Wo.  Kp = 9 Cin and Ktp = 9 Cout,
  * each rounded up to a multiple of 16.  All pointers are device pointers; every
  * call only enqueues on the context stream.  These calls need no geometry.
+ * Activation pointers are 16-byte aligned when their channel count is a multiple
+ * of 8 (8-byte when a multiple of 4).
  * Errors: AF_ERR_ARG for Cin or Cout outside 1..32, stride not 1 or 2, non-
- * positive sizes or a null required pointer. */
+ * positive sizes, activations of 2 GiB or more (B H W max(Cin, Cout) BF16 values)
+ * or a null required pointer. */
 
 /* Packs FP32 weights w[Cout][3][3][Cin] into the BF16 operands of the forward,
  * wpack [32][Kp] (row = output channel), and of the backward-data pass, wtpack
@@ -258,14 +261,17 @@ af_status af_polar_to_grid(af_ctx* ctx, const float* map, int nr, int nt, double
                            double t0, double dt, int nx, int nz, double x0, double z0,
                            double dx, double dz, float s_base, float scale, float* s_dev);
 
-/* Kernel timing with HIP events on the context stream.  While enabled, every
- * kernel the library launches is bracketed by two events; af_profile_read waits
- * for the stream, returns the summed milliseconds and launch counts per kernel
- * family (arrays of AF_K_COUNT entries, host) and clears the record. */
+/* Kernel timing with HIP events on the context stream.  While enabled, each
+ * kernel of the loss, gradient and update calls and each convolution call (the
+ * weight gradient counts its partial-sum reduce with it) is bracketed by two
+ * events; af_profile_read waits for the stream, returns the summed milliseconds
+ * and launch counts per kernel family (arrays of AF_K_COUNT entries, host) and
+ * clears the record. */
 enum {
   AF_K_PREPARE = 0, AF_K_TABLE = 1, AF_K_DAS_FWD = 2, AF_K_CMPE = 3, AF_K_FINALIZE = 4,
   AF_K_GSCALE = 5, AF_K_DAS_ADJ = 6, AF_K_PATH_ADJ = 7, AF_K_FOLD = 8, AF_K_ADAM = 9,
-  AF_K_EXPORT = 10, AF_K_COUNT = 11
+  AF_K_EXPORT = 10, AF_K_CONV_FWD = 11, AF_K_CONV_BWD_DATA = 12, AF_K_CONV_BWD_WEIGHT = 13,
+  AF_K_COUNT = 14
 };
 af_status af_set_profiling(af_ctx* ctx, int enable);
 af_status af_profile_read(af_ctx* ctx, double* ms, long long* calls);

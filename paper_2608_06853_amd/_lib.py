@@ -35,7 +35,8 @@ EXPORTS = [
     "af_conv3x3_bwd_weight", "af_mse_loss", "af_adam_update", "af_features", "af_polar_to_grid",
 ]
 KERNELS = ["prepare_grid", "table", "das_fwd", "cmpe", "finalize", "gscale", "das_adj",
-           "path_adj", "grad_fold", "adam", "export"]
+           "path_adj", "grad_fold", "adam", "export", "conv_fwd", "conv_bwd_data",
+           "conv_bwd_weight"]
 
 
 class LossParams(C.Structure):

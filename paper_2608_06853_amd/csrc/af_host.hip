@@ -831,6 +831,8 @@ static af_status conv_args(af_ctx* c, int B, int H, int W, int Cin, int Cout, in
   if (B <= 0 || H <= 0 || W <= 0 || Cin < 1 || Cin > 32 || Cout < 1 || Cout > 32 ||
       (stride != 1 && stride != 2))
     return fail(c, AF_ERR_ARG, "af_conv3x3: need 1 <= Cin, Cout <= 32, stride 1 or 2, positive sizes");
+  if ((long long)B * H * W * std::max(Cin, Cout) * 2 >= (1LL << 31))
+    return fail(c, AF_ERR_ARG, "af_conv3x3: activations of 2 GiB or more");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, AF_ERR_HIP, "hipSetDevice");
   return AF_OK;
 }
@@ -849,8 +851,9 @@ af_status af_conv3x3_fwd(af_ctx* c, int B, int H, int W, int Cin, int Cout, int 
   af_status st = conv_args(c, B, H, W, Cin, Cout, stride);
   if (st != AF_OK) return st;
   if (!in || !wpack || !bias || (!out && !outf)) return fail(c, AF_ERR_ARG, "af_conv3x3_fwd: null pointer");
-  AF_HIP(af::launch_conv_fwd(c, B, H, W, Cin, Cout, stride, relu, in, wpack, bias, out, outf),
-         "conv fwd");
+  AF_KERNEL(AF_K_CONV_FWD,
+            af::launch_conv_fwd(c, B, H, W, Cin, Cout, stride, relu, in, wpack, bias, out, outf),
+            "conv fwd");
   return AF_OK;
 }
 
@@ -859,8 +862,9 @@ af_status af_conv3x3_bwd_data(af_ctx* c, int B, int H, int W, int Cin, int Cout,
   af_status st = conv_args(c, B, H, W, Cin, Cout, stride);
   if (st != AF_OK) return st;
   if (!dout || !wtpack || !din) return fail(c, AF_ERR_ARG, "af_conv3x3_bwd_data: null pointer");
-  AF_HIP(af::launch_conv_bwd_data(c, B, H, W, Cin, Cout, stride, dout, wtpack, act, din),
-         "conv bwd data");
+  AF_KERNEL(AF_K_CONV_BWD_DATA,
+            af::launch_conv_bwd_data(c, B, H, W, Cin, Cout, stride, dout, wtpack, act, din),
+            "conv bwd data");
   return AF_OK;
 }
 
@@ -869,8 +873,9 @@ af_status af_conv3x3_bwd_weight(af_ctx* c, int B, int H, int W, int Cin, int Cou
   af_status st = conv_args(c, B, H, W, Cin, Cout, stride);
   if (st != AF_OK) return st;
   if (!in || !dout || !dw || !db) return fail(c, AF_ERR_ARG, "af_conv3x3_bwd_weight: null pointer");
-  AF_HIP(af::launch_conv_bwd_weight(c, B, H, W, Cin, Cout, stride, in, dout, dw, db),
-         "conv bwd weight");
+  AF_KERNEL(AF_K_CONV_BWD_WEIGHT,
+            af::launch_conv_bwd_weight(c, B, H, W, Cin, Cout, stride, in, dout, dw, db),
+            "conv bwd weight");
   return AF_OK;
 }
 

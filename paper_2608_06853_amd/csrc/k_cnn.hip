@@ -8,6 +8,8 @@
 // element j of the 16-wide accumulator):
 //   A[m = l % 32][k = 8 (l / 32) + i],  B[k = 8 (l / 32) + i][n = l % 32],
 //   C[m = 8 (j / 4) + 4 (l / 32) + j % 4][n = l % 32].
+#include <algorithm>
+#include <climits>
 #include <cstdint>
 
 #include "af_internal.h"
@@ -36,35 +38,84 @@ __device__ inline bf16x8 zero8() {
   return z;
 }
 
-// --- forward ----------------------------------------------------------------------
-// A[m = output pixel][k = tap * Cin + ci] = in[pixel shifted by tap][ci]
-__device__ inline bf16x8 fwd_a(const ConvShape& s, const u16* __restrict__ in, long long p, int k0) {
-  const long long M = (long long)s.B * s.Ho * s.Wo;
-  if (p >= M) return zero8();
-  const int xo = (int)(p % s.Wo);
-  const long long t = p / s.Wo;
-  const int yo = (int)(t % s.Ho);
-  const int b = (int)(t / s.Ho);
-  if ((s.Cin & 7) == 0) {
-    const int tap = k0 / s.Cin, ci0 = k0 - tap * s.Cin;
-    if (tap >= 9) return zero8();
-    const int yi = yo * s.stride + tap / 3 - 1, xi = xo * s.stride + tap % 3 - 1;
-    if (yi < 0 || yi >= s.H || xi < 0 || xi >= s.W) return zero8();
-    return *reinterpret_cast<const bf16x8*>(in + (((long long)b * s.H + yi) * s.W + xi) * s.Cin + ci0);
+// Pixel p = (b * rows + y) * cols + x of a B x rows x cols image, split once per
+// lane; valid = false past the last pixel.
+struct Pix {
+  bool valid;
+  int b, y, x;
+};
+__device__ inline Pix split_pixel(long long p, int B, int rows, int cols) {
+  Pix q{false, 0, 0, 0};
+  if (p >= (long long)B * rows * cols) return q;
+  const long long t = p / cols;
+  q.valid = true;
+  q.x = (int)(p - t * cols);
+  q.b = (int)(t / rows);
+  q.y = (int)(t - (long long)q.b * rows);
+  return q;
+}
+
+// acc += sum over K-steps k = 0, 16, .., K - 16 of W[:, k..k+15] X[k..k+15, :] (the
+// weight row of this lane at wrow, the pixel operand from opnd(k)).  The loads of U
+// K-steps are issued before their MFMAs so that U are in flight per wave; steps past
+// the end load the last step again and skip its MFMA.
+template <int U, class Op>
+__device__ inline f32x16 kloop(int K, const u16* __restrict__ wrow, f32x16 acc, Op opnd) {
+  for (int k0 = 0; k0 < K; k0 += 16 * U) {
+    bf16x8 w[U], x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = min(k0 + 16 * u, K - 16);
+      w[u] = *reinterpret_cast<const bf16x8*>(wrow + k);
+      x[u] = opnd(k);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + 16 * u < K) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[u], x[u], acc, 0, 0, 0);
   }
-  bf16x8 v = zero8();
+  return acc;
+}
+
+// Buffer resource over a tensor of `bytes` (below 2 GiB): a raw buffer load at a
+// byte offset at or past the end returns zero instead of faulting, which makes the
+// padding taps free of branches.  Word 3 = 0x00020000 (32-bit data format), the value
+// for raw buffer access on gfx9-family chips.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr uint32_t OOB = 0x80000000u;    // past every record (tensors are below 2 GiB)
+__device__ inline Rsrc make_rsrc(const void* p, long long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+// --- forward ----------------------------------------------------------------------
+// Im2col operand X[pixel][k = tap * Cin + ci] = in[pixel shifted by tap][ci]: the 8
+// values k0 .. k0 + 7 of output pixel q.
+// Branch-free: a lane whose tap falls outside the image loads element 0 and keeps
+// zero, so the loads of several K-steps can be in flight together.
+// fwd_v: Cin a multiple of 8, one 16-byte load; fwd_e: element by element.
+__device__ inline bf16x8 fwd_v(const ConvShape& s, Rsrc in, const Pix& q, int k0) {
+  const int tap = k0 / s.Cin, ci0 = k0 - tap * s.Cin;
+  const int yi = q.y * s.stride + tap / 3 - 1, xi = q.x * s.stride + tap % 3 - 1;
+  const bool ok = q.valid & (tap < 9) & (yi >= 0) & (yi < s.H) & (xi >= 0) & (xi < s.W);
+  const uint32_t e = (((uint32_t)q.b * s.H + (uint32_t)yi) * s.W + (uint32_t)xi) * s.Cin + ci0;
+  return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(in, ok ? 2 * e : OOB, 0, 0));
+}
+__device__ inline bf16x8 fwd_e(const ConvShape& s, Rsrc in, const Pix& q, int k0) {
+  bf16x8 v;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int k = k0 + i;
     const int tap = k / s.Cin, ci = k - tap * s.Cin;
-    if (tap >= 9) continue;
-    const int yi = yo * s.stride + tap / 3 - 1, xi = xo * s.stride + tap % 3 - 1;
-    if (yi < 0 || yi >= s.H || xi < 0 || xi >= s.W) continue;
-    v[i] = as_bf16(in[(((long long)b * s.H + yi) * s.W + xi) * s.Cin + ci]);
+    const int yi = q.y * s.stride + tap / 3 - 1, xi = q.x * s.stride + tap % 3 - 1;
+    const bool ok = q.valid & (tap < 9) & (yi >= 0) & (yi < s.H) & (xi >= 0) & (xi < s.W);
+    const uint32_t e = (((uint32_t)q.b * s.H + (uint32_t)yi) * s.W + (uint32_t)xi) * s.Cin + ci;
+    v[i] = as_bf16(__builtin_amdgcn_raw_buffer_load_b16(in, ok ? 2 * e : OOB, 0, 0));
   }
   return v;
 }
 
+// The product is taken transposed, C[m = co][n = pixel] = W X^T, so that a lane's
+// accumulators are channels 8q + 4 (l / 32) + 0..3 (q = 0..3) of one pixel: each
+// group of four is one 8-byte store.
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvShape s, const u16* __restrict__ in,
                                                   const u16* __restrict__ wp,
                                                   const float* __restrict__ bias, int relu,
@@ -72,61 +123,80 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvShape s, const u16* __rest
   const int l = threadIdx.x & 63;
   const long long base = (long long)blockIdx.x * 128 + (threadIdx.x >> 6) * 32;
   const int hi = l >> 5, lo = l & 31;
+  const Pix q = split_pixel(base + lo, s.B, s.Ho, s.Wo);
+  const Rsrc rin = make_rsrc(in, 2LL * s.B * s.H * s.W * s.Cin);
+  const u16* wrow = wp + (long long)lo * s.Kp + 8 * hi;
   f32x16 acc = {};
-  for (int k0 = 0; k0 < s.Kp; k0 += 16) {
-    const bf16x8 a = fwd_a(s, in, base + lo, k0 + 8 * hi);
-    const bf16x8 b = *reinterpret_cast<const bf16x8*>(wp + (long long)lo * s.Kp + k0 + 8 * hi);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-  }
+  if ((s.Cin & 7) == 0)
+    acc = kloop<6>(s.Kp, wrow, acc, [&](int k) { return fwd_v(s, rin, q, k + 8 * hi); });
+  else
+    acc = kloop<2>(s.Kp, wrow, acc, [&](int k) { return fwd_e(s, rin, q, k + 8 * hi); });
   const long long M = (long long)s.B * s.Ho * s.Wo;
-  const int n = lo;
-  if (n >= s.Cout) return;
-  const float bn = bias[n];
+  const long long p = base + lo;
+  if (p >= M) return;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const long long p = base + 8 * (j >> 2) + 4 * hi + (j & 3);
-    if (p >= M) continue;
-    float v = acc[j] + bn;
-    if (outf) outf[p * s.Cout + n] = v;
-    if (relu) v = fmaxf(v, 0.f);
-    if (out) out[p * s.Cout + n] = f2bf(v);
+  for (int q = 0; q < 4; ++q) {
+    const int c0 = 8 * q + 4 * hi;
+    if (c0 >= s.Cout) continue;
+    float v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = acc[4 * q + r] + (c0 + r < s.Cout ? bias[c0 + r] : 0.f);
+    if (outf) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (c0 + r < s.Cout) outf[p * s.Cout + c0 + r] = v[r];
+    }
+    if (!out) continue;
+    if (relu) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.f);
+    }
+    if ((s.Cout & 3) == 0) {
+      uint2 w2;
+      w2.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+      w2.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+      *reinterpret_cast<uint2*>(out + p * s.Cout + c0) = w2;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (c0 + r < s.Cout) out[p * s.Cout + c0 + r] = f2bf(v[r]);
+    }
   }
 }
 
 // --- backward data --------------------------------------------------------------------
 // dIn[b][yi][xi][ci] = sum_{tap, co} W[co][tap][ci] dOut[b][yo][xo][co] with
-// yi = yo * stride + ky - 1.  A[m = input pixel][k = tap * Cout + co].
-__device__ inline bf16x8 bwd_a(const ConvShape& s, const u16* __restrict__ dout, long long p, int k0) {
-  const long long M = (long long)s.B * s.H * s.W;
-  if (p >= M) return zero8();
-  const int xi = (int)(p % s.W);
-  const long long t = p / s.W;
-  const int yi = (int)(t % s.H);
-  const int b = (int)(t / s.H);
-  bf16x8 v = zero8();
-  if ((s.Cout & 7) == 0) {
-    const int tap = k0 / s.Cout, co0 = k0 - tap * s.Cout;
-    if (tap >= 9) return v;
-    const int ny = yi + 1 - tap / 3, nx = xi + 1 - tap % 3;
-    if (ny < 0 || nx < 0 || ny % s.stride || nx % s.stride) return v;
-    const int yo = ny / s.stride, xo = nx / s.stride;
-    if (yo >= s.Ho || xo >= s.Wo) return v;
-    return *reinterpret_cast<const bf16x8*>(dout + (((long long)b * s.Ho + yo) * s.Wo + xo) * s.Cout + co0);
-  }
+// yi = yo * stride + ky - 1.  Operand dOut[input pixel][k = tap * Cout + co].
+// bwd_v: Cout a multiple of 8, one 16-byte load; bwd_e: element by element.  The
+// stride is 1 or 2, so the parity test and the halving are bit operations.
+__device__ inline bf16x8 bwd_v(const ConvShape& s, Rsrc dout, const Pix& q, int k0) {
+  const int tap = k0 / s.Cout, co0 = k0 - tap * s.Cout;
+  const int ny = q.y + 1 - tap / 3, nx = q.x + 1 - tap % 3;
+  const int sh = s.stride - 1;
+  const int yo = ny >> sh, xo = nx >> sh;
+  const bool ok = q.valid & (tap < 9) & (ny >= 0) & (nx >= 0) & (((ny | nx) & sh) == 0) &
+                  (yo < s.Ho) & (xo < s.Wo);
+  const uint32_t e = (((uint32_t)q.b * s.Ho + (uint32_t)yo) * s.Wo + (uint32_t)xo) * s.Cout + co0;
+  return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(dout, ok ? 2 * e : OOB, 0, 0));
+}
+__device__ inline bf16x8 bwd_e(const ConvShape& s, Rsrc dout, const Pix& q, int k0) {
+  bf16x8 v;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int k = k0 + i;
     const int tap = k / s.Cout, co = k - tap * s.Cout;
-    if (tap >= 9) continue;
-    const int ny = yi + 1 - tap / 3, nx = xi + 1 - tap % 3;
-    if (ny < 0 || nx < 0 || ny % s.stride || nx % s.stride) continue;
-    const int yo = ny / s.stride, xo = nx / s.stride;
-    if (yo >= s.Ho || xo >= s.Wo) continue;
-    v[i] = as_bf16(dout[(((long long)b * s.Ho + yo) * s.Wo + xo) * s.Cout + co]);
+    const int ny = q.y + 1 - tap / 3, nx = q.x + 1 - tap % 3;
+    const int sh = s.stride - 1;
+    const int yo = ny >> sh, xo = nx >> sh;
+    const bool ok = q.valid & (tap < 9) & (ny >= 0) & (nx >= 0) & (((ny | nx) & sh) == 0) &
+                    (yo < s.Ho) & (xo < s.Wo);
+    const uint32_t e = (((uint32_t)q.b * s.Ho + (uint32_t)yo) * s.Wo + (uint32_t)xo) * s.Cout + co;
+    v[i] = as_bf16(__builtin_amdgcn_raw_buffer_load_b16(dout, ok ? 2 * e : OOB, 0, 0));
   }
   return v;
 }
 
+// Transposed like the forward: C[m = ci][n = input pixel], four channels per store.
 __global__ __launch_bounds__(256) void k_conv_bwd_data(ConvShape s, const u16* __restrict__ dout,
                                                        const u16* __restrict__ wtp,
                                                        const u16* __restrict__ act,
@@ -134,96 +204,228 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(ConvShape s, const u16* _
   const int l = threadIdx.x & 63;
   const long long base = (long long)blockIdx.x * 128 + (threadIdx.x >> 6) * 32;
   const int hi = l >> 5, lo = l & 31;
+  const Pix q = split_pixel(base + lo, s.B, s.H, s.W);
+  const Rsrc rdo = make_rsrc(dout, 2LL * s.B * s.Ho * s.Wo * s.Cout);
+  const u16* wrow = wtp + (long long)lo * s.Ktp + 8 * hi;
   f32x16 acc = {};
-  for (int k0 = 0; k0 < s.Ktp; k0 += 16) {
-    const bf16x8 a = bwd_a(s, dout, base + lo, k0 + 8 * hi);
-    const bf16x8 b = *reinterpret_cast<const bf16x8*>(wtp + (long long)lo * s.Ktp + k0 + 8 * hi);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-  }
+  if ((s.Cout & 7) == 0)
+    acc = kloop<6>(s.Ktp, wrow, acc, [&](int k) { return bwd_v(s, rdo, q, k + 8 * hi); });
+  else
+    acc = kloop<2>(s.Ktp, wrow, acc, [&](int k) { return bwd_e(s, rdo, q, k + 8 * hi); });
   const long long M = (long long)s.B * s.H * s.W;
-  const int n = lo;
-  if (n >= s.Cin) return;
+  const long long p = base + lo;
+  if (p >= M) return;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const long long p = base + 8 * (j >> 2) + 4 * hi + (j & 3);
-    if (p >= M) continue;
-    float v = acc[j];
+  for (int q = 0; q < 4; ++q) {
+    const int c0 = 8 * q + 4 * hi;
+    if (c0 >= s.Cin) continue;
+    float v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = acc[4 * q + r];
+    const long long o = p * s.Cin + c0;
     // ReLU of the layer below: its output was positive where the gradient passes
-    if (act && !((float)as_bf16(act[p * s.Cin + n]) > 0.f)) v = 0.f;
-    din[p * s.Cin + n] = f2bf(v);
+    if ((s.Cin & 3) == 0) {
+      if (act) {
+        const uint2 a2 = *reinterpret_cast<const uint2*>(act + o);
+        const uint32_t aw[2] = {a2.x, a2.y};
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (!((float)as_bf16((u16)(aw[r >> 1] >> (16 * (r & 1)))) > 0.f)) v[r] = 0.f;
+      }
+      uint2 w2;
+      w2.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+      w2.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+      *reinterpret_cast<uint2*>(din + o) = w2;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (c0 + r >= s.Cin) continue;
+        if (act && !((float)as_bf16(act[o + r]) > 0.f)) v[r] = 0.f;
+        din[o + r] = f2bf(v[r]);
+      }
+    }
   }
 }
 
 // --- backward weight ------------------------------------------------------------------
-// dW[co][kw] = sum_pixels dOut[p][co] in[p shifted by tap(kw)][ci(kw)]:
-// GEMM with M = Cout (32), N = Kp (tiles of 32), K = the workgroup's pixels.
+// dW[co][kw] = sum over output pixels p of dOut[p][co] X[p][kw], where X[p][kw] is the
+// input under tap(kw) of pixel p: a GEMM with M = Cout (32), N = Kp in tiles of 32 and
+// K = pixels.  The matrix cores want 8 consecutive K values per lane, but both
+// operands are stored channel-fastest, so a workgroup stages chunks of 64 output
+// pixels in LDS transposed (pixel fastest): dOut^T [co][p] and X^T [kw][p].  One
+// 16-byte LDS read then gives a lane its 8 pixels of either operand.  Global loads
+// are 16 bytes (8 channels of one pixel) when the channel count allows it.
+constexpr int WB_CHUNK = 64;             // output pixels per staged chunk (4 MFMA K-steps)
+constexpr int WB_LD = WB_CHUNK + 8;      // LDS row stride in BF16 values (16 B of padding)
+constexpr int WB_ROWS = 288;             // X^T rows: Kp of the widest layer (Cin = 32)
+constexpr int WB_MAX_WG = 768;           // three workgroups per CU fit in LDS
+constexpr int WB_GROUPS = 32;            // partial groups of the first reduce pass
+
+__device__ inline bf16x8 lds8(const u16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+// Each workgroup accumulates over the chunks blockIdx.x, blockIdx.x + gridDim.x, ...
+// With four or more weight tiles each wave owns whole tiles (tiles wave, wave + 4,
+// wave + 8) over all K-steps; with fewer, the waves split the K-steps of every tile
+// and their sums are added in LDS.  The workgroup writes one partial slab: the
+// [32][cols] weight block followed by the 32 bias sums.
 __global__ __launch_bounds__(256) void k_conv_bwd_weight(ConvShape s, const u16* __restrict__ in,
                                                          const u16* __restrict__ dout,
-                                                         int pix_per_wg, float* __restrict__ part,
-                                                         float* __restrict__ bpart) {
-  const int l = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+                                                         int n_chunks, float* __restrict__ part) {
+  __shared__ __align__(16) u16 DT[32 * WB_LD];
+  __shared__ __align__(16) u16 XT[WB_ROWS * WB_LD];
+  const int tid = threadIdx.x, l = tid & 63, wave = tid >> 6;
   const int hi = l >> 5, lo = l & 31;
   const long long M = (long long)s.B * s.Ho * s.Wo;
-  const long long p_beg = (long long)blockIdx.x * pix_per_wg;
-  const long long p_end = min(M, p_beg + pix_per_wg);
-  const int n_tiles = s.Kp / 32 + ((s.Kp % 32) ? 1 : 0);
-  float* mypart = part + (long long)blockIdx.x * 32 * (n_tiles * 32);
-  for (int tile = wave; tile < n_tiles; tile += 4) {
-    f32x16 acc = {};
-    const int kw = tile * 32 + lo;            // weight column of this lane (B operand)
-    const int tap = kw / s.Cin, ci = kw - tap * s.Cin;
-    const bool kw_ok = tap < 9 && kw < s.Kp;
-    for (long long p0 = p_beg; p0 < p_end; p0 += 16) {
-      bf16x8 a = zero8(), b = zero8();
+  const int n_tiles = (s.Kp + 31) / 32, cols = n_tiles * 32;
+  const int kval = 9 * s.Cin;
+  const bool split = n_tiles < 4;
+  // rows that no chunk writes (channels past Cout, columns past 9 Cin) stay zero
+  for (int i = tid; i < (32 - s.Cout) * WB_LD; i += 256) DT[s.Cout * WB_LD + i] = 0;
+  for (int i = tid; i < (cols - kval) * WB_LD; i += 256) XT[kval * WB_LD + i] = 0;
+
+  f32x16 acc[3] = {};
+  float bsum = 0.f;
+  const int pp = l;        // staging: lane = pixel of the chunk, wave = channel group
+  for (int ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
+    const long long p = (long long)ch * WB_CHUNK + pp;
+    const bool pv = p < M;
+    int yo = 0, xo = 0;
+    long long pix = 0;     // input pixel under the centre tap
+    if (pv) {
+      xo = (int)(p % s.Wo);
+      const long long t = p / s.Wo;
+      yo = (int)(t % s.Ho);
+      pix = ((t / s.Ho) * s.H + (long long)yo * s.stride) * s.W + (long long)xo * s.stride;
+    }
+    unsigned okm = 0;      // taps whose input pixel lies inside the image
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const long long p = p0 + 8 * hi + i;
-        if (p >= p_end) continue;
-        if (lo < s.Cout) a[i] = as_bf16(dout[p * s.Cout + lo]);
-        if (kw_ok) {
-          const int xo = (int)(p % s.Wo);
-          const long long t = p / s.Wo;
-          const int yo = (int)(t % s.Ho);
-          const int bb = (int)(t / s.Ho);
-          const int yi = yo * s.stride + tap / 3 - 1, xi = xo * s.stride + tap % 3 - 1;
-          if (yi >= 0 && yi < s.H && xi >= 0 && xi < s.W)
-            b[i] = as_bf16(in[(((long long)bb * s.H + yi) * s.W + xi) * s.Cin + ci]);
-        }
+    for (int tap = 0; tap < 9; ++tap) {
+      const int yi = yo * s.stride + tap / 3 - 1, xi = xo * s.stride + tap % 3 - 1;
+      if (pv && yi >= 0 && yi < s.H && xi >= 0 && xi < s.W) okm |= 1u << tap;
+    }
+    __syncthreads();       // the previous chunk's operands have been read
+    // all nine taps of a channel group are loaded before any is stored
+    if ((s.Cout & 7) == 0) {
+      for (int g = wave; g < (s.Cout >> 3); g += 4) {
+        const bf16x8 v = pv ? *reinterpret_cast<const bf16x8*>(dout + p * s.Cout + 8 * g) : zero8();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) DT[(8 * g + e) * WB_LD + pp] = as_u16(v[e]);
       }
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    } else {
+      for (int c = wave; c < s.Cout; c += 4) DT[c * WB_LD + pp] = pv ? dout[p * s.Cout + c] : (u16)0;
+    }
+    if ((s.Cin & 7) == 0) {
+      for (int g = wave; g < (s.Cin >> 3); g += 4) {
+        bf16x8 v[9];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+          const long long off = (pix + (long long)(tap / 3 - 1) * s.W + (tap % 3 - 1)) * s.Cin;
+          v[tap] = (okm >> tap & 1u) ? *reinterpret_cast<const bf16x8*>(in + off + 8 * g) : zero8();
+        }
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) XT[(tap * s.Cin + 8 * g + e) * WB_LD + pp] = as_u16(v[tap][e]);
+      }
+    } else {
+      for (int ci = wave; ci < s.Cin; ci += 4) {
+        u16 v[9];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+          const long long off = (pix + (long long)(tap / 3 - 1) * s.W + (tap % 3 - 1)) * s.Cin;
+          v[tap] = (okm >> tap & 1u) ? in[off + ci] : (u16)0;
+        }
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) XT[(tap * s.Cin + ci) * WB_LD + pp] = v[tap];
+      }
+    }
+    __syncthreads();
+    if (tid < 32) {        // bias gradient: this chunk's dOut summed per channel
+#pragma unroll
+      for (int q = 0; q < WB_CHUNK; q += 8) {
+        const bf16x8 v = lds8(DT + tid * WB_LD + q);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bsum += (float)v[e];
+      }
     }
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int m = 8 * (j >> 2) + 4 * hi + (j & 3);   // output channel
-      mypart[(long long)m * (n_tiles * 32) + tile * 32 + lo] = acc[j];
+    for (int ks = 0; ks < 4; ++ks) {
+      if (split && ks != wave) continue;
+      const bf16x8 a = lds8(DT + lo * WB_LD + 16 * ks + 8 * hi);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int t = split ? j : wave + 4 * j;
+        if (t < n_tiles)
+          acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              a, lds8(XT + (t * 32 + lo) * WB_LD + 16 * ks + 8 * hi), acc[j], 0, 0, 0);
+      }
     }
   }
-  // bias gradient partials: sum of dOut over this workgroup's pixels
-  if (threadIdx.x < 32) {
-    float sb = 0.f;
-    if ((int)threadIdx.x < s.Cout)
-      for (long long p = p_beg; p < p_end; ++p) sb += (float)as_bf16(dout[p * s.Cout + threadIdx.x]);
-    bpart[(long long)blockIdx.x * 32 + threadIdx.x] = sb;
+  if (split) {             // waves 1-3 hand their sums to wave 0 through LDS (3 x 3 x 4 KB)
+    float* red = reinterpret_cast<float*>(XT);
+    __syncthreads();
+    if (wave > 0) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        if (j < n_tiles)
+#pragma unroll
+          for (int jj = 0; jj < 16; ++jj) red[(((wave - 1) * 3 + j) * 16 + jj) * 64 + l] = acc[j][jj];
+    }
+    __syncthreads();
+    if (wave == 0) {
+      for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          if (j < n_tiles)
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) acc[j][jj] += red[((w * 3 + j) * 16 + jj) * 64 + l];
+    }
   }
+  float* slab = part + (long long)blockIdx.x * (32 * cols + 32);
+  if (!split || wave == 0) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int t = split ? j : wave + 4 * j;
+      if (t >= n_tiles) continue;
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        const int m = 8 * (jj >> 2) + 4 * hi + (jj & 3);   // output channel
+        slab[m * cols + t * 32 + lo] = acc[j][jj];
+      }
+    }
+  }
+  if (tid < 32) slab[32 * cols + tid] = bsum;
 }
 
-// dW[co][k] (k < 9 Cin) and dbias: fixed-order sums of the workgroup partials.
-__global__ __launch_bounds__(256) void k_conv_wreduce(const float* __restrict__ part,
-                                                      const float* __restrict__ bpart, int n_wg,
+// First reduce pass: slab element e summed over the partials of group blockIdx.y
+// (partials per_group * y ... per_group * (y + 1) - 1, in order).
+__global__ __launch_bounds__(256) void k_conv_wsum(const float* __restrict__ part, int n_part,
+                                                   int per_group, int slab_len,
+                                                   float* __restrict__ part2) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= slab_len) return;
+  const int w0 = blockIdx.y * per_group, w1 = min(n_part, w0 + per_group);
+  float s = 0.f;
+  for (int w = w0; w < w1; ++w) s += part[(long long)w * slab_len + e];
+  part2[(long long)blockIdx.y * slab_len + e] = s;
+}
+
+// Second pass: dW[co][k] (k < 9 Cin) and dbias summed over the groups in order.
+__global__ __launch_bounds__(256) void k_conv_wreduce(const float* __restrict__ part2, int n_groups,
                                                       int cols, int cout, int kvalid,
                                                       float* __restrict__ dw,
                                                       float* __restrict__ db) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
+  const int slab_len = 32 * cols + 32;
   if (idx < cout * kvalid) {
     const int co = idx / kvalid, k = idx - co * kvalid;
     float s = 0.f;
-    for (int w = 0; w < n_wg; ++w) s += part[((long long)w * 32 + co) * cols + k];
+    for (int g = 0; g < n_groups; ++g) s += part2[(long long)g * slab_len + co * cols + k];
     dw[idx] = s;
   }
   if (idx < cout) {
     float s = 0.f;
-    for (int w = 0; w < n_wg; ++w) s += bpart[(long long)w * 32 + idx];
+    for (int g = 0; g < n_groups; ++g) s += part2[(long long)g * slab_len + 32 * cols + idx];
     db[idx] = s;
   }
 }
@@ -361,20 +563,27 @@ hipError_t launch_conv_bwd_weight(af_ctx* c, int B, int H, int W, int Cin, int C
                                   const void* in, const void* dout, float* dw, float* db) {
   const ConvShape s = shape(B, H, W, Cin, Cout, stride);
   const long long M = (long long)B * s.Ho * s.Wo;
-  const int pix_per_wg = 2048;
-  const int n_wg = (int)((M + pix_per_wg - 1) / pix_per_wg);
-  const int n_tiles = s.Kp / 32 + ((s.Kp % 32) ? 1 : 0);
-  const int cols = n_tiles * 32;
-  hipError_t e = c->d_cnn_part.ensure(sizeof(float) * ((size_t)n_wg * 32 * cols + (size_t)n_wg * 32));
+  const long long n_chunks = (M + WB_CHUNK - 1) / WB_CHUNK;
+  if (n_chunks > INT_MAX) return hipErrorInvalidValue;
+  // about four chunks per workgroup, at most three workgroups per CU
+  const int n_wg = (int)std::min<long long>(WB_MAX_WG, (n_chunks + 3) / 4);
+  const int cols = (s.Kp + 31) / 32 * 32;
+  const int slab_len = 32 * cols + 32;
+  const int per_group = (n_wg + WB_GROUPS - 1) / WB_GROUPS;
+  const int n_groups = (n_wg + per_group - 1) / per_group;
+  hipError_t e = c->d_cnn_part.ensure(sizeof(float) * (size_t)(n_wg + n_groups) * slab_len);
   if (e != hipSuccess) return e;
   float* part = c->d_cnn_part.as<float>();
-  float* bpart = part + (size_t)n_wg * 32 * cols;
+  float* part2 = part + (size_t)n_wg * slab_len;
   hipLaunchKernelGGL(k_conv_bwd_weight, dim3(n_wg), dim3(256), 0, c->stream, s, (const u16*)in,
-                     (const u16*)dout, pix_per_wg, part, bpart);
+                     (const u16*)dout, (int)n_chunks, part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_conv_wsum, dim3((slab_len + 255) / 256, n_groups), dim3(256), 0, c->stream,
+                     part, n_wg, per_group, slab_len, part2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int n = Cout * 9 * Cin;
-  hipLaunchKernelGGL(k_conv_wreduce, dim3((n + 255) / 256), dim3(256), 0, c->stream, part, bpart,
-                     n_wg, cols, Cout, 9 * Cin, dw, db);
+  hipLaunchKernelGGL(k_conv_wreduce, dim3((n + 255) / 256), dim3(256), 0, c->stream, part2,
+                     n_groups, cols, Cout, 9 * Cin, dw, db);
   return hipGetLastError();
 }
 

@@ -36,3 +36,17 @@ def test_binding_names_every_entry_point():
     src = open(os.path.join(ROOT, "paper_2608_06853_amd", "_lib.py")).read()
     missing = [n for n in declared() if n not in src]
     assert not missing, f"no binding for: {missing}"
+
+
+def test_kernel_family_names_follow_the_header():
+    """The binding's per-family timing names are in the order of the header's
+    AF_K_ ids, one per id."""
+    from paper_2608_06853_amd import _lib
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    ids = {k: int(v) for k, v in re.findall(r"\b(AF_K_[A-Z_]+)\s*=\s*(\d+)", text)}
+    count = ids.pop("AF_K_COUNT")
+    assert sorted(ids.values()) == list(range(count))
+    assert len(_lib.KERNELS) == count
+    for name, i in ids.items():
+        short = name[len("AF_K_"):].lower()
+        assert _lib.KERNELS[i].replace("_grid", "").replace("grad_", "") == short, (name, _lib.KERNELS[i])

@@ -67,6 +67,35 @@ def test_single_layer(ci, co, st):
     assert e_dx < 4e-3 and e_dw < 1e-5 and e_db < 1e-5
 
 
+@pytest.mark.parametrize("ci,co,st,B,H,W", [
+    (32, 32, 2, 3, 70, 45),    # nine weight tiles: each wave owns tiles; many chunks per workgroup
+    (8, 16, 1, 2, 33, 40),     # three tiles (Kp 80): the waves split the K-steps
+    (4, 8, 2, 2, 50, 37),      # two tiles, element-wise input staging
+    (2, 32, 1, 4, 64, 64),     # the first layer's shape
+    (32, 1, 1, 3, 40, 41),     # one output channel, ragged last chunk
+])
+def test_weight_gradient_many_chunks(ci, co, st, B, H, W):
+    """Weight and bias gradients over many 64-pixel chunks per workgroup, with a
+    ragged tail, against the oracle."""
+    import torch
+    rng = np.random.default_rng(ci * 1000 + co * 10 + st)
+    ctx = _ctx()
+    Ho, Wo = (H - 1) // st + 1, (W - 1) // st + 1
+    x = _bf16(rng.standard_normal((B, H, W, ci)))
+    dout = _bf16(rng.standard_normal((B, Ho, Wo, co)))
+    dw = torch.empty(co * 9 * ci, device="cuda")
+    db = torch.empty(co, device="cuda")
+    ctx.conv3x3_bwd_weight(B, H, W, ci, co, st, x.cuda().contiguous().view(-1),
+                           dout.cuda().contiguous().view(-1), dw, db)
+    w0 = np.zeros((co, 3, 3, ci))
+    _, dwo, dbo = ocnn.conv3x3_backward(x.float().numpy().astype(np.float64), w0, st,
+                                        dout.float().numpy().astype(np.float64))
+    e_dw = G.rel(dw.cpu().numpy().reshape(dwo.shape), dwo)
+    e_db = G.rel(db.cpu().numpy(), dbo)
+    print("dw", ci, co, st, B, H, W, e_dw, e_db, flush=True)
+    assert e_dw < 1e-5 and e_db < 1e-5
+
+
 def test_network_gradients_match_oracle():
     import torch
     from paper_2608_06853_amd import cnn
