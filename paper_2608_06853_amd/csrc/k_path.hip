@@ -11,8 +11,8 @@
 // wavefront's private copy of the padded grid with plain LDS read-add-writes
 // (no LDS atomics).  Lanes spread over two neighbouring cells are summed as one
 // window of 4 x 5 or 5 x 4 nodes; lanes spread wider are handled one cell at a
-// time.  The rays of two neighbouring elements are walked together and summed by
-// the same reduce whenever their cells allow it.  The copies are summed into one
+// time.  The rays of four neighbouring elements are walked together and summed by
+// the same reduce whenever their cells allow it (else by pairs).  The copies are summed into one
 // partial grid per workgroup, and a second kernel adds the partial grids node by
 // node in a fixed order.
 #include "af_internal.h"
@@ -256,6 +256,20 @@ __device__ inline void scatter_one(float* grid, int cell, bool live, int lead, i
     scatter_rounds(grid, c0, c[0], az, wx, lane, my_off);
 }
 
+// Ray point k of the rays of two elements (either may be idle in a lane): one
+// reduce when their cells allow it, else each element on its own.
+__device__ inline void scatter_pair(float* grid, const int (&cell)[2], const bool (&live)[2],
+                                    int lead, int lead0, int lead1, int W,
+                                    const float (&az)[2][4], const float (&wx)[2][4], int lane,
+                                    int my_off) {
+  const int c0 = __builtin_amdgcn_readlane(live[0] ? cell[0] : cell[1], lead);
+  const int cu[2] = {live[0] ? cell[0] : c0, live[1] ? cell[1] : c0};
+  if (scatter_union<2>(grid, c0, W, cu, az, wx, lane, my_off)) return;
+  // the two ray points of a lane lie wider apart: each element on its own
+  scatter_one(grid, cell[0], live[0], lead0, W, az[0], wx[0], lane, my_off);
+  scatter_one(grid, cell[1], live[1], lead1, W, az[1], wx[1], lane, my_off);
+}
+
 __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
   extern __shared__ float sg[];  // [4 wavefronts][nodes]
   const Geo& g = A.g;
@@ -279,14 +293,15 @@ __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
   const int my_tap = (lane >> 2) & 15;
   const int my_off = (my_tap >> 2) * W + (my_tap & 3);
 
-  // Elements two at a time: the rays of neighbouring elements to the same points
+  // Elements four at a time: the rays of neighbouring elements to the same points
   // run side by side, so at a step their ray points usually share one cell (or two
-  // neighbouring cells) and one reduce covers both.
-  for (int a = tr.x; a <= tr.y; a += 2) {  // wavefront-uniform loop
-    Ray R[2];
-    unsigned long long lm[2];
+  // neighbouring cells) and one reduce covers all four; otherwise the step falls
+  // back to the two pairs, and a pair to its single elements.
+  for (int a = tr.x; a <= tr.y; a += 4) {  // wavefront-uniform loop
+    Ray R[4];
+    unsigned long long lm[4];
 #pragma unroll
-    for (int n = 0; n < 2; ++n) {
+    for (int n = 0; n < 4; ++n) {
       const int e = a + n;
       const bool act = e <= tr.y && e >= pr.x && e <= pr.y;
       float gbar = 0.f;
@@ -304,30 +319,66 @@ __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
         R[n].dv = (vp - ruv.y) * inv_n;
       }
     }
-    if ((lm[0] | lm[1]) == 0ull) continue;
-    if (lm[0] == 0ull || lm[1] == 0ull) {  // one element with work
-      const Ray& r = lm[0] != 0ull ? R[0] : R[1];
-      const int lead = __ffsll((long long)(lm[0] | lm[1])) - 1;
+    const unsigned long long all = lm[0] | lm[1] | lm[2] | lm[3];
+    if (all == 0ull) continue;
+    int leads[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) leads[n] = __ffsll((long long)lm[n]) - 1;
+    if (lm[0] != 0ull && lm[1] != 0ull && lm[2] != 0ull && lm[3] != 0ull) {
+      const int lead = __ffsll((long long)all) - 1;
+      const int lead01 = __ffsll((long long)(lm[0] | lm[1])) - 1;
+      const int lead23 = __ffsll((long long)(lm[2] | lm[3])) - 1;
       for (int k = 0; k <= g.n_seg; ++k) {
-        float az[4], wx[4];
-        const int cell = ray_point(r, k, g.n_seg, umax, vmax, W, az, wx);
-        scatter_one(grid, cell, r.live, lead, W, az, wx, lane, my_off);
+        float az[4][4], wx[4][4];
+        int cell[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) cell[n] = ray_point(R[n], k, g.n_seg, umax, vmax, W, az[n], wx[n]);
+        // a lane's first live ray point; idle ray points join the leader's cell
+        const int mine = R[0].live ? cell[0] : R[1].live ? cell[1] : R[2].live ? cell[2] : cell[3];
+        const int c0 = __builtin_amdgcn_readlane(mine, lead);
+        int cu[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) cu[n] = R[n].live ? cell[n] : c0;
+        if (scatter_union<4>(grid, c0, W, cu, az, wx, lane, my_off)) continue;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int c2[2] = {cell[2 * h], cell[2 * h + 1]};
+          const bool l2[2] = {R[2 * h].live, R[2 * h + 1].live};
+          const float a2[2][4] = {{az[2 * h][0], az[2 * h][1], az[2 * h][2], az[2 * h][3]},
+                                  {az[2 * h + 1][0], az[2 * h + 1][1], az[2 * h + 1][2], az[2 * h + 1][3]}};
+          const float w2[2][4] = {{wx[2 * h][0], wx[2 * h][1], wx[2 * h][2], wx[2 * h][3]},
+                                  {wx[2 * h + 1][0], wx[2 * h + 1][1], wx[2 * h + 1][2], wx[2 * h + 1][3]}};
+          scatter_pair(grid, c2, l2, h == 0 ? lead01 : lead23, leads[2 * h], leads[2 * h + 1], W,
+                       a2, w2, lane, my_off);
+        }
       }
       continue;
     }
-    const int lead = __ffsll((long long)(lm[0] | lm[1])) - 1;
-    const int lead0 = __ffsll((long long)lm[0]) - 1, lead1 = __ffsll((long long)lm[1]) - 1;
-    for (int k = 0; k <= g.n_seg; ++k) {
-      float az[2][4], wx[2][4];
-      int cell[2];
+    // some element of the four has no work in this wavefront: pairs and singles
 #pragma unroll
-      for (int n = 0; n < 2; ++n) cell[n] = ray_point(R[n], k, g.n_seg, umax, vmax, W, az[n], wx[n]);
-      const int c0 = __builtin_amdgcn_readlane(R[0].live ? cell[0] : cell[1], lead);
-      const int cu[2] = {R[0].live ? cell[0] : c0, R[1].live ? cell[1] : c0};
-      if (scatter_union<2>(grid, c0, W, cu, az, wx, lane, my_off)) continue;
-      // the two ray points of a lane lie wider apart: each element on its own
-      scatter_one(grid, cell[0], R[0].live, lead0, W, az[0], wx[0], lane, my_off);
-      scatter_one(grid, cell[1], R[1].live, lead1, W, az[1], wx[1], lane, my_off);
+    for (int h = 0; h < 2; ++h) {
+      const unsigned long long m0 = lm[2 * h], m1 = lm[2 * h + 1];
+      if ((m0 | m1) == 0ull) continue;
+      if (m0 == 0ull || m1 == 0ull) {  // one element with work
+        const Ray& r = m0 != 0ull ? R[2 * h] : R[2 * h + 1];
+        const int lead = __ffsll((long long)(m0 | m1)) - 1;
+        for (int k = 0; k <= g.n_seg; ++k) {
+          float az[4], wx[4];
+          const int cell = ray_point(r, k, g.n_seg, umax, vmax, W, az, wx);
+          scatter_one(grid, cell, r.live, lead, W, az, wx, lane, my_off);
+        }
+        continue;
+      }
+      const int lead = __ffsll((long long)(m0 | m1)) - 1;
+      const bool l2[2] = {R[2 * h].live, R[2 * h + 1].live};
+      for (int k = 0; k <= g.n_seg; ++k) {
+        float az[2][4], wx[2][4];
+        int cell[2];
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+          cell[n] = ray_point(R[2 * h + n], k, g.n_seg, umax, vmax, W, az[n], wx[n]);
+        scatter_pair(grid, cell, l2, lead, leads[2 * h], leads[2 * h + 1], W, az, wx, lane, my_off);
+      }
     }
   }
   __syncthreads();

@@ -130,3 +130,37 @@ def test_linear_array_errors():
         assert e.value.status == _lib.AF_ERR_ARG
     ctx.set_refraction_search(0)
     ctx.set_refraction_search(4096)
+
+
+def test_convolution_arguments_are_rejected():
+    """Channel counts outside 1..32, a stride other than 1 or 2 and activations of
+    2 GiB or more are refused before anything is launched; the buffers are sized for
+    the requested shapes, so nothing could be read out of bounds either way."""
+    import torch
+    from paper_2608_06853_amd import _lib
+    ctx = _ctx()
+    B, H, W = 1, 8, 8
+    for ci, co, st in [(33, 32, 1), (32, 0, 1), (16, 16, 3)]:
+        kp, _ = ctx.conv_shapes(ci, co)
+        ho, wo = (H - 1) // st + 1, (W - 1) // st + 1
+        x = torch.zeros(B * H * W * ci, device="cuda", dtype=torch.bfloat16)
+        wp = torch.zeros(32 * kp, device="cuda", dtype=torch.bfloat16)
+        b = torch.zeros(co, device="cuda")
+        out = torch.zeros(B * ho * wo * co, device="cuda", dtype=torch.bfloat16)
+        with pytest.raises(_lib.AfError) as e:
+            ctx.conv3x3_fwd(B, H, W, ci, co, st, True, x, wp, b, out=out)
+        assert e.value.status == _lib.AF_ERR_ARG
+    # 8192 x 8192 pixels x 16 channels of BF16 = 2 GiB: refused; one row less runs
+    ci = co = 16
+    kp, _ = ctx.conv_shapes(ci, co)
+    wp = torch.zeros(32 * kp, device="cuda", dtype=torch.bfloat16)
+    b = torch.zeros(co, device="cuda")
+    x = torch.zeros(8192 * 8192 * ci, device="cuda", dtype=torch.bfloat16)
+    out = torch.empty_like(x)
+    with pytest.raises(_lib.AfError) as e:
+        ctx.conv3x3_fwd(1, 8192, 8192, ci, co, 1, True, x, wp, b, out=out)
+    assert e.value.status == _lib.AF_ERR_ARG and "2 GiB" in str(e.value)
+    n = 8191 * 8192 * ci
+    ctx.conv3x3_fwd(1, 8191, 8192, ci, co, 1, True, x[:n], wp, b, out=out[:n])
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(out[:n]).item()) == 0
