@@ -137,3 +137,41 @@ def test_training_fits_a_batch():
     losses = [float(net.train_step(x, y, B, 3e-3).item()) for _ in range(150)]
     print("loss first/last", losses[0], losses[-1], flush=True)
     assert losses[-1] < 0.2 * losses[0]
+
+
+@pytest.mark.parametrize("ci,co,st,B,H,W", [
+    (3, 5, 2, 1, 1, 1),        # one pixel, odd channel counts (element-wise paths)
+    (1, 1, 1, 1, 1, 2),        # one input and one output channel
+    (12, 4, 2, 3, 2, 3),       # Cin not a multiple of 8, Cout a multiple of 4 (8-byte stores)
+])
+def test_degenerate_shapes(ci, co, st, B, H, W):
+    """Forward, input gradient and weight gradient at sizes below one tile."""
+    import torch
+    rng = np.random.default_rng(ci * 7 + co * 3 + st + H)
+    ctx = _ctx()
+    Ho, Wo = (H - 1) // st + 1, (W - 1) // st + 1
+    x = _bf16(rng.standard_normal((B, H, W, ci)))
+    w32 = rng.standard_normal((co, 9 * ci)).astype(np.float32) * 0.3
+    wq = _bf16(w32).float().numpy().reshape(co, 3, 3, ci).astype(np.float64)
+    b = rng.standard_normal(co).astype(np.float32)
+    kp, ktp = ctx.conv_shapes(ci, co)
+    wp = torch.empty(32 * kp, device="cuda", dtype=torch.bfloat16)
+    wtp = torch.empty(32 * ktp, device="cuda", dtype=torch.bfloat16)
+    ctx.conv3x3_pack(ci, co, torch.from_numpy(w32).cuda(), wp, wtp)
+    xd = x.cuda().contiguous().view(-1)
+    outf = torch.empty(B * Ho * Wo * co, device="cuda")
+    ctx.conv3x3_fwd(B, H, W, ci, co, st, False, xd, wp, torch.from_numpy(b).cuda(), outf=outf)
+    xo = x.float().numpy().astype(np.float64)
+    ref = ocnn.conv3x3(xo, wq, b.astype(np.float64), st)
+    assert G.rel(outf.cpu().numpy().reshape(ref.shape), ref) < 1e-5
+    dout = _bf16(rng.standard_normal((B, Ho, Wo, co)))
+    din = torch.empty(B * H * W * ci, device="cuda", dtype=torch.bfloat16)
+    ctx.conv3x3_bwd_data(B, H, W, ci, co, st, dout.cuda().contiguous().view(-1), wtp, None, din)
+    dw = torch.empty(co * 9 * ci, device="cuda")
+    db = torch.empty(co, device="cuda")
+    ctx.conv3x3_bwd_weight(B, H, W, ci, co, st, xd, dout.cuda().contiguous().view(-1), dw, db)
+    dx, dwo, dbo = ocnn.conv3x3_backward(xo, wq, st, dout.float().numpy().astype(np.float64))
+    e = (G.rel(din.float().cpu().numpy().reshape(dx.shape), dx),
+         G.rel(dw.cpu().numpy().reshape(dwo.shape), dwo), G.rel(db.cpu().numpy(), dbo))
+    print("degenerate", ci, co, st, B, H, W, e, flush=True)
+    assert e[0] < 4e-3 and e[1] < 1e-5 and e[2] < 1e-5
