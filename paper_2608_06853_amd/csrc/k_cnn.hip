@@ -113,6 +113,23 @@ __device__ inline bf16x8 fwd_e(const ConvShape& s, Rsrc in, const Pix& q, int k0
   return v;
 }
 
+// fwd_c2: Cin = 2 (the first layer): the values k0 .. k0 + 7 are taps k0 / 2 .. k0 / 2 + 3
+// with both channels each, so four 4-byte loads.
+__device__ inline bf16x8 fwd_c2(const ConvShape& s, Rsrc in, const Pix& q, int k0) {
+  bf16x8 v;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int tap = (k0 >> 1) + j;
+    const int yi = q.y * s.stride + tap / 3 - 1, xi = q.x * s.stride + tap % 3 - 1;
+    const bool ok = q.valid & (tap < 9) & (yi >= 0) & (yi < s.H) & (xi >= 0) & (xi < s.W);
+    const uint32_t e = (((uint32_t)q.b * s.H + (uint32_t)yi) * s.W + (uint32_t)xi) * 2u;
+    const uint32_t d = __builtin_amdgcn_raw_buffer_load_b32(in, ok ? 2 * e : OOB, 0, 0);
+    v[2 * j] = as_bf16((u16)(d & 0xffffu));
+    v[2 * j + 1] = as_bf16((u16)(d >> 16));
+  }
+  return v;
+}
+
 // The product is taken transposed, C[m = co][n = pixel] = W X^T, so that a lane's
 // accumulators are channels 8q + 4 (l / 32) + 0..3 (q = 0..3) of one pixel: each
 // group of four is one 8-byte store.
@@ -129,6 +146,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvShape s, const u16* __rest
   f32x16 acc = {};
   if ((s.Cin & 7) == 0)
     acc = kloop<6>(s.Kp, wrow, acc, [&](int k) { return fwd_v(s, rin, q, k + 8 * hi); });
+  else if (s.Cin == 2)
+    acc = kloop<2>(s.Kp, wrow, acc, [&](int k) { return fwd_c2(s, rin, q, k + 8 * hi); });
   else
     acc = kloop<2>(s.Kp, wrow, acc, [&](int k) { return fwd_e(s, rin, q, k + 8 * hi); });
   const long long M = (long long)s.B * s.Ho * s.Wo;
@@ -224,6 +243,83 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(ConvShape s, const u16* _
     for (int r = 0; r < 4; ++r) v[r] = acc[4 * q + r];
     const long long o = p * s.Cin + c0;
     // ReLU of the layer below: its output was positive where the gradient passes
+    if ((s.Cin & 3) == 0) {
+      if (act) {
+        const uint2 a2 = *reinterpret_cast<const uint2*>(act + o);
+        const uint32_t aw[2] = {a2.x, a2.y};
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (!((float)as_bf16((u16)(aw[r >> 1] >> (16 * (r & 1)))) > 0.f)) v[r] = 0.f;
+      }
+      uint2 w2;
+      w2.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+      w2.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+      *reinterpret_cast<uint2*>(din + o) = w2;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (c0 + r >= s.Cin) continue;
+        if (act && !((float)as_bf16(act[o + r]) > 0.f)) v[r] = 0.f;
+        din[o + r] = f2bf(v[r]);
+      }
+    }
+  }
+}
+
+// Stride 2 with Cout a multiple of 16: wave w of a workgroup takes the input pixels
+// of parity class (y mod 2, x mod 2) = (w / 2, w % 2) at 32 consecutive positions
+// (b, i, j) of the half-resolution grid, pixel (2 i + y mod 2, 2 j + x mod 2), so the
+// four waves cover the same 2 x 64 patch and complete its cache lines together.
+// Only taps with y + 1 - ky and x + 1 - kx even reach an output pixel, so the class
+// fixes them for the whole wave: ky = 1 for even rows, ky in {0, 2} for odd rows
+// (likewise kx), 1, 2 or 4 taps instead of 9.  Each tap spans Cout / 16 whole
+// K-steps of the packed weights.
+__global__ __launch_bounds__(256) void k_conv_bwd_data_s2(ConvShape s,
+                                                          const u16* __restrict__ dout,
+                                                          const u16* __restrict__ wtp,
+                                                          const u16* __restrict__ act,
+                                                          u16* __restrict__ din) {
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int hi = l >> 5, lo = l & 31;
+  const int py = wave >> 1, px = wave & 1;
+  const int Hc = (s.H + 1) >> 1, Wc = (s.W + 1) >> 1;
+  const Pix qc = split_pixel((long long)blockIdx.x * 32 + lo, s.B, Hc, Wc);
+  const int y = py + 2 * qc.y, x = px + 2 * qc.x;
+  const bool valid = qc.valid & (y < s.H) & (x < s.W);
+  const Rsrc rdo = make_rsrc(dout, 2LL * s.B * s.Ho * s.Wo * s.Cout);
+  const u16* wrow = wtp + (long long)lo * s.Ktp + 8 * hi;
+  const int nsub = s.Cout >> 4;           // K-steps per tap (1 or 2)
+  bf16x8 w[8], d[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {           // i = (tap a, tap b, K-step of the tap)
+    const int a = i >> 2, b = (i >> 1) & 1, sub = i & 1;
+    const bool use = (a <= py) & (b <= px) & (sub < nsub);
+    const int ky = py ? 2 * a : 1, kx = px ? 2 * b : 1;
+    const int k0 = (3 * ky + kx) * s.Cout + 16 * sub;
+    const int yo = (y + 1 - ky) >> 1, xo = (x + 1 - kx) >> 1;   // y + 1 - ky >= 0 in every class
+    const bool ok = use & valid & (yo < s.Ho) & (xo < s.Wo);
+    const uint32_t e = (((uint32_t)qc.b * s.Ho + (uint32_t)yo) * s.Wo + (uint32_t)xo) * s.Cout +
+                       16 * sub + 8 * hi;
+    w[i] = *reinterpret_cast<const bf16x8*>(wrow + (use ? k0 : 0));
+    d[i] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rdo, ok ? 2 * e : OOB, 0, 0));
+  }
+  f32x16 acc = {};
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int a = i >> 2, b = (i >> 1) & 1, sub = i & 1;
+    if ((a <= py) & (b <= px) & (sub < nsub))
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[i], d[i], acc, 0, 0, 0);
+  }
+  if (!valid) return;
+  const long long p = ((long long)qc.b * s.H + y) * s.W + x;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c0 = 8 * q + 4 * hi;
+    if (c0 >= s.Cin) continue;
+    float v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = acc[4 * q + r];
+    const long long o = p * s.Cin + c0;
     if ((s.Cin & 3) == 0) {
       if (act) {
         const uint2 a2 = *reinterpret_cast<const uint2*>(act + o);
@@ -553,6 +649,13 @@ hipError_t launch_conv_fwd(af_ctx* c, int B, int H, int W, int Cin, int Cout, in
 hipError_t launch_conv_bwd_data(af_ctx* c, int B, int H, int W, int Cin, int Cout, int stride,
                                 const void* dout, const void* wtp, const void* act, void* din) {
   const ConvShape s = shape(B, H, W, Cin, Cout, stride);
+  if (stride == 2 && (Cout & 15) == 0) {
+    const long long mc = (long long)B * ((H + 1) / 2) * ((W + 1) / 2);
+    hipLaunchKernelGGL(k_conv_bwd_data_s2, dim3((unsigned)((mc + 31) / 32)), dim3(256), 0,
+                       c->stream, s, (const u16*)dout, (const u16*)wtp, (const u16*)act,
+                       (u16*)din);
+    return hipGetLastError();
+  }
   const long long M = (long long)B * H * W;
   hipLaunchKernelGGL(k_conv_bwd_data, dim3((unsigned)((M + 127) / 128)), dim3(256), 0, c->stream, s,
                      (const u16*)dout, (const u16*)wtp, (const u16*)act, (u16*)din);

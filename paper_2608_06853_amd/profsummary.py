@@ -43,9 +43,10 @@ FAMILIES = {
     "sim_synth": (r"k_sim_synth\(", "k_sim.hip"),
     "sim_times": (r"k_sim_times\(", "k_sim.hip"),
     "conv_fwd": (r"k_conv_fwd\(", "k_cnn.hip"),
-    "conv_bwd_data": (r"k_conv_bwd_data\(", "k_cnn.hip"),
+    "conv_bwd_data": (r"k_conv_bwd_data(_s2)?\(", "k_cnn.hip"),
     "conv_bwd_weight": (r"k_conv_bwd_weight\(", "k_cnn.hip"),
     "conv_wreduce": (r"k_conv_wreduce\(", "k_cnn.hip"),
+    "conv_wsum": (r"k_conv_wsum\(", "k_cnn.hip"),
     "copy": (r"__amd_rocclr_copyBuffer", None),
 }
 

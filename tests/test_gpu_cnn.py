@@ -143,6 +143,9 @@ def test_training_fits_a_batch():
     (3, 5, 2, 1, 1, 1),        # one pixel, odd channel counts (element-wise paths)
     (1, 1, 1, 1, 1, 2),        # one input and one output channel
     (12, 4, 2, 3, 2, 3),       # Cin not a multiple of 8, Cout a multiple of 4 (8-byte stores)
+    (8, 16, 2, 2, 3, 1),       # stride-2 input gradient by parity class; two classes empty
+    (32, 32, 2, 1, 5, 7),      # the same with two K-steps per tap, odd height and width
+    (2, 8, 1, 3, 9, 11),       # the two-channel forward operand of the first layer
 ])
 def test_degenerate_shapes(ci, co, st, B, H, W):
     """Forward, input gradient and weight gradient at sizes below one tile."""
