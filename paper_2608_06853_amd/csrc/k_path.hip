@@ -107,12 +107,9 @@ __device__ inline int ray_point(const Ray& r, int k, int nseg, float umax, float
   const float u = __builtin_amdgcn_fmed3f(fmaf((float)k, r.du, r.u0), 0.f, umax);
   const float v = __builtin_amdgcn_fmed3f(fmaf((float)k, r.dv, r.v0), 0.f, vmax);
   const int j0 = (int)u, i0 = (int)v;
-  float wz[4];
-  keys_weights(u - (float)j0, wx[0], wx[1], wx[2], wx[3]);
-  keys_weights(v - (float)i0, wz[0], wz[1], wz[2], wz[3]);
+  keys_weights(__builtin_amdgcn_fractf(u), wx[0], wx[1], wx[2], wx[3]);  // u, v >= 0: u - j0
   const float ck = (k == 0 || k == nseg) ? 0.5f * r.coef : r.coef;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) az[q] = ck * wz[q];
+  keys_weights_scaled(__builtin_amdgcn_fractf(v), ck, az[0], az[1], az[2], az[3]);
   return i0 * W + j0;
 }
 
