@@ -26,6 +26,9 @@ __device__ inline double wave_sum(double v) {
 }
 
 constexpr int CMPE_WAVES = 4;
+// Row stride (float2) of a subaperture image in LDS: one more than the sub-tile, so
+// the rows that neighbouring pair entries read start two banks apart.
+constexpr int SS = SUB + 1;
 
 // One workgroup of 4 wavefronts per 64-point sub-tile.  Phase 1 forms, for this
 // sub-tile, the full image and block energy per point and every subaperture
@@ -74,8 +77,8 @@ __global__ __launch_bounds__(256) void k_cmpe(CmpeArgs A) {
   const int npr = max(0, pHi - pLo + 1);
   const int np2 = npr * npr;
   const int nS = npr > 0 ? npr + 1 : 0;
-  float2* Ss = sm;                                   // [nS * nS][SUB]
-  float2* gC = Ss + (size_t)nS * nS * SUB;           // [pps][np2]
+  float2* Ss = sm;                                   // [nS * nS][SS]
+  float2* gC = Ss + (size_t)nS * nS * SS;            // [pps][np2]
   float* er = reinterpret_cast<float*>(gC + (size_t)pps * np2);
   float* rh = er + (size_t)pps * np2;                // rho of each entry, -1 if no energy
 
@@ -101,7 +104,7 @@ __global__ __launch_bounds__(256) void k_cmpe(CmpeArgs A) {
   for (int idx = wv; idx < nS * nS; idx += CMPE_WAVES) {
     const int si = pLo + idx / nS, sj = pLo + idx % nS;
     const float2 a = bget(si, sj), b = bget(si + 1, sj), c = bget(si, sj + 1), d = bget(si + 1, sj + 1);
-    Ss[(size_t)idx * SUB + lane] = make_float2(a.x + b.x + c.x + d.x, a.y + b.y + c.y + d.y);
+    Ss[(size_t)idx * SS + lane] = make_float2(a.x + b.x + c.x + d.x, a.y + b.y + c.y + d.y);
   }
   __syncthreads();
 
@@ -110,8 +113,8 @@ __global__ __launch_bounds__(256) void k_cmpe(CmpeArgs A) {
   for (int item = tid; item < pps * np2; item += CMPE_WAVES * SUB) {
     const int q = item / np2, pr = item - q * np2;
     const int i = pLo + pr / npr, j = pLo + pr % npr;
-    const float2* Xs = Ss + (size_t)((i - pLo) * nS + (j + 1 - pLo)) * SUB + q * M;
-    const float2* Ys = Ss + (size_t)((i + 1 - pLo) * nS + (j - pLo)) * SUB + q * M;
+    const float2* Xs = Ss + (size_t)((i - pLo) * nS + (j + 1 - pLo)) * SS + q * M;
+    const float2* Ys = Ss + (size_t)((i + 1 - pLo) * nS + (j - pLo)) * SS + q * M;
     float cx = 0.f, cy = 0.f, ex = 0.f, ey = 0.f;
     for (int m = 0; m < M; ++m) {
       const float2 X = Xs[m], Y = Ys[m];
@@ -184,13 +187,13 @@ __global__ __launch_bounds__(256) void k_cmpe(CmpeArgs A) {
             if (i < 0 || j < 0 || i > g.nsub - 1 || j > g.nsub - 1) continue;
             if (i >= pLo && i <= pHi && j - 1 >= pLo && j - 1 <= pHi) {
               const float2 c = gq[(i - pLo) * npr + (j - 1 - pLo)];
-              const float2 y = Ss[(size_t)((i + 1 - pLo) * nS + (j - 1 - pLo)) * SUB + lane];
+              const float2 y = Ss[(size_t)((i + 1 - pLo) * nS + (j - 1 - pLo)) * SS + lane];
               G.x += c.x * y.x - c.y * y.y;
               G.y += c.x * y.y + c.y * y.x;
             }
             if (i - 1 >= pLo && i - 1 <= pHi && j >= pLo && j <= pHi) {
               const float2 c = gq[(i - 1 - pLo) * npr + (j - pLo)];
-              const float2 x = Ss[(size_t)((i - 1 - pLo) * nS + (j + 1 - pLo)) * SUB + lane];
+              const float2 x = Ss[(size_t)((i - 1 - pLo) * nS + (j + 1 - pLo)) * SS + lane];
               G.x += c.x * x.x + c.y * x.y;
               G.y += c.x * x.y - c.y * x.x;
             }
@@ -302,11 +305,12 @@ __global__ __launch_bounds__(256) void k_export_img(Geo g, const float2* __restr
 
 int cmpe_span_limit(int pps) {
   // dynamic LDS of k_cmpe for a tile spanning n blocks: (n + 1)^2 subaperture
-  // images of SUB points plus pps * n^2 pair entries; the static arrays take the rest
+  // images of SUB points (row stride SS) plus pps * n^2 pair entries; the static
+  // arrays take the rest
   const size_t budget = 160 * 1024 - sizeof(float) * CMPE_WAVES * 3 * SUB -
                         sizeof(double) * CMPE_WAVES * 3 - 256;
   for (int n = MAX_NBA; n >= 1; --n) {
-    const size_t need = sizeof(float2) * (size_t)(n + 1) * (n + 1) * SUB +
+    const size_t need = sizeof(float2) * (size_t)(n + 1) * (n + 1) * SS +
                         (sizeof(float2) + 2 * sizeof(float)) * (size_t)pps * n * n;
     if (need <= budget) return n;
   }
@@ -333,7 +337,7 @@ hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g,
   const int nba = c->nba_max;
   const int npr = nba;      // upper bound of pair rows (and columns)
   const int nS = nba + 1;   // upper bound of subaperture rows
-  const size_t lds = sizeof(float2) * (size_t)nS * nS * SUB +
+  const size_t lds = sizeof(float2) * (size_t)nS * nS * SS +
                      (sizeof(float2) + 2 * sizeof(float)) * (size_t)c->pps * npr * npr;
   hipLaunchKernelGGL(k_cmpe, dim3((unsigned)(c->P_int / SUB)), dim3(CMPE_WAVES * SUB), lds,
                      c->stream, A);
