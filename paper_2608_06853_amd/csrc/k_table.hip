@@ -12,17 +12,26 @@
 namespace af {
 namespace {
 
+// Row stride of the LDS grid copy for grids up to 64 nodes wide: as a constant,
+// the 16 taps of a path point are immediate offsets from one LDS address.
+constexpr int TAB_LDS_W = 67;
+
 // One instantiation per refraction mode (arc or flat lens, root or discrete
-// search), so the default mode keeps its own register allocation.
-template <int MODE>
+// search), so the default mode keeps its own register allocation; FIXED_W copies
+// the grid at row stride TAB_LDS_W (grids with nx + 3 <= TAB_LDS_W).
+template <int MODE, bool FIXED_W>
 __global__ __launch_bounds__(256) void k_table(TableArgs A) {
   extern __shared__ float G[];
   const Geo& g = A.g;
   const int2 w = A.work[blockIdx.x];
   const int tile = w.x, a0 = w.y;
   const int4 tr = A.tiles[tile];
-  const int gsz = g.W * (g.nz + 3);
-  for (int i = threadIdx.x; i < gsz; i += 256) G[i] = A.gdev[i];
+  const int WL = FIXED_W ? TAB_LDS_W : g.W;
+  const int gsz = WL * (g.nz + 3);
+  for (int i = threadIdx.x; i < gsz; i += 256) {
+    const int r = i / WL, c = i - r * WL;
+    G[i] = c < g.W ? A.gdev[r * g.W + c] : 0.f;
+  }
   __syncthreads();
 
   const long long p = (long long)tile * TILE + threadIdx.x;
@@ -50,7 +59,7 @@ __global__ __launch_bounds__(256) void k_table(TableArgs A) {
       const double4 el = A.elem[a];
       const RayOut r = refract<MODE>(el, pp, g.dlens, g.icl, icm, g.nsearch);
       const float u0 = (r.refx - g.x0) * g.idx, v0 = (r.refz - g.z0) * g.idz;
-      const float acc = path_sum(G, g.W, u0, v0, (up - u0) * inv_n, (vp - v0) * inv_n, g.n_seg,
+      const float acc = path_sum(G, WL, u0, v0, (up - u0) * inv_n, (vp - v0) * inv_n, g.n_seg,
                                  umax, vmax);
       const float dT = r.l2 * acc * inv_n;
       ruv = make_float2(u0, v0);
@@ -92,20 +101,21 @@ hipError_t launch_table(af_ctx* c) {
   A.ray_uv = c->d_ray_uv.as<float2>();
   A.ray_l2 = c->d_ray_l2.as<float>();
   if (c->n_tab_work == 0) return hipSuccess;
-  const size_t lds = sizeof(float) * (size_t)(c->nx + 3) * (c->nz + 3);
+  const bool fixed = c->nx + 3 <= TAB_LDS_W;
+  const size_t lds = sizeof(float) * (size_t)(fixed ? TAB_LDS_W : c->nx + 3) * (c->nz + 3);
+  const dim3 grid(c->n_tab_work), block(256);
+#define AF_TABLE_LAUNCH(M)                                                        \
+  if (fixed)                                                                      \
+    hipLaunchKernelGGL((k_table<M, true>), grid, block, lds, c->stream, A);      \
+  else                                                                            \
+    hipLaunchKernelGGL((k_table<M, false>), grid, block, lds, c->stream, A);
   switch (refract_mode(A.g.flat != 0, A.g.nsearch, A.g.dlens)) {
-    case ARC_ROOT:
-      hipLaunchKernelGGL(k_table<ARC_ROOT>, dim3(c->n_tab_work), dim3(256), lds, c->stream, A);
-      break;
-    case ARC_SEARCH:
-      hipLaunchKernelGGL(k_table<ARC_SEARCH>, dim3(c->n_tab_work), dim3(256), lds, c->stream, A);
-      break;
-    case FLAT_ROOT:
-      hipLaunchKernelGGL(k_table<FLAT_ROOT>, dim3(c->n_tab_work), dim3(256), lds, c->stream, A);
-      break;
-    default:
-      hipLaunchKernelGGL(k_table<FLAT_SEARCH>, dim3(c->n_tab_work), dim3(256), lds, c->stream, A);
+    case ARC_ROOT: AF_TABLE_LAUNCH(ARC_ROOT); break;
+    case ARC_SEARCH: AF_TABLE_LAUNCH(ARC_SEARCH); break;
+    case FLAT_ROOT: AF_TABLE_LAUNCH(FLAT_ROOT); break;
+    default: AF_TABLE_LAUNCH(FLAT_SEARCH);
   }
+#undef AF_TABLE_LAUNCH
   return hipGetLastError();
 }
 
