@@ -44,10 +44,11 @@ MICRO = afsynth.configs.MICRO
 
 @functools.lru_cache(maxsize=8)
 def case(name: str, t0: float = 0.0, t_ttp: float = 0.0, patch: int = 3, block: int | None = None,
-         perturb: float = 0.01, d_lens: float | None = None, n_search: int = 0):
+         perturb: float = 0.01, d_lens: float | None = None, n_search: int = 0,
+         grid_nx: int | None = None):
     """(cfg, oracle problem, iq complex64, s [nz][nx] float32, loss params).
     d_lens = 0 gives the lens-free (straight-ray) model; n_search >= 2 the discrete
-    refraction search."""
+    refraction search; grid_nx replaces the slowness grid's width."""
     base = {"micro": MICRO, "c1_small": C1_SMALL, "micro_linear": afsynth.configs.MICRO_LINEAR}[name]
     arr = replace(base.array, t_ttp=t_ttp)
     if d_lens is not None:
@@ -55,6 +56,8 @@ def case(name: str, t0: float = 0.0, t_ttp: float = 0.0, patch: int = 3, block: 
     cfg = base.with_(array=arr, acq=replace(base.acq, t0=t0), img=replace(base.img, patch=patch))
     if block is not None:
         cfg = cfg.with_(method=replace(cfg.method, block=block))
+    if grid_nx is not None:
+        cfg = cfg.with_(method=replace(cfg.method, nx=grid_nx))
     med = afsynth.medium_for(cfg)
     iq = problems.simulate_iq(cfg, med, n_seg=64).astype(np.complex64)
     prob = problems.problem(cfg, iq.astype(np.complex128))

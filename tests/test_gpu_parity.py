@@ -26,7 +26,8 @@ CASES = [("micro", 0.0, 0.0, 3, None), ("c1_small", 0.0, 0.0, 3, None),
          ("micro_linear", 0.0, 0.0, 3, None), ("micro_linear", 0.4, 0.58, 3, None),
          ("micro_linear", 0.0, 0.0, 3, None, 0.01, 0.0),
          ("micro_linear", 0.0, 0.0, 3, None, 0.01, None, 24),
-         ("micro_linear", 0.0, 0.0, 1, 2), ("c1_small", 0.5, 0.6, 3, None)]
+         ("micro_linear", 0.0, 0.0, 1, 2), ("c1_small", 0.5, 0.6, 3, None),
+         ("micro", 0.0, 0.0, 3, None, 0.01, None, 0, 66)]   # grid wider than 64 nodes
 IDS = ["-".join(str(v) for v in k) for k in CASES]
 
 
