@@ -502,7 +502,8 @@ __global__ __launch_bounds__(256) void k_conv_wsum(const float* __restrict__ par
   if (e >= slab_len) return;
   const int w0 = blockIdx.y * per_group, w1 = min(n_part, w0 + per_group);
   float s = 0.f;
-  for (int w = w0; w < w1; ++w) s += part[(long long)w * slab_len + e];
+#pragma unroll 8
+  for (int w = w0; w < w1; ++w) s += part[(long long)w * slab_len + e];  // loads in flight together
   part2[(long long)blockIdx.y * slab_len + e] = s;
 }
 
@@ -516,11 +517,13 @@ __global__ __launch_bounds__(256) void k_conv_wreduce(const float* __restrict__ 
   if (idx < cout * kvalid) {
     const int co = idx / kvalid, k = idx - co * kvalid;
     float s = 0.f;
+#pragma unroll 8
     for (int g = 0; g < n_groups; ++g) s += part2[(long long)g * slab_len + co * cols + k];
     dw[idx] = s;
   }
   if (idx < cout) {
     float s = 0.f;
+#pragma unroll 8
     for (int g = 0; g < n_groups; ++g) s += part2[(long long)g * slab_len + 32 * cols + idx];
     db[idx] = s;
   }
