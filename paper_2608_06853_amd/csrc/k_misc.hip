@@ -101,7 +101,8 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
                                                   af_loss_params lp, int n_pix) {
   __shared__ double red[256];
   double e = 0, nv = 0, b = 0;
-  for (int i = threadIdx.x; i < n_part; i += 256) {
+#pragma unroll 4
+  for (int i = threadIdx.x; i < n_part; i += 256) {  // unrolled: loads of 4 partials in flight
     e += part[4 * i + 0];
     nv += part[4 * i + 1];
     b += part[4 * i + 2];
