@@ -15,7 +15,7 @@ curvature of the curvilinear array; x is lateral and z points into the body.
 from .configs import (ArrayCfg, AcqCfg, ImgCfg, MethodCfg, Config, CONFIGS,
                       config_by_name)
 from .geometry import (element_positions, element_span, pixel_centres,
-                       patch_spacing, slowness_box, sim_box, lens_radius, lens_correction,
+                       patch_spacing, slowness_box, sim_box, lens_radius,
                        is_linear)
 from .media import (Medium, medium_for, sample_speed, speed_on_grid,
                     random_iq)
@@ -23,6 +23,6 @@ from .media import (Medium, medium_for, sample_speed, speed_on_grid,
 __all__ = [
     "ArrayCfg", "AcqCfg", "ImgCfg", "MethodCfg", "Config", "CONFIGS",
     "config_by_name", "element_positions", "element_span", "pixel_centres",
-    "patch_spacing", "slowness_box", "sim_box", "lens_radius", "lens_correction", "is_linear", "Medium",
+    "patch_spacing", "slowness_box", "sim_box", "lens_radius", "is_linear", "Medium",
     "medium_for", "sample_speed", "speed_on_grid", "random_iq",
 ]

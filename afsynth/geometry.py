@@ -30,13 +30,6 @@ def lens_radius(arr: ArrayCfg) -> float:
     return arr.radius + arr.d_lens
 
 
-def lens_correction(arr: ArrayCfg, c_ref: float = 1.540) -> float:
-    """Scalar round-trip lens offset (us) of the conventional model: the extra time
-    of crossing the lens twice at normal incidence at the lens speed instead of
-    the reference speed, 2 d (1/c_lens - 1/c_ref)."""
-    return 2.0 * arr.d_lens * (1.0 / arr.c_lens - 1.0 / c_ref)
-
-
 def element_polar_angles(arr: ArrayCfg) -> np.ndarray:
     a = np.arange(arr.n_elem, dtype=np.float64)
     return (a - (arr.n_elem - 1) / 2.0) * (arr.pitch / arr.radius)

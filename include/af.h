@@ -39,7 +39,7 @@ typedef enum {
   AF_ERR_STATE = -2,    /* call out of order (e.g. beamform before set_slowness) */
   AF_ERR_HIP = -3,      /* HIP runtime error; see af_last_error */
   AF_ERR_OOM = -4,      /* device allocation failed */
-  AF_ERR_NUMERIC = -5   /* non-finite input slowness */
+  AF_ERR_NUMERIC = -5   /* slowness not finite and positive (af_set_slowness, af_simulate) */
 } af_status;
 
 typedef struct { float x, y; } af_complex;
@@ -94,13 +94,28 @@ af_status af_set_geometry(af_ctx* ctx, int n_elem, const double* elem_xz, int n_
                     int n_samples, double fs, double t0, double fd, int block,
                     double fnum, int n_seg);
 
-/* Lens of the bent-ray model (Eqs. 7-8): thickness d_lens (elements sit that far
- * behind the concentric lens arc, or below the flat lens surface z_elem + d_lens
- * of a linear array), lens speed c_lens, time-to-peak t_ttp added to every round
- * trip.  d_lens = 0 is the lens-free model: straight rays from the
- * elements (the uncorrected baseline of the paper's comparisons).
- * Errors: AF_ERR_ARG for d_lens < 0 or c_lens <= 0. */
-af_status af_set_lens(af_ctx* ctx, double d_lens, double c_lens, double t_ttp);
+/* Lens model of the beamformer (Section II-B).  The physical lens is a layer of
+ * thickness d_lens (elements sit that far behind the concentric lens arc, or
+ * below the flat lens surface z_elem + d_lens of a linear array) and speed
+ * c_lens; t_ttp is the time-to-peak offset of the received envelope, added to
+ * every round trip.  `mode` selects how the beamformer accounts for the lens:
+ *   AF_LENS_BENT          bent rays refracted at the lens surface by Fermat's
+ *                         principle (Eqs. 7-8), the default;
+ *   AF_LENS_CONVENTIONAL  straight rays from the elements plus the scalar lens
+ *                         offset of Eq. 6, read as the round-trip excess time of
+ *                         crossing the lens along the element normal at c_lens
+ *                         instead of c_ref: 2 d_lens (1/c_lens - 1/c_ref);
+ *   AF_LENS_NONE          straight rays from the elements and no lens term (the
+ *                         uncorrected baseline of the paper's comparisons).
+ * c_ref (mm/us) is used by AF_LENS_CONVENTIONAL only.  The channel-data
+ * simulator (af_simulate) always uses the physical lens with bent rays.  With a
+ * straight-ray mode the slowness grid must cover the element positions, where
+ * the rays start (af_set_slowness checks it).
+ * Errors: AF_ERR_ARG for d_lens < 0, c_lens <= 0, a non-finite t_ttp, an
+ * unknown mode, or c_ref <= 0 with AF_LENS_CONVENTIONAL. */
+enum { AF_LENS_BENT = 0, AF_LENS_CONVENTIONAL = 1, AF_LENS_NONE = 2 };
+af_status af_set_lens(af_ctx* ctx, double d_lens, double c_lens, double t_ttp, int mode,
+                      double c_ref);
 
 /* Refraction-point rule of the lens model (Section III-A, model implementation):
  * n_search = 0 (the default) takes the exact Fermat stationary point (continuous
@@ -118,10 +133,15 @@ af_status af_set_refraction_search(af_ctx* ctx, int n_search);
 /* Slowness grid s ~ 1/c (Section III-A): node (i, j) at (x0 + j dx, z0 + i dz),
  * values [nz][nx] float32 at `s_dev` (device), copied on the context stream.
  * At most (nx+3)(nz+3) = 9600 padded nodes (e.g. 95 x 95).
- * The grid box must contain every evaluation point and the lens arc over the
- * angles of the elements and points (AF_ERR_ARG otherwise); needs geometry and
- * lens first (AF_ERR_STATE).  Non-finite or non-positive values are reported as
- * AF_ERR_NUMERIC by the next loss call's terms (total = NaN). */
+ * The grid box must contain every evaluation point and the lens arc (the element
+ * arc for a straight-ray lens model) over the angles of the elements and points
+ * (AF_ERR_ARG otherwise); needs geometry and lens first (AF_ERR_STATE).
+ * The copied values are read back and checked on the host, which synchronises
+ * the stream: a node that is not finite and positive gives AF_ERR_NUMERIC, and
+ * the context then has no slowness until the next successful call.
+ * (af_autofocus_step reads its s_dev on the device only: a non-finite or
+ * non-positive value there shows as total = NaN in its terms; the kernels then
+ * treat the affected rays as masked, so no index leaves its buffer.) */
 af_status af_set_slowness(af_ctx* ctx, int nx, int nz, double x0, double z0, double dx,
                     double dz, const float* s_dev);
 
@@ -181,11 +201,11 @@ af_status af_forward(af_ctx* ctx, const af_complex* iq_dev, const af_loss_params
 af_status af_backward(af_ctx* ctx, const af_complex* iq_dev, const af_loss_params* lp,
                 const af_complex* gblk_dev, float* grad_dev);
 
-/* One plain-method iteration: the loss at s_dev (terms_dev), its gradient by a
- * backward pass that recomputes the travel-time table instead of keeping the
- * forward's, then an Adam step (the paper's Eq. 9 uses plain descent; Adam
- * replaces it here) updating s_dev, m_dev, v_dev ([nz][nx], device, in place).
- * step is 1-based.  The context's slowness becomes the updated s. */
+/* One plain-method iteration: the loss at s_dev (terms_dev), its gradient (the
+ * same passes as af_loss_and_grad), then an Adam step (the paper's Eq. 9 uses
+ * plain descent; Adam replaces it here) updating s_dev, m_dev, v_dev ([nz][nx],
+ * device, in place).  step is 1-based.  The context's slowness becomes the
+ * updated s. */
 af_status af_autofocus_step(af_ctx* ctx, const af_complex* iq_dev, const af_loss_params* lp,
                       const af_adam_params* ap, int step, float* s_dev, float* m_dev,
                       float* v_dev, float* terms_dev);
@@ -251,15 +271,22 @@ af_status af_mse_loss(af_ctx* ctx, int n, const float* out, const float* label, 
 af_status af_adam_update(af_ctx* ctx, int n, const af_adam_params* ap, int step, float* p,
                          float* m, float* v, const float* g);
 /* NHWC BF16 network input from C channel-major FP32 maps [C][n]:
- * out[i][c] = (maps[c][i] - shift[c]) * scale[c] (shift, scale: device, C floats). */
+ * out[i][c] = bf16((maps[c][i] - shift[c]) * scale[c]), the difference and product
+ * in FP32, rounded to BF16 to nearest even (shift, scale: device, C floats). */
 af_status af_features(af_ctx* ctx, long long n, int C, const float* maps, const float* shift,
                       const float* scale, void* out_bf16);
 /* Slowness grid [nz][nx] (node (i, j) at (x0 + j dx, z0 + i dz)) from a polar map
- * [nr][nt] (rows: radius r0 + a dr; columns: polar angle t0 + b dt):
- * s = s_base + scale * bilinear(map) at the node's radius and angle, clamped. */
+ * [nr][nt] (rows: radius r0 + a dr; columns: polar angle t0 + b dt, angles from
+ * the z axis towards x):  with u = (|node| - r0)/dr and v = (angle - t0)/dt, each
+ * clamped to the map's index range, s = s_base + scale * (bilinear interpolation
+ * of the map at (u, v)), then clamped to [s_lo, s_hi] (a non-finite value gives
+ * s_lo), so a network output always yields a slowness the hot path accepts.
+ * Errors: AF_ERR_ARG for nr or nt < 2, non-positive sizes or steps, or
+ * 0 < s_lo <= s_hi violated. */
 af_status af_polar_to_grid(af_ctx* ctx, const float* map, int nr, int nt, double r0, double dr,
                            double t0, double dt, int nx, int nz, double x0, double z0,
-                           double dx, double dz, float s_base, float scale, float* s_dev);
+                           double dx, double dz, float s_base, float scale, float s_lo,
+                           float s_hi, float* s_dev);
 
 /* Kernel timing with HIP events on the context stream.  While enabled, each
  * kernel of the loss, gradient and update calls and each convolution call (the

@@ -14,4 +14,4 @@ the reading it takes.
 
 Units: mm, us, MHz; speed in mm/us, slowness in us/mm.
 """
-from . import geometry, fermat, path, das, cmpe, reg, model, adam, sweep, simulate  # noqa: F401
+from . import geometry, fermat, lens, path, das, cmpe, reg, model, adam, sweep, simulate  # noqa: F401

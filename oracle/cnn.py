@@ -79,3 +79,49 @@ def backward(params, acts, dout):
 def mse(out, label, scale):
     d = out - label
     return float(scale * np.sum(d * d)), 2.0 * scale * d
+
+
+# --- the glue around the network: its input features and its output resampling ---------------
+# (the learned warm start is an extension; the paper has no learned part)
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Nearest BF16 value of every entry (ties to even), returned in float64.
+
+    BF16 keeps the sign, the 8 exponent bits and the top 7 fraction bits of an
+    IEEE single; the value is first rounded to single precision and its low 16
+    bits then rounded away to nearest even."""
+    b = np.asarray(x, dtype=np.float64).astype(np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (b >> 16) & 1
+    r = ((b + 0x7FFF + lsb) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def features(maps: np.ndarray, shift: np.ndarray, scale: np.ndarray) -> np.ndarray:
+    """Network input from channel-major feature maps [C][n]: the entries
+    (maps[c][i] - shift[c]) * scale[c] in pixel-major order [n][C] (not rounded)."""
+    maps = np.asarray(maps, dtype=np.float64)
+    return ((maps - shift[:, None]) * scale[:, None]).T.copy()
+
+
+def polar_to_grid(pmap: np.ndarray, r0: float, dr: float, t0: float, dt: float, nx: int,
+                  nz: int, x0: float, z0: float, dx: float, dz: float, s_base: float,
+                  scale: float, s_lo: float, s_hi: float) -> np.ndarray:
+    """Slowness on the node grid [nz][nx] from a polar map [nr][nt] whose rows are
+    radii r0 + a dr and columns polar angles t0 + b dt (angle from the z axis
+    towards x).  At node (x0 + j dx, z0 + i dz): the fractional map indices of its
+    radius and angle, each clamped to the map; bilinear interpolation between the
+    four surrounding map entries; s_base + scale * value, clamped to [s_lo, s_hi]."""
+    pmap = np.asarray(pmap, dtype=np.float64)
+    nr, nt = pmap.shape
+    out = np.empty((nz, nx))
+    for i in range(nz):
+        for j in range(nx):
+            x, z = x0 + j * dx, z0 + i * dz
+            u = min(max((np.hypot(x, z) - r0) / dr, 0.0), nr - 1.0)
+            v = min(max((np.arctan2(x, z) - t0) / dt, 0.0), nt - 1.0)
+            a, b = min(int(u), nr - 2), min(int(v), nt - 2)
+            fu, fv = u - a, v - b
+            val = ((1 - fu) * ((1 - fv) * pmap[a, b] + fv * pmap[a, b + 1])
+                   + fu * ((1 - fv) * pmap[a + 1, b] + fv * pmap[a + 1, b + 1]))
+            out[i, j] = min(max(s_base + scale * val, s_lo), s_hi)
+    return out

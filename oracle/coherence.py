@@ -31,7 +31,7 @@ def channel_images(prob: Problem, s: np.ndarray, c_med: float | None = None) -> 
     images of single-element blocks."""
     h = prob.apod()
     T = np.where(h, travel_times(prob, s, h, c_med), 0.0)
-    b1 = das.das_blocks(prob.iq, T, h, t0=prob.t0, fs=prob.fs, fd=prob.fd, t_ttp=prob.t_ttp,
+    b1 = das.das_blocks(prob.iq, T, h, t0=prob.t0, fs=prob.fs, fd=prob.fd, t_ttp=prob.tau_offset,
                         block=1)
     return b1.sum(axis=0)
 

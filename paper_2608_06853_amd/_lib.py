@@ -24,6 +24,8 @@ _lib = C.CDLL(LIB_PATH)
 AF_OK, AF_ERR_ARG, AF_ERR_STATE, AF_ERR_HIP, AF_ERR_OOM, AF_ERR_NUMERIC = 0, -1, -2, -3, -4, -5
 TERM_CMPE, TERM_TV, TERM_SV, TERM_SB, TERM_TOTAL, TERM_NVALID, TERM_CMED = range(7)
 N_TERMS = 8
+LENS_BENT, LENS_CONVENTIONAL, LENS_NONE = 0, 1, 2
+LENS_MODES = {"bent": LENS_BENT, "conventional": LENS_CONVENTIONAL, "none": LENS_NONE}
 (Q_P, Q_P_INTERNAL, Q_NBLK, Q_GBLK_ELEMS, Q_ACTIVE_PAIRS, Q_ACTIVE_SAMPLES, Q_TILES, Q_NA_MAX,
  Q_NBA_MAX) = range(9)
 
@@ -56,7 +58,7 @@ _sig = {
     "af_destroy": (None, [_vp]),
     "af_last_error": (C.c_char_p, [_vp]),
     "af_set_geometry": (C.c_int, [_vp, _i, _vp, _i, _vp, _i, _d, _i, _d, _d, _d, _i, _d, _i]),
-    "af_set_lens": (C.c_int, [_vp, _d, _d, _d]),
+    "af_set_lens": (C.c_int, [_vp, _d, _d, _d, _i, _d]),
     "af_set_refraction_search": (C.c_int, [_vp, _i]),
     "af_set_slowness": (C.c_int, [_vp, _i, _i, _d, _d, _d, _d, _vp]),
     "af_beamform": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
@@ -80,7 +82,7 @@ _sig = {
     "af_adam_update": (C.c_int, [_vp, _i, C.POINTER(AdamParams), _i, _vp, _vp, _vp, _vp]),
     "af_features": (C.c_int, [_vp, C.c_longlong, _i, _vp, _vp, _vp, _vp]),
     "af_polar_to_grid": (C.c_int, [_vp, _vp, _i, _i, _d, _d, _d, _d, _i, _i, _d, _d, _d, _d,
-                                   C.c_float, C.c_float, _vp]),
+                                   C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -170,8 +172,9 @@ class Context:
                                        int(n_samples), float(fs), float(t0), float(fd), int(block),
                                        float(fnum), int(n_seg)))
 
-    def set_lens(self, d_lens, c_lens, t_ttp=0.0):
-        self._chk(_lib.af_set_lens(self._h, float(d_lens), float(c_lens), float(t_ttp)))
+    def set_lens(self, d_lens, c_lens, t_ttp=0.0, mode=LENS_BENT, c_ref=1.540):
+        self._chk(_lib.af_set_lens(self._h, float(d_lens), float(c_lens), float(t_ttp), int(mode),
+                                   float(c_ref)))
 
     def set_refraction_search(self, n_search: int):
         self._chk(_lib.af_set_refraction_search(self._h, int(n_search)))
@@ -327,12 +330,14 @@ class Context:
                                    _dev(scale, torch.float32, C_, "scale"),
                                    _dev(out, torch.bfloat16, n * C_, "out")))
 
-    def polar_to_grid(self, pmap, nr, nt, r0, dr, t0, dt, nx, nz, x0, z0, dx, dz, s_base, scale, s):
+    def polar_to_grid(self, pmap, nr, nt, r0, dr, t0, dt, nx, nz, x0, z0, dx, dz, s_base, scale,
+                      s_lo, s_hi, s):
         import torch
         self._chk(_lib.af_polar_to_grid(self._h, _dev(pmap, torch.float32, nr * nt, "map"), nr, nt,
                                         float(r0), float(dr), float(t0), float(dt), nx, nz,
                                         float(x0), float(z0), float(dx), float(dz), float(s_base),
-                                        float(scale), _dev(s, torch.float32, nx * nz, "s")))
+                                        float(scale), float(s_lo), float(s_hi),
+                                        _dev(s, torch.float32, nx * nz, "s")))
 
     def query(self, what: int) -> int:
         out = C.c_longlong(0)

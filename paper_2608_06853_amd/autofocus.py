@@ -34,6 +34,8 @@ class Acquisition:
     t0: float                # us
     fd: float                # MHz (demodulation = centre frequency)
     n_samples: int
+    lens_mode: int = _lib.LENS_BENT   # beamformer's lens model (_lib.LENS_*)
+    c_ref: float = 1.540     # mm/us, reference speed of the conventional lens offset
 
 
 @dataclass
@@ -115,7 +117,7 @@ class Beamformer:
         self.acq, self.grid = acq, grid
         self.device = torch.device("cuda", device)
         self.ctx = _lib.Context(device)
-        self.ctx.set_lens(acq.d_lens, acq.c_lens, acq.t_ttp)
+        self.ctx.set_lens(acq.d_lens, acq.c_lens, acq.t_ttp, acq.lens_mode, acq.c_ref)
         self.ctx.set_refraction_search(n_search)
         self.img = None
         self.set_imaging(img)

@@ -30,6 +30,27 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
+def inputs():
+    """Every file the library is built from: the HIP sources, their headers and the ABI."""
+    hdr = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    return sources() + sorted(hdr) + [os.path.join(ROOT, "include", "af.h")]
+
+
+def stale() -> bool:
+    """True when libaf.so is missing or older than any file it is built from."""
+    if not os.path.exists(LIB):
+        return True
+    t = os.path.getmtime(LIB)
+    return any(os.path.getmtime(f) > t for f in inputs())
+
+
+def ensure_built(verbose: bool = False) -> str:
+    """Builds libaf.so when it is missing or stale; returns its path."""
+    if stale():
+        build(verbose=verbose)
+    return LIB
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]

@@ -31,6 +31,7 @@ FEAT_H = FEAT_W = 128
 OUT_H = OUT_W = 32
 DS_SCALE = 0.03          # us/mm per unit of network output
 S_BASE = 1.0 / 1.540
+SPEED_MIN, SPEED_MAX = 1.340, 1.740   # mm/us, the global sweep's range
 
 
 def out_size(n, stride):
@@ -288,6 +289,8 @@ def predict_slowness(net: WarmStartNet, fm: FeatureMaker, iq, cfg, grid: af.Grid
     out = net.forward(x.view(1, FEAT_H, FEAT_W, 2), 1)
     og = OutGrid.for_config(cfg)
     s = torch.empty(grid.shape, device=fm.bf.device)
+    # the prediction is kept inside the sweep's speed range (1340-1740 m/s)
     fm.bf.ctx.polar_to_grid(out.reshape(-1), OUT_H, OUT_W, og.r0, og.dr, og.t0, og.dt, grid.nx,
-                            grid.nz, grid.x0, grid.z0, grid.dx, grid.dz, S_BASE, DS_SCALE, s)
+                            grid.nz, grid.x0, grid.z0, grid.dx, grid.dz, S_BASE, DS_SCALE,
+                            1.0 / SPEED_MAX, 1.0 / SPEED_MIN, s)
     return s

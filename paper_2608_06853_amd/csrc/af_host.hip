@@ -104,6 +104,20 @@ void kd_partition(int* idx, int n, int unit, int sub, const std::vector<double>&
   }
 }
 
+// Every node of a slowness grid on the device must be finite and positive: reads
+// the n values back (the stream is synchronised) and checks them on the host.
+af_status check_slowness(af_ctx* c, const float* s_dev, size_t n, const char* who) {
+  std::vector<float> h(n);
+  AF_HIP(hipMemcpyAsync(h.data(), s_dev, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream), who);
+  AF_HIP(hipStreamSynchronize(c->stream), who);
+  for (size_t i = 0; i < n; ++i)
+    if (!(h[i] > 0.f) || !std::isfinite(h[i]))
+      return fail(c, AF_ERR_NUMERIC,
+                  std::string(who) + ": slowness node " + std::to_string(i) +
+                      " is not finite and positive");
+  return AF_OK;
+}
+
 template <class T>
 af_status upload(af_ctx* c, DBuf& b, const std::vector<T>& v, const char* what) {
   AF_ALLOC(b, sizeof(T) * std::max<size_t>(v.size(), 1), what);
@@ -533,13 +547,28 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
   return AF_OK;
 }
 
-af_status af_set_lens(af_ctx* c, double d_lens, double c_lens, double t_ttp) {
+af_status af_set_lens(af_ctx* c, double d_lens, double c_lens, double t_ttp, int mode,
+                      double c_ref) {
   if (!c) return AF_ERR_ARG;
-  if (!(d_lens >= 0) || !(c_lens > 0) || !std::isfinite(t_ttp))
+  if (!(d_lens >= 0) || !(c_lens > 0) || !std::isfinite(t_ttp) || !std::isfinite(d_lens) ||
+      !std::isfinite(c_lens))
     return fail(c, AF_ERR_ARG, "af_set_lens: need d_lens >= 0, c_lens > 0, finite t_ttp");
-  c->d_lens = d_lens;
+  if (mode != AF_LENS_BENT && mode != AF_LENS_CONVENTIONAL && mode != AF_LENS_NONE)
+    return fail(c, AF_ERR_ARG, "af_set_lens: unknown lens mode");
+  if (mode == AF_LENS_CONVENTIONAL && !(c_ref > 0 && std::isfinite(c_ref)))
+    return fail(c, AF_ERR_ARG, "af_set_lens: the conventional model needs c_ref > 0");
+  c->lens_mode = mode;
+  c->d_lens_phys = d_lens;
+  c->t_ttp_phys = t_ttp;
   c->c_lens = c_lens;
+  c->c_ref = mode == AF_LENS_CONVENTIONAL ? c_ref : 1.54;
+  // the bent-ray model traces the lens (Eqs. 7-8); the straight-ray models start
+  // their rays at the elements, the conventional one adding the scalar lens
+  // offset of Eq. 6 (round trip through the lens along the normal at c_lens
+  // instead of c_ref) to the time-to-peak constant
+  c->d_lens = mode == AF_LENS_BENT ? d_lens : 0.0;
   c->t_ttp = t_ttp;
+  if (mode == AF_LENS_CONVENTIONAL) c->t_ttp += 2.0 * d_lens * (1.0 / c_lens - 1.0 / c_ref);
   c->has_lens = true;
   c->has_grid = false;
   return AF_OK;
@@ -628,8 +657,11 @@ af_status af_set_slowness(af_ctx* c, int nx, int nz, double x0, double z0, doubl
   AF_ALLOC(c->d_gpad, sizeof(float) * np, "padded gradient");
   AF_ALLOC(c->d_gpart, sizeof(float) * np * std::max(c->n_order, 1), "partial gradients");
   AF_ALLOC(c->d_terms, sizeof(float) * 8, "terms");
+  c->has_grid = false;  // until the new values have passed the check
   AF_HIP(hipMemcpyAsync(c->d_s.p, s_dev, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream),
          "af_set_slowness copy");
+  af_status st = check_slowness(c, c->d_s.as<float>(), n, "af_set_slowness");
+  if (st != AF_OK) return st;
   c->has_grid = true;
   return AF_OK;
 }
@@ -785,10 +817,8 @@ af_status af_autofocus_step(af_ctx* c, const af_complex* iq, const af_loss_param
   if ((st = check_lp(c, lp)) != AF_OK) return st;
   const size_t n = (size_t)c->nx * c->nz;
   AF_HIP(hipMemcpyAsync(c->d_s.p, s, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream), "copy s");
-  // forward, then a backward that rebuilds the travel-time table (no table is
-  // kept from the forward pass)
+  // forward, then the backward on the table the forward built
   if ((st = run_forward(c, iq, lp, terms, nullptr, true, false)) != AF_OK) return st;
-  if ((st = run_tables(c, lp)) != AF_OK) return st;
   if ((st = run_backward(c, iq, c->d_bblk.as<float2>(), false, c->d_grad.as<float>())) != AF_OK)
     return st;
   AF_KERNEL(AF_K_ADAM, af::launch_adam(c, ap, step, s, m, v, c->d_grad.as<float>()), "adam");
@@ -820,6 +850,8 @@ af_status af_simulate(af_ctx* c, int n_scat, const double* scat_xz, const float*
   if ((size_t)2 * c->Ns * sizeof(float) > 64 * 1024)
     return fail(c, AF_ERR_ARG, "af_simulate: records longer than 8192 samples");
   AF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  af_status st = check_slowness(c, s_true, (size_t)nx * nz, "af_simulate");
+  if (st != AF_OK) return st;
   AF_HIP(af::launch_simulate(c, n_scat, scat_xz, amp, nx, nz, x0, z0, dx, dz, s_true, n_seg, fc,
                              frac_bw, reinterpret_cast<float2*>(iq)),
          "simulate");
@@ -908,13 +940,17 @@ af_status af_features(af_ctx* c, long long n, int C, const float* maps, const fl
 
 af_status af_polar_to_grid(af_ctx* c, const float* map, int nr, int nt, double r0, double dr,
                            double t0, double dt, int nx, int nz, double x0, double z0, double dx,
-                           double dz, float s_base, float scale, float* s) {
+                           double dz, float s_base, float scale, float s_lo, float s_hi,
+                           float* s) {
   if (!c) return AF_ERR_ARG;
-  if (!map || !s || nr < 2 || nt < 2 || nx < 1 || nz < 1 || !(dr > 0) || !(dt > 0))
+  if (!map || !s || nr < 2 || nt < 2 || nx < 1 || nz < 1 || !(dr > 0) || !(dt > 0) ||
+      !(dx > 0) || !(dz > 0))
     return fail(c, AF_ERR_ARG, "af_polar_to_grid: bad argument");
+  if (!(s_lo > 0.f) || !(s_hi >= s_lo) || !std::isfinite(s_hi))
+    return fail(c, AF_ERR_ARG, "af_polar_to_grid: need 0 < s_lo <= s_hi");
   AF_HIP(hipSetDevice(c->device), "hipSetDevice");
   AF_HIP(af::launch_polar_to_grid(c, map, nr, nt, r0, dr, t0, dt, nx, nz, x0, z0, dx, dz, s_base,
-                                  scale, s),
+                                  scale, s_lo, s_hi, s),
          "polar_to_grid");
   return AF_OK;
 }

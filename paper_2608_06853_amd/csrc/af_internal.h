@@ -139,7 +139,11 @@ struct af_ctx {
   std::vector<int> tile_order;              // tiles with work, heaviest first
   int n_tab_work = 0, n_das_work = 0, n_order = 0;
 
-  // lens
+  // lens: the physical lens (d_lens_phys, c_lens, t_ttp_phys) and the beamformer's
+  // model of it -- the lens thickness its rays refract through (d_lens: 0 for the
+  // straight-ray models) and the scalar added to every round trip (t_ttp)
+  int lens_mode = AF_LENS_BENT;
+  double d_lens_phys = 0, t_ttp_phys = 0, c_ref = 1.54;
   double d_lens = 0, c_lens = 1, t_ttp = 0;
   int n_search = 0;
   bool flat = false;      // linear array: every element on one line z = const
@@ -228,5 +232,6 @@ hipError_t launch_features(af_ctx* c, long long n, int C, const float* maps, con
                            const float* scale, void* out);
 hipError_t launch_polar_to_grid(af_ctx* c, const float* map, int nr, int nt, double r0, double dr,
                                 double t0, double dt, int nx, int nz, double x0, double z0,
-                                double dx, double dz, float s_base, float scale, float* s);
+                                double dx, double dz, float s_base, float scale, float s_lo,
+                                float s_hi, float* s);
 }  // namespace af

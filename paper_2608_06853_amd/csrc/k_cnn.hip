@@ -600,12 +600,13 @@ __global__ __launch_bounds__(256) void k_features(long long n, int C, const floa
 
 // Slowness grid from a polar map: s[i][j] = s_base + scale * bilinear(map) at the
 // node's (radius, angle), clamped to the map; map rows are radii r0 + a dr,
-// columns angles t0 + b dt.
+// columns angles t0 + b dt; the result is clamped to [s_lo, s_hi].
 __global__ __launch_bounds__(256) void k_polar_to_grid(const float* __restrict__ map, int nr, int nt,
                                                        double r0, double dr, double t0, double dt,
                                                        int nx, int nz, double x0, double z0,
                                                        double dx, double dz, float s_base,
-                                                       float scale, float* __restrict__ s) {
+                                                       float scale, float s_lo, float s_hi,
+                                                       float* __restrict__ s) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= nx * nz) return;
   const int i = idx / nx, j = idx - i * nx;
@@ -619,7 +620,7 @@ __global__ __launch_bounds__(256) void k_polar_to_grid(const float* __restrict__
   const float m00 = map[a0 * nt + b0], m01 = map[a0 * nt + b0 + 1];
   const float m10 = map[(a0 + 1) * nt + b0], m11 = map[(a0 + 1) * nt + b0 + 1];
   const float val = (1 - fu) * ((1 - fv) * m00 + fv * m01) + fu * ((1 - fv) * m10 + fv * m11);
-  s[idx] = s_base + scale * val;
+  s[idx] = fminf(fmaxf(s_base + scale * val, s_lo), s_hi);  // NaN -> s_lo
 }
 
 ConvShape shape(int B, int H, int W, int Cin, int Cout, int stride) {
@@ -725,9 +726,10 @@ hipError_t launch_features(af_ctx* c, long long n, int C, const float* maps, con
 
 hipError_t launch_polar_to_grid(af_ctx* c, const float* map, int nr, int nt, double r0, double dr,
                                 double t0, double dt, int nx, int nz, double x0, double z0,
-                                double dx, double dz, float s_base, float scale, float* s) {
+                                double dx, double dz, float s_base, float scale, float s_lo,
+                                float s_hi, float* s) {
   hipLaunchKernelGGL(k_polar_to_grid, dim3((nx * nz + 255) / 256), dim3(256), 0, c->stream, map, nr,
-                     nt, r0, dr, t0, dt, nx, nz, x0, z0, dx, dz, s_base, scale, s);
+                     nt, r0, dr, t0, dt, nx, nz, x0, z0, dx, dz, s_base, scale, s_lo, s_hi, s);
   return hipGetLastError();
 }
 

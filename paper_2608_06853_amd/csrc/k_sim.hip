@@ -103,7 +103,10 @@ hipError_t launch_simulate(af_ctx* c, int n_scat, const double* scat_xz, const f
                                nullptr)) != hipSuccess)
     return e;
   SimGeo sg{nx, nz, nx + 3, n_seg, (float)x0, (float)z0, (float)(1.0 / dx), (float)(1.0 / dz)};
-  const Geo g = c->geo();
+  // the physical lens with bent rays, whatever lens model the beamformer uses
+  Geo g = c->geo();
+  g.dlens = c->d_lens_phys;
+  g.t_ttp = c->t_ttp_phys;
   hipLaunchKernelGGL(k_sim_times, dim3((n_scat + 255) / 256, c->N), dim3(256), 0, c->stream, g, sg,
                      c->d_elem.as<double4>(), d_spol.as<double4>(), d_sxy.as<float2>(), n_scat,
                      d_gd.as<float>(), d_sc.as<double>(), d_T.as<double>());

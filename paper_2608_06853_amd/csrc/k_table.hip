@@ -15,6 +15,7 @@ namespace {
 // Row stride of the LDS grid copy for grids up to 64 nodes wide: as a constant,
 // the 16 taps of a path point are immediate offsets from one LDS address.
 constexpr int TAB_LDS_W = 67;
+constexpr size_t TAB_LDS_BYTES = 160 * 1024;  // LDS of one workgroup on gfx950
 
 // One instantiation per refraction mode (arc or flat lens, root or discrete
 // search), so the default mode keeps its own register allocation; FIXED_W copies
@@ -59,24 +60,42 @@ __global__ __launch_bounds__(256) void k_table(TableArgs A) {
       const double4 el = A.elem[a];
       const RayOut r = refract<MODE>(el, pp, g.dlens, g.icl, icm, g.nsearch);
       const float u0 = (r.refx - g.x0) * g.idx, v0 = (r.refz - g.z0) * g.idz;
-      const float acc = path_sum(G, WL, u0, v0, (up - u0) * inv_n, (vp - v0) * inv_n, g.n_seg,
-                                 umax, vmax);
-      const float dT = r.l2 * acc * inv_n;
-      ruv = make_float2(u0, v0);
-      rl2 = r.l2;
-      const double uh = (r.t_hom + u_off) * g.fs;
-      const double kh = floor(uh);
-      float uf = (float)(uh - kh) + dT * fsf;
-      const float cf = floorf(uf);
-      e.ui = (int)kh + (int)cf;
-      e.uf = uf - cf;
-      double cyc = (r.t_hom + half_ttp) * g.fd;
-      cyc -= rint(cyc);
-      const float cy = (float)cyc + dT * fdf;
-      float sn, cs;
-      sincospif(2.f * cy, &sn, &cs);
-      e.er = cs;
-      e.ei = sn;
+      // A slowness that is not finite and positive (reported by af_set_slowness; a
+      // caller's own s in the optimiser loop is not re-read on the host) can give a
+      // non-finite ray or time.  Such an entry is written as masked, so every sample
+      // index the DAS kernels form stays bounded (|ui| < 2^29) and every grid
+      // position the path kernels clamp is finite.
+      bool ok = isfinite(u0) && isfinite(v0) && isfinite(r.l2) && isfinite(r.t_hom);
+      float dT = 0.f;
+      double uh = 0.0;
+      if (ok) {
+        const float acc = path_sum(G, WL, u0, v0, (up - u0) * inv_n, (vp - v0) * inv_n,
+                                   g.n_seg, umax, vmax);
+        dT = r.l2 * acc * inv_n;
+        uh = (r.t_hom + u_off) * g.fs;
+        ok = fabs(uh) < 268435456.0 && fabsf(dT * fsf) < 268435456.f;  // 2^28; false for NaN
+      }
+      if (ok) {
+        ruv = make_float2(u0, v0);
+        rl2 = r.l2;
+        const double kh = floor(uh);
+        float uf = (float)(uh - kh) + dT * fsf;
+        const float cf = floorf(uf);
+        e.ui = (int)kh + (int)cf;
+        e.uf = uf - cf;
+        double cyc = (r.t_hom + half_ttp) * g.fd;
+        cyc -= rint(cyc);
+        const float cy = (float)cyc + dT * fdf;
+        float sn, cs;
+        sincospif(2.f * cy, &sn, &cs);
+        e.er = cs;
+        e.ei = sn;
+      } else {
+        e.ui = 0;
+        e.uf = 0.f;
+        e.er = 0.f;
+        e.ei = 0.f;
+      }
     }
     A.tab[(size_t)a * g.P + p] = e;
     A.ray_uv[(size_t)a * g.P + p] = ruv;
@@ -101,7 +120,9 @@ hipError_t launch_table(af_ctx* c) {
   A.ray_uv = c->d_ray_uv.as<float2>();
   A.ray_l2 = c->d_ray_l2.as<float>();
   if (c->n_tab_work == 0) return hipSuccess;
-  const bool fixed = c->nx + 3 <= TAB_LDS_W;
+  // the fixed row stride only where its copy fits the LDS of a workgroup
+  const bool fixed = c->nx + 3 <= TAB_LDS_W &&
+                     sizeof(float) * (size_t)TAB_LDS_W * (c->nz + 3) <= TAB_LDS_BYTES;
   const size_t lds = sizeof(float) * (size_t)(fixed ? TAB_LDS_W : c->nx + 3) * (c->nz + 3);
   const dim3 grid(c->n_tab_work), block(256);
 #define AF_TABLE_LAUNCH(M)                                                        \

@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 import afsynth
-from . import autofocus as af
+from . import _lib, autofocus as af
 
 SWEEP_MAX = 1.740
 
@@ -26,7 +26,7 @@ def geometry(cfg, lens_model: str = "bent"):
 
     * ``bent``: the two-layer Fermat ray through the lens (Eqs. 7-8);
     * ``conventional``: straight rays from the elements plus the scalar round-trip
-      lens offset of Eq. 6 (``afsynth.lens_correction``);
+      lens offset of Eq. 6, which the library forms from the lens constants;
     * ``none``: straight rays from the elements, no lens term.
 
     Pixels are the same physical points in every model; the slowness grid of the
@@ -41,13 +41,9 @@ def geometry(cfg, lens_model: str = "bent"):
     cover = np.concatenate([centres, afsynth.pixel_centres(arr, img, depth_scale=smax)])
     arr_box = arr if lens_model == "bent" else replace(arr, d_lens=0.0)
     x0, z0, dx, dz = afsynth.slowness_box(arr_box, cover, sp * smax, met.nx, met.nz)
-    d_lens, t_ttp = arr.d_lens, arr.t_ttp
-    if lens_model != "bent":
-        d_lens = 0.0
-        if lens_model == "conventional":
-            t_ttp = t_ttp + afsynth.lens_correction(arr, img.c_ref)
-    acqd = af.Acquisition(elem_xz=elem, d_lens=d_lens, c_lens=arr.c_lens, t_ttp=t_ttp,
-                          fs=acq.fs, t0=acq.t0, fd=acq.fc, n_samples=acq.n_samples)
+    acqd = af.Acquisition(elem_xz=elem, d_lens=arr.d_lens, c_lens=arr.c_lens, t_ttp=arr.t_ttp,
+                          fs=acq.fs, t0=acq.t0, fd=acq.fc, n_samples=acq.n_samples,
+                          lens_mode=_lib.LENS_MODES[lens_model], c_ref=img.c_ref)
     imgd = af.Imaging(centres=centres, patch=img.patch, spacing=sp, block=met.block,
                       fnum=met.fnum, n_seg=met.n_seg)
     grid = af.Grid(nx=met.nx, nz=met.nz, x0=x0, z0=z0, dx=dx, dz=dz)
@@ -72,15 +68,12 @@ def simulate(bf: af.Beamformer, cfg, med, cover) -> torch.Tensor:
 
 def build(cfg, seed=None, device: int = 0, lens_model: str = "bent"):
     """(Beamformer of ``lens_model`` at a uniform 1/c_ref slowness, channel data,
-    medium).  The channel data always come from the bent-ray physics of the lens."""
-    acqd, imgd, grid, cover = geometry(cfg)
+    medium).  The channel data always come from the bent-ray physics of the lens
+    (the library's simulator uses the physical lens whatever the lens model)."""
+    acqd, imgd, grid, cover = geometry(cfg, lens_model)
     bf = af.Beamformer(acqd, imgd, grid, device)
     med = afsynth.medium_for(cfg, seed)
     iq = simulate(bf, cfg, med, cover)
-    if lens_model != "bent":
-        acqm, imgm, gridm, _ = geometry(cfg, lens_model)
-        bf = af.Beamformer(acqm, imgm, gridm, device)
-        grid = gridm
     bf.set_slowness(torch.full(grid.shape, 1.0 / cfg.img.c_ref, device=bf.device))
     return bf, iq, med
 

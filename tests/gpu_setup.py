@@ -16,11 +16,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def ensure_built():
-    lib = os.path.join(ROOT, "paper_2608_06853_amd", "libaf.so")
-    if not os.path.exists(lib):
-        from paper_2608_06853_amd import build
-        build.build()
-    return lib
+    """Builds the library when it is missing or older than its sources."""
+    from paper_2608_06853_amd import build
+    return build.ensure_built()
 
 
 def gpu_available() -> bool:
@@ -45,10 +43,13 @@ MICRO = afsynth.configs.MICRO
 @functools.lru_cache(maxsize=8)
 def case(name: str, t0: float = 0.0, t_ttp: float = 0.0, patch: int = 3, block: int | None = None,
          perturb: float = 0.01, d_lens: float | None = None, n_search: int = 0,
-         grid_nx: int | None = None):
+         grid_nx: int | None = None, lens_model: str = "bent", rho: float = 0.5,
+         grid_nz: int | None = None):
     """(cfg, oracle problem, iq complex64, s [nz][nx] float32, loss params).
-    d_lens = 0 gives the lens-free (straight-ray) model; n_search >= 2 the discrete
-    refraction search; grid_nx replaces the slowness grid's width."""
+    d_lens = 0 gives a lens-free array; lens_model "conventional" or "none" the
+    straight-ray models of the beamformer (the channel data still come from the
+    physical lens); n_search >= 2 the discrete refraction search; grid_nx and
+    grid_nz replace the slowness grid's size; rho is the CMPE threshold."""
     base = {"micro": MICRO, "c1_small": C1_SMALL, "micro_linear": afsynth.configs.MICRO_LINEAR}[name]
     arr = replace(base.array, t_ttp=t_ttp)
     if d_lens is not None:
@@ -58,15 +59,23 @@ def case(name: str, t0: float = 0.0, t_ttp: float = 0.0, patch: int = 3, block: 
         cfg = cfg.with_(method=replace(cfg.method, block=block))
     if grid_nx is not None:
         cfg = cfg.with_(method=replace(cfg.method, nx=grid_nx))
+    if grid_nz is not None:
+        cfg = cfg.with_(method=replace(cfg.method, nz=grid_nz))
     med = afsynth.medium_for(cfg)
     iq = problems.simulate_iq(cfg, med, n_seg=64).astype(np.complex64)
     prob = problems.problem(cfg, iq.astype(np.complex128))
     prob.n_search = n_search
+    prob.lens_model = lens_model
+    if lens_model != "bent":  # straight rays start at the elements: the grid covers them
+        x0, z0, dx, dz, nx, nz = prob.grid
+        zl = float(np.min(prob.elem_xz[:, 1])) - 0.25
+        z1 = z0 + (nz - 1) * dz
+        prob.grid = (x0, zl, dx, (z1 - zl) / (nz - 1), nx, nz)
     s_true = problems.true_slowness(cfg, med, prob)
     rng = np.random.default_rng(cfg.seed + 11)
     s = (s_true * (1.0 + perturb * rng.standard_normal(s_true.shape))).astype(np.float32)
     lp = problems.loss_params(cfg, sb_ref=float(np.mean(np.abs(iq)) ** 2 * 50.0))
-    lp = model.LossParams(**{**lp.__dict__, "w_sb": 0.05, "rho_thresh": 0.5})
+    lp = model.LossParams(**{**lp.__dict__, "w_sb": 0.05, "rho_thresh": rho})
     return cfg, prob, iq, s, lp
 
 
@@ -78,9 +87,11 @@ def lib_params(lp):
 
 def beamformer(cfg, prob, device=0):
     from paper_2608_06853_amd import autofocus as af
+    from paper_2608_06853_amd import _lib
     acq = af.Acquisition(elem_xz=prob.elem_xz, d_lens=prob.d_lens, c_lens=prob.c_lens,
                          t_ttp=prob.t_ttp, fs=prob.fs, t0=prob.t0, fd=prob.fd,
-                         n_samples=prob.iq.shape[2])
+                         n_samples=prob.iq.shape[2], lens_mode=_lib.LENS_MODES[prob.lens_model],
+                         c_ref=prob.c_ref)
     img = af.Imaging(centres=prob.centres, patch=prob.patch, spacing=prob.spacing,
                      block=prob.block, fnum=prob.fnum, n_seg=prob.n_seg)
     x0, z0, dx, dz, nx, nz = prob.grid

@@ -52,3 +52,16 @@ def simulate_iq(cfg, medium, n_seg=None):
                              (x0, z0, dx, dz, nx, nz), n_seg or cfg.sim_nseg,
                              medium.scat_xz, medium.scat_amp, t0=acq.t0, fs=acq.fs,
                              fd=acq.fc, ns=acq.n_samples, fc=acq.fc, frac_bw=acq.frac_bw)
+
+
+def smooth_slowness(grid, seed):
+    """Smooth seeded slowness around 1/1540 us/mm on the node grid (three plane
+    waves of 1 % amplitude)."""
+    x0, z0, dx, dz, nx, nz = grid
+    rng = np.random.default_rng(seed)
+    X, Z = np.meshgrid(np.linspace(0, 1, nx), np.linspace(0, 1, nz))
+    s = np.full((nz, nx), 1.0 / 1.54)
+    for _ in range(3):
+        kx, kz, ph = rng.uniform(0.5, 2.0), rng.uniform(0.5, 2.0), rng.uniform(0, 2 * np.pi)
+        s += 0.01 / 1.54 * np.cos(2 * np.pi * (kx * X + kz * Z) + ph)
+    return s.astype(np.float32)

@@ -178,3 +178,54 @@ def test_degenerate_shapes(ci, co, st, B, H, W):
          G.rel(dw.cpu().numpy().reshape(dwo.shape), dwo), G.rel(db.cpu().numpy(), dbo))
     print("degenerate", ci, co, st, B, H, W, e, flush=True)
     assert e[0] < 4e-3 and e[1] < 1e-5 and e[2] < 1e-5
+
+
+def test_features_match_oracle():
+    """Network input: (map - shift) * scale in FP32, rounded to BF16 to nearest
+    even, against the FP64 value rounded by the oracle.  The two can differ by one
+    BF16 step only where the FP64 value lies within FP32 rounding of a tie."""
+    import torch
+    ctx = _ctx()
+    rng = np.random.default_rng(7)
+    C, n = 2, 128 * 128 + 37
+    maps = rng.standard_normal((C, n)).astype(np.float32)
+    shift = np.array([0.6, 0.3], np.float32)
+    scale = np.array([2.0, 3.0], np.float32)
+    out = torch.empty(n * C, device="cuda", dtype=torch.bfloat16)
+    ctx.features(torch.from_numpy(maps.ravel()).cuda(), torch.from_numpy(shift).cuda(),
+                 torch.from_numpy(scale).cuda(), out)
+    got = out.float().cpu().numpy().astype(np.float64).reshape(n, C)
+    exact = ocnn.features(maps, shift.astype(np.float64), scale.astype(np.float64))
+    want = ocnn.bf16_round(exact)
+    differ = got != want
+    # where they differ, the exact value is a BF16 tie up to FP32 rounding
+    lo = np.minimum(got, want)
+    hi = np.maximum(got, want)
+    tie = np.abs(exact - 0.5 * (lo + hi)) <= 4e-7 * np.abs(exact)
+    print("features: entries", got.size, "differing", int(differ.sum()), flush=True)
+    assert np.all(tie[differ])
+    assert differ.mean() < 1e-3
+
+
+@pytest.mark.parametrize("clamp", [False, True])
+def test_polar_to_grid_matches_oracle(clamp):
+    """Output resampling of the network: slowness on the node grid from the polar
+    map (bilinear, clamped to the map), against the oracle at every node."""
+    import torch
+    ctx = _ctx()
+    rng = np.random.default_rng(11)
+    nr, nt = 32, 32
+    pmap = rng.standard_normal((nr, nt)).astype(np.float32)
+    r0, dr, t0, dt = 41.5, 1.8, -0.15, 0.0095
+    nx, nz, x0, z0, dx, dz = 37, 29, -22.0, 36.0, 1.3, 2.4      # reaches past the map
+    s_lo, s_hi = (0.62, 0.68) if clamp else (0.1, 10.0)
+    out = torch.empty(nz * nx, device="cuda")
+    ctx.polar_to_grid(torch.from_numpy(pmap.ravel()).cuda(), nr, nt, r0, dr, t0, dt, nx, nz, x0,
+                      z0, dx, dz, 1.0 / 1.54, 0.03, s_lo, s_hi, out)
+    got = out.cpu().numpy().reshape(nz, nx).astype(np.float64)
+    want = ocnn.polar_to_grid(pmap, r0, dr, t0, dt, nx, nz, x0, z0, dx, dz, 1.0 / 1.54, 0.03,
+                              s_lo, s_hi)
+    err = np.max(np.abs(got - want) / np.abs(want))
+    print("polar_to_grid max rel err", err, "clamped nodes",
+          int(np.sum((want == s_lo) | (want == s_hi))), flush=True)
+    assert err < 1e-5

@@ -164,3 +164,43 @@ def test_convolution_arguments_are_rejected():
     ctx.conv3x3_fwd(1, 8191, 8192, ci, co, 1, True, x[:n], wp, b, out=out[:n])
     torch.cuda.synchronize()
     assert int(torch.count_nonzero(out[:n]).item()) == 0
+
+
+def test_non_finite_or_non_positive_slowness_is_reported():
+    """af_set_slowness reads the grid back and rejects a node that is not finite and
+    positive with AF_ERR_NUMERIC (the context then has no slowness); in the
+    optimiser loop, where the caller's s stays on the device, such a value makes the
+    loss NaN while every kernel keeps its indices inside its buffers."""
+    import torch
+    from paper_2608_06853_amd import _lib
+    cfg, prob, iq, s, lp = G.case("micro")
+    bf = G.beamformer(cfg, prob)
+    iq_d = torch.from_numpy(iq).cuda()
+    x0, z0, dx, dz, nx, nz = prob.grid
+    for bad in (np.inf, -np.inf, np.nan, -0.5, 0.0):
+        sb = s.copy()
+        sb[nz // 2, nx // 3] = bad
+        print("slowness node set to", bad, flush=True)
+        with pytest.raises(_lib.AfError) as e:
+            bf.ctx.set_slowness(nx, nz, x0, z0, dx, dz, torch.from_numpy(sb).cuda())
+        assert e.value.status == _lib.AF_ERR_NUMERIC
+        with pytest.raises(_lib.AfError) as e:       # no slowness after the failure
+            bf.ctx.loss_and_grad(iq_d, G.lib_params(lp), bf.empty_terms(), None)
+        assert e.value.status == _lib.AF_ERR_STATE
+    bf.set_slowness(torch.from_numpy(s).cuda())
+    lpl = G.lib_params(lp)
+    ap = _lib.adam_params(lr=0.002)
+    for bad in (np.inf, np.nan, -0.5):
+        sd = torch.from_numpy(s).cuda().clone()
+        sd[nz // 2, nx // 3] = float(bad)
+        m = torch.zeros_like(sd)
+        v = torch.zeros_like(sd)
+        terms = bf.empty_terms()
+        print("autofocus step with a slowness node of", bad, flush=True)
+        bf.ctx.autofocus_step(iq_d, lpl, ap, 1, sd, m, v, terms)
+        torch.cuda.synchronize()
+        assert not np.isfinite(terms.cpu().numpy()[_lib.TERM_TOTAL])
+    # the context still works with a valid slowness afterwards
+    terms, grad = bf.loss_and_grad(iq_d, lpl, torch.from_numpy(s).cuda())
+    f, go = model.loss_and_grad(prob, s.astype(np.float64), lp)
+    assert G.rel(grad.cpu().numpy(), go) < 1e-3

@@ -13,12 +13,16 @@ from oracle import model
 pytestmark = pytest.mark.gpu
 
 # (config, t0, t_ttp, patch, block, perturbation, lens thickness, refraction
-# candidates); after the first four come the lens-free straight-ray model, the
-# conventional model (straight rays plus a scalar round-trip lens offset in the
-# time-to-peak constant) and the bent-ray model with the discrete refraction search;
-# then four cases of a linear array with a flat lens (plain, timing offsets,
-# lens-free, discrete search), the linear array with 1 x 1 patches and blocks of 2,
-# and the small curvilinear case with timing offsets.
+# candidates, grid width, lens model, CMPE threshold, grid height); after the
+# first four come a lens-free array (d_lens = 0) with and without a time-to-peak
+# offset and the bent-ray model with the discrete refraction search; then four
+# cases of a linear array with a flat lens (plain, timing offsets, lens-free,
+# discrete search), the linear array with 1 x 1 patches and blocks of 2, the small
+# curvilinear case with timing offsets, a grid wider than 64 nodes; the
+# conventional model of Eq. 6 (curvilinear and linear) and the model without lens
+# correction, both beamforming data of the physical lens; the configured CMPE
+# threshold 0.9; and a tall, narrow grid (4 x 700 nodes) whose fixed-stride copy
+# would not fit in LDS.
 CASES = [("micro", 0.0, 0.0, 3, None), ("c1_small", 0.0, 0.0, 3, None),
          ("micro", 0.7, 0.35, 3, None), ("micro", 0.0, 0.0, 1, 2),
          ("micro", 0.0, 0.0, 3, None, 0.01, 0.0), ("micro", 0.0, 0.5, 3, None, 0.01, 0.0),
@@ -27,7 +31,13 @@ CASES = [("micro", 0.0, 0.0, 3, None), ("c1_small", 0.0, 0.0, 3, None),
          ("micro_linear", 0.0, 0.0, 3, None, 0.01, 0.0),
          ("micro_linear", 0.0, 0.0, 3, None, 0.01, None, 24),
          ("micro_linear", 0.0, 0.0, 1, 2), ("c1_small", 0.5, 0.6, 3, None),
-         ("micro", 0.0, 0.0, 3, None, 0.01, None, 0, 66)]   # grid wider than 64 nodes
+         ("micro", 0.0, 0.0, 3, None, 0.01, None, 0, 66),   # grid wider than 64 nodes
+         ("micro", 0.0, 0.3, 3, None, 0.01, None, 0, None, "conventional"),
+         ("micro_linear", 0.0, 0.58, 3, None, 0.01, None, 0, None, "conventional"),
+         ("micro", 0.0, 0.0, 3, None, 0.01, None, 0, None, "none"),
+         ("micro", 0.0, 0.0, 3, None, 0.01, None, 0, None, "bent", 0.9),
+         ("c1_small", 0.0, 0.0, 3, None, 0.01, None, 0, None, "bent", 0.9),
+         ("micro", 0.0, 0.0, 3, None, 0.01, None, 0, 4, "bent", 0.5, 700)]
 IDS = ["-".join(str(v) for v in k) for k in CASES]
 
 
@@ -75,9 +85,27 @@ def test_block_images_and_maps(key):
     e_cc = G.rel(mp[2], f["cmcc"])
     print("blk", e_blk, "img", e_img, "cf", e_cf, "cmcc", e_cc, flush=True)
     assert e_blk < 1e-4 and e_img < 1e-4 and e_cf < 1e-4 and e_cc < 1e-4
-    # integrated CMPE map: per-pixel means agree except where a pair sits on rho_thresh
-    d = np.abs(mp[0] - f["cmpe_map"])
-    assert np.mean(d < 1e-3) > 0.98
+    # integrated CMPE map: a pixel whose pairs all lie clear of rho_thresh has the
+    # same valid set in FP32 and FP64 and must agree to 1e-4; pixels with a pair
+    # within the band (where the two precisions may decide differently) are few
+    amb = ambiguous_pixels(f["bsub"], prob.n_patch, lp.rho_thresh)
+    keep = ~amb
+    e_map = G.rel(mp[0][keep], f["cmpe_map"][keep])
+    print("cmpe map rel", e_map, "ambiguous pixels", int(amb.sum()), "of", amb.size, flush=True)
+    assert e_map < 1e-4 and amb.mean() < 0.05
+
+
+RHO_BAND = 1e-4   # |rho - rho_thresh| below which FP32 and FP64 may judge a pair differently
+
+
+def ambiguous_pairs(bsub, n_patch, rho_thresh):
+    d = ocmpe.cmpe(bsub, n_patch, rho_thresh)
+    pos = (d["ex"] > ocmpe.MIN_ENERGY) & (d["ey"] > ocmpe.MIN_ENERGY)
+    return pos & (np.abs(d["rho"] - rho_thresh) < RHO_BAND)
+
+
+def ambiguous_pixels(bsub, n_patch, rho_thresh):
+    return np.any(ambiguous_pairs(bsub, n_patch, rho_thresh), axis=(0, 1))
 
 
 @pytest.mark.parametrize("key", CASES, ids=IDS)
@@ -89,10 +117,16 @@ def test_loss_and_gradient(key):
     f, go = model.loss_and_grad(prob, s.astype(np.float64), lp)
     print("gpu", t[:7], "oracle", f["cmpe"], f["tv"], f["sv"], f["sb"], f["total"], f["n_valid"],
           flush=True)
-    assert abs(t[5] - f["n_valid"]) <= max(2, 1e-3 * f["n_valid"])
+    # valid-pair counts may differ only by pairs within the band around rho_thresh;
+    # each such pair moves the CMPE mean by at most pi / n_valid
+    n_amb = int(ambiguous_pairs(f["bsub"], prob.n_patch, lp.rho_thresh).sum())
+    dn = abs(t[5] - f["n_valid"])
+    print("n_valid gpu", t[5], "oracle", f["n_valid"], "ambiguous pairs", n_amb, flush=True)
+    assert dn <= n_amb
+    slack = np.pi * dn / max(f["n_valid"], 1)
     for k, name in enumerate(["cmpe", "tv", "sv", "sb", "total"]):
-        tol = 1e-4 if abs(t[5] - f["n_valid"]) == 0 else 2e-3
-        assert abs(t[k] - f[name]) <= tol * max(abs(f[name]), 1e-6), name
+        tol = 1e-4 * max(abs(f[name]), 1e-6) + (slack if name in ("cmpe", "total") else 0.0)
+        assert abs(t[k] - f[name]) <= tol, name
     eg = G.rel(grad.cpu().numpy(), go)
     print("grad rel err", eg, flush=True)
     assert eg < 1e-3
