@@ -66,7 +66,8 @@ enum {
 af_status af_create(af_ctx** out, int device, void* stream);
 /* Free every device buffer the context owns.  Safe on NULL. */
 void af_destroy(af_ctx* ctx);
-/* Last error text of `ctx` (static string if ctx is NULL); never NULL. */
+/* Last error text of `ctx`; with ctx NULL, why this thread's last failed
+ * af_create failed (a static text if none did); never NULL. */
 const char* af_last_error(const af_ctx* ctx);
 
 /* Static acquisition and imaging geometry (Section II-A, Eqs. 2-5; Section III-A).
@@ -209,6 +210,44 @@ af_status af_backward(af_ctx* ctx, const af_complex* iq_dev, const af_loss_param
 af_status af_autofocus_step(af_ctx* ctx, const af_complex* iq_dev, const af_loss_params* lp,
                       const af_adam_params* ap, int step, float* s_dev, float* m_dev,
                       float* v_dev, float* terms_dev);
+
+/* Dynamic CMPE grid of the global-speed initialisation (Section II-C, Sound Speed
+ * Estimation; Section III-A): the pixels of af_set_geometry are taken as laid out
+ * for the speed c_ref (mm/us).  At a sweep speed c_g every pixel's depth below the
+ * physical lens surface is stretched by c_g / c_ref -- along its polar angle for a
+ * curvilinear array, straight down for a linear one -- and the patch spacing
+ * becomes c_g / (2 fc) (lambda_g / 2), so the same time samples stay under each
+ * pixel.  Speeds may range over [c_min, c_max].  The pixel-to-tile assignment of
+ * af_set_geometry is kept; the context then needs af_set_slowness again, with a
+ * grid that covers the points at every speed of the range (AF_ERR_STATE until
+ * then).
+ * A later af_set_geometry ends the dynamic grid.
+ * Errors: AF_ERR_STATE before geometry and lens; AF_ERR_ARG for c_ref, fc or c_min
+ * not positive, or c_max < c_min. */
+af_status af_set_dynamic_grid(af_ctx* ctx, double c_ref, double fc, double c_min, double c_max);
+
+/* Moves the dynamic grid's points to speed c_g on the device (positions, active
+ * element ranges of Eq. 4, tile ranges), reads the tiles' ranges back (the stream
+ * is synchronised) and rebuilds the work lists.  The slowness is not changed.
+ * Errors: AF_ERR_STATE without a dynamic grid; AF_ERR_ARG for c_g outside
+ * [c_min, c_max], a point whose active elements are not contiguous or a tile that
+ * spans more active blocks than the CMPE stage holds (the context then needs
+ * af_set_geometry again). */
+af_status af_set_sweep_speed(af_ctx* ctx, double c_g);
+
+/* Global-speed sweep of the model initialisation (Section II-C): for each of the n
+ * speeds (host array, within the dynamic grid's range) the CMPE of the uniform
+ * slowness 1/c_g, on the dynamic grid of c_g (dynamic != 0) or on the one grid of
+ * static_c for every speed (dynamic = 0, the static grid it replaces).  cmpe_dev:
+ * float[n] (device).  *best (host) is the speed of the lowest CMPE, the first one
+ * on ties; the context is left on the grid of the best speed (dynamic) or the
+ * static grid, with the uniform slowness 1/best.  Synchronises the stream once per
+ * speed (af_set_sweep_speed) and at the end.
+ * Errors: AF_ERR_STATE without geometry, lens, slowness or dynamic grid;
+ * AF_ERR_ARG for n < 1, null pointers, or speeds outside the range. */
+af_status af_sweep(af_ctx* ctx, const af_complex* iq_dev, const af_loss_params* lp, int n,
+                   const double* speeds, int dynamic, double static_c, float* cmpe_dev,
+                   double* best);
 
 /* One-way travel times T[a][p] (us) at the current slowness, caller point
  * order, float32 [n_elem][P] (device); entries outside the apodisation are NaN. */

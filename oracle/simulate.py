@@ -37,15 +37,18 @@ def scatterer_times(elem_xz, d_lens, c_lens, s_true, grid, n_seg, scat_xz):
     return r["l1"] / c_lens + tm
 
 
-def synthesize(T: np.ndarray, amp: np.ndarray, *, t_ttp, t0, fs, fd, ns, fc, frac_bw):
-    """Channel data [N][N][Ns] complex128 from one-way times T [N][K]."""
+def synthesize(T: np.ndarray, amp: np.ndarray, *, t_ttp, t0, fs, fd, ns, fc, frac_bw,
+               rows=None):
+    """Channel data [N][N][Ns] complex128 from one-way times T [N][K]; with ``rows``
+    (transmit indices) only those records, [len(rows)][N][Ns]."""
     n = T.shape[0]
+    rows = range(n) if rows is None else list(rows)
     sig = pulse_sigma(fc, frac_bw)
     half = 6.0 * sig
     width = int(math.floor(2.0 * half * fs)) + 2
-    out = np.zeros((n, n, ns), dtype=np.complex128)
+    out = np.zeros((len(rows), n, ns), dtype=np.complex128)
     offs = np.arange(width)
-    for t in range(n):
+    for i, t in enumerate(rows):
         for r in range(n):
             tau = T[t] + T[r] + t_ttp
             n0 = np.ceil((tau - half - t0) * fs).astype(np.int64)
@@ -57,7 +60,7 @@ def synthesize(T: np.ndarray, amp: np.ndarray, *, t_ttp, t0, fs, fd, ns, fc, fra
                 np.exp(-2j * np.pi * fd * tau)[:, None]
             val = np.where(ok, val, 0.0)
             ii = np.where(ok, idx, 0).ravel()
-            out[t, r] += np.bincount(ii, weights=val.real.ravel(), minlength=ns) + \
+            out[i, r] += np.bincount(ii, weights=val.real.ravel(), minlength=ns) + \
                 1j * np.bincount(ii, weights=val.imag.ravel(), minlength=ns)
     return out
 

@@ -23,6 +23,7 @@ from __future__ import annotations
 import numpy as np
 
 from .fermat import is_linear
+from . import cmpe
 from .model import Problem, LossParams, forward
 
 
@@ -45,11 +46,14 @@ def scaled_centres(centres: np.ndarray, elem_xz: np.ndarray, d_lens: float, c_g:
 
 
 def sweep(prob: Problem, lp: LossParams, fc: float, c_ref: float = 1.540,
-          speeds: np.ndarray | None = None, dynamic: bool = True, static_c: float = 1.500):
-    """CMPE for each homogeneous speed.  Returns (speeds, cmpe values, best speed)."""
+          speeds: np.ndarray | None = None, dynamic: bool = True, static_c: float = 1.500,
+          rho_band: float | None = None):
+    """CMPE for each homogeneous speed.  Returns (speeds, cmpe values, best speed);
+    with ``rho_band`` also, per speed, (n_valid, number of pairs with energy whose
+    rho lies within rho_band of rho_thresh)."""
     speeds = sweep_speeds() if speeds is None else speeds
     x0, z0, dx, dz, nx, nz = prob.grid
-    vals = []
+    vals, info = [], []
     for c_g in speeds:
         if dynamic:
             cen = scaled_centres(prob.centres, prob.elem_xz, prob.d_lens, c_g, c_ref)
@@ -59,6 +63,15 @@ def sweep(prob: Problem, lp: LossParams, fc: float, c_ref: float = 1.540,
             sp = static_c / (2.0 * fc)
         p = Problem(**{**prob.__dict__, "centres": cen, "spacing": sp, "_cache": {}})
         s = np.full((nz, nx), 1.0 / c_g)
-        vals.append(forward(p, s, lp)["cmpe"])
+        f = forward(p, s, lp, keep=rho_band is not None)
+        vals.append(f["cmpe"])
+        if rho_band is not None:
+            d = cmpe.cmpe(f["bsub"], p.n_patch, lp.rho_thresh)
+            pos = (d["ex"] > cmpe.MIN_ENERGY) & (d["ey"] > cmpe.MIN_ENERGY)
+            info.append((f["n_valid"], int(np.sum(pos & (np.abs(d["rho"] - lp.rho_thresh)
+                                                           < rho_band)))))
     vals = np.array(vals)
-    return speeds, vals, float(speeds[int(np.argmin(vals))])
+    best = float(speeds[int(np.argmin(vals))])
+    if rho_band is not None:
+        return speeds, vals, best, info
+    return speeds, vals, best

@@ -19,6 +19,11 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2608_06853_amd.build` "
                       "(or __graft_entry__.build()); there is no CPU fallback")
 
+# torch first: its HIP runtime is then the one libaf.so binds to (both carry the
+# soname libamdhip64.so.7).  Loaded the other way round, torch brings a second HIP
+# runtime into the process and the library's runtime finds no usable device.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 AF_OK, AF_ERR_ARG, AF_ERR_STATE, AF_ERR_HIP, AF_ERR_OOM, AF_ERR_NUMERIC = 0, -1, -2, -3, -4, -5
@@ -32,9 +37,11 @@ LENS_MODES = {"bent": LENS_BENT, "conventional": LENS_CONVENTIONAL, "none": LENS
 EXPORTS = [
     "af_create", "af_destroy", "af_last_error", "af_set_geometry", "af_set_lens",
     "af_set_refraction_search", "af_set_slowness", "af_beamform", "af_loss_and_grad", "af_forward", "af_backward",
-    "af_autofocus_step", "af_travel_times", "af_simulate", "af_query", "af_set_profiling",
+    "af_autofocus_step", "af_travel_times", "af_set_dynamic_grid", "af_set_sweep_speed",
+    "af_sweep", "af_simulate", "af_query", "af_set_profiling",
     "af_profile_read", "af_conv3x3_pack", "af_conv3x3_fwd", "af_conv3x3_bwd_data",
-    "af_conv3x3_bwd_weight", "af_mse_loss", "af_adam_update", "af_features", "af_polar_to_grid",
+    "af_conv3x3_bwd_weight", "af_mse_loss", "af_adam_update",
+    "af_features", "af_polar_to_grid",
 ]
 KERNELS = ["prepare_grid", "table", "das_fwd", "cmpe", "finalize", "gscale", "das_adj",
            "path_adj", "grad_fold", "adam", "export", "conv_fwd", "conv_bwd_data",
@@ -70,6 +77,10 @@ _sig = {
     "af_autofocus_step": (C.c_int, [_vp, _vp, C.POINTER(LossParams), C.POINTER(AdamParams), _i,
                                     _vp, _vp, _vp, _vp]),
     "af_travel_times": (C.c_int, [_vp, _vp]),
+    "af_set_dynamic_grid": (C.c_int, [_vp, _d, _d, _d, _d]),
+    "af_set_sweep_speed": (C.c_int, [_vp, _d]),
+    "af_sweep": (C.c_int, [_vp, _vp, C.POINTER(LossParams), _i, _vp, _i, _d, _vp,
+                           C.POINTER(C.c_double)]),
     "af_simulate": (C.c_int, [_vp, _i, _vp, _vp, _i, _i, _d, _d, _d, _d, _vp, _i, _d, _d, _vp]),
     "af_query": (C.c_int, [_vp, _i, C.POINTER(C.c_longlong)]),
     "af_set_profiling": (C.c_int, [_vp, _i]),
@@ -140,7 +151,7 @@ class Context:
         h = _vp()
         st = _lib.af_create(C.byref(h), device, _vp(stream.cuda_stream))
         if st != AF_OK:
-            raise AfError(st, "af_create failed")
+            raise AfError(st, _lib.af_last_error(None).decode())
         self._h = h
         self.n_elem = self.n_samples = self.n_pix = self.patch = 0
         self.nx = self.nz = 0
@@ -236,6 +247,25 @@ class Context:
                                          _dev(m, torch.float32, n, "m"),
                                          _dev(v, torch.float32, n, "v"),
                                          _dev(terms, torch.float32, N_TERMS, "terms")))
+
+    def set_dynamic_grid(self, c_ref, fc, c_min, c_max):
+        self._chk(_lib.af_set_dynamic_grid(self._h, float(c_ref), float(fc), float(c_min),
+                                           float(c_max)))
+
+    def set_sweep_speed(self, c_g):
+        self._chk(_lib.af_set_sweep_speed(self._h, float(c_g)))
+
+    def sweep(self, iq, lp, speeds, dynamic, static_c, cmpe_out) -> float:
+        """Returns the best speed; cmpe_out (device, float32 [len(speeds)]) gets the CMPE
+        of every speed."""
+        import torch
+        sp = _host(speeds)
+        best = C.c_double(0.0)
+        self._chk(_lib.af_sweep(self._h, _dev(iq, torch.complex64, None, "iq"), C.byref(lp),
+                                sp.size, sp.ctypes.data, int(bool(dynamic)), float(static_c),
+                                _dev(cmpe_out, torch.float32, sp.size, "cmpe_out"),
+                                C.byref(best)))
+        return best.value
 
     def travel_times(self, out):
         import torch

@@ -69,42 +69,7 @@ def is_linear(acq: Acquisition) -> bool:
     return bool(np.max(np.abs(z - z[0])) <= 1e-9 * (1.0 + np.max(np.abs(acq.elem_xz[:, 0]))))
 
 
-def lens_radius(acq: Acquisition) -> float:
-    return float(np.hypot(acq.elem_xz[0, 0], acq.elem_xz[0, 1])) + acq.d_lens
-
-
-class DynamicGrid:
-    """Dynamic CMPE grid of a base pixel layout: at speed c_g every pixel's depth
-    below the lens surface is stretched by c_g/c_ref -- along its polar angle for a
-    curvilinear array, straight down for a linear one -- and the kernel spacing
-    becomes lambda_g/2 = c_g/(2 fc), so the same time samples are observed.  The
-    decomposition of the base layout is taken once."""
-
-    def __init__(self, img: Imaging, acq: Acquisition, c_ref: float, fc: float):
-        self.img, self.c_ref, self.fc = img, c_ref, fc
-        if is_linear(acq):
-            self.rl = float(acq.elem_xz[0, 1]) + acq.d_lens       # lens surface plane
-            self.depth = img.centres[:, 1] - self.rl
-            self.dirs = None
-        else:
-            self.rl = lens_radius(acq)
-            rho = np.hypot(img.centres[:, 0], img.centres[:, 1])
-            th = np.arctan2(img.centres[:, 0], img.centres[:, 1])
-            self.depth = rho - self.rl
-            self.dirs = np.stack([np.sin(th), np.cos(th)], axis=1)
-
-    def at(self, c_g: float) -> Imaging:
-        d_g = self.depth * (c_g / self.c_ref)
-        if self.dirs is None:
-            centres = np.stack([self.img.centres[:, 0], self.rl + d_g], axis=1)
-        else:
-            centres = (self.rl + d_g)[:, None] * self.dirs
-        return replace(self.img, centres=centres, spacing=c_g / (2.0 * self.fc))
-
-
-def scaled_imaging(img: Imaging, acq: Acquisition, c_g: float, c_ref: float, fc: float) -> Imaging:
-    """The dynamic CMPE grid of ``img`` at speed c_g (see DynamicGrid)."""
-    return DynamicGrid(img, acq, c_ref, fc).at(c_g)
+SWEEP_MIN, SWEEP_MAX = 1.340, 1.740   # mm/us, the global sweep's range (Section III-A)
 
 
 class Beamformer:
@@ -130,8 +95,26 @@ class Beamformer:
         self.ctx.set_geometry(a.elem_xz, img.centres, img.patch, img.spacing, a.n_samples, a.fs,
                               a.t0, a.fd, img.block, img.fnum, img.n_seg)
         self.img = img
+        self.dynamic = None
         if keep_slowness and getattr(self, "s", None) is not None:
             self.set_slowness(self.s)
+
+    def set_dynamic_grid(self, c_ref: float, fc: float, c_min: float = SWEEP_MIN,
+                         c_max: float = SWEEP_MAX):
+        """The library's dynamic CMPE grid over the current pixels (laid out for c_ref);
+        af_set_sweep_speed then moves them.  The slowness is set again."""
+        self.ctx.set_dynamic_grid(c_ref, fc, c_min, c_max)
+        self.dynamic = (c_ref, fc, c_min, c_max)
+        s = getattr(self, "s", None)
+        self.set_slowness(s if s is not None else
+                          torch.full(self.grid.shape, 1.0 / c_ref, device=self.device))
+
+    def set_speed(self, c_g: float, c_ref: float, fc: float):
+        """Points of the dynamic grid of speed c_g (set up for (c_ref, fc) on first use)."""
+        d = self.dynamic
+        if d is None or d[:2] != (c_ref, fc) or not d[2] <= c_g <= d[3]:
+            self.set_dynamic_grid(c_ref, fc, min(SWEEP_MIN, c_g), max(SWEEP_MAX, c_g))
+        self.ctx.set_sweep_speed(c_g)
 
     def set_slowness(self, s: torch.Tensor):
         g = self.grid
@@ -238,25 +221,18 @@ def sweep(bf: Beamformer, iq, lp, fc: float, c_ref: float = 1.540, speeds=None, 
     every speed is evaluated on the one grid laid out for ``static_c`` (the static
     grid the dynamic one replaces).  Leaves ``bf`` on the grid of the best speed
     (dynamic) or the static grid, with a uniform slowness.  Returns
-    (speeds, values, best)."""
-    speeds = sweep_speeds() if speeds is None else np.asarray(speeds)
-    dyn = DynamicGrid(bf.img, bf.acq, c_ref, fc)
-    static = None if dynamic else dyn.at(static_c)
-    terms = bf.empty_terms()
+    (speeds, values, best).  The library moves the points (af_set_dynamic_grid,
+    af_sweep); the pixels of ``bf.img`` are the layout of c_ref."""
+    speeds = sweep_speeds() if speeds is None else np.asarray(speeds, dtype=np.float64)
+    lo = min(float(speeds.min()), static_c if not dynamic else np.inf)
+    hi = max(float(speeds.max()), static_c if not dynamic else -np.inf)
+    d = bf.dynamic
+    if d is None or d[:2] != (c_ref, fc) or not (d[2] <= lo and hi <= d[3]):
+        bf.set_dynamic_grid(c_ref, fc, lo, hi)
     vals = torch.empty(len(speeds), device=bf.device)
-    if static is not None:
-        bf.set_imaging(static, keep_slowness=False)
-    for k, c_g in enumerate(speeds):
-        if static is None:
-            bf.set_imaging(dyn.at(float(c_g)), keep_slowness=False)
-        bf.set_slowness(torch.full(bf.grid.shape, 1.0 / float(c_g), device=bf.device))
-        bf.ctx.loss_and_grad(iq, lp, terms, None)
-        vals[k] = terms[_lib.TERM_CMPE]
-    vals = vals.cpu().numpy().astype(np.float64)
-    best = float(speeds[int(np.argmin(vals))])
-    bf.set_imaging(dyn.at(best) if static is None else static, keep_slowness=False)
-    bf.set_slowness(torch.full(bf.grid.shape, 1.0 / best, device=bf.device))
-    return speeds, vals, best
+    best = bf.ctx.sweep(iq, lp, speeds, dynamic, static_c, vals)
+    bf.s = torch.full(bf.grid.shape, 1.0 / best, device=bf.device)
+    return speeds, vals.cpu().numpy().astype(np.float64), best
 
 
 @dataclass

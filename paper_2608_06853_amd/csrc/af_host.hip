@@ -18,6 +18,8 @@ using af::SUB;
 namespace {
 
 const char* kNoCtx = "af: null context";
+// why the last af_create of this thread failed (af_last_error(NULL) returns it)
+thread_local std::string g_create_err;
 
 af_status fail(af_ctx* c, af_status st, const std::string& msg) {
   if (c) c->err = msg;
@@ -128,6 +130,67 @@ af_status upload(af_ctx* c, DBuf& b, const std::vector<T>& v, const char* what) 
   return AF_OK;
 }
 
+// From the active element range of every tile (c->tile_lo, c->tile_hi): the tile
+// descriptors (element and block ranges), the table work list (chunks of
+// TAB_CHUNK elements per tile), the DAS work list and the heaviest-first tile
+// order of the adjoints; uploads all four.  A tile spanning more active blocks
+// than the CMPE stage holds in LDS is rejected.
+af_status build_work_lists(af_ctx* c, const char* who) {
+  const int n_tiles = c->n_tiles, block = c->S;
+  std::vector<int4> tiles(n_tiles);
+  std::vector<int2> tabwork, daswork;
+  std::vector<std::pair<long long, int>> load;
+  c->na_max = 1;
+  c->nba_max = 1;
+  for (int t = 0; t < n_tiles; ++t) {
+    const int LO = c->tile_lo[t], HI = c->tile_hi[t];
+    if (LO > HI) {
+      tiles[t] = make_int4(1, 0, 1, 0);
+      continue;
+    }
+    const int bLO = LO / block, bHI = HI / block;
+    tiles[t] = make_int4(LO, HI, bLO, bHI);
+    c->na_max = std::max(c->na_max, HI - LO + 1);
+    c->nba_max = std::max(c->nba_max, bHI - bLO + 1);
+    for (int a0 = LO; a0 <= HI; a0 += af::TAB_CHUNK) tabwork.push_back(make_int2(t, a0));
+    load.push_back({(long long)(HI - LO + 1) * (HI - LO + 1), t});
+  }
+  if (c->nba_max > af::cmpe_span_limit(c->pps))
+    return fail(c, AF_ERR_ARG, std::string(who) +
+                                   ": a tile spans more active blocks than the CMPE stage holds");
+  std::stable_sort(load.begin(), load.end(), [](auto& a, auto& b) { return a.first > b.first; });
+  c->tile_order.clear();
+  for (auto& l : load) c->tile_order.push_back(l.second);
+  // DAS work items (tile, receive block).  Workgroups are dealt to the XCDs
+  // round-robin (workgroup b runs on XCD b % 8), so every receive block is given
+  // to one XCD, and its tiles follow in k-d (spatial) order: the channel records
+  // of that block then stay in the XCD's L2 while neighbouring tiles reuse their
+  // time windows.  Shorter queues are padded with empty items (tile -1).
+  {
+    constexpr int NXCD = 8;
+    std::vector<std::vector<int2>> q(NXCD);
+    for (int t = 0; t < n_tiles; ++t) {
+      const int4 tr = tiles[t];
+      if (tr.x > tr.y) continue;
+      for (int jb = tr.z; jb <= tr.w; ++jb) q[jb % NXCD].push_back(make_int2(t, jb));
+    }
+    size_t L = 0;
+    for (auto& v : q) L = std::max(L, v.size());
+    for (size_t i = 0; i < L; ++i)
+      for (int x = 0; x < NXCD; ++x)
+        daswork.push_back(i < q[x].size() ? q[x][i] : make_int2(-1, 0));
+  }
+  c->n_tab_work = (int)tabwork.size();
+  c->n_das_work = (int)daswork.size();
+  c->n_order = (int)c->tile_order.size();
+  af_status st;
+  if ((st = upload(c, c->d_tiles, tiles, "tiles")) != AF_OK) return st;
+  if ((st = upload(c, c->d_tabwork, tabwork, "work list")) != AF_OK) return st;
+  if ((st = upload(c, c->d_daswork, daswork, "work list")) != AF_OK) return st;
+  if ((st = upload(c, c->d_order, c->tile_order, "tile order")) != AF_OK) return st;
+  return AF_OK;
+}
+
 }  // namespace
 
 af::Geo af_ctx::geo() const {
@@ -165,8 +228,20 @@ af_status af_create(af_ctx** out, int device, void* stream) {
   if (!out) return AF_ERR_ARG;
   *out = nullptr;
   int n = 0;
-  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return AF_ERR_ARG;
-  if (hipSetDevice(device) != hipSuccess) return AF_ERR_HIP;
+  const hipError_t ec = hipGetDeviceCount(&n);
+  if (ec != hipSuccess) {
+    g_create_err = std::string("af_create: hipGetDeviceCount: ") + hipGetErrorString(ec);
+    return AF_ERR_HIP;
+  }
+  if (device < 0 || device >= n) {
+    g_create_err = "af_create: no HIP device " + std::to_string(device);
+    return AF_ERR_ARG;
+  }
+  const hipError_t es = hipSetDevice(device);
+  if (es != hipSuccess) {
+    g_create_err = std::string("af_create: hipSetDevice: ") + hipGetErrorString(es);
+    return AF_ERR_HIP;
+  }
   af_ctx* c = new af_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
@@ -186,7 +261,9 @@ void af_destroy(af_ctx* c) {
   delete c;
 }
 
-const char* af_last_error(const af_ctx* c) { return c ? c->err.c_str() : kNoCtx; }
+const char* af_last_error(const af_ctx* c) {
+  return c ? c->err.c_str() : (g_create_err.empty() ? kNoCtx : g_create_err.c_str());
+}
 
 af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pix,
                           const double* pix_xz, int patch, double spacing, int n_samples,
@@ -477,61 +554,18 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
       c->active_samples += samples[t * 8];
     }
   }
-  std::vector<int4> tiles(n_tiles);
-  std::vector<int2> tabwork, daswork;
-  std::vector<std::pair<long long, int>> load;
-  c->na_max = 1;
-  c->nba_max = 1;
-  for (int t = 0; t < n_tiles; ++t) {
-    const int LO = c->tile_lo[t], HI = c->tile_hi[t];
-    if (LO > HI) {
-      tiles[t] = make_int4(1, 0, 1, 0);
-      continue;
-    }
-    const int bLO = LO / block, bHI = HI / block;
-    tiles[t] = make_int4(LO, HI, bLO, bHI);
-    c->na_max = std::max(c->na_max, HI - LO + 1);
-    c->nba_max = std::max(c->nba_max, bHI - bLO + 1);
-    for (int a0 = LO; a0 <= HI; a0 += af::TAB_CHUNK) tabwork.push_back(make_int2(t, a0));
-    load.push_back({(long long)(HI - LO + 1) * (HI - LO + 1), t});
-  }
-  if (c->nba_max > span_max)
-    return fail(c, AF_ERR_ARG, "af_set_geometry: a tile spans more active blocks than the CMPE stage holds");
-  std::stable_sort(load.begin(), load.end(), [](auto& a, auto& b) { return a.first > b.first; });
-  c->tile_order.clear();
-  for (auto& l : load) c->tile_order.push_back(l.second);
-  // DAS work items (tile, receive block).  Workgroups are dealt to the XCDs
-  // round-robin (workgroup b runs on XCD b % 8), so every receive block is given
-  // to one XCD, and its tiles follow in k-d (spatial) order: the channel records
-  // of that block then stay in the XCD's L2 while neighbouring tiles reuse their
-  // time windows.  Shorter queues are padded with empty items (tile -1).
-  {
-    constexpr int NXCD = 8;
-    std::vector<std::vector<int2>> q(NXCD);
-    for (int t = 0; t < n_tiles; ++t) {
-      const int4 tr = tiles[t];
-      if (tr.x > tr.y) continue;
-      for (int jb = tr.z; jb <= tr.w; ++jb) q[jb % NXCD].push_back(make_int2(t, jb));
-    }
-    size_t L = 0;
-    for (auto& v : q) L = std::max(L, v.size());
-    for (size_t i = 0; i < L; ++i)
-      for (int x = 0; x < NXCD; ++x)
-        daswork.push_back(i < q[x].size() ? q[x][i] : make_int2(-1, 0));
-  }
-  c->n_tab_work = (int)tabwork.size();
-  c->n_das_work = (int)daswork.size();
-  c->n_order = (int)c->tile_order.size();
-
   af_status st;
+  if ((st = build_work_lists(c, "af_set_geometry")) != AF_OK) return st;
+  // element frames (position and the orientation of Eq. 3) for the dynamic grid
+  c->elem_frame.resize(N);
+  for (int a = 0; a < N; ++a)
+    c->elem_frame[a] = make_double4(elem_xz[2 * a], elem_xz[2 * a + 1], cth[a], sth[a]);
+  c->pix_xz.assign(pix_xz, pix_xz + 2 * (size_t)n_pix);
+  c->dyn_on = false;
   if ((st = upload(c, c->d_elem, el, "elements")) != AF_OK) return st;
   if ((st = upload(c, c->d_ptpol, ptpol, "points")) != AF_OK) return st;
   if ((st = upload(c, c->d_ptxy, ptxy, "points")) != AF_OK) return st;
   if ((st = upload(c, c->d_prange, prange, "point ranges")) != AF_OK) return st;
-  if ((st = upload(c, c->d_tiles, tiles, "tiles")) != AF_OK) return st;
-  if ((st = upload(c, c->d_tabwork, tabwork, "work list")) != AF_OK) return st;
-  if ((st = upload(c, c->d_daswork, daswork, "work list")) != AF_OK) return st;
-  if ((st = upload(c, c->d_order, c->tile_order, "tile order")) != AF_OK) return st;
   if ((st = upload(c, c->d_c2i, c->c2i, "point map")) != AF_OK) return st;
   if ((st = upload(c, c->d_i2c, c->i2c, "point map")) != AF_OK) return st;
 
@@ -602,7 +636,13 @@ af_status af_set_slowness(af_ctx* c, int nx, int nz, double x0, double z0, doubl
     amin = std::min(amin, c->elem_pol[a]);
     amax = std::max(amax, c->elem_pol[a]);
   }
-  {
+  if (c->dyn_on) {
+    // dynamic grid: the box and angle range of every point at every speed of the sweep
+    if (!inside(c->dyn_box[0], c->dyn_box[2]) || !inside(c->dyn_box[1], c->dyn_box[3]))
+      return fail(c, AF_ERR_ARG, "af_set_slowness: grid does not cover every point of the dynamic grid");
+    amin = std::min(amin, c->dyn_ang[0]);
+    amax = std::max(amax, c->dyn_ang[1]);
+  } else {
     const int nthr = host_threads(c->P);
     std::vector<double> tmin(nthr * 8, 1e300), tmax(nthr * 8, -1e300);  // one cache line apart
     std::vector<long long> out(nthr * 8, 0);
@@ -655,7 +695,9 @@ af_status af_set_slowness(af_ctx* c, int nx, int nz, double x0, double z0, doubl
   AF_ALLOC(c->d_grad, sizeof(float) * n, "gradient");
   AF_ALLOC(c->d_gdev, sizeof(float) * np, "deviation grid");
   AF_ALLOC(c->d_gpad, sizeof(float) * np, "padded gradient");
-  AF_ALLOC(c->d_gpart, sizeof(float) * np * std::max(c->n_order, 1), "partial gradients");
+  // one partial grid per tile that has work (at most every tile: the dynamic grid may
+  // give more tiles work than the layout of af_set_geometry)
+  AF_ALLOC(c->d_gpart, sizeof(float) * np * std::max(c->n_tiles, 1), "partial gradients");
   AF_ALLOC(c->d_terms, sizeof(float) * 8, "terms");
   c->has_grid = false;  // until the new values have passed the check
   AF_HIP(hipMemcpyAsync(c->d_s.p, s_dev, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream),
@@ -724,6 +766,64 @@ af_status run_backward(af_ctx* c, const af_complex* iq, const float2* gblk, bool
 af_status check_lp(af_ctx* c, const af_loss_params* lp) {
   if (!lp) return fail(c, AF_ERR_ARG, "af: null loss parameters");
   if (!(lp->sb_ref > 0)) return fail(c, AF_ERR_ARG, "af: sb_ref must be > 0");
+  return AF_OK;
+}
+
+// The physical lens surface the dynamic grid measures depth from: the radius of
+// the concentric arc, or the z of the flat lens plane.
+double dyn_lens_surface(const af_ctx* c) {
+  return c->flat ? c->elem_xz[1] + c->d_lens_phys : c->elem_R[0] + c->d_lens_phys;
+}
+
+// Caller point p of the dynamic grid at relative speed k = c_g / c_ref with patch
+// spacing sp (host; the device does the same in k_sweep_points): the pixel's
+// depth below the lens surface scaled by k along its polar angle (arc) or straight
+// down (line), then the patch offset.
+void dyn_point(const af_ctx* c, double rl, double k, double sp, long long p, double& x,
+               double& z) {
+  const int q = (int)(p / c->M), m = (int)(p % c->M), h = c->patch / 2;
+  const double cx = c->pix_xz[2 * (size_t)q], cz = c->pix_xz[2 * (size_t)q + 1];
+  if (c->flat) {
+    x = cx;
+    z = rl + (cz - rl) * k;
+  } else {
+    const double rho = std::sqrt(cx * cx + cz * cz);
+    const double f = (rl + (rho - rl) * k) / rho;
+    x = cx * f;
+    z = cz * f;
+  }
+  x += (double)(m % c->patch - h) * sp;
+  z += (double)(m / c->patch - h) * sp;
+}
+
+// Moves the points of the dynamic grid to speed c_g on the device, reads the
+// tiles' active element ranges back (the stream is synchronised) and rebuilds
+// the work lists from them.  A failure leaves the context without geometry.
+af_status move_points(af_ctx* c, double c_g, const char* who) {
+  c->has_geom = false;
+  AF_HIP(af::launch_sweep_points(c, c_g / c->dyn_cref, c_g / (2.0 * c->dyn_fc),
+                                 dyn_lens_surface(c), c->d_tstat.as<af::TileStat>()),
+         who);
+  std::vector<af::TileStat> ts(c->n_tiles);
+  AF_HIP(hipMemcpyAsync(ts.data(), c->d_tstat.p, sizeof(af::TileStat) * ts.size(),
+                        hipMemcpyDeviceToHost, c->stream),
+         who);
+  AF_HIP(hipStreamSynchronize(c->stream), who);
+  c->active_pairs = 0;
+  c->active_samples = 0;
+  for (int t = 0; t < c->n_tiles; ++t) {
+    if (ts[t].bad)
+      return fail(c, AF_ERR_ARG, std::string(who) + ": active elements of a point are not contiguous");
+    c->tile_lo[t] = ts[t].lo;
+    c->tile_hi[t] = ts[t].hi;
+    c->active_pairs += ts[t].pairs;
+    c->active_samples += ts[t].samples;
+  }
+  af_status st = build_work_lists(c, who);
+  if (st != AF_OK) return st;
+  c->spacing = c_g / (2.0 * c->dyn_fc);
+  c->dyn_c = c_g;
+  c->has_geom = true;
   return AF_OK;
 }
 
@@ -822,6 +922,108 @@ af_status af_autofocus_step(af_ctx* c, const af_complex* iq, const af_loss_param
   if ((st = run_backward(c, iq, c->d_bblk.as<float2>(), false, c->d_grad.as<float>())) != AF_OK)
     return st;
   AF_KERNEL(AF_K_ADAM, af::launch_adam(c, ap, step, s, m, v, c->d_grad.as<float>()), "adam");
+  return AF_OK;
+}
+
+af_status af_set_dynamic_grid(af_ctx* c, double c_ref, double fc, double c_min, double c_max) {
+  if (!c) return AF_ERR_ARG;
+  if (!c->has_geom || !c->has_lens)
+    return fail(c, AF_ERR_STATE, "af_set_dynamic_grid: set geometry and lens first");
+  if (!(c_ref > 0) || !(fc > 0) || !(c_min > 0) || !(c_max >= c_min) || !std::isfinite(c_max) ||
+      !std::isfinite(c_ref) || !std::isfinite(fc))
+    return fail(c, AF_ERR_ARG, "af_set_dynamic_grid: need c_ref, fc > 0 and 0 < c_min <= c_max");
+  AF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  const double rl = dyn_lens_surface(c);
+  // per internal point: its pixel centre and patch offset (units of the spacing);
+  // a padding slot repeats the first point of its tile, as in the geometry set-up
+  const int M = c->M, h = c->patch / 2;
+  std::vector<double4> base(c->P_int);
+  for (long long pi = 0; pi < c->P_int; ++pi) {
+    int pc = c->i2c[pi];
+    if (pc < 0) pc = c->i2c[(pi / TILE) * TILE];
+    const int q = pc / M, m = pc % M;
+    base[pi] = make_double4(c->pix_xz[2 * (size_t)q], c->pix_xz[2 * (size_t)q + 1],
+                            (double)(m % c->patch - h), (double)(m / c->patch - h));
+  }
+  // every point moves on a straight line as the speed changes (its position is
+  // affine in c_g), so the points at c_min and c_max bound the box and the polar
+  // angles (monotone along a line that misses the origin) of every speed
+  double box[4] = {1e300, -1e300, 1e300, -1e300}, ang[2] = {1e300, -1e300};
+  for (double cg : {c_min, c_max}) {
+    const double k = cg / c_ref, sp = cg / (2.0 * fc);
+    for (long long p = 0; p < c->P; ++p) {
+      double x, z;
+      dyn_point(c, rl, k, sp, p, x, z);
+      box[0] = std::min(box[0], x);
+      box[1] = std::max(box[1], x);
+      box[2] = std::min(box[2], z);
+      box[3] = std::max(box[3], z);
+      const double a = c->flat ? x : std::atan2(x, z);
+      ang[0] = std::min(ang[0], a);
+      ang[1] = std::max(ang[1], a);
+    }
+  }
+  af_status st;
+  if ((st = upload(c, c->d_dyn_base, base, "dynamic grid")) != AF_OK) return st;
+  if ((st = upload(c, c->d_elemf, c->elem_frame, "element frames")) != AF_OK) return st;
+  AF_ALLOC(c->d_tstat, sizeof(af::TileStat) * (size_t)std::max(c->n_tiles, 1), "tile statistics");
+  c->dyn_on = true;
+  c->dyn_cref = c_ref;
+  c->dyn_fc = fc;
+  c->dyn_cmin = c_min;
+  c->dyn_cmax = c_max;
+  c->dyn_c = 0.0;  // the points are still those of af_set_geometry
+  std::copy(box, box + 4, c->dyn_box);
+  std::copy(ang, ang + 2, c->dyn_ang);
+  c->has_grid = false;  // the slowness grid must now cover every speed of the sweep
+  return AF_OK;
+}
+
+af_status af_set_sweep_speed(af_ctx* c, double c_g) {
+  if (!c) return AF_ERR_ARG;
+  if (!c->dyn_on) return fail(c, AF_ERR_STATE, "af_set_sweep_speed: no dynamic grid");
+  if (!(c_g >= c->dyn_cmin * (1.0 - 1e-12) && c_g <= c->dyn_cmax * (1.0 + 1e-12)))
+    return fail(c, AF_ERR_ARG, "af_set_sweep_speed: speed outside the dynamic grid's range");
+  AF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  return move_points(c, c_g, "af_set_sweep_speed");
+}
+
+af_status af_sweep(af_ctx* c, const af_complex* iq, const af_loss_params* lp, int n,
+                   const double* speeds, int dynamic, double static_c, float* cmpe_dev,
+                   double* best) {
+  af_status st = ready(c, iq);
+  if (st != AF_OK) return st;
+  if ((st = check_lp(c, lp)) != AF_OK) return st;
+  if (!c->dyn_on) return fail(c, AF_ERR_STATE, "af_sweep: no dynamic grid");
+  if (n < 1 || !speeds || !cmpe_dev || !best) return fail(c, AF_ERR_ARG, "af_sweep: bad argument");
+  auto in_range = [&](double v) {
+    return v >= c->dyn_cmin * (1.0 - 1e-12) && v <= c->dyn_cmax * (1.0 + 1e-12);
+  };
+  for (int k = 0; k < n; ++k)
+    if (!in_range(speeds[k])) return fail(c, AF_ERR_ARG, "af_sweep: speed outside the dynamic grid's range");
+  if (!dynamic && !in_range(static_c))
+    return fail(c, AF_ERR_ARG, "af_sweep: static speed outside the dynamic grid's range");
+  const int ns = c->nx * c->nz;
+  if (!dynamic && (st = move_points(c, static_c, "af_sweep")) != AF_OK) return st;
+  for (int k = 0; k < n; ++k) {
+    if (dynamic && (st = move_points(c, speeds[k], "af_sweep")) != AF_OK) return st;
+    AF_HIP(af::launch_fill(c, c->d_s.as<float>(), ns, (float)(1.0 / speeds[k])), "uniform slowness");
+    if ((st = run_forward(c, iq, lp, c->d_terms.as<float>(), nullptr, false, false)) != AF_OK)
+      return st;
+    AF_HIP(hipMemcpyAsync(cmpe_dev + k, c->d_terms.as<float>() + AF_TERM_CMPE, sizeof(float),
+                          hipMemcpyDeviceToDevice, c->stream),
+           "af_sweep copy");
+  }
+  std::vector<float> v(n);
+  AF_HIP(hipMemcpyAsync(v.data(), cmpe_dev, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream),
+         "af_sweep read-back");
+  AF_HIP(hipStreamSynchronize(c->stream), "af_sweep read-back");
+  int kb = 0;  // the lowest CMPE, the first one on ties
+  for (int k = 1; k < n; ++k)
+    if (v[k] < v[kb]) kb = k;
+  *best = speeds[kb];
+  if (dynamic && (st = move_points(c, speeds[kb], "af_sweep")) != AF_OK) return st;
+  AF_HIP(af::launch_fill(c, c->d_s.as<float>(), ns, (float)(1.0 / speeds[kb])), "uniform slowness");
   return AF_OK;
 }
 

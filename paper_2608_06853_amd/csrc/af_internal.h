@@ -97,6 +97,13 @@ struct CmpeArgs {
   int write_g;
 };
 
+// Per-tile result of the dynamic-grid point update: active element range, whether
+// some point's active elements are not contiguous, active rays and samples.
+struct TileStat {
+  int lo, hi, bad, pad;
+  long long pairs, samples;
+};
+
 struct PathArgs {
   Geo g;
   const float2* ray_uv;   // ray start and medium leg of every table entry (k_table)
@@ -136,6 +143,15 @@ struct af_ctx {
   std::vector<int> tile_lo, tile_hi;
   int na_max = 0, nba_max = 0;
   long long active_pairs = 0, active_samples = 0;
+  std::vector<double4> elem_frame;          // element (x, z, cos, sin) of the orientation of Eq. 3
+  std::vector<double> pix_xz;               // caller pixel centres of af_set_geometry [n_pix][2]
+  // dynamic CMPE grid (af_set_dynamic_grid): the pixels of af_set_geometry are the
+  // layout of speed dyn_cref; af_set_sweep_speed moves them on the device
+  bool dyn_on = false;
+  double dyn_cref = 1.54, dyn_fc = 1.0, dyn_cmin = 1.54, dyn_cmax = 1.54, dyn_c = 1.54;
+  double dyn_box[4] = {0, 0, 0, 0};         // x_lo, x_hi, z_lo, z_hi of every point at every speed
+  double dyn_ang[2] = {0, 0};               // polar angle (x on a line) range of the same
+  af::DBuf d_dyn_base, d_elemf, d_tstat, d_dynflag;
   std::vector<int> tile_order;              // tiles with work, heaviest first
   int n_tab_work = 0, n_das_work = 0, n_order = 0;
 
@@ -206,6 +222,10 @@ hipError_t launch_channel_images(af_ctx* c, const float2* iq, float2* X);
 hipError_t launch_export_rx(af_ctx* c, const float2* X, float2* out);
 hipError_t launch_loc(af_ctx* c, const float2* X, float* loc);
 hipError_t launch_path_adj(af_ctx* c);
+// dynamic grid: points at k = c_g / c_ref with patch spacing `spacing` from the lens
+// surface rl, their active element ranges, and per tile the statistics in tstat
+hipError_t launch_sweep_points(af_ctx* c, double k, double spacing, double rl, TileStat* tstat);
+hipError_t launch_fill(af_ctx* c, float* x, int n, float v);
 hipError_t launch_grad_fold(af_ctx* c, float* grad);
 hipError_t launch_adam(af_ctx* c, const af_adam_params* ap, int step, float* s, float* m,
                        float* v, const float* grad);

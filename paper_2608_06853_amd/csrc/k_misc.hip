@@ -182,7 +182,17 @@ __global__ __launch_bounds__(256) void k_adam(int n, float lr, float b1, float b
   s_copy[i] = si;
 }
 
+__global__ __launch_bounds__(256) void k_fill(float* __restrict__ x, int n, float v) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
 }  // namespace
+
+hipError_t launch_fill(af_ctx* c, float* x, int n, float v) {
+  hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, c->stream, x, n, v);
+  return hipGetLastError();
+}
 
 hipError_t launch_prepare_grid(af_ctx* c, const float* s, int nx, int nz, float* gdev, double* scal,
                                int do_reg, const af_loss_params* lp, float* regg) {

@@ -103,10 +103,10 @@ def run_learned(bf: af.Beamformer, iq, cfg, net, fm: cnn.FeatureMaker, target: f
     lp = lp or workloads.loss_params(cfg)
     base = bf.img
     terms = bf.empty_terms()
-    dyn = af.DynamicGrid(base, bf.acq, cfg.img.c_ref, cfg.acq.fc)
+    c_ref, fc = cfg.img.c_ref, cfg.acq.fc
 
     def loss_on(c_grid, s):
-        bf.set_imaging(dyn.at(c_grid), keep_slowness=False)
+        bf.set_speed(c_grid, c_ref, fc)   # the dynamic grid of c_grid
         bf.set_slowness(s)
         bf.ctx.loss_and_grad(iq, lp, terms, None)
         return float(terms[_lib.TERM_TOTAL].item())
@@ -123,15 +123,13 @@ def run_learned(bf: af.Beamformer, iq, cfg, net, fm: cnn.FeatureMaker, target: f
         lattice = af.sweep_speeds()
         k0 = int(np.argmin(np.abs(lattice - c_mean)))
         local = lattice[max(0, k0 - window):k0 + window + 1]
-        bf.set_imaging(base, keep_slowness=False)
-        _, vals, best = af.sweep(bf, iq, lp, cfg.acq.fc, speeds=local)
+        _, vals, best = af.sweep(bf, iq, lp, fc, c_ref, speeds=local)
         if float(np.min(vals)) <= l_hom:
             start, s_init, c_grid = "local_sweep", bf.s, best
         else:
-            bf.set_imaging(base, keep_slowness=False)
-            _, _, c_grid = af.sweep(bf, iq, lp, cfg.acq.fc)
+            _, _, c_grid = af.sweep(bf, iq, lp, fc, c_ref)
             start, s_init = "sweep", bf.s
-    bf.set_imaging(dyn.at(c_grid), keep_slowness=False)
+    bf.set_speed(c_grid, c_ref, fc)
     bf.set_slowness(s_init)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0

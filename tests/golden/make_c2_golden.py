@@ -3,11 +3,16 @@ gradient of the whole clinical workload in the benchmark's launch configuration
 (128 elements, 128 transmits, 2560 samples, 256 x 256 pixels x 3 x 3 points to
 160 mm, 32 x 32 grid covering every speed of the dynamic-grid sweep).
 
-Inputs: seeded circular Gaussian channel data (afsynth.random_iq, seed of the
-configuration) and a seeded smooth slowness (problems.smooth_slowness), CMPE
-threshold 0.5 (noise data have few pairs above the configured 0.9).  The
-oracle evaluates disjoint chunks of pixels in parallel processes on every host
-core (oracle.model.loss_and_grad_parts) and combines them
+Inputs: channel data the oracle simulates (oracle.simulate, 64 ray segments)
+from the clinical medium with 2000 point scatterers (the configuration's seed;
+fewer than its speckle density, so that the simulation takes seconds), the true
+slowness of that medium on the grid perturbed by 1 % seeded noise, and the
+configured loss parameters (CMPE threshold 0.9).  Coherent echoes keep the
+gradient a coherent sum over the valid pairs; on noise data every pair adds a
+term of random sign, and the few pairs whose validity FP32 and FP64 judge
+differently then move it by about sqrt(flips / n_valid).  The oracle evaluates
+disjoint chunks of pixels in parallel processes on every host core
+(oracle.model.loss_and_grad_parts) and combines them
 (oracle.model.combine_parts).  Nothing here calls the GPU library.
 
     python tests/golden/make_c2_golden.py [--workers N] [--chunk PIXELS]
@@ -35,21 +40,27 @@ from oracle import model  # noqa: E402
 
 OUT = os.path.join(HERE, "c2_clinical_loss_grad.json")
 CONFIG = "c2_clinical"
+N_SCAT = 2000
+SIM_NSEG = 64
 DEPTH_SCALE = 1.740 / 1.540
-RHO = 0.5
 RHO_BAND = 1e-4
 
-_state = {}
 
-
-def setup():
-    cfg = afsynth.config_by_name(CONFIG)
+def inputs(workers=None):
+    """(cfg, oracle problem with its channel data, slowness, loss parameters) of the
+    comparison; the GPU test builds the same inputs."""
+    cfg = afsynth.config_by_name(CONFIG).with_(n_scat_random=N_SCAT)
+    med = afsynth.medium_for(cfg)
     prob = problems.problem(cfg, depth_scale_max=DEPTH_SCALE)
-    prob.iq = afsynth.random_iq(cfg.array.n_elem, cfg.acq.n_samples, seed=cfg.seed)
-    s = problems.smooth_slowness(prob.grid, cfg.seed)
+    prob.iq = problems.simulate_iq_parallel(cfg, med, SIM_NSEG, workers)
+    s_true = problems.true_slowness(cfg, med, prob)
+    rng = np.random.default_rng(cfg.seed + 11)
+    s = (s_true * (1.0 + 0.01 * rng.standard_normal(s_true.shape))).astype(np.float32)
     lp = problems.loss_params(cfg)
-    lp = model.LossParams(**{**lp.__dict__, "rho_thresh": RHO})
     return cfg, prob, s, lp
+
+
+_state = {}
 
 
 def _init():
@@ -69,7 +80,7 @@ def main():
     ap.add_argument("--workers", type=int, default=os.cpu_count())
     ap.add_argument("--chunk", type=int, default=256)
     args = ap.parse_args()
-    cfg, prob, s, lp = setup()
+    cfg, prob, s, lp = inputs(args.workers)
     _state.update(prob=prob, s=s, lp=lp)
     n_pix = prob.centres.shape[0]
     chunks = [(q, min(q + args.chunk, n_pix)) for q in range(0, n_pix, args.chunk)]
@@ -82,8 +93,10 @@ def main():
                 print(f"  {k + 1}/{len(chunks)} chunks, {time.perf_counter() - t0:.0f} s",
                       flush=True)
     terms, g = model.combine_parts(parts, s, lp, prob.grid)
-    out = {"config": CONFIG, "iq": f"afsynth.random_iq(seed={cfg.seed})",
-           "slowness": f"problems.smooth_slowness(seed={cfg.seed})", "rho_thresh": RHO,
+    out = {"config": CONFIG, "n_scat": N_SCAT, "sim_nseg": SIM_NSEG,
+           "iq": "oracle.simulate of afsynth.medium_for(c2_clinical, n_scat_random=2000)",
+           "slowness": "true slowness x (1 + 0.01 N(0,1)), seed + 11",
+           "rho_thresh": float(lp.rho_thresh),
            "rho_band": RHO_BAND, "n_near": int(sum(p["n_near"] for p in parts)),
            "n_pix": n_pix, "terms": {k: float(v) for k, v in terms.items()},
            "grad": [[float(v) for v in row] for row in g],

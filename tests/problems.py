@@ -65,3 +65,40 @@ def smooth_slowness(grid, seed):
         kx, kz, ph = rng.uniform(0.5, 2.0), rng.uniform(0.5, 2.0), rng.uniform(0, 2 * np.pi)
         s += 0.01 / 1.54 * np.cos(2 * np.pi * (kx * X + kz * Z) + ph)
     return s.astype(np.float32)
+
+
+_sim = {}
+
+
+def _sim_rows(rows):
+    a = _sim
+    return simulate.synthesize(a["T"], a["amp"], t_ttp=a["t_ttp"], t0=a["t0"], fs=a["fs"],
+                               fd=a["fd"], ns=a["ns"], fc=a["fc"], frac_bw=a["frac_bw"],
+                               rows=rows).astype(np.complex64)
+
+
+def simulate_iq_parallel(cfg, medium, n_seg, workers=None):
+    """Oracle-simulated channel data [N][N][Ns] (complex64) for ``medium``: the
+    scatterer times in chunks of scatterers, the transmit records in parallel
+    processes (fork, all host cores by default)."""
+    import multiprocessing as mp
+    import os
+    arr, acq = cfg.array, cfg.acq
+    elem = afsynth.element_positions(arr)
+    centres = afsynth.pixel_centres(arr, cfg.img)
+    sp = afsynth.patch_spacing(cfg.img, acq)
+    grid = afsynth.sim_box(arr, np.concatenate([centres, medium.scat_xz]), sp, cfg.sim_spacing)
+    x0, z0, dx, dz, nx, nz = grid
+    s_true = 1.0 / afsynth.speed_on_grid(medium, x0, z0, dx, dz, nx, nz)
+    # all elements together (the array's shape decides arc or line), scatterers in chunks
+    T = np.concatenate([simulate.scatterer_times(elem, arr.d_lens, arr.c_lens, s_true, grid,
+                                                 n_seg, medium.scat_xz[k:k + 128])
+                        for k in range(0, medium.n_scat, 128)], axis=1)
+    _sim.update(T=T, amp=medium.scat_amp, t_ttp=arr.t_ttp, t0=acq.t0, fs=acq.fs, fd=acq.fc,
+                ns=acq.n_samples, fc=acq.fc, frac_bw=acq.frac_bw)
+    workers = workers or min(16, os.cpu_count() or 1)
+    n = arr.n_elem
+    chunks = [list(range(t, min(t + 4, n))) for t in range(0, n, 4)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_sim_rows, chunks)
+    return np.concatenate(parts)

@@ -224,20 +224,28 @@ GOLDEN_C2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
 def test_c2_full_launch_against_oracle_golden():
     """The whole clinical workload in the benchmark's launch configuration (2,341
     tiles) against the FP64 oracle's loss and gradient of every grid node, computed
-    on the host in pixel chunks by tests/golden/make_c2_golden.py on the same seeded
-    noise channel data and smooth slowness.  The valid-pair counts may differ only
-    by pairs within 1e-4 of the threshold (counted by the oracle)."""
+    on the host in pixel chunks by tests/golden/make_c2_golden.py.  The inputs are
+    rebuilt here exactly as that script builds them: channel data the oracle
+    simulates from the seeded clinical medium with 2000 scatterers (about half a
+    minute on the host cores), the perturbed true slowness and the configured loss
+    parameters.  The valid-pair counts may differ only by pairs within 1e-4 of the
+    threshold (counted by the oracle)."""
+    import importlib.util
     import json
     import torch
     G.ensure_built()
     with open(GOLDEN_C2) as fh:
         gold = json.load(fh)
-    cfg = afsynth.config_by_name(gold["config"])
-    bf, prob = _launch(cfg)
-    iq = afsynth.random_iq(cfg.array.n_elem, cfg.acq.n_samples, seed=cfg.seed)
-    s = problems.smooth_slowness(prob.grid, cfg.seed)
-    lp = problems.loss_params(cfg)
-    lp = model.LossParams(**{**lp.__dict__, "rho_thresh": gold["rho_thresh"]})
+    spec = importlib.util.spec_from_file_location(
+        "make_c2_golden", os.path.join(os.path.dirname(GOLDEN_C2), "make_c2_golden.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    print("c2 full launch: simulating the channel data with the oracle", flush=True)
+    cfg, prob, s, lp = mk.inputs()
+    assert cfg.name == gold["config"] and lp.rho_thresh == gold["rho_thresh"]
+    bf, prob_l = _launch(cfg)
+    assert np.allclose(prob_l.grid, prob.grid)
+    iq = prob.iq
     terms, grad = bf.loss_and_grad(torch.from_numpy(iq).cuda().reshape(-1), G.lib_params(lp),
                                    torch.from_numpy(s).cuda())
     t = terms.cpu().numpy()
