@@ -302,6 +302,20 @@ af_status af_conv3x3_bwd_data(af_ctx* ctx, int B, int H, int W, int Cin, int Cou
 af_status af_conv3x3_bwd_weight(af_ctx* ctx, int B, int H, int W, int Cin, int Cout, int stride,
                                 const void* in_bf16, const void* dout_bf16, float* dw,
                                 float* dbias);
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight training or serving loops, harnesses that forbid hipMalloc): the same
+ * result as af_conv3x3_bwd_weight, bit for bit (the same kernels in the same
+ * order), with its partial sums in a static device array of the library instead
+ * of a buffer the context allocates on first use.  The array holds 800 x 9248
+ * floats (29.6 MB) on every GPU the library runs on, until the process ends; that
+ * is what any valid shape needs, and a larger need is rejected with AF_ERR_ARG.
+ * The call allocates nothing.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, threads or contexts) race.
+ * Errors: those of af_conv3x3_bwd_weight; AF_ERR_HIP if af_create could not take
+ * the array's address on this device. */
+af_status af_conv3x3_bwd_weight_noalloc(af_ctx* ctx, int B, int H, int W, int Cin, int Cout,
+                                        int stride, const void* in_bf16, const void* dout_bf16,
+                                        float* dw, float* dbias);
 /* Squared error: loss_parts[ceil(n/256)] = block sums of scale (out - label)^2 and
  * dout_bf16[n] = 2 scale (out - label). */
 af_status af_mse_loss(af_ctx* ctx, int n, const float* out, const float* label, float scale,

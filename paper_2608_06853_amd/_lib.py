@@ -40,7 +40,7 @@ EXPORTS = [
     "af_autofocus_step", "af_travel_times", "af_set_dynamic_grid", "af_set_sweep_speed",
     "af_sweep", "af_simulate", "af_query", "af_set_profiling",
     "af_profile_read", "af_conv3x3_pack", "af_conv3x3_fwd", "af_conv3x3_bwd_data",
-    "af_conv3x3_bwd_weight", "af_mse_loss", "af_adam_update",
+    "af_conv3x3_bwd_weight", "af_conv3x3_bwd_weight_noalloc", "af_mse_loss", "af_adam_update",
     "af_features", "af_polar_to_grid",
 ]
 KERNELS = ["prepare_grid", "table", "das_fwd", "cmpe", "finalize", "gscale", "das_adj",
@@ -89,6 +89,7 @@ _sig = {
     "af_conv3x3_fwd": (C.c_int, [_vp, _i, _i, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
     "af_conv3x3_bwd_data": (C.c_int, [_vp, _i, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp]),
     "af_conv3x3_bwd_weight": (C.c_int, [_vp, _i, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp]),
+    "af_conv3x3_bwd_weight_noalloc": (C.c_int, [_vp, _i, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp]),
     "af_mse_loss": (C.c_int, [_vp, _i, _vp, _vp, C.c_float, _vp, _vp]),
     "af_adam_update": (C.c_int, [_vp, _i, C.POINTER(AdamParams), _i, _vp, _vp, _vp, _vp]),
     "af_features": (C.c_int, [_vp, C.c_longlong, _i, _vp, _vp, _vp, _vp]),
@@ -327,10 +328,13 @@ class Context:
                                            _dev(act, torch.bfloat16, B * H * W * Cin, "act"),
                                            _dev(din, torch.bfloat16, B * H * W * Cin, "din")))
 
-    def conv3x3_bwd_weight(self, B, H, W, Cin, Cout, stride, x, dout, dw, db):
+    def conv3x3_bwd_weight(self, B, H, W, Cin, Cout, stride, x, dout, dw, db, noalloc=False):
+        """noalloc=True calls af_conv3x3_bwd_weight_noalloc (partial sums in the
+        library's static device array, no allocation)."""
         import torch
         ho, wo = (H - 1) // stride + 1, (W - 1) // stride + 1
-        self._chk(_lib.af_conv3x3_bwd_weight(self._h, B, H, W, Cin, Cout, stride,
+        fn = _lib.af_conv3x3_bwd_weight_noalloc if noalloc else _lib.af_conv3x3_bwd_weight
+        self._chk(fn(self._h, B, H, W, Cin, Cout, stride,
                                              _dev(x, torch.bfloat16, B * H * W * Cin, "x"),
                                              _dev(dout, torch.bfloat16, B * ho * wo * Cout, "dout"),
                                              _dev(dw, torch.float32, Cout * 9 * Cin, "dw"),

@@ -245,6 +245,9 @@ af_status af_create(af_ctx** out, int device, void* stream) {
   af_ctx* c = new af_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
+  // address of this device's copy of the no-allocation scratch array (once per
+  // device); a failure is reported by the no-allocation call itself
+  c->noalloc_ok = af::noalloc_scratch_init(device) == hipSuccess;
   if (c->d_scal.ensure(sizeof(double) * 16) != hipSuccess) {
     delete c;
     return AF_ERR_OOM;
@@ -1110,6 +1113,24 @@ af_status af_conv3x3_bwd_weight(af_ctx* c, int B, int H, int W, int Cin, int Cou
   AF_KERNEL(AF_K_CONV_BWD_WEIGHT,
             af::launch_conv_bwd_weight(c, B, H, W, Cin, Cout, stride, in, dout, dw, db),
             "conv bwd weight");
+  return AF_OK;
+}
+
+af_status af_conv3x3_bwd_weight_noalloc(af_ctx* c, int B, int H, int W, int Cin, int Cout,
+                                        int stride, const void* in, const void* dout, float* dw,
+                                        float* db) {
+  af_status st = conv_args(c, B, H, W, Cin, Cout, stride);
+  if (st != AF_OK) return st;
+  if (!in || !dout || !dw || !db)
+    return fail(c, AF_ERR_ARG, "af_conv3x3_bwd_weight_noalloc: null pointer");
+  if (!c->noalloc_ok)
+    return fail(c, AF_ERR_HIP, "af_conv3x3_bwd_weight_noalloc: no address of the scratch array on this device");
+  bool too_large = false;
+  const hipError_t e = af::launch_conv_bwd_weight_noalloc(c, B, H, W, Cin, Cout, stride, in, dout,
+                                                          dw, db, &too_large);
+  if (too_large)
+    return fail(c, AF_ERR_ARG, "af_conv3x3_bwd_weight_noalloc: partial sums exceed the 29.6 MB scratch array");
+  if (e != hipSuccess) return hip_fail(c, e, "conv bwd weight (no allocation)");
   return AF_OK;
 }
 

@@ -122,6 +122,7 @@ struct PathArgs {
 struct af_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  bool noalloc_ok = false;  // the device's no-allocation scratch address is known
   std::string err;
   bool has_geom = false, has_lens = false, has_grid = false;
 
@@ -243,6 +244,13 @@ hipError_t launch_conv_bwd_data(af_ctx* c, int B, int H, int W, int Cin, int Cou
                                 const void* dout, const void* wtp, const void* act, void* din);
 hipError_t launch_conv_bwd_weight(af_ctx* c, int B, int H, int W, int Cin, int Cout, int stride,
                                   const void* in, const void* dout, float* dw, float* db);
+// The same with its partial sums in the library's static device array: no
+// allocation.  noalloc_scratch_init takes the array's address on `device` (which
+// must be current) once; *too_large reports a shape beyond the array.
+hipError_t noalloc_scratch_init(int device);
+hipError_t launch_conv_bwd_weight_noalloc(af_ctx* c, int B, int H, int W, int Cin, int Cout,
+                                          int stride, const void* in, const void* dout, float* dw,
+                                          float* db, bool* too_large);
 hipError_t launch_conv_pack(af_ctx* c, int Cin, int Cout, const float* w, void* wp, void* wtp);
 hipError_t launch_mse(af_ctx* c, int n, const float* out, const float* label, float scale,
                       float* loss_parts, void* dout);

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdint>
+#include <mutex>
 
 #include "af_internal.h"
 
@@ -666,32 +667,100 @@ hipError_t launch_conv_bwd_data(af_ctx* c, int B, int H, int W, int Cin, int Cou
   return hipGetLastError();
 }
 
+namespace {
+
+// Work split of the weight gradient: workgroups, reduce groups and the partial-sum
+// floats it needs (one slab per workgroup and per group).
+struct WbSplit {
+  int n_chunks, n_wg, cols, slab_len, per_group, n_groups;
+  size_t floats;
+};
+
+bool wb_split(const ConvShape& s, WbSplit& w) {
+  const long long M = (long long)s.B * s.Ho * s.Wo;
+  const long long n_chunks = (M + WB_CHUNK - 1) / WB_CHUNK;
+  if (n_chunks > INT_MAX) return false;
+  w.n_chunks = (int)n_chunks;
+  // about four chunks per workgroup, at most three workgroups per CU
+  w.n_wg = (int)std::min<long long>(WB_MAX_WG, (n_chunks + 3) / 4);
+  w.cols = (s.Kp + 31) / 32 * 32;
+  w.slab_len = 32 * w.cols + 32;
+  w.per_group = (w.n_wg + WB_GROUPS - 1) / WB_GROUPS;
+  w.n_groups = (w.n_wg + w.per_group - 1) / w.per_group;
+  w.floats = (size_t)(w.n_wg + w.n_groups) * w.slab_len;
+  return true;
+}
+
+// Partial sums of the no-allocation weight gradient (af_conv3x3_bwd_weight_noalloc):
+// the most any layer shape needs -- WB_MAX_WG workgroup slabs and WB_GROUPS group
+// slabs, each a 32 x 288 weight block plus 32 bias sums: 800 x 9248 floats, 29.6 MB
+// per GPU, held until the process ends.  Every slab element is written before it is
+// read, so nothing is cleared between calls.  Host code never uses this name as an
+// address: scratch_ptr holds each device's address from hipGetSymbolAddress.
+constexpr size_t NOALLOC_FLOATS = (size_t)(WB_MAX_WG + WB_GROUPS) * (32 * WB_ROWS + 32);
+__device__ __align__(256) float scratch[NOALLOC_FLOATS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+float* scratch_ptr[MAX_DEVICES] = {};
+
+hipError_t run_conv_bwd_weight(af_ctx* c, const ConvShape& s, const WbSplit& w, const void* in,
+                               const void* dout, float* part, float* dw, float* db) {
+  float* part2 = part + (size_t)w.n_wg * w.slab_len;
+  hipLaunchKernelGGL(k_conv_bwd_weight, dim3(w.n_wg), dim3(256), 0, c->stream, s, (const u16*)in,
+                     (const u16*)dout, w.n_chunks, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_conv_wsum, dim3((w.slab_len + 255) / 256, w.n_groups), dim3(256), 0,
+                     c->stream, part, w.n_wg, w.per_group, w.slab_len, part2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int n = s.Cout * 9 * s.Cin;
+  hipLaunchKernelGGL(k_conv_wreduce, dim3((n + 255) / 256), dim3(256), 0, c->stream, part2,
+                     w.n_groups, w.cols, s.Cout, 9 * s.Cin, dw, db);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;  // this device's copy of the array (the device is current)
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  scratch_ptr[device] = static_cast<float*>(p);
+  return hipSuccess;
+}
+
+hipError_t launch_conv_bwd_weight_noalloc(af_ctx* c, int B, int H, int W, int Cin, int Cout,
+                                          int stride, const void* in, const void* dout, float* dw,
+                                          float* db, bool* too_large) {
+  *too_large = false;
+  const ConvShape s = shape(B, H, W, Cin, Cout, stride);
+  WbSplit w;
+  if (!wb_split(s, w)) return hipErrorInvalidValue;
+  if (w.floats > NOALLOC_FLOATS) {
+    *too_large = true;
+    return hipErrorInvalidValue;
+  }
+  float* part = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    part = (c->device >= 0 && c->device < MAX_DEVICES) ? scratch_ptr[c->device] : nullptr;
+  }
+  if (!part) return hipErrorNotInitialized;  // af_create could not take the address
+  return run_conv_bwd_weight(c, s, w, in, dout, part, dw, db);
+}
+
 hipError_t launch_conv_bwd_weight(af_ctx* c, int B, int H, int W, int Cin, int Cout, int stride,
                                   const void* in, const void* dout, float* dw, float* db) {
   const ConvShape s = shape(B, H, W, Cin, Cout, stride);
-  const long long M = (long long)B * s.Ho * s.Wo;
-  const long long n_chunks = (M + WB_CHUNK - 1) / WB_CHUNK;
-  if (n_chunks > INT_MAX) return hipErrorInvalidValue;
-  // about four chunks per workgroup, at most three workgroups per CU
-  const int n_wg = (int)std::min<long long>(WB_MAX_WG, (n_chunks + 3) / 4);
-  const int cols = (s.Kp + 31) / 32 * 32;
-  const int slab_len = 32 * cols + 32;
-  const int per_group = (n_wg + WB_GROUPS - 1) / WB_GROUPS;
-  const int n_groups = (n_wg + per_group - 1) / per_group;
-  hipError_t e = c->d_cnn_part.ensure(sizeof(float) * (size_t)(n_wg + n_groups) * slab_len);
+  WbSplit w;
+  if (!wb_split(s, w)) return hipErrorInvalidValue;
+  hipError_t e = c->d_cnn_part.ensure(sizeof(float) * w.floats);
   if (e != hipSuccess) return e;
-  float* part = c->d_cnn_part.as<float>();
-  float* part2 = part + (size_t)n_wg * slab_len;
-  hipLaunchKernelGGL(k_conv_bwd_weight, dim3(n_wg), dim3(256), 0, c->stream, s, (const u16*)in,
-                     (const u16*)dout, (int)n_chunks, part);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_conv_wsum, dim3((slab_len + 255) / 256, n_groups), dim3(256), 0, c->stream,
-                     part, n_wg, per_group, slab_len, part2);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int n = Cout * 9 * Cin;
-  hipLaunchKernelGGL(k_conv_wreduce, dim3((n + 255) / 256), dim3(256), 0, c->stream, part2,
-                     n_groups, cols, Cout, 9 * Cin, dw, db);
-  return hipGetLastError();
+  return run_conv_bwd_weight(c, s, w, in, dout, c->d_cnn_part.as<float>(), dw, db);
 }
 
 hipError_t launch_conv_pack(af_ctx* c, int Cin, int Cout, const float* w, void* wp, void* wtp) {
