@@ -30,7 +30,11 @@ METRIC = "DAS fwd+bwd Gsamples/s (tx·rx·pix); autofocus s-to-target CMP error,
 UNIT = "Gsamples/s"
 
 # MI355X published peaks
-PEAK_FP32_TFLOPS = 157.3        # 256 CU x 2.4 GHz x 256 FP32 flop/clk/CU
+PEAK_FP32_TFLOPS = 157.3        # 256 CU x 2.4 GHz x 256 FP32 flop/clk/CU (packed FP32)
+# The library is built without packed FP32 instructions (they have given wrong
+# results on these boxes), so one FMA per lane per issue is the attainable vector
+# ceiling: 256 CU x 2.4 GHz x 128 flop/clk/CU.
+PEAK_FP32_NONPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2500.0       # dense MFMA, no sparsity
 
@@ -40,7 +44,8 @@ FLOPS_PER_UNIT = {
     "das_fwd": 14.0,     # per active (t, r, point) sample: interpolate (6) + rotate-accumulate (8)
     "das_adj": 22.0,     # per active sample: interpolate + derivative (12) + rotate (6) + Re/acc (4)
     "table": 64.0,       # per ray point: bicubic weights (20) + 16 taps (40) + position (4)
-    "path_adj": 44.0,    # per ray point: weights (20) + 16 scatter products (20) + position (4)
+    "path_adj": 60.0,    # per ray point: weights (20) + 16 scatter products (20) + the 16
+                         # additions into the grid (16) + position (4)
 }
 
 
@@ -50,7 +55,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2_clinical")
-    ap.add_argument("--cpu-pixels", type=int, default=192,
+    ap.add_argument("--cpu-pixels", type=int, default=1024,
                     help="pixels of the bounded oracle sample (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (HBM counter scale)")
@@ -66,33 +71,58 @@ def workload(cfg, device=0):
     return workloads.build(cfg, device=device)
 
 
+_cpu = {}
+
+
+def _cpu_init():
+    from threadpoolctl import threadpool_limits
+    _cpu["limits"] = threadpool_limits(limits=1)   # one thread per process
+
+
+def _cpu_chunk(sel):
+    from oracle import model
+    prob, s, lp = _cpu["prob"], _cpu["s"], _cpu["lp"]
+    sub = model.Problem(**{**prob.__dict__, "centres": prob.centres[sel], "_cache": {}})
+    return model.loss_and_grad_parts(sub, s, lp)
+
+
 def cpu_baseline(cfg, n_pix_sample: int):
-    """The FP64 oracle as it stands on a bounded sample of the same workload: the
-    full array and channel-data shape, ``n_pix_sample`` pixels spread over the image."""
+    """The FP64 oracle as it stands, on the host's cores (one process per core, at
+    most 16), on a bounded sample of the same workload: the full array and
+    channel-data shape, every k-th pixel of the image (n_pix_sample of them), dealt
+    round-robin into one chunk per process so that every chunk spans all depths;
+    the chunks' sums are combined as the whole loss_and_grad would combine them
+    (oracle.model.combine_parts)."""
+    import multiprocessing as mp
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import afsynth
     import problems
     from oracle import model
 
     prob = problems.problem(cfg, depth_scale_max=1.74 / 1.54)
-    rng = np.random.default_rng(0)
-    sel = np.sort(rng.choice(prob.centres.shape[0], n_pix_sample, replace=False))
-    prob = model.Problem(**{**prob.__dict__, "centres": prob.centres[sel], "_cache": {}})
+    n_all = prob.centres.shape[0]
+    stride = max(1, n_all // n_pix_sample)
+    sel = np.arange(0, n_all, stride)[:n_pix_sample]
     prob.iq = afsynth.random_iq(cfg.array.n_elem, cfg.acq.n_samples, seed=cfg.seed)
     x0, z0, dx, dz, nx, nz = prob.grid
     s = np.full((nz, nx), 1.0 / 1.54)
     lp = problems.loss_params(cfg)
-    from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):
+    _cpu.update(prob=prob, s=s, lp=lp)
+    workers = max(1, min(16, os.cpu_count() or 1, len(sel)))
+    chunks = [sel[w::workers] for w in range(workers)]
+    with mp.get_context("fork").Pool(workers, initializer=_cpu_init) as pool:
         t0 = time.perf_counter()
-        model.loss_and_grad(prob, s, lp)
+        parts = pool.map(_cpu_chunk, chunks, chunksize=1)
+        model.combine_parts(parts, s, lp, prob.grid)
         dt = time.perf_counter() - t0
-    samples = cfg.array.n_elem ** 2 * n_pix_sample * prob.n_patch
-    return dict(value=samples / dt / 1e9, unit=UNIT, cores=1, kind="oracle",
-                sample=f"{n_pix_sample} of {cfg.img.n_depth * cfg.img.n_angle} pixels "
-                       f"(x{prob.n_patch} points), full {cfg.array.n_elem}x{cfg.array.n_elem}"
-                       f"x{cfg.acq.n_samples} channel data, one loss_and_grad in "
-                       f"{dt:.1f} s (numpy single thread)")
+    samples = cfg.array.n_elem ** 2 * len(sel) * prob.n_patch
+    return dict(value=samples / dt / 1e9, unit=UNIT, cores=workers, kind="oracle",
+                sample=f"{len(sel)} of {n_all} pixels (x{prob.n_patch} points: every "
+                       f"{stride}th pixel of the image), full "
+                       f"{cfg.array.n_elem}x{cfg.array.n_elem}x{cfg.acq.n_samples} channel "
+                       f"data, loss and gradient in one chunk per process on {workers} "
+                       f"processes: {dt:.1f} s; scaled per sample, the whole image would take "
+                       f"about {dt * n_all / len(sel):.0f} s")
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_clinical_hbm_traffic.txt")
@@ -113,17 +143,19 @@ def measured_traffic(cfg_name: str, family: str):
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "c2_clinical_valu_counters.txt")
 
 
-def measured_issue(cfg_name: str, family: str):
-    """VALU instructions per CU per ns and active-lane share of ``family`` from the
-    committed SQ counter summary, or None when there is none for this workload or
-    the kernel's sources changed since."""
+def measured_issue(cfg_name: str, family: str, units: float):
+    """VALU instructions per CU per ns, active-lane share and VALU lane-instructions
+    per algorithmic unit of ``family`` from the committed SQ counter summary, or None
+    when there is none for this workload or the kernel's sources changed since."""
     from paper_2608_06853_amd import profsummary
     if cfg_name != "c2_clinical" or not os.path.exists(COUNTERS_FILE):
         return None
     rec = profsummary.read_counters(COUNTERS_FILE).get(family)
     if rec is None or rec[0] != profsummary.source_hash(family):
         return None
-    return {"valu_instr_per_cu_per_ns": rec[1], "active_lane_share": rec[2]}
+    lane_instr = rec[3] * 64.0 * rec[2]
+    return {"valu_instr_per_cu_per_ns": rec[1], "active_lane_share": rec[2],
+            "valu_lane_instr_per_unit": round(lane_instr / units, 2) if units > 0 else None}
 
 
 def plain_loop_report():
@@ -496,9 +528,12 @@ def main():
         tr = measured_traffic(cfg.name, dom)
         roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
+                "frac_nonpacked": round(ach / PEAK_FP32_NONPACKED_TFLOPS, 4),
+                "flop_per_unit": FLOPS_PER_UNIT[dom], "units_per_launch": units[dom],
                 "traffic": tr, "traffic_unit": "bytes per launch",
                 "avg_launch_ms": round(avg_s * 1e3, 4),
-                "valu_issue": measured_issue(cfg.name, dom)}
+                "valu_issue": measured_issue(cfg.name, dom, units[dom])}
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": UNIT, "n_gpus": 1,

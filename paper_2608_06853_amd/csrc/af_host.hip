@@ -162,17 +162,23 @@ af_status build_work_lists(af_ctx* c, const char* who) {
   c->tile_order.clear();
   for (auto& l : load) c->tile_order.push_back(l.second);
   // DAS work items (tile, receive block).  Workgroups are dealt to the XCDs
-  // round-robin (workgroup b runs on XCD b % 8), so every receive block is given
-  // to one XCD, and its tiles follow in k-d (spatial) order: the channel records
-  // of that block then stay in the XCD's L2 while neighbouring tiles reuse their
-  // time windows.  Shorter queues are padded with empty items (tile -1).
+  // round-robin (workgroup b runs on XCD b % 8).  The tiles with work, in k-d
+  // (spatial) order, are cut into runs of 16 that are dealt to the XCDs in turn,
+  // and all receive blocks of a tile go to the same XCD, one after another: the
+  // table entries of a tile, which every one of its items reads, are then fetched
+  // into one XCD's L2 once, and the 16 neighbouring tiles of a run reuse their
+  // channel-data windows there.  Runs of 16 (rather than one long run per XCD)
+  // keep the eight queues close in length when the work per tile varies across
+  // the image.  Shorter queues are padded with empty items (tile -1).
   {
-    constexpr int NXCD = 8;
+    constexpr int NXCD = 8, RUN = 16;
     std::vector<std::vector<int2>> q(NXCD);
+    int n_live = 0;
     for (int t = 0; t < n_tiles; ++t) {
       const int4 tr = tiles[t];
       if (tr.x > tr.y) continue;
-      for (int jb = tr.z; jb <= tr.w; ++jb) q[jb % NXCD].push_back(make_int2(t, jb));
+      const int x = (n_live++ / RUN) % NXCD;
+      for (int jb = tr.z; jb <= tr.w; ++jb) q[x].push_back(make_int2(t, jb));
     }
     size_t L = 0;
     for (auto& v : q) L = std::max(L, v.size());

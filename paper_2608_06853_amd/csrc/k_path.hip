@@ -75,6 +75,13 @@ __device__ inline float reduce_scatter16(float v[16], int lane) {
   return h1;
 }
 
+// Adds the 16 tap sums of acc (summed over the wavefront) to the wavefront's grid
+// copy at cell c; acc is consumed.
+__device__ inline void flush16(float* grid, int c, float (&acc)[16], int lane, int my_off) {
+  const float sum = reduce_scatter16(acc, lane);
+  if ((lane & 3) == 0) grid[c + my_off] += sum;
+}
+
 // Sum over the wavefront of v[r], r = 0..3: every lane returns the sum of
 // v[l >> 4].  The half-wave swaps leave row r (16 lanes) holding value r summed
 // over four lanes; rotations by 8, 4, 2 and 1 inside the row finish the sum.
@@ -99,18 +106,30 @@ struct Ray {
   bool live;
 };
 
-// Ray point k of every lane: returns its cell and the two weight vectors whose
-// outer product az x wx gives the 16 tap weights (trapezoid end weights folded
-// into az).
-__device__ inline int ray_point(const Ray& r, int k, int nseg, float umax, float vmax, int W,
-                                float az[4], float wx[4]) {
-  const float u = __builtin_amdgcn_fmed3f(fmaf((float)k, r.du, r.u0), 0.f, umax);
-  const float v = __builtin_amdgcn_fmed3f(fmaf((float)k, r.dv, r.v0), 0.f, vmax);
-  const int j0 = (int)u, i0 = (int)v;
+// Ray point k of every lane: its grid position (clamped to the node range) and cell.
+__device__ inline int ray_pos(const Ray& r, int k, float umax, float vmax, int W, float& u,
+                              float& v) {
+  u = __builtin_amdgcn_fmed3f(fmaf((float)k, r.du, r.u0), 0.f, umax);
+  v = __builtin_amdgcn_fmed3f(fmaf((float)k, r.dv, r.v0), 0.f, vmax);
+  return (int)v * W + (int)u;
+}
+
+// The two weight vectors of ray point k at (u, v) whose outer product az x wx gives
+// the 16 tap weights (trapezoid end weights folded into az).
+__device__ inline void ray_weights(const Ray& r, int k, int nseg, float u, float v, float az[4],
+                                   float wx[4]) {
   keys_weights(__builtin_amdgcn_fractf(u), wx[0], wx[1], wx[2], wx[3]);  // u, v >= 0: u - j0
   const float ck = (k == 0 || k == nseg) ? 0.5f * r.coef : r.coef;
   keys_weights_scaled(__builtin_amdgcn_fractf(v), ck, az[0], az[1], az[2], az[3]);
-  return i0 * W + j0;
+}
+
+// Ray point k of every lane: returns its cell and the two weight vectors.
+__device__ inline int ray_point(const Ray& r, int k, int nseg, float umax, float vmax, int W,
+                                float az[4], float wx[4]) {
+  float u, v;
+  const int cell = ray_pos(r, k, umax, vmax, W, u, v);
+  ray_weights(r, k, nseg, u, v, az, wx);
+  return cell;
 }
 
 // NR ray points per lane whose cells lie in two neighbouring cells, cb and cb + 1
@@ -267,7 +286,7 @@ __device__ inline void scatter_pair(float* grid, const int (&cell)[2], const boo
   scatter_one(grid, cell[1], live[1], lead1, W, az[1], wx[1], lane, my_off);
 }
 
-__global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_path_adj(PathArgs A) {
   extern __shared__ float sg[];  // [4 wavefronts][nodes]
   const Geo& g = A.g;
   const int tid = threadIdx.x;
@@ -325,17 +344,53 @@ __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
       const int lead = __ffsll((long long)all) - 1;
       const int lead01 = __ffsll((long long)(lm[0] | lm[1])) - 1;
       const int lead23 = __ffsll((long long)(lm[2] | lm[3])) - 1;
+      // Consecutive steps whose ray points all lie in one cell, the same cell, add
+      // their products into acc and share one reduce (flushed when the cell changes
+      // or a step spreads over more cells).
+      // acc is all zeros whenever c_acc is -1, so a step that falls back below holds
+      // no pending sums in registers.
+      float acc[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+      int c_acc = -1;  // wavefront-uniform: the cell of the pending sums in acc (-1: none)
       for (int k = 0; k <= g.n_seg; ++k) {
-        float az[4][4], wx[4][4];
+        float u[4], v[4];
         int cell[4];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) cell[n] = ray_point(R[n], k, g.n_seg, umax, vmax, W, az[n], wx[n]);
+        for (int n = 0; n < 4; ++n) cell[n] = ray_pos(R[n], k, umax, vmax, W, u[n], v[n]);
         // a lane's first live ray point; idle ray points join the leader's cell
         const int mine = R[0].live ? cell[0] : R[1].live ? cell[1] : R[2].live ? cell[2] : cell[3];
         const int c0 = __builtin_amdgcn_readlane(mine, lead);
         int cu[4];
+        bool one = true;
 #pragma unroll
-        for (int n = 0; n < 4; ++n) cu[n] = R[n].live ? cell[n] : c0;
+        for (int n = 0; n < 4; ++n) {
+          cu[n] = R[n].live ? cell[n] : c0;
+          one = one && cu[n] == c0;
+        }
+        if (__ballot(!one) == 0ull) {  // the usual case: one cell for the whole wavefront
+          if (c0 != c_acc && c_acc >= 0) {
+            flush16(grid, c_acc, acc, lane, my_off);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+          }
+          c_acc = c0;
+#pragma unroll
+          for (int n = 0; n < 4; ++n) {
+            float az[4], wx[4];
+            ray_weights(R[n], k, g.n_seg, u[n], v[n], az, wx);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[i] = fmaf(az[i >> 2], wx[i & 3], acc[i]);
+          }
+          continue;
+        }
+        if (c_acc >= 0) flush16(grid, c_acc, acc, lane, my_off);
+        c_acc = -1;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+        float az[4][4], wx[4][4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) ray_weights(R[n], k, g.n_seg, u[n], v[n], az[n], wx[n]);
         if (scatter_union<4>(grid, c0, W, cu, az, wx, lane, my_off)) continue;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -349,6 +404,7 @@ __global__ __launch_bounds__(256) void k_path_adj(PathArgs A) {
                        a2, w2, lane, my_off);
         }
       }
+      if (c_acc >= 0) flush16(grid, c_acc, acc, lane, my_off);
       continue;
     }
     // some element of the four has no work in this wavefront: pairs and singles

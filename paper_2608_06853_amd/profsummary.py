@@ -51,15 +51,20 @@ def source_hash(family: str) -> str:
 
 
 def read_counters(path: str) -> dict:
-    """{family: (source hash, VALU instructions per CU per ns, lane utilisation)}
-    from a counter summary."""
+    """{family: (source hash, VALU instructions per CU per ns, lane utilisation,
+    SQ_INSTS_VALU per dispatch)} from a counter summary (columns named by its last
+    header line)."""
     out = {}
+    cols = []
     with open(path) as f:
         for line in f:
+            if line.startswith("# family"):
+                cols = line[1:].split()
             if line.startswith("#") or not line.strip():
                 continue
             p = line.split()
-            out[p[0]] = (p[1], float(p[3]), float(p[4]))
+            n_valu = float(p[cols.index("SQ_INSTS_VALU")]) if "SQ_INSTS_VALU" in cols else float("nan")
+            out[p[0]] = (p[1], float(p[3]), float(p[4]), n_valu)
     return out
 
 
