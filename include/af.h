@@ -131,6 +131,18 @@ af_status af_set_lens(af_ctx* ctx, double d_lens, double c_lens, double t_ttp, i
 #define AF_MAX_SEARCH 4096
 af_status af_set_refraction_search(af_ctx* ctx, int n_search);
 
+/* Reduction order of the gradient (the adjoint of Eq. 5 feeds every travel time
+ * T[a][p] from the samples where element a transmits and from those where it
+ * receives).  on = 0 (the default): the transmit-role sums, which span the work
+ * items of several receive blocks, are added with floating-point atomics, so the
+ * last bits of the gradient may differ between runs.  on = 1: every work item
+ * writes its partial sums to a slab of its own (device memory the context owns:
+ * per tile, active elements x receive blocks x 256 points, 4 bytes each) and the
+ * path adjoint adds them in a fixed order, so loss and gradient are the same bit
+ * for bit on every run, at a few percent more time.  Applies from the next call
+ * on.  Errors: AF_ERR_ARG for other values, AF_ERR_OOM. */
+af_status af_set_deterministic(af_ctx* ctx, int on);
+
 /* Slowness grid s ~ 1/c (Section III-A): node (i, j) at (x0 + j dx, z0 + i dz),
  * values [nz][nx] float32 at `s_dev` (device), copied on the context stream.
  * At most (nx+3)(nz+3) = 9600 padded nodes (e.g. 95 x 95).

@@ -36,7 +36,7 @@ LENS_MODES = {"bent": LENS_BENT, "conventional": LENS_CONVENTIONAL, "none": LENS
 
 EXPORTS = [
     "af_create", "af_destroy", "af_last_error", "af_set_geometry", "af_set_lens",
-    "af_set_refraction_search", "af_set_slowness", "af_beamform", "af_loss_and_grad", "af_forward", "af_backward",
+    "af_set_refraction_search", "af_set_deterministic", "af_set_slowness", "af_beamform", "af_loss_and_grad", "af_forward", "af_backward",
     "af_autofocus_step", "af_travel_times", "af_set_dynamic_grid", "af_set_sweep_speed",
     "af_sweep", "af_simulate", "af_query", "af_set_profiling",
     "af_profile_read", "af_conv3x3_pack", "af_conv3x3_fwd", "af_conv3x3_bwd_data",
@@ -67,6 +67,7 @@ _sig = {
     "af_set_geometry": (C.c_int, [_vp, _i, _vp, _i, _vp, _i, _d, _i, _d, _d, _d, _i, _d, _i]),
     "af_set_lens": (C.c_int, [_vp, _d, _d, _d, _i, _d]),
     "af_set_refraction_search": (C.c_int, [_vp, _i]),
+    "af_set_deterministic": (C.c_int, [_vp, _i]),
     "af_set_slowness": (C.c_int, [_vp, _i, _i, _d, _d, _d, _d, _vp]),
     "af_beamform": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "af_channel_images": (C.c_int, [_vp, _vp, _vp]),
@@ -190,6 +191,9 @@ class Context:
 
     def set_refraction_search(self, n_search: int):
         self._chk(_lib.af_set_refraction_search(self._h, int(n_search)))
+
+    def set_deterministic(self, on: bool):
+        self._chk(_lib.af_set_deterministic(self._h, 1 if on else 0))
 
     def set_slowness(self, nx, nz, x0, z0, dx, dz, s):
         import torch

@@ -76,14 +76,16 @@ class Beamformer:
     """Library context bound to one acquisition, evaluation grid and slowness grid."""
 
     def __init__(self, acq: Acquisition, img: Imaging, grid: Grid, device: int = 0,
-                 n_search: int = 0):
+                 n_search: int = 0, deterministic: bool = False):
         """``n_search`` = 0 refracts at the exact Fermat root, >= 2 by the discrete
-        search over that many lens points."""
+        search over that many lens points; ``deterministic`` fixes the reduction
+        order of the gradient (bit-for-bit repeatable, a few percent slower)."""
         self.acq, self.grid = acq, grid
         self.device = torch.device("cuda", device)
         self.ctx = _lib.Context(device)
         self.ctx.set_lens(acq.d_lens, acq.c_lens, acq.t_ttp, acq.lens_mode, acq.c_ref)
         self.ctx.set_refraction_search(n_search)
+        self.ctx.set_deterministic(deterministic)
         self.img = None
         self.set_imaging(img)
         self.s = None

@@ -186,10 +186,21 @@ af_status build_work_lists(af_ctx* c, const char* who) {
       for (int x = 0; x < NXCD; ++x)
         daswork.push_back(i < q[x].size() ? q[x][i] : make_int2(-1, 0));
   }
+  // slabs of the transmit-role sums of the DAS adjoint (one per DAS work item)
+  std::vector<long long> tbase(std::max(n_tiles, 1), 0);
+  long long n_gtp = 0;
+  for (int t = 0; t < n_tiles; ++t) {
+    const int4 tr = tiles[t];
+    tbase[t] = n_gtp;
+    if (tr.x <= tr.y) n_gtp += (long long)(tr.w - tr.z + 1) * (tr.y - tr.x + 1) * af::TILE;
+  }
+  c->n_gtp = n_gtp;
   c->n_tab_work = (int)tabwork.size();
   c->n_das_work = (int)daswork.size();
   c->n_order = (int)c->tile_order.size();
   af_status st;
+  if (c->det) AF_ALLOC(c->d_gtp, sizeof(float) * (size_t)std::max(n_gtp, 1LL), "transmit-role sums");
+  if ((st = upload(c, c->d_tbase, tbase, "slab offsets")) != AF_OK) return st;
   if ((st = upload(c, c->d_tiles, tiles, "tiles")) != AF_OK) return st;
   if ((st = upload(c, c->d_tabwork, tabwork, "work list")) != AF_OK) return st;
   if ((st = upload(c, c->d_daswork, daswork, "work list")) != AF_OK) return st;
@@ -622,6 +633,17 @@ af_status af_set_refraction_search(af_ctx* c, int n_search) {
   if (n_search != 0 && (n_search < 2 || n_search > AF_MAX_SEARCH))
     return fail(c, AF_ERR_ARG, "af_set_refraction_search: n_search must be 0 or in [2, 4096]");
   c->n_search = n_search;
+  return AF_OK;
+}
+
+af_status af_set_deterministic(af_ctx* c, int on) {
+  if (!c) return AF_ERR_ARG;
+  if (on != 0 && on != 1) return fail(c, AF_ERR_ARG, "af_set_deterministic: on must be 0 or 1");
+  if (on && c->n_gtp > 0) {
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, AF_ERR_HIP, "hipSetDevice");
+    AF_ALLOC(c->d_gtp, sizeof(float) * (size_t)c->n_gtp, "transmit-role sums");
+  }
+  c->det = on != 0;
   return AF_OK;
 }
 

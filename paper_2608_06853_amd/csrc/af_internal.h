@@ -78,7 +78,10 @@ struct DasArgs {
   const double* gscal;    // null: gblk is final; else dL/dB = gblk * gscal[5] + gsb[p]
   const float2* gsb;      // [P] speckle-brightness gradient per point
   float* gT;              // [n_elem][P]  dL/dT, receive role (adjoint output)
-  float* gT2;             // [n_elem][P]  dL/dT, transmit role (atomic adds)
+  float* gT2;             // [n_elem][P]  dL/dT, transmit role (atomic adds; default mode)
+  float* gtp;             // deterministic mode: transmit-role partial sums, one slab per
+                          // (tile, receive block)
+  const long long* tbase; // [n_tiles] offset of a tile's slabs in gtp
 };
 
 struct CmpeArgs {
@@ -113,7 +116,9 @@ struct PathArgs {
   const int4* tiles;
   const int* order;
   const float* gT;        // dL/dT [n_elem][P], receive role
-  const float* gT2;       // dL/dT [n_elem][P], transmit role
+  const float* gT2;       // dL/dT [n_elem][P], transmit role (default mode)
+  const float* gtp;       // deterministic mode: transmit-role slabs (DasArgs::gtp)
+  const long long* tbase;
   float* gpart;           // [n_wg][padded nodes] per-workgroup partial grids
 };
 
@@ -177,6 +182,12 @@ struct af_ctx {
   af::DBuf d_chan;  // receive-channel images, allocated by the coherence calls only
   af::DBuf d_s, d_gdev, d_regg, d_scal, d_tab, d_bblk, d_g, d_gT, d_gsb, d_part, d_gpad, d_gpart,
       d_grad, d_terms, d_maps, d_img;
+  // Transmit-role sums of dL/dT: for every tile and receive block jb of its range
+  // one slab [element e - LO][TILE] of sums over the receive elements of jb; the
+  // slabs of a tile follow in jb order from d_tbase[tile].
+  af::DBuf d_gtp, d_tbase;
+  long long n_gtp = 0;
+  bool det = false;  // deterministic mode (af_set_deterministic)
 
   af::Geo geo() const;
 

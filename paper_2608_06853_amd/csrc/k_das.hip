@@ -249,11 +249,16 @@ __device__ inline void das_adj_t(const float2* __restrict__ base, int ns, const 
 // dL/dT[a][p]: for each sample, D = Re(conj(G) (v' + j w v) E_t E_r) feeds the
 // transmit element t and the receive element r.  One workgroup per (tile,
 // receive block) as in the forward: the receive-role sums of its S elements are
-// complete and written directly; the transmit-role sums of every t are partial
-// (one per receive block) and are added with global atomics.
+// complete and written directly; the transmit-role sums of every t of the tile
+// are partial (over the S receive elements of this block).  By default they are
+// added into gT2 with global float atomics (merged in L2; the order of the adds,
+// and so the last bits of the sum, vary from run to run).  With DET they go with
+// plain stores into this item's own slab, which the path adjoint adds up in
+// receive-block order: the gradient is then the same bit for bit on every run,
+// at the cost of writing and reading every slab through HBM.
 // The register budget is capped at 128 so that 4 wavefronts fit per SIMD; without
 // the cap the compiler lands at 131 registers and loses one wavefront per SIMD.
-template <int S>
+template <int S, bool DET>
 __global__ __launch_bounds__(256, 4) void k_das_adj(DasArgs A) {
   const Geo& g = A.g;
   const int2 w = A.work[blockIdx.x];
@@ -279,7 +284,16 @@ __global__ __launch_bounds__(256, 4) void k_das_adj(DasArgs A) {
   for (int k = 0; k < S; ++k) grx[k] = 0.f;
   const WaveRange wr = wave_range(A.prange, p, tr, jb, S);
   const float gi = A.gscal ? (float)A.gscal[5] : 0.f;
-  if (wr.rx_active && wr.lo <= wr.hi) {
+  // DET: this item's slab (workgroup-uniform base), slot (t - tr.x) * TILE + lane point
+  float* __restrict__ slab =
+      DET ? A.gtp + A.tbase[tile] + (long long)(jb - tr.z) * (tr.y - tr.x + 1) * TILE : nullptr;
+  const int me = (int)threadIdx.x - tr.x * TILE;
+  const bool busy = wr.rx_active && wr.lo <= wr.hi;
+  // transmit elements the wavefront does not visit below hold zero sums
+  if (DET)
+    for (int t = tr.x; t <= tr.y; ++t)
+      if (!busy || t < wr.lo || t > wr.hi) slab[t * TILE + me] = 0.f;
+  if (busy) {
     for (int ib = max(tr.z, wr.lo / S); ib <= min(tr.w, wr.hi / S); ++ib) {
       const int t0 = max(ib * S, wr.lo), t1 = min(ib * S + S - 1, wr.hi);
       float2 G = A.gblk[((long long)ib * g.nblk + jb) * P + p];
@@ -299,7 +313,10 @@ __global__ __launch_bounds__(256, 4) void k_das_adj(DasArgs A) {
           const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
           float gtx = 0.f;
           das_adj_t<S>(base, ns, et, rx, !inside, qx, qy, fsf, om, grx, gtx);
-          if (gtx != 0.f) atomicAdd(A.gT2 + (long long)t * P + p, gtx);
+          if (DET) slab[t * TILE + me] = gtx;
+          else if (gtx != 0.f) atomicAdd(A.gT2 + (long long)t * P + p, gtx);
+        } else if (DET) {
+          slab[t * TILE + me] = 0.f;
         }
         et = en;
       }
@@ -444,10 +461,14 @@ hipError_t das_fwd_s(af_ctx* c, const DasArgs& A) {
 
 template <int S>
 hipError_t das_adj_s(af_ctx* c, const DasArgs& A) {
+  if (c->det) {
+    hipLaunchKernelGGL((k_das_adj<S, true>), dim3(c->n_das_work), dim3(256), 0, c->stream, A);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_zero_tx, dim3(c->n_tiles), dim3(256), 0, c->stream, A.g, A.tiles, A.gT2);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_das_adj<S>, dim3(c->n_das_work), dim3(256), 0, c->stream, A);
+  hipLaunchKernelGGL((k_das_adj<S, false>), dim3(c->n_das_work), dim3(256), 0, c->stream, A);
   return hipGetLastError();
 }
 
@@ -523,6 +544,8 @@ hipError_t launch_das_adj(af_ctx* c, const float2* iq, const float2* gblk, bool 
   A.gsb = c->d_gsb.as<float2>();
   A.gT = c->d_gT.as<float>();
   A.gT2 = c->d_gT.as<float>() + (size_t)c->N * c->P_int;
+  A.gtp = c->d_gtp.as<float>();
+  A.tbase = c->d_tbase.as<long long>();
   switch (c->S) {
     case 1: return das_adj_s<1>(c, A);
     case 2: return das_adj_s<2>(c, A);

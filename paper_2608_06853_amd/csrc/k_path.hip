@@ -286,6 +286,7 @@ __device__ inline void scatter_pair(float* grid, const int (&cell)[2], const boo
   scatter_one(grid, cell[1], live[1], lead1, W, az[1], wx[1], lane, my_off);
 }
 
+template <bool DET>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_path_adj(PathArgs A) {
   extern __shared__ float sg[];  // [4 wavefronts][nodes]
   const Geo& g = A.g;
@@ -321,7 +322,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       const int e = a + n;
       const bool act = e <= tr.y && e >= pr.x && e <= pr.y;
       float gbar = 0.f;
-      if (act) gbar = A.gT[(long long)e * g.P + p] + A.gT2[(long long)e * g.P + p];
+      if (act) {
+        gbar = A.gT[(long long)e * g.P + p];  // receive role
+        if (DET) {  // the transmit-role slabs in receive-block order
+          const float* q = A.gtp + A.tbase[tile] + (long long)(e - tr.x) * TILE + tid;
+          const long long slab = (long long)(tr.y - tr.x + 1) * TILE;
+          for (int jb = tr.z; jb <= tr.w; ++jb) gbar += q[(long long)(jb - tr.z) * slab];
+        } else {
+          gbar += A.gT2[(long long)e * g.P + p];
+        }
+      }
       R[n].live = act && gbar != 0.f;
       lm[n] = __ballot(R[n].live);
       R[n].coef = 0.f;
@@ -500,9 +510,15 @@ hipError_t launch_path_adj(af_ctx* c) {
   A.order = c->d_order.as<int>();
   A.gT = c->d_gT.as<float>();
   A.gT2 = c->d_gT.as<float>() + (size_t)c->N * c->P_int;
+  A.gtp = c->d_gtp.as<float>();
+  A.tbase = c->d_tbase.as<long long>();
+
   A.gpart = c->d_gpart.as<float>();
   const size_t lds = sizeof(float) * (size_t)nodes * 4;
-  hipLaunchKernelGGL(k_path_adj, dim3(c->n_order), dim3(256), lds, c->stream, A);
+  if (c->det)
+    hipLaunchKernelGGL(k_path_adj<true>, dim3(c->n_order), dim3(256), lds, c->stream, A);
+  else
+    hipLaunchKernelGGL(k_path_adj<false>, dim3(c->n_order), dim3(256), lds, c->stream, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n_chunk = (c->n_order + PCHUNK - 1) / PCHUNK;

@@ -175,6 +175,36 @@ def test_full_size_gradient_directional(full):
     assert err < 1e-2
 
 
+def test_gradient_bitwise_reproducible(full):
+    """In deterministic mode every reduction of the loss and gradient runs in a
+    fixed order (no floating-point atomics), so two evaluations at the same
+    slowness agree bit for bit, also with an evaluation at another slowness in
+    between; the default mode (atomic transmit-role sums) agrees with it to
+    rounding."""
+    import torch
+    cfg, bf, iq_d, s, *_ = full
+    lp = G.lib_params(_lp(cfg))
+    s_d = torch.from_numpy(s).cuda()
+    t0, g0 = bf.loss_and_grad(iq_d, lp, s_d)
+    t0, g0 = t0.clone(), g0.clone()
+    bf.ctx.set_deterministic(True)
+    try:
+        t1, g1 = bf.loss_and_grad(iq_d, lp, s_d)
+        t1, g1 = t1.clone(), g1.clone()
+        bf.loss_and_grad(iq_d, lp, torch.from_numpy((s * 1.01).astype(np.float32)).cuda())
+        t2, g2 = bf.loss_and_grad(iq_d, lp, s_d)
+        torch.cuda.synchronize()
+    finally:
+        bf.ctx.set_deterministic(False)
+    assert torch.isfinite(g1).all() and float(g1.abs().max()) > 0
+    assert torch.equal(t1, t2)
+    assert torch.equal(g1, g2)
+    assert torch.equal(t0, t1)  # the forward pass is the same in both modes
+    e = G.rel(g0.cpu().numpy(), g1.cpu().numpy())
+    print(cfg.name, "default vs deterministic gradient rel", e, flush=True)
+    assert e < 1e-5
+
+
 def _launch(cfg):
     """The benchmark's launch configuration of ``cfg`` (geometry, lens, slowness grid)
     and the oracle problem of the same geometry."""
