@@ -17,6 +17,7 @@ FAMILIES = {
     "table": (r"k_table[<(]", "k_table.hip"),
     "das_fwd": (r"k_das_fwd<", "k_das.hip"),
     "das_adj": (r"k_das_adj<", "k_das.hip"),
+    "zero_tx": (r"k_zero_tx\(", "k_das.hip"),
     "das_rx": (r"k_das_rx<", "k_das.hip"),
     "loc": (r"k_loc\(", "k_das.hip"),
     "cmpe": (r"k_cmpe\(", "k_cmpe.hip"),
