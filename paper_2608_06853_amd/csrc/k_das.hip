@@ -79,10 +79,10 @@ __device__ inline void gather(const float2* __restrict__ base, int ns, const Tab
       ok[k] = sample_pos(et.ui, et.uf, rx[k].ui, rx[k].uf, ns, kk, fr[k]);
       if (!ok[k]) kk = 0;
     } else {
+      // fsum lies in [0, 2): its integer part is the carry, its fraction the weight
       const float fsum = et.uf + rx[k].uf;
-      const int carry = fsum >= 1.f ? 1 : 0;
-      kk = et.ui + rx[k].ui + carry;
-      fr[k] = fsum - (float)carry;
+      kk = et.ui + rx[k].ui + (int)fsum;
+      fr[k] = __builtin_amdgcn_fractf(fsum);
       ok[k] = true;
     }
     const float2* q = base + (unsigned)(k * ns + kk);
@@ -132,21 +132,20 @@ __device__ inline bool wave_silent(const TabEntry& et, const Rx (&rx)[S], int ns
   return wave_silent(et, rx_span<S>(rx), ns);
 }
 
-template <int S>
+template <int S, bool CHECK>
 __device__ inline void das_fwd_t(const float2* __restrict__ base, int ns, const TabEntry& et,
-                                 const Rx (&rx)[S], bool check, float2& acc) {
+                                 const Rx (&rx)[S], float2& acc) {
   float2 a0[S], a1[S];
   float fr[S];
   bool ok[S];
-  if (check) gather<S, true>(base, ns, et, rx, a0, a1, fr, ok);
-  else gather<S, false>(base, ns, et, rx, a0, a1, fr, ok);
+  gather<S, CHECK>(base, ns, et, rx, a0, a1, fr, ok);
   float ax = 0.f, ay = 0.f;
 #pragma unroll
   for (int k = 0; k < S; ++k) {
     const float f = fr[k];
     float vx = fmaf(f, a1[k].x - a0[k].x, a0[k].x);
     float vy = fmaf(f, a1[k].y - a0[k].y, a0[k].y);
-    if (check) {
+    if (CHECK) {
       vx = ok[k] ? vx : 0.f;
       vy = ok[k] ? vy : 0.f;
     }
@@ -168,8 +167,10 @@ __device__ inline WaveRange wave_range(const int2* __restrict__ prange, long lon
   const int2 pr = prange[p];
   const bool act = pr.x <= pr.y;
   WaveRange w;
-  w.lo = max(wave_min(act ? pr.x : 1 << 30), tr.x);
-  w.hi = min(wave_max(act ? pr.y : -1), tr.y);
+  // the same in every lane: read from lane 0 so that loops over the range, and
+  // the addresses formed from it, live in scalar registers
+  w.lo = __builtin_amdgcn_readfirstlane(max(wave_min(act ? pr.x : 1 << 30), tr.x));
+  w.hi = __builtin_amdgcn_readfirstlane(min(wave_max(act ? pr.y : -1), tr.y));
   const bool hit = act && pr.x <= jb * S + S - 1 && pr.y >= jb * S;
   w.rx_active = __ballot(hit) != 0ull;
   return w;
@@ -209,11 +210,9 @@ __global__ __launch_bounds__(256) void k_das_fwd(DasArgs A) {
       TabEntry et = A.tab[(long long)t0 * P + p];
       for (int t = t0; t <= t1; ++t) {
         const TabEntry en = A.tab[(long long)min(t + 1, t1) * P + p];
-        const bool inside = interior(et, rmin, rmax, ns);
-        if (inside || !wave_silent(et, sp, ns)) {
-          const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
-          das_fwd_t<S>(base, ns, et, rx, !inside, acc);
-        }
+        const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
+        if (interior(et, rmin, rmax, ns)) das_fwd_t<S, false>(base, ns, et, rx, acc);
+        else if (!wave_silent(et, sp, ns)) das_fwd_t<S, true>(base, ns, et, rx, acc);
         et = en;
       }
     }
@@ -221,26 +220,27 @@ __global__ __launch_bounds__(256) void k_das_fwd(DasArgs A) {
   }
 }
 
-template <int S>
+template <int S, bool CHECK>
 __device__ inline void das_adj_t(const float2* __restrict__ base, int ns, const TabEntry& et,
-                                 const Rx (&rx)[S], bool check, float qx, float qy, float fsf,
-                                 float om, float (&grx)[S], float& gtx) {
+                                 const Rx (&rx)[S], float qx, float qy, float fsf, float om,
+                                 float (&grx)[S], float& gtx) {
   float2 a0[S], a1[S];
   float fr[S];
   bool ok[S];
-  if (check) gather<S, true>(base, ns, et, rx, a0, a1, fr, ok);
-  else gather<S, false>(base, ns, et, rx, a0, a1, fr, ok);
+  gather<S, CHECK>(base, ns, et, rx, a0, a1, fr, ok);
 #pragma unroll
   for (int k = 0; k < S; ++k) {
     const float f = fr[k];
+    // D = Re(Q E_r (fs v' + j om v)) = fs Re(P v') - om Im(P v) with P = Q E_r,
+    // where v' = a1 - a0 is the sample slope and v the interpolated sample
+    const float px = fmaf(qx, rx[k].e.x, -qy * rx[k].e.y);
+    const float py = fmaf(qx, rx[k].e.y, qy * rx[k].e.x);
     const float dx = a1[k].x - a0[k].x, dy = a1[k].y - a0[k].y;
     const float vx = fmaf(f, dx, a0[k].x), vy = fmaf(f, dy, a0[k].y);
-    const float wx = fmaf(fsf, dx, -om * vy);
-    const float wy = fmaf(fsf, dy, om * vx);
-    const float zx = wx * rx[k].e.x - wy * rx[k].e.y;
-    const float zy = wx * rx[k].e.y + wy * rx[k].e.x;
-    float D = qx * zx - qy * zy;
-    if (check) D = ok[k] ? D : 0.f;
+    const float re_pd = fmaf(px, dx, -py * dy);
+    const float im_pv = fmaf(px, vy, py * vx);
+    float D = fmaf(fsf, re_pd, -om * im_pv);
+    if (CHECK) D = ok[k] ? D : 0.f;
     gtx += D;
     grx[k] += D;
   }
@@ -312,7 +312,8 @@ __global__ __launch_bounds__(256, 4) void k_das_adj(DasArgs A) {
           const float qy = G.x * et.ei - G.y * et.er;
           const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
           float gtx = 0.f;
-          das_adj_t<S>(base, ns, et, rx, !inside, qx, qy, fsf, om, grx, gtx);
+          if (inside) das_adj_t<S, false>(base, ns, et, rx, qx, qy, fsf, om, grx, gtx);
+          else das_adj_t<S, true>(base, ns, et, rx, qx, qy, fsf, om, grx, gtx);
           if (DET) slab[t * TILE + me] = gtx;
           else if (gtx != 0.f) atomicAdd(A.gT2 + (long long)t * P + p, gtx);
         } else if (DET) {
