@@ -140,13 +140,13 @@ MICRO = Config(
 # 1049.4 m/s, 0.67 mm, t_ttp 578.3 ns; 128 captured elements, 7.35 MHz) and its
 # phantom hyperparameters (Table II: F 0.75, 32 segments, w1 7, no second-order
 # term), on a bi-layer phantom (1575 m/s layer over 1490/1516/1540 m/s), imaged
-# to 25 mm (deeper pixels see all 16 blocks, one more than the CMPE stage holds).
+# to 36 mm, about the depth the 1536-sample record reaches at 1490 m/s.
 L1 = Config(
     name="l1_linear",
     array=ArrayCfg(n_elem=128, radius=math.inf, pitch=0.2, d_lens=0.67, c_lens=1.0494,
                    t_ttp=0.5783),
     acq=AcqCfg(fc=7.35, fs=29.4, n_samples=1536),
-    img=ImgCfg(n_depth=128, n_angle=128, depth_min=2.0, depth_max=25.0),
+    img=ImgCfg(n_depth=128, n_angle=128, depth_min=2.0, depth_max=36.0),
     method=MethodCfg(block=8, fnum=0.75, n_seg=32, nx=16, nz=16, lr=0.003, w1=7.0,
                      kx1=0.001, kz1=0.02, w2=0.0, kx2=0.0, kz2=0.0, n_iter=200),
     medium="linear_bilayer", seed=31, scat_density=6.0, sim_spacing=0.25,

@@ -85,11 +85,12 @@ const char* af_last_error(const af_ctx* ctx);
  *   fnum      F of the apodisation |x'| <= (F/2) z' (Eq. 4, literal form).
  *   n_seg     ray segments after the lens (N_segments).
  * Caller order of points: p = q * patch^2 + m for pixel q, patch point m.
+ * Tiles whose points span more active blocks than the CMPE stage stages in LDS
+ * (15 at 3 x 3 patches) run that stage from device memory the context owns
+ * (about 0.7 MB per such tile at 16 blocks), at some cost in speed.
  * Errors: AF_ERR_ARG if n_elem < 3, block does not divide n_elem, patch is not
- * 1 or 3, sizes are not positive, the elements are out of order, the active
- * element set of a point is not contiguous, or a pixel spans more active blocks
- * than the CMPE stage holds in LDS (15 at 3 x 3 patches: the aperture is too
- * wide for the block size). */
+ * 1 or 3, sizes are not positive, the elements are out of order or the active
+ * element set of a point is not contiguous; AF_ERR_OOM. */
 af_status af_set_geometry(af_ctx* ctx, int n_elem, const double* elem_xz, int n_pix,
                     const double* pix_xz, int patch, double patch_spacing,
                     int n_samples, double fs, double t0, double fd, int block,
@@ -242,9 +243,8 @@ af_status af_set_dynamic_grid(af_ctx* ctx, double c_ref, double fc, double c_min
  * element ranges of Eq. 4, tile ranges), reads the tiles' ranges back (the stream
  * is synchronised) and rebuilds the work lists.  The slowness is not changed.
  * Errors: AF_ERR_STATE without a dynamic grid; AF_ERR_ARG for c_g outside
- * [c_min, c_max], a point whose active elements are not contiguous or a tile that
- * spans more active blocks than the CMPE stage holds (the context then needs
- * af_set_geometry again). */
+ * [c_min, c_max] or a point whose active elements are not contiguous (the context
+ * then needs af_set_geometry again); AF_ERR_OOM. */
 af_status af_set_sweep_speed(af_ctx* ctx, double c_g);
 
 /* Global-speed sweep of the model initialisation (Section II-C): for each of the n
@@ -378,7 +378,8 @@ enum {
   AF_Q_ACTIVE_SAMPLES = 5, /* sum over points of active (t, r) pairs */
   AF_Q_TILES = 6,
   AF_Q_NA_MAX = 7,       /* largest active element range of a tile */
-  AF_Q_NBA_MAX = 8       /* largest active block range of a tile */
+  AF_Q_NBA_MAX = 8,      /* largest active block range of a tile */
+  AF_Q_WIDE_TILES = 9    /* tiles whose CMPE stage runs from device memory */
 };
 af_status af_query(af_ctx* ctx, int what, long long* out);
 

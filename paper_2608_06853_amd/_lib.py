@@ -32,7 +32,7 @@ N_TERMS = 8
 LENS_BENT, LENS_CONVENTIONAL, LENS_NONE = 0, 1, 2
 LENS_MODES = {"bent": LENS_BENT, "conventional": LENS_CONVENTIONAL, "none": LENS_NONE}
 (Q_P, Q_P_INTERNAL, Q_NBLK, Q_GBLK_ELEMS, Q_ACTIVE_PAIRS, Q_ACTIVE_SAMPLES, Q_TILES, Q_NA_MAX,
- Q_NBA_MAX) = range(9)
+ Q_NBA_MAX, Q_WIDE_TILES) = range(10)
 
 EXPORTS = [
     "af_create", "af_destroy", "af_last_error", "af_set_geometry", "af_set_lens",

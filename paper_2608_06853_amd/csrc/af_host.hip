@@ -133,9 +133,9 @@ af_status upload(af_ctx* c, DBuf& b, const std::vector<T>& v, const char* what) 
 // From the active element range of every tile (c->tile_lo, c->tile_hi): the tile
 // descriptors (element and block ranges), the table work list (chunks of
 // TAB_CHUNK elements per tile), the DAS work list and the heaviest-first tile
-// order of the adjoints; uploads all four.  A tile spanning more active blocks
-// than the CMPE stage holds in LDS is rejected.
-af_status build_work_lists(af_ctx* c, const char* who) {
+// order of the adjoints, the slab offsets of the deterministic mode and the CMPE
+// stage's split into LDS and device-memory tiles; uploads them.
+af_status build_work_lists(af_ctx* c) {
   const int n_tiles = c->n_tiles, block = c->S;
   std::vector<int4> tiles(n_tiles);
   std::vector<int2> tabwork, daswork;
@@ -155,9 +155,26 @@ af_status build_work_lists(af_ctx* c, const char* who) {
     for (int a0 = LO; a0 <= HI; a0 += af::TAB_CHUNK) tabwork.push_back(make_int2(t, a0));
     load.push_back({(long long)(HI - LO + 1) * (HI - LO + 1), t});
   }
-  if (c->nba_max > af::cmpe_span_limit(c->pps))
-    return fail(c, AF_ERR_ARG, std::string(who) +
-                                   ": a tile spans more active blocks than the CMPE stage holds");
+  // CMPE stage: tiles wider than its LDS staging holds take the device-memory path
+  {
+    const int lim = af::cmpe_span_limit(c->pps);
+    std::vector<int> wide(std::max(n_tiles, 1), -1);
+    c->nba_lds = 1;
+    c->n_wide = 0;
+    for (int t = 0; t < n_tiles; ++t) {
+      const int4 tr = tiles[t];
+      if (tr.x > tr.y) continue;
+      const int nb = tr.w - tr.z + 1;
+      if (nb > lim) wide[t] = c->n_wide++;
+      else c->nba_lds = std::max(c->nba_lds, nb);
+    }
+    c->wstride = af::cmpe_wide_stride(c->nba_max, c->pps);
+    af_status st = upload(c, c->d_wide, wide, "wide tiles");
+    if (st != AF_OK) return st;
+    if (c->n_wide > 0)
+      AF_ALLOC(c->d_cmpe_wide, sizeof(float2) * 4 * (size_t)c->n_wide * c->wstride,
+               "CMPE staging of wide tiles");
+  }
   std::stable_sort(load.begin(), load.end(), [](auto& a, auto& b) { return a.first > b.first; });
   c->tile_order.clear();
   for (auto& l : load) c->tile_order.push_back(l.second);
@@ -449,8 +466,10 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
   // Pack the pixels, in k-d order, into sub-tiles of pps and tiles of 4 sub-tiles.
   // A tile is closed early (its remaining slots become padding) when the next
   // pixel would widen its span of active blocks beyond what the CMPE kernel
-  // stages in LDS; with compact images this never happens and the packing
-  // follows the k-d units exactly.  slot[k] = tile * ppt + sub-tile * pps + s.
+  // stages in LDS, or beyond the pixel's own span where that is wider (such a
+  // tile takes the CMPE stage's device-memory path); with compact images this
+  // never happens and the packing follows the k-d units exactly.
+  // slot[k] = tile * ppt + sub-tile * pps + s.
   const int span_max = af::cmpe_span_limit(pps);
   std::vector<long long> slot(n_pix);
   int n_tiles = 0;
@@ -475,13 +494,11 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
     for (int k = 0; k < n_pix; ++k) {
       const int q = ord[k];
       const int plo = pspan[q].x, phi = pspan[q].y;
-      if (plo <= phi && phi - plo + 1 > span_max)
-        return fail(c, AF_ERR_ARG, "af_set_geometry: a pixel spans more active blocks than the CMPE stage holds (aperture too wide for the block size)");
       bool new_tile = t < 0;
       if (!new_tile && plo <= phi) {
         const int nlo = bhi < blo ? plo : std::min(blo, plo);
         const int nhi = bhi < blo ? phi : std::max(bhi, phi);
-        new_tile = nhi - nlo + 1 > span_max;
+        new_tile = nhi - nlo + 1 > std::max(span_max, phi - plo + 1);
       }
       if (!new_tile && sidx == pps) {  // current sub-tile full: next sub-tile or tile
         if (w == 3) new_tile = true;
@@ -575,7 +592,7 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
     }
   }
   af_status st;
-  if ((st = build_work_lists(c, "af_set_geometry")) != AF_OK) return st;
+  if ((st = build_work_lists(c)) != AF_OK) return st;
   // element frames (position and the orientation of Eq. 3) for the dynamic grid
   c->elem_frame.resize(N);
   for (int a = 0; a < N; ++a)
@@ -850,7 +867,7 @@ af_status move_points(af_ctx* c, double c_g, const char* who) {
     c->active_pairs += ts[t].pairs;
     c->active_samples += ts[t].samples;
   }
-  af_status st = build_work_lists(c, who);
+  af_status st = build_work_lists(c);
   if (st != AF_OK) return st;
   c->spacing = c_g / (2.0 * c->dyn_fc);
   c->dyn_c = c_g;
@@ -1245,6 +1262,7 @@ af_status af_query(af_ctx* c, int what, long long* out) {
     case AF_Q_TILES: *out = c->n_tiles; break;
     case AF_Q_NA_MAX: *out = c->na_max; break;
     case AF_Q_NBA_MAX: *out = c->nba_max; break;
+    case AF_Q_WIDE_TILES: *out = c->n_wide; break;
     default: return fail(c, AF_ERR_ARG, "af_query: unknown item");
   }
   return AF_OK;

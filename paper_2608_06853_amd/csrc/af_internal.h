@@ -98,6 +98,13 @@ struct CmpeArgs {
   float rho_thresh;
   float sb_scale;         // -2 w_sb / (sb_ref n_pix)
   int write_g;
+  // Tiles whose span of active blocks is too wide for LDS keep their subaperture
+  // images and pair entries in device memory instead: wide[tile] is the tile's
+  // index among them (-1: the LDS path), each of its 4 sub-tiles owns wstride
+  // float2 of wscr.
+  const int* wide;
+  float2* wscr;
+  long long wstride;
 };
 
 // Per-tile result of the dynamic-grid point update: active element range, whether
@@ -148,6 +155,9 @@ struct af_ctx {
   std::vector<int> prange_lo, prange_hi;    // per internal point
   std::vector<int> tile_lo, tile_hi;
   int na_max = 0, nba_max = 0;
+  int nba_lds = 0;     // widest span among the tiles on the LDS path of the CMPE stage
+  int n_wide = 0;      // tiles on its device-memory path
+  long long wstride = 0;
   long long active_pairs = 0, active_samples = 0;
   std::vector<double4> elem_frame;          // element (x, z, cos, sin) of the orientation of Eq. 3
   std::vector<double> pix_xz;               // caller pixel centres of af_set_geometry [n_pix][2]
@@ -186,6 +196,7 @@ struct af_ctx {
   // one slab [element e - LO][TILE] of sums over the receive elements of jb; the
   // slabs of a tile follow in jb order from d_tbase[tile].
   af::DBuf d_gtp, d_tbase;
+  af::DBuf d_wide, d_cmpe_wide;  // CMPE stage of wide tiles (CmpeArgs::wide, wscr)
   long long n_gtp = 0;
   bool det = false;  // deterministic mode (af_set_deterministic)
 
@@ -221,6 +232,7 @@ hipError_t launch_prepare_grid(af_ctx* c, const float* s, int nx, int nz, float*
 hipError_t launch_table(af_ctx* c);
 hipError_t launch_das_fwd(af_ctx* c, const float2* iq, float2* bblk);
 int cmpe_span_limit(int pps);  // largest tile span in blocks whose CMPE stage fits in LDS
+long long cmpe_wide_stride(int nba, int pps);  // float2 per sub-tile of a wide tile
 hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g, float rho,
                        float sb_scale, float* map_cmpe, float* map_cf, float* map_cmcc,
                        float2* img);

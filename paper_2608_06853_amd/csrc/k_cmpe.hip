@@ -11,7 +11,10 @@
 //
 // Four wavefronts own one sub-tile of 64 points (whole patches plus padding) and
 // stage its subaperture images in LDS.  Partial sums go to a per-sub-tile slot
-// and are reduced in fixed order afterwards (deterministic).
+// and are reduced in fixed order afterwards (deterministic).  A tile whose span
+// of active blocks is too wide for LDS (deep points of a linear array see every
+// block) runs the same code in a second launch with the staging area in device
+// memory.
 #include "af_internal.h"
 
 namespace af {
@@ -36,7 +39,9 @@ constexpr int SS = SUB + 1;
 // use, in LDS.  Phase 2 evaluates the (pixel, pair) entries; phase 3 writes the
 // gradient of every active block image as the sum of dL/dS over the four
 // subapertures that contain it.  The block images are read only in phase 1, so
-// the gradient may overwrite them in place.
+// the gradient may overwrite them in place.  WIDE: only the tiles of the
+// device-memory path, whose staging area is their slice of A.wscr.
+template <bool WIDE>
 __global__ __launch_bounds__(256) void k_cmpe(CmpeArgs A) {
   extern __shared__ float2 sm[];
   __shared__ float pimg[CMPE_WAVES][3][SUB];
@@ -48,11 +53,13 @@ __global__ __launch_bounds__(256) void k_cmpe(CmpeArgs A) {
   const long long tile = p0 / TILE;
   const int w = (int)((p0 % TILE) / SUB);
   const int4 tr = A.tiles[tile];
+  const int wix = A.wide[tile];
+  if ((wix >= 0) != WIDE) return;  // the other launch owns this sub-tile
   const int M = g.patch2, pps = g.pps;
   const long long P = g.P;
   const long long slot0 = tile * (4 * pps) + (long long)w * pps;
 
-  if (tr.x > tr.y) {
+  if (tr.x > tr.y) {  // (a tile without work is never wide)
     if (tid < SUB) {
       A.gsb[p0 + tid] = make_float2(0.f, 0.f);
       if (A.img) A.img[p0 + tid] = make_float2(0.f, 0.f);
@@ -77,7 +84,7 @@ __global__ __launch_bounds__(256) void k_cmpe(CmpeArgs A) {
   const int npr = max(0, pHi - pLo + 1);
   const int np2 = npr * npr;
   const int nS = npr > 0 ? npr + 1 : 0;
-  float2* Ss = sm;                                   // [nS * nS][SS]
+  float2* Ss = WIDE ? A.wscr + (long long)(wix * 4 + w) * A.wstride : sm;  // [nS * nS][SS]
   float2* gC = Ss + (size_t)nS * nS * SS;            // [pps][np2]
   float* er = reinterpret_cast<float*>(gC + (size_t)pps * np2);
   float* rh = er + (size_t)pps * np2;                // rho of each entry, -1 if no energy
@@ -303,6 +310,12 @@ __global__ __launch_bounds__(256) void k_export_img(Geo g, const float2* __restr
 
 }  // namespace
 
+long long cmpe_wide_stride(int nba, int pps) {
+  // the dynamic LDS layout of k_cmpe for a span of nba blocks, in float2: the
+  // subaperture images, then pps * nba^2 pair entries of one float2 and two floats
+  return (long long)(nba + 1) * (nba + 1) * SS + 2LL * pps * nba * nba;
+}
+
 int cmpe_span_limit(int pps) {
   // dynamic LDS of k_cmpe for a tile spanning n blocks: (n + 1)^2 subaperture
   // images of SUB points (row stride SS) plus pps * n^2 pair entries; the static
@@ -334,13 +347,16 @@ hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g,
   A.rho_thresh = rho;
   A.sb_scale = sb_scale;
   A.write_g = write_g;
-  const int nba = c->nba_max;
-  const int npr = nba;      // upper bound of pair rows (and columns)
-  const int nS = nba + 1;   // upper bound of subaperture rows
-  const size_t lds = sizeof(float2) * (size_t)nS * nS * SS +
-                     (sizeof(float2) + 2 * sizeof(float)) * (size_t)c->pps * npr * npr;
-  hipLaunchKernelGGL(k_cmpe, dim3((unsigned)(c->P_int / SUB)), dim3(CMPE_WAVES * SUB), lds,
-                     c->stream, A);
+  A.wide = c->d_wide.as<int>();
+  A.wscr = c->d_cmpe_wide.as<float2>();
+  A.wstride = c->wstride;
+  const int nba = c->nba_lds;  // widest span of the LDS path
+  const size_t lds = sizeof(float2) * (size_t)cmpe_wide_stride(nba, c->pps);
+  const dim3 grid((unsigned)(c->P_int / SUB)), block(CMPE_WAVES * SUB);
+  hipLaunchKernelGGL(k_cmpe<false>, grid, block, lds, c->stream, A);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || c->n_wide == 0) return e;
+  hipLaunchKernelGGL(k_cmpe<true>, grid, block, 0, c->stream, A);
   return hipGetLastError();
 }
 

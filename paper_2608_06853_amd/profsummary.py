@@ -22,7 +22,7 @@ FAMILIES = {
     "loc": (r"k_loc\(", "k_das.hip"),
     "cmpe": (r"k_cmpe\(", "k_cmpe.hip"),
     "gscale": (r"k_gscale\(", "k_misc.hip"),
-    "path_adj": (r"k_path_adj\(", "k_path.hip"),
+    "path_adj": (r"k_path_adj[<(]", "k_path.hip"),
     "path_chunk": (r"k_path_chunk\(", "k_path.hip"),
     "path_reduce": (r"k_path_reduce\(", "k_path.hip"),
     "prepare_grid": (r"k_prepare_grid\(", "k_misc.hip"),

@@ -39,6 +39,18 @@ C1_SMALL = afsynth.configs.C1.with_(
 
 MICRO = afsynth.configs.MICRO
 
+# A linear array whose deeper pixels see more than 15 of its 24 blocks (48
+# elements in blocks of 2): their tiles run the CMPE stage from device memory,
+# the shallow ones from LDS.  12 x 8 pixels from 4 to 24 mm.
+_ML = afsynth.configs.MICRO_LINEAR
+WIDE_LINEAR = _ML.with_(
+    name="wide_linear",
+    array=replace(_ML.array, n_elem=48),
+    acq=replace(_ML.acq, n_samples=1024),
+    img=afsynth.ImgCfg(n_depth=12, n_angle=8, depth_min=4.0, depth_max=24.0),
+    method=replace(_ML.method, block=2),
+)
+
 
 @functools.lru_cache(maxsize=8)
 def case(name: str, t0: float = 0.0, t_ttp: float = 0.0, patch: int = 3, block: int | None = None,
@@ -50,7 +62,8 @@ def case(name: str, t0: float = 0.0, t_ttp: float = 0.0, patch: int = 3, block: 
     straight-ray models of the beamformer (the channel data still come from the
     physical lens); n_search >= 2 the discrete refraction search; grid_nx and
     grid_nz replace the slowness grid's size; rho is the CMPE threshold."""
-    base = {"micro": MICRO, "c1_small": C1_SMALL, "micro_linear": afsynth.configs.MICRO_LINEAR}[name]
+    base = {"micro": MICRO, "c1_small": C1_SMALL, "micro_linear": afsynth.configs.MICRO_LINEAR,
+            "wide_linear": WIDE_LINEAR}[name]
     arr = replace(base.array, t_ttp=t_ttp)
     if d_lens is not None:
         arr = replace(arr, d_lens=d_lens)

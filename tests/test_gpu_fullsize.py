@@ -8,12 +8,14 @@ compared with the FP64 oracle computed for those pixels alone:
 * travel times of every element to every point of 40 random pixels (1e-6);
 * block images and the coherence-factor map at those pixels (1e-4);
 * loss and gradient of a context holding only the sampled pixels (same array,
-  channel data and grid) against the oracle (1e-4 / 1e-3);
+  channel data and grid) against the oracle (1e-4 / 1e-3), the loss on the noise
+  data and on coherent echoes the oracle simulates, the gradient on the echoes;
 * at full size, the gradient along a smooth direction against a central
   difference of the library's own loss (a property that holds at any size).
 
 The channel data of the oracle comparisons are seeded circular Gaussian noise
-(afsynth.random_iq): oracle inputs never come from the library.  The directional
+(afsynth.random_iq) or echoes of seeded scatterers simulated by the oracle:
+oracle inputs never come from the library.  The directional
 check compares the library with itself and runs on echoes the library simulates
 through the seeded medium."""
 import os
@@ -105,13 +107,29 @@ def test_block_images_sampled(full):
     assert e_blk < 1e-4 and e_cf < 1e-4 and e_cc < 1e-4
 
 
-def test_loss_and_gradient_sampled_pixels(full):
+N_SCAT_COHERENT = 600
+
+
+@pytest.fixture(scope="module")
+def coherent(full):
+    """Channel data the oracle simulates (64 ray segments) from the configuration's
+    medium with 600 seeded point scatterers: coherent echoes, computed on the host."""
+    cfg = full[0]
+    c = cfg.with_(n_scat_random=N_SCAT_COHERENT)
+    return problems.simulate_iq_parallel(c, afsynth.medium_for(c), 64)
+
+
+def _sampled_loss_and_grad(full, iq):
+    """Library and oracle loss terms and gradient of a context holding only the
+    sampled pixels, on channel data ``iq`` [N][N][Ns]; asserts the terms."""
     import torch
     from dataclasses import replace
     from paper_2608_06853_amd import autofocus as af
-    cfg, bf, iq_d, s, sel, sub, acqd, imgd, grid = full
+    cfg, bf, _, s, sel, sub, acqd, imgd, grid = full
     lp = _lp(cfg)
+    sub = model.Problem(**{**sub.__dict__, "_cache": {}, "iq": iq.astype(np.complex128)})
     bs = af.Beamformer(acqd, replace(imgd, centres=imgd.centres[sel]), grid)
+    iq_d = torch.from_numpy(np.ascontiguousarray(iq, dtype=np.complex64)).cuda().reshape(-1)
     terms, grad = bs.loss_and_grad(iq_d, G.lib_params(lp), torch.from_numpy(s).cuda())
     t = terms.cpu().numpy()
     fo, go = model.loss_and_grad(sub, s.astype(np.float64), lp)
@@ -127,8 +145,26 @@ def test_loss_and_gradient_sampled_pixels(full):
     dn = abs(t[5] - fo["n_valid"])
     assert dn <= n_near
     assert abs(t[4] - fo["total"]) <= 1e-4 * abs(fo["total"]) + np.pi * dn / fo["n_valid"]
-    eg = G.rel(grad.cpu().numpy(), go)
-    print(cfg.name, "sampled-pixel grad rel err", eg, "valid-count difference", dn, flush=True)
+    return grad.cpu().numpy(), go, dn
+
+
+def test_loss_sampled_pixels_noise(full):
+    """Loss terms on the seeded noise data."""
+    cfg = full[0]
+    iq = afsynth.random_iq(cfg.array.n_elem, cfg.acq.n_samples, seed=cfg.seed)
+    _sampled_loss_and_grad(full, iq)
+
+
+def test_loss_and_gradient_sampled_pixels(full, coherent):
+    """Loss terms and gradient on coherent echoes.  (On noise data the gradient at
+    deep points of the linear array is a sum of terms of random sign that cancel to
+    about 1e-4 of their magnitude, so FP32 rounding alone moves it by about 1e-3;
+    the terms above are compared on noise data as well.)"""
+    cfg = full[0]
+    g, go, dn = _sampled_loss_and_grad(full, coherent)
+    eg = G.rel(g, go)
+    print(cfg.name, "sampled-pixel grad rel err (coherent echoes)", eg, "valid-count difference",
+          dn, flush=True)
     assert eg < 1e-3
 
 

@@ -21,8 +21,9 @@ pytestmark = pytest.mark.gpu
 # curvilinear case with timing offsets, a grid wider than 64 nodes; the
 # conventional model of Eq. 6 (curvilinear and linear) and the model without lens
 # correction, both beamforming data of the physical lens; the configured CMPE
-# threshold 0.9; and a tall, narrow grid (4 x 700 nodes) whose fixed-stride copy
-# would not fit in LDS.
+# threshold 0.9; a tall, narrow grid (4 x 700 nodes) whose fixed-stride copy
+# would not fit in LDS; and a linear array whose deep pixels span up to 24 blocks
+# (more than the CMPE stage stages in LDS: those tiles run it from device memory).
 CASES = [("micro", 0.0, 0.0, 3, None), ("c1_small", 0.0, 0.0, 3, None),
          ("micro", 0.7, 0.35, 3, None), ("micro", 0.0, 0.0, 1, 2),
          ("micro", 0.0, 0.0, 3, None, 0.01, 0.0), ("micro", 0.0, 0.5, 3, None, 0.01, 0.0),
@@ -37,7 +38,8 @@ CASES = [("micro", 0.0, 0.0, 3, None), ("c1_small", 0.0, 0.0, 3, None),
          ("micro", 0.0, 0.0, 3, None, 0.01, None, 0, None, "none"),
          ("micro", 0.0, 0.0, 3, None, 0.01, None, 0, None, "bent", 0.9),
          ("c1_small", 0.0, 0.0, 3, None, 0.01, None, 0, None, "bent", 0.9),
-         ("micro", 0.0, 0.0, 3, None, 0.01, None, 0, 4, "bent", 0.5, 700)]
+         ("micro", 0.0, 0.0, 3, None, 0.01, None, 0, 4, "bent", 0.5, 700),
+         ("wide_linear", 0.0, 0.0, 3, None)]
 IDS = ["-".join(str(v) for v in k) for k in CASES]
 
 
@@ -54,6 +56,18 @@ def _setup(key):
     s_d = torch.from_numpy(s).cuda()
     bf.set_slowness(s_d)
     return cfg, prob, iq, s, lp, bf, iq_d, s_d
+
+
+def test_wide_case_uses_device_memory_cmpe():
+    """The wide linear case really spans more blocks than the LDS staging holds, and
+    only some of its tiles take the device-memory path."""
+    from paper_2608_06853_amd import _lib
+    cfg, prob, iq, s, lp, bf, iq_d, s_d = _setup(("wide_linear", 0.0, 0.0, 3, None))
+    n_wide = bf.ctx.query(_lib.Q_WIDE_TILES)
+    print("wide tiles", n_wide, "of", bf.ctx.query(_lib.Q_TILES), "largest span",
+          bf.ctx.query(_lib.Q_NBA_MAX), flush=True)
+    assert bf.ctx.query(_lib.Q_NBA_MAX) > 15
+    assert 0 < n_wide < bf.ctx.query(_lib.Q_TILES)
 
 
 @pytest.mark.parametrize("key", CASES, ids=IDS)
