@@ -27,6 +27,8 @@
 #ifndef AF_H_
 #define AF_H_
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -143,6 +145,22 @@ af_status af_set_refraction_search(af_ctx* ctx, int n_search);
  * for bit on every run, at a few percent more time.  Applies from the next call
  * on.  Errors: AF_ERR_ARG for other values, AF_ERR_OOM. */
 af_status af_set_deterministic(af_ctx* ctx, int on);
+
+/* Bounded-memory mode (recomputation instead of storage).  bytes = 0 (the
+ * default): the travel-time table of every (element, point), its rays and the
+ * block images of every point are held at once (for the clinical workload about
+ * 2.3 GB, for the 192-element, 512 x 512 pixel one about 27 GB).  bytes > 0: the
+ * points are processed in chunks of whole tiles whose table, rays, block images
+ * and time gradient fit in about `bytes` of device memory (at least one tile per
+ * chunk); af_loss_and_grad and af_autofocus_step then evaluate the loss over all
+ * chunks first and, in the gradient pass, recompute each chunk's table and block
+ * images instead of keeping them (about 1.5 times the work of the unbounded
+ * call); af_beamform, af_travel_times and af_sweep run chunk by chunk.
+ * af_forward, af_backward, af_channel_images and af_lag_one_coherence hand data
+ * of every point across the boundary and return AF_ERR_STATE under a budget.
+ * Takes effect at once (the chunk buffers are freed and sized again) or at
+ * af_set_geometry.  Errors: AF_ERR_OOM, AF_ERR_HIP. */
+af_status af_set_memory_budget(af_ctx* ctx, size_t bytes);
 
 /* Slowness grid s ~ 1/c (Section III-A): node (i, j) at (x0 + j dx, z0 + i dz),
  * values [nz][nx] float32 at `s_dev` (device), copied on the context stream.
@@ -379,7 +397,9 @@ enum {
   AF_Q_TILES = 6,
   AF_Q_NA_MAX = 7,       /* largest active element range of a tile */
   AF_Q_NBA_MAX = 8,      /* largest active block range of a tile */
-  AF_Q_WIDE_TILES = 9    /* tiles whose CMPE stage runs from device memory */
+  AF_Q_WIDE_TILES = 9,   /* tiles whose CMPE stage runs from device memory */
+  AF_Q_CHUNKS = 10,      /* chunks of tiles the hot path runs over (1 without a budget) */
+  AF_Q_DEVICE_BYTES = 11 /* device memory the context holds */
 };
 af_status af_query(af_ctx* ctx, int what, long long* out);
 

@@ -32,11 +32,11 @@ N_TERMS = 8
 LENS_BENT, LENS_CONVENTIONAL, LENS_NONE = 0, 1, 2
 LENS_MODES = {"bent": LENS_BENT, "conventional": LENS_CONVENTIONAL, "none": LENS_NONE}
 (Q_P, Q_P_INTERNAL, Q_NBLK, Q_GBLK_ELEMS, Q_ACTIVE_PAIRS, Q_ACTIVE_SAMPLES, Q_TILES, Q_NA_MAX,
- Q_NBA_MAX, Q_WIDE_TILES) = range(10)
+ Q_NBA_MAX, Q_WIDE_TILES, Q_CHUNKS, Q_DEVICE_BYTES) = range(12)
 
 EXPORTS = [
     "af_create", "af_destroy", "af_last_error", "af_set_geometry", "af_set_lens",
-    "af_set_refraction_search", "af_set_deterministic", "af_set_slowness", "af_beamform", "af_loss_and_grad", "af_forward", "af_backward",
+    "af_set_refraction_search", "af_set_deterministic", "af_set_memory_budget", "af_set_slowness", "af_beamform", "af_loss_and_grad", "af_forward", "af_backward",
     "af_autofocus_step", "af_travel_times", "af_set_dynamic_grid", "af_set_sweep_speed",
     "af_sweep", "af_simulate", "af_query", "af_set_profiling",
     "af_profile_read", "af_conv3x3_pack", "af_conv3x3_fwd", "af_conv3x3_bwd_data",
@@ -68,6 +68,7 @@ _sig = {
     "af_set_lens": (C.c_int, [_vp, _d, _d, _d, _i, _d]),
     "af_set_refraction_search": (C.c_int, [_vp, _i]),
     "af_set_deterministic": (C.c_int, [_vp, _i]),
+    "af_set_memory_budget": (C.c_int, [_vp, C.c_size_t]),
     "af_set_slowness": (C.c_int, [_vp, _i, _i, _d, _d, _d, _d, _vp]),
     "af_beamform": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "af_channel_images": (C.c_int, [_vp, _vp, _vp]),
@@ -194,6 +195,9 @@ class Context:
 
     def set_deterministic(self, on: bool):
         self._chk(_lib.af_set_deterministic(self._h, 1 if on else 0))
+
+    def set_memory_budget(self, nbytes: int):
+        self._chk(_lib.af_set_memory_budget(self._h, int(nbytes)))
 
     def set_slowness(self, nx, nz, x0, z0, dx, dz, s):
         import torch

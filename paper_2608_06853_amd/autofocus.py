@@ -76,16 +76,19 @@ class Beamformer:
     """Library context bound to one acquisition, evaluation grid and slowness grid."""
 
     def __init__(self, acq: Acquisition, img: Imaging, grid: Grid, device: int = 0,
-                 n_search: int = 0, deterministic: bool = False):
+                 n_search: int = 0, deterministic: bool = False, memory_budget: int = 0):
         """``n_search`` = 0 refracts at the exact Fermat root, >= 2 by the discrete
         search over that many lens points; ``deterministic`` fixes the reduction
-        order of the gradient (bit-for-bit repeatable, a few percent slower)."""
+        order of the gradient (bit-for-bit repeatable, a few percent slower);
+        ``memory_budget`` > 0 bounds the device memory of the per-point buffers
+        (bytes) by recomputing the travel times in the gradient pass."""
         self.acq, self.grid = acq, grid
         self.device = torch.device("cuda", device)
         self.ctx = _lib.Context(device)
         self.ctx.set_lens(acq.d_lens, acq.c_lens, acq.t_ttp, acq.lens_mode, acq.c_ref)
         self.ctx.set_refraction_search(n_search)
         self.ctx.set_deterministic(deterministic)
+        self.ctx.set_memory_budget(memory_budget)
         self.img = None
         self.set_imaging(img)
         self.s = None
@@ -183,15 +186,24 @@ class CmpeLoss(torch.autograd.Function):
     """total = L_CMPE + w1 R_TV + w2 R_SV - w_sb SB/SB_ref as a function of the slowness.
 
     forward keeps only dL/dB^blk (no travel-time table); backward recomputes the
-    table at the same slowness and runs the DAS and path adjoints."""
+    table at the same slowness and runs the DAS and path adjoints.  Under a memory
+    budget the library's chunked call forms the gradient in the forward (it
+    recomputes each chunk's table there) and only the gradient grid is kept."""
 
     @staticmethod
     def forward(ctx, s, bf: Beamformer, iq, lp):
         bf.set_slowness(s)
         terms = bf.empty_terms()
-        gblk = torch.empty(bf.ctx.query(_lib.Q_GBLK_ELEMS), device=bf.device, dtype=torch.complex64)
-        bf.ctx.forward(iq, lp, terms, gblk)
-        ctx.bf, ctx.iq, ctx.lp, ctx.gblk = bf, iq, lp, gblk
+        ctx.bf, ctx.iq, ctx.lp = bf, iq, lp
+        if bf.ctx.query(_lib.Q_CHUNKS) > 1:
+            grad = torch.empty(bf.grid.shape, device=bf.device)
+            bf.ctx.loss_and_grad(iq, lp, terms, grad)
+            ctx.grad, ctx.gblk = grad, None
+        else:
+            gblk = torch.empty(bf.ctx.query(_lib.Q_GBLK_ELEMS), device=bf.device,
+                               dtype=torch.complex64)
+            bf.ctx.forward(iq, lp, terms, gblk)
+            ctx.grad, ctx.gblk = None, gblk
         ctx.save_for_backward(s)
         ctx.mark_non_differentiable(terms)
         return terms[_lib.TERM_TOTAL].clone(), terms
@@ -200,9 +212,11 @@ class CmpeLoss(torch.autograd.Function):
     def backward(ctx, g_total, g_terms):
         (s,) = ctx.saved_tensors
         bf = ctx.bf
-        bf.set_slowness(s)
-        grad = torch.empty(bf.grid.shape, device=bf.device)
-        bf.ctx.backward(ctx.iq, ctx.lp, ctx.gblk, grad)
+        grad = ctx.grad
+        if grad is None:
+            bf.set_slowness(s)
+            grad = torch.empty(bf.grid.shape, device=bf.device)
+            bf.ctx.backward(ctx.iq, ctx.lp, ctx.gblk, grad)
         return (g_total * grad).view_as(s), None, None, None
 
 

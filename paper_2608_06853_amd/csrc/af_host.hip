@@ -130,16 +130,23 @@ af_status upload(af_ctx* c, DBuf& b, const std::vector<T>& v, const char* what) 
   return AF_OK;
 }
 
+// Device bytes of the chunk-sized buffers per point: table entry, ray start and
+// medium leg, the two dL/dT roles per element, and the block images.
+size_t bytes_per_point(const af_ctx* c) {
+  return (size_t)c->N * (sizeof(af::TabEntry) + sizeof(float2) + 3 * sizeof(float)) +
+         (size_t)c->nb * c->nb * sizeof(float2);
+}
+
 // From the active element range of every tile (c->tile_lo, c->tile_hi): the tile
-// descriptors (element and block ranges), the table work list (chunks of
-// TAB_CHUNK elements per tile), the DAS work list and the heaviest-first tile
-// order of the adjoints, the slab offsets of the deterministic mode and the CMPE
-// stage's split into LDS and device-memory tiles; uploads them.
+// descriptors (element and block ranges); the chunks of consecutive tiles (one
+// chunk unless a memory budget is set); for every chunk, with chunk-local tile
+// indices, the table work list (TAB_CHUNK elements per tile), the DAS work list,
+// the heaviest-first tile order of the adjoints, the slab offsets of the
+// deterministic mode and the CMPE stage's split into LDS and device-memory tiles;
+// uploads them and sizes the chunk buffers.
 af_status build_work_lists(af_ctx* c) {
   const int n_tiles = c->n_tiles, block = c->S;
   std::vector<int4> tiles(n_tiles);
-  std::vector<int2> tabwork, daswork;
-  std::vector<std::pair<long long, int>> load;
   c->na_max = 1;
   c->nba_max = 1;
   for (int t = 0; t < n_tiles; ++t) {
@@ -152,80 +159,154 @@ af_status build_work_lists(af_ctx* c) {
     tiles[t] = make_int4(LO, HI, bLO, bHI);
     c->na_max = std::max(c->na_max, HI - LO + 1);
     c->nba_max = std::max(c->nba_max, bHI - bLO + 1);
-    for (int a0 = LO; a0 <= HI; a0 += af::TAB_CHUNK) tabwork.push_back(make_int2(t, a0));
-    load.push_back({(long long)(HI - LO + 1) * (HI - LO + 1), t});
   }
   // CMPE stage: tiles wider than its LDS staging holds take the device-memory path
+  const int lim = af::cmpe_span_limit(c->pps);
+  c->wstride = af::cmpe_wide_stride(c->nba_max, c->pps);
+  c->nba_lds = 1;
+  c->n_wide = 0;
+  std::vector<char> is_wide(std::max(n_tiles, 1), 0);
+  for (int t = 0; t < n_tiles; ++t) {
+    const int4 tr = tiles[t];
+    if (tr.x > tr.y) continue;
+    const int nb = tr.w - tr.z + 1;
+    if (nb > lim) {
+      is_wide[t] = 1;
+      ++c->n_wide;
+    } else {
+      c->nba_lds = std::max(c->nba_lds, nb);
+    }
+  }
+  auto slab_floats = [&](int t) {
+    const int4 tr = tiles[t];
+    return tr.x > tr.y ? 0LL : (long long)(tr.w - tr.z + 1) * (tr.y - tr.x + 1) * af::TILE;
+  };
+  // chunks: consecutive tiles while their buffers fit the budget (at least one tile)
+  c->chunks.clear();
   {
-    const int lim = af::cmpe_span_limit(c->pps);
-    std::vector<int> wide(std::max(n_tiles, 1), -1);
-    c->nba_lds = 1;
-    c->n_wide = 0;
+    const size_t per_tile = af::TILE * bytes_per_point(c);
+    const size_t wide_bytes = sizeof(float2) * 4 * (size_t)c->wstride;
+    af::Chunk ch;
+    size_t used = 0;
     for (int t = 0; t < n_tiles; ++t) {
+      const size_t need = per_tile + (is_wide[t] ? wide_bytes : 0) +
+                          (c->det ? sizeof(float) * (size_t)slab_floats(t) : 0);
+      if (c->mem_budget > 0 && ch.n_tiles > 0 && used + need > c->mem_budget) {
+        c->chunks.push_back(ch);
+        ch = af::Chunk();
+        ch.t0 = t;
+        used = 0;
+      }
+      ++ch.n_tiles;
+      used += need;
+    }
+    c->chunks.push_back(ch);  // (an empty chunk when there are no tiles)
+  }
+  std::vector<int2> tabwork, daswork;
+  std::vector<int> order, wide(std::max(n_tiles, 1), -1);
+  std::vector<long long> tbase(std::max(n_tiles, 1), 0);
+  c->P_chunk = 0;
+  c->wide_max = 0;
+  c->gtp_max = 0;
+  for (af::Chunk& ch : c->chunks) {
+    const int t0 = ch.t0, t1 = ch.t0 + ch.n_tiles;
+    c->P_chunk = std::max(c->P_chunk, (long long)ch.n_tiles * af::TILE);
+    ch.tab_off = (int)tabwork.size();
+    ch.das_off = (int)daswork.size();
+    ch.ord_off = (int)order.size();
+    std::vector<std::pair<long long, int>> load;
+    for (int t = t0; t < t1; ++t) {
       const int4 tr = tiles[t];
       if (tr.x > tr.y) continue;
-      const int nb = tr.w - tr.z + 1;
-      if (nb > lim) wide[t] = c->n_wide++;
-      else c->nba_lds = std::max(c->nba_lds, nb);
+      for (int a0 = tr.x; a0 <= tr.y; a0 += af::TAB_CHUNK) tabwork.push_back(make_int2(t - t0, a0));
+      load.push_back({(long long)(tr.y - tr.x + 1) * (tr.y - tr.x + 1), t - t0});
+      if (is_wide[t]) wide[t] = ch.n_wide++;
+      tbase[t] = ch.n_gtp;
+      ch.n_gtp += slab_floats(t);
     }
-    c->wstride = af::cmpe_wide_stride(c->nba_max, c->pps);
-    af_status st = upload(c, c->d_wide, wide, "wide tiles");
-    if (st != AF_OK) return st;
-    if (c->n_wide > 0)
-      AF_ALLOC(c->d_cmpe_wide, sizeof(float2) * 4 * (size_t)c->n_wide * c->wstride,
-               "CMPE staging of wide tiles");
-  }
-  std::stable_sort(load.begin(), load.end(), [](auto& a, auto& b) { return a.first > b.first; });
-  c->tile_order.clear();
-  for (auto& l : load) c->tile_order.push_back(l.second);
-  // DAS work items (tile, receive block).  Workgroups are dealt to the XCDs
-  // round-robin (workgroup b runs on XCD b % 8).  The tiles with work, in k-d
-  // (spatial) order, are cut into runs of 16 that are dealt to the XCDs in turn,
-  // and all receive blocks of a tile go to the same XCD, one after another: the
-  // table entries of a tile, which every one of its items reads, are then fetched
-  // into one XCD's L2 once, and the 16 neighbouring tiles of a run reuse their
-  // channel-data windows there.  Runs of 16 (rather than one long run per XCD)
-  // keep the eight queues close in length when the work per tile varies across
-  // the image.  Shorter queues are padded with empty items (tile -1).
-  {
+    std::stable_sort(load.begin(), load.end(), [](auto& a, auto& b) { return a.first > b.first; });
+    for (auto& l : load) order.push_back(l.second);
+    // DAS work items (tile, receive block).  Workgroups are dealt to the XCDs
+    // round-robin (workgroup b runs on XCD b % 8).  The tiles with work, in k-d
+    // (spatial) order, are cut into runs of 16 that are dealt to the XCDs in turn,
+    // and all receive blocks of a tile go to the same XCD, one after another: the
+    // table entries of a tile, which every one of its items reads, are then
+    // fetched into one XCD's L2 once, and the 16 neighbouring tiles of a run reuse
+    // their channel-data windows there.  Runs of 16 (rather than one long run per
+    // XCD) keep the eight queues close in length when the work per tile varies
+    // across the image.  Shorter queues are padded with empty items (tile -1).
     constexpr int NXCD = 8, RUN = 16;
     std::vector<std::vector<int2>> q(NXCD);
     int n_live = 0;
-    for (int t = 0; t < n_tiles; ++t) {
+    for (int t = t0; t < t1; ++t) {
       const int4 tr = tiles[t];
       if (tr.x > tr.y) continue;
       const int x = (n_live++ / RUN) % NXCD;
-      for (int jb = tr.z; jb <= tr.w; ++jb) q[x].push_back(make_int2(t, jb));
+      for (int jb = tr.z; jb <= tr.w; ++jb) q[x].push_back(make_int2(t - t0, jb));
     }
     size_t L = 0;
-    for (auto& v : q) L = std::max(L, v.size());
+    for (auto& w : q) L = std::max(L, w.size());
     for (size_t i = 0; i < L; ++i)
-      for (int x = 0; x < NXCD; ++x)
-        daswork.push_back(i < q[x].size() ? q[x][i] : make_int2(-1, 0));
+      for (int x = 0; x < NXCD; ++x) daswork.push_back(i < q[x].size() ? q[x][i] : make_int2(-1, 0));
+    ch.n_tab = (int)tabwork.size() - ch.tab_off;
+    ch.n_das = (int)daswork.size() - ch.das_off;
+    ch.n_ord = (int)order.size() - ch.ord_off;
+    c->wide_max = std::max(c->wide_max, ch.n_wide);
+    c->gtp_max = std::max(c->gtp_max, ch.n_gtp);
   }
-  // slabs of the transmit-role sums of the DAS adjoint (one per DAS work item)
-  std::vector<long long> tbase(std::max(n_tiles, 1), 0);
-  long long n_gtp = 0;
-  for (int t = 0; t < n_tiles; ++t) {
-    const int4 tr = tiles[t];
-    tbase[t] = n_gtp;
-    if (tr.x <= tr.y) n_gtp += (long long)(tr.w - tr.z + 1) * (tr.y - tr.x + 1) * af::TILE;
-  }
-  c->n_gtp = n_gtp;
-  c->n_tab_work = (int)tabwork.size();
-  c->n_das_work = (int)daswork.size();
-  c->n_order = (int)c->tile_order.size();
   af_status st;
-  if (c->det) AF_ALLOC(c->d_gtp, sizeof(float) * (size_t)std::max(n_gtp, 1LL), "transmit-role sums");
-  if ((st = upload(c, c->d_tbase, tbase, "slab offsets")) != AF_OK) return st;
   if ((st = upload(c, c->d_tiles, tiles, "tiles")) != AF_OK) return st;
   if ((st = upload(c, c->d_tabwork, tabwork, "work list")) != AF_OK) return st;
   if ((st = upload(c, c->d_daswork, daswork, "work list")) != AF_OK) return st;
-  if ((st = upload(c, c->d_order, c->tile_order, "tile order")) != AF_OK) return st;
+  if ((st = upload(c, c->d_order, order, "tile order")) != AF_OK) return st;
+  if ((st = upload(c, c->d_wide, wide, "wide tiles")) != AF_OK) return st;
+  if ((st = upload(c, c->d_tbase, tbase, "slab offsets")) != AF_OK) return st;
+  // the chunk-sized buffers
+  const size_t Pc = (size_t)std::max(c->P_chunk, 1LL), N = (size_t)c->N;
+  AF_ALLOC(c->d_tab, sizeof(af::TabEntry) * N * Pc, "travel-time table");
+  AF_ALLOC(c->d_ray_uv, sizeof(float2) * N * Pc, "ray starts");
+  AF_ALLOC(c->d_ray_l2, sizeof(float) * N * Pc, "ray medium legs");
+  AF_ALLOC(c->d_bblk, sizeof(float2) * (size_t)c->nb * c->nb * Pc, "block images");
+  AF_ALLOC(c->d_gT, sizeof(float) * 2 * N * Pc, "time gradient");
+  if (c->wide_max > 0)
+    AF_ALLOC(c->d_cmpe_wide, sizeof(float2) * 4 * (size_t)c->wide_max * c->wstride,
+             "CMPE staging of wide tiles");
+  if (c->det) AF_ALLOC(c->d_gtp, sizeof(float) * (size_t)std::max(c->gtp_max, 1LL), "transmit-role sums");
+  if (c->nx > 0)  // a slowness grid is set: its per-workgroup partial grids for one chunk
+    AF_ALLOC(c->d_gpart, sizeof(float) * (size_t)(c->nx + 3) * (c->nz + 3) * (Pc / af::TILE),
+             "partial gradients");
+  c->select(0);
   return AF_OK;
 }
 
 }  // namespace
+
+void af_ctx::select(int k) {
+  const af::Chunk& ch = chunks[k];
+  v.t0 = ch.t0;
+  v.n_tiles = ch.n_tiles;
+  v.p0 = (long long)ch.t0 * TILE;
+  v.P = (long long)ch.n_tiles * TILE;
+  v.tiles = d_tiles.as<int4>() + ch.t0;
+  v.prange = d_prange.as<int2>() + v.p0;
+  v.ptxy = d_ptxy.as<float2>() + v.p0;
+  v.ptpol = d_ptpol.as<double4>() + v.p0;
+  v.tabwork = d_tabwork.as<int2>() + ch.tab_off;
+  v.n_tab_work = ch.n_tab;
+  v.daswork = d_daswork.as<int2>() + ch.das_off;
+  v.n_das_work = ch.n_das;
+  v.order = d_order.as<int>() + ch.ord_off;
+  v.n_order = ch.n_ord;
+  v.wide = d_wide.as<int>() + ch.t0;
+  v.n_wide = ch.n_wide;
+  v.tbase = d_tbase.as<long long>() + ch.t0;
+  const size_t nm = (size_t)n_tiles * ppt;  // slots of one map
+  v.map_cmpe = d_maps.as<float>() + (size_t)ch.t0 * ppt;
+  v.map_cf = v.map_cmpe + nm;
+  v.map_cmcc = v.map_cmpe + 2 * nm;
+  v.part = d_part.as<double>() + (size_t)ch.t0 * 4 * (TILE / SUB);  // 4 per sub-tile
+  v.gsb = d_gsb.as<float2>() + v.p0;
+}
 
 af::Geo af_ctx::geo() const {
   af::Geo g{};
@@ -237,7 +318,7 @@ af::Geo af_ctx::geo() const {
   g.n_seg = n_seg;
   g.patch2 = M;
   g.pps = pps;
-  g.P = P_int;
+  g.P = v.P;  // the points of the current view
   g.fs = fs;
   g.fd = fd;
   g.t0 = t0;
@@ -592,7 +673,6 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
     }
   }
   af_status st;
-  if ((st = build_work_lists(c)) != AF_OK) return st;
   // element frames (position and the orientation of Eq. 3) for the dynamic grid
   c->elem_frame.resize(N);
   for (int a = 0; a < N; ++a)
@@ -606,14 +686,10 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
   if ((st = upload(c, c->d_c2i, c->c2i, "point map")) != AF_OK) return st;
   if ((st = upload(c, c->d_i2c, c->i2c, "point map")) != AF_OK) return st;
 
-  AF_ALLOC(c->d_tab, sizeof(af::TabEntry) * (size_t)N * P_int, "travel-time table");
-  AF_ALLOC(c->d_ray_uv, sizeof(float2) * (size_t)N * P_int, "ray starts");
-  AF_ALLOC(c->d_ray_l2, sizeof(float) * (size_t)N * P_int, "ray medium legs");
-  AF_ALLOC(c->d_bblk, sizeof(float2) * (size_t)c->nb * c->nb * P_int, "block images");
-  AF_ALLOC(c->d_gT, sizeof(float) * 2 * (size_t)N * P_int, "time gradient");
   AF_ALLOC(c->d_gsb, sizeof(float2) * (size_t)P_int, "brightness gradient");
   AF_ALLOC(c->d_part, sizeof(double) * 4 * (size_t)(P_int / SUB), "partials");
   AF_ALLOC(c->d_maps, sizeof(float) * 3 * (size_t)n_tiles * ppt, "maps");
+  if ((st = build_work_lists(c)) != AF_OK) return st;  // chunks and their buffers
   c->has_geom = true;
   return AF_OK;
 }
@@ -656,12 +732,26 @@ af_status af_set_refraction_search(af_ctx* c, int n_search) {
 af_status af_set_deterministic(af_ctx* c, int on) {
   if (!c) return AF_ERR_ARG;
   if (on != 0 && on != 1) return fail(c, AF_ERR_ARG, "af_set_deterministic: on must be 0 or 1");
-  if (on && c->n_gtp > 0) {
-    if (hipSetDevice(c->device) != hipSuccess) return fail(c, AF_ERR_HIP, "hipSetDevice");
-    AF_ALLOC(c->d_gtp, sizeof(float) * (size_t)c->n_gtp, "transmit-role sums");
-  }
   c->det = on != 0;
+  if (!c->has_geom) return AF_OK;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AF_ERR_HIP, "hipSetDevice");
+  // under a memory budget the slabs count towards it: the chunks are cut again
+  if (c->mem_budget > 0) return build_work_lists(c);
+  if (c->det) AF_ALLOC(c->d_gtp, sizeof(float) * (size_t)std::max(c->gtp_max, 1LL), "transmit-role sums");
   return AF_OK;
+}
+
+af_status af_set_memory_budget(af_ctx* c, size_t bytes) {
+  if (!c) return AF_ERR_ARG;
+  c->mem_budget = bytes;
+  if (!c->has_geom) return AF_OK;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AF_ERR_HIP, "hipSetDevice");
+  AF_HIP(hipStreamSynchronize(c->stream), "af_set_memory_budget");
+  // free the chunk-sized buffers so that a smaller chunk really holds less memory
+  for (af::DBuf* b : {&c->d_tab, &c->d_ray_uv, &c->d_ray_l2, &c->d_bblk, &c->d_gT, &c->d_gtp,
+                      &c->d_cmpe_wide, &c->d_gsum, &c->d_chan})
+    b->release();
+  return build_work_lists(c);
 }
 
 af_status af_set_slowness(af_ctx* c, int nx, int nz, double x0, double z0, double dx, double dz,
@@ -743,9 +833,10 @@ af_status af_set_slowness(af_ctx* c, int nx, int nz, double x0, double z0, doubl
   AF_ALLOC(c->d_grad, sizeof(float) * n, "gradient");
   AF_ALLOC(c->d_gdev, sizeof(float) * np, "deviation grid");
   AF_ALLOC(c->d_gpad, sizeof(float) * np, "padded gradient");
-  // one partial grid per tile that has work (at most every tile: the dynamic grid may
-  // give more tiles work than the layout of af_set_geometry)
-  AF_ALLOC(c->d_gpart, sizeof(float) * np * std::max(c->n_tiles, 1), "partial gradients");
+  // one partial grid per tile of a chunk that has work (at most every tile of the
+  // chunk: the dynamic grid may give more tiles work than the layout of
+  // af_set_geometry)
+  AF_ALLOC(c->d_gpart, sizeof(float) * np * std::max(c->P_chunk / TILE, 1LL), "partial gradients");
   AF_ALLOC(c->d_terms, sizeof(float) * 8, "terms");
   c->has_grid = false;  // until the new values have passed the check
   AF_HIP(hipMemcpyAsync(c->d_s.p, s_dev, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream),
@@ -769,45 +860,84 @@ af_status ready(af_ctx* c, const void* iq) {
   return AF_OK;
 }
 
-// grid prep (c_med, deviation grid, regulariser) + travel-time table
-af_status run_tables(af_ctx* c, const af_loss_params* lp) {
+// grid prep: c_med, the deviation grid, the regulariser (with lp)
+af_status run_prepare(af_ctx* c, const af_loss_params* lp) {
   AF_KERNEL(AF_K_PREPARE,
             af::launch_prepare_grid(c, c->d_s.as<float>(), c->nx, c->nz, c->d_gdev.as<float>(),
                                     c->d_scal.as<double>(), lp ? 1 : 0, lp, c->d_regg.as<float>()),
             "prepare_grid");
-  AF_KERNEL(AF_K_TABLE, af::launch_table(c), "table");
   return AF_OK;
 }
 
-// forward: tables, DAS, CMPE (+G), terms; G goes to `gout` (or in place into the block images)
-// write_g: form dL/dB^blk; scale_now: apply its final scale (1/n_valid and the
-// speckle term) here, for a caller that receives it, instead of in the adjoint.
-af_status run_forward(af_ctx* c, const af_complex* iq, const af_loss_params* lp, float* terms,
-                      float2* gout, bool write_g, bool scale_now) {
-  af_status st = run_tables(c, lp);
-  if (st != AF_OK) return st;
-  const float2* iqf = reinterpret_cast<const float2*>(iq);
-  AF_KERNEL(AF_K_DAS_FWD, af::launch_das_fwd(c, iqf, c->d_bblk.as<float2>()), "das_fwd");
+// Table, block images and CMPE stage of the current view; with write_g the
+// unscaled dL/dB^blk goes to gout (or in place into the block images).
+af_status run_view_forward(af_ctx* c, const float2* iq, const af_loss_params* lp, bool write_g,
+                           float2* gout) {
+  AF_KERNEL(AF_K_TABLE, af::launch_table(c), "table");
+  AF_KERNEL(AF_K_DAS_FWD, af::launch_das_fwd(c, iq, c->d_bblk.as<float2>()), "das_fwd");
   const float sb_scale = (float)(-2.0 * lp->w_sb / ((double)lp->sb_ref * c->n_pix));
   float2* g = gout ? gout : c->d_bblk.as<float2>();
   AF_KERNEL(AF_K_CMPE,
             af::launch_cmpe(c, c->d_bblk.as<float2>(), g, write_g ? 1 : 0, lp->rho_thresh,
-                            sb_scale, c->d_maps.as<float>(),
-                            c->d_maps.as<float>() + c->n_tiles * c->ppt,
-                            c->d_maps.as<float>() + 2 * (size_t)c->n_tiles * c->ppt, nullptr),
+                            sb_scale, c->v.map_cmpe, c->v.map_cf, c->v.map_cmcc, nullptr),
             "cmpe");
-  AF_KERNEL(AF_K_FINALIZE, af::launch_finalize(c, lp, terms), "finalize");
-  if (write_g && scale_now) AF_KERNEL(AF_K_GSCALE, af::launch_gscale(c, g), "gscale");
-  c->rho_last = lp->rho_thresh;
   return AF_OK;
 }
 
-af_status run_backward(af_ctx* c, const af_complex* iq, const float2* gblk, bool scaled,
-                       float* grad) {
-  AF_KERNEL(AF_K_DAS_ADJ, af::launch_das_adj(c, reinterpret_cast<const float2*>(iq), gblk, scaled),
-            "das_adj");
-  AF_KERNEL(AF_K_PATH_ADJ, af::launch_path_adj(c), "path_adj");
+// Adjoint of the current view's forward (dL/dB^blk in gblk, scaled: final, else
+// scaled on the fly from the terms of finalize): its grid sums into out [nodes].
+af_status run_view_backward(af_ctx* c, const float2* iq, const float2* gblk, bool scaled,
+                            float* out) {
+  AF_KERNEL(AF_K_DAS_ADJ, af::launch_das_adj(c, iq, gblk, scaled), "das_adj");
+  AF_KERNEL(AF_K_PATH_ADJ, af::launch_path_adj(c, out), "path_adj");
+  return AF_OK;
+}
+
+// The objective (terms) and, with grad, its gradient with respect to the slowness.
+// One chunk: forward and adjoint on the same table.  Several chunks (bounded
+// memory): a forward pass over the chunks gives the terms (the CMPE mean needs
+// every chunk's valid pairs); the adjoint pass then recomputes each chunk's table
+// and block images instead of keeping them, and the chunks' grid sums are added
+// in chunk order.
+af_status run_loss(af_ctx* c, const af_complex* iq, const af_loss_params* lp, float* terms,
+                   float* grad) {
+  const float2* iqf = reinterpret_cast<const float2*>(iq);
+  af_status st = run_prepare(c, lp);
+  if (st != AF_OK) return st;
+  const int K = (int)c->chunks.size();
+  const bool g = grad != nullptr;
+  for (int k = 0; k < K; ++k) {
+    c->select(k);
+    if ((st = run_view_forward(c, iqf, lp, g && K == 1, nullptr)) != AF_OK) return st;
+  }
+  AF_KERNEL(AF_K_FINALIZE, af::launch_finalize(c, lp, terms), "finalize");
+  c->rho_last = lp->rho_thresh;
+  if (!g) return AF_OK;
+  if (K == 1) {
+    if ((st = run_view_backward(c, iqf, c->d_bblk.as<float2>(), false, c->d_gpad.as<float>())) != AF_OK)
+      return st;
+  } else {
+    const size_t nodes = (size_t)(c->nx + 3) * (c->nz + 3);
+    AF_ALLOC(c->d_gsum, sizeof(float) * nodes * K, "chunk grid sums");
+    for (int k = 0; k < K; ++k) {
+      c->select(k);
+      if ((st = run_view_forward(c, iqf, lp, true, nullptr)) != AF_OK) return st;
+      if ((st = run_view_backward(c, iqf, c->d_bblk.as<float2>(), false,
+                                  c->d_gsum.as<float>() + nodes * k)) != AF_OK)
+        return st;
+    }
+    AF_HIP(af::launch_sum_grids(c, c->d_gsum.as<float>(), K, c->d_gpad.as<float>()), "chunk sums");
+  }
   AF_KERNEL(AF_K_FOLD, af::launch_grad_fold(c, grad), "grad_fold");
+  return AF_OK;
+}
+
+// The calls that hand the whole [nb][nb][P] block-image gradient, or the receive
+// channel images of every point, to or from the caller need every point at once.
+af_status need_unbounded(af_ctx* c, const char* who) {
+  if (c->bounded())
+    return fail(c, AF_ERR_STATE, std::string(who) + ": not available under a memory budget");
+  c->select(0);
   return AF_OK;
 }
 
@@ -883,24 +1013,30 @@ af_status af_beamform(af_ctx* c, const af_complex* iq, af_complex* blk, af_compl
                       float* maps) {
   af_status st = ready(c, iq);
   if (st != AF_OK) return st;
-  if ((st = run_tables(c, nullptr)) != AF_OK) return st;
-  AF_HIP(af::launch_das_fwd(c, reinterpret_cast<const float2*>(iq), c->d_bblk.as<float2>()), "das_fwd");
-  if (maps)
-    AF_HIP(af::launch_cmpe(c, c->d_bblk.as<float2>(), nullptr, 0, c->rho_last, 0.f,
-                           c->d_maps.as<float>(), c->d_maps.as<float>() + c->n_tiles * c->ppt,
-                           c->d_maps.as<float>() + 2 * (size_t)c->n_tiles * c->ppt, nullptr),
-           "cmpe maps");
-  if (blk || img || maps)
-    AF_HIP(af::launch_export_images(c, c->d_bblk.as<float2>(), reinterpret_cast<float2*>(blk),
-                                    reinterpret_cast<float2*>(img), maps),
-           "export images");
+  if ((st = run_prepare(c, nullptr)) != AF_OK) return st;
+  const float2* iqf = reinterpret_cast<const float2*>(iq);
+  for (int k = 0; k < (int)c->chunks.size(); ++k) {
+    c->select(k);
+    AF_KERNEL(AF_K_TABLE, af::launch_table(c), "table");
+    AF_HIP(af::launch_das_fwd(c, iqf, c->d_bblk.as<float2>()), "das_fwd");
+    if (maps)
+      AF_HIP(af::launch_cmpe(c, c->d_bblk.as<float2>(), nullptr, 0, c->rho_last, 0.f,
+                             c->v.map_cmpe, c->v.map_cf, c->v.map_cmcc, nullptr),
+             "cmpe maps");
+    if (blk || img || maps)
+      AF_HIP(af::launch_export_images(c, c->d_bblk.as<float2>(), reinterpret_cast<float2*>(blk),
+                                      reinterpret_cast<float2*>(img), maps),
+             "export images");
+  }
   return AF_OK;
 }
 
 static af_status channel_images(af_ctx* c, const af_complex* iq) {
   af_status st = ready(c, iq);
   if (st != AF_OK) return st;
-  if ((st = run_tables(c, nullptr)) != AF_OK) return st;
+  if ((st = need_unbounded(c, "af_channel_images / af_lag_one_coherence")) != AF_OK) return st;
+  if ((st = run_prepare(c, nullptr)) != AF_OK) return st;
+  AF_KERNEL(AF_K_TABLE, af::launch_table(c), "table");
   AF_ALLOC(c->d_chan, sizeof(float2) * (size_t)c->N * c->P_int, "channel images");
   AF_HIP(af::launch_channel_images(c, reinterpret_cast<const float2*>(iq), c->d_chan.as<float2>()),
          "channel images");
@@ -930,10 +1066,7 @@ af_status af_loss_and_grad(af_ctx* c, const af_complex* iq, const af_loss_params
   if (st != AF_OK) return st;
   if ((st = check_lp(c, lp)) != AF_OK) return st;
   if (!terms) return fail(c, AF_ERR_ARG, "af_loss_and_grad: null terms");
-  if ((st = run_forward(c, iq, lp, terms, nullptr, grad != nullptr, false)) != AF_OK) return st;
-  if (!grad) return AF_OK;
-  // the table of this call is still current: the adjoint uses it directly
-  return run_backward(c, iq, c->d_bblk.as<float2>(), false, grad);
+  return run_loss(c, iq, lp, terms, grad);
 }
 
 af_status af_forward(af_ctx* c, const af_complex* iq, const af_loss_params* lp, float* terms,
@@ -942,7 +1075,15 @@ af_status af_forward(af_ctx* c, const af_complex* iq, const af_loss_params* lp, 
   if (st != AF_OK) return st;
   if ((st = check_lp(c, lp)) != AF_OK) return st;
   if (!terms || !gblk) return fail(c, AF_ERR_ARG, "af_forward: null output");
-  return run_forward(c, iq, lp, terms, reinterpret_cast<float2*>(gblk), true, true);
+  if ((st = need_unbounded(c, "af_forward")) != AF_OK) return st;
+  if ((st = run_prepare(c, lp)) != AF_OK) return st;
+  float2* g = reinterpret_cast<float2*>(gblk);
+  if ((st = run_view_forward(c, reinterpret_cast<const float2*>(iq), lp, true, g)) != AF_OK)
+    return st;
+  AF_KERNEL(AF_K_FINALIZE, af::launch_finalize(c, lp, terms), "finalize");
+  AF_KERNEL(AF_K_GSCALE, af::launch_gscale(c, g), "gscale");  // the final scale, for the caller
+  c->rho_last = lp->rho_thresh;
+  return AF_OK;
 }
 
 af_status af_backward(af_ctx* c, const af_complex* iq, const af_loss_params* lp,
@@ -951,8 +1092,16 @@ af_status af_backward(af_ctx* c, const af_complex* iq, const af_loss_params* lp,
   if (st != AF_OK) return st;
   if ((st = check_lp(c, lp)) != AF_OK) return st;
   if (!gblk || !grad) return fail(c, AF_ERR_ARG, "af_backward: null buffer");
-  if ((st = run_tables(c, lp)) != AF_OK) return st;  // recompute: no table is stored between calls
-  return run_backward(c, iq, reinterpret_cast<const float2*>(gblk), true, grad);
+  if ((st = need_unbounded(c, "af_backward")) != AF_OK) return st;
+  // recompute: no table is kept between calls
+  if ((st = run_prepare(c, lp)) != AF_OK) return st;
+  AF_KERNEL(AF_K_TABLE, af::launch_table(c), "table");
+  if ((st = run_view_backward(c, reinterpret_cast<const float2*>(iq),
+                              reinterpret_cast<const float2*>(gblk), true,
+                              c->d_gpad.as<float>())) != AF_OK)
+    return st;
+  AF_KERNEL(AF_K_FOLD, af::launch_grad_fold(c, grad), "grad_fold");
+  return AF_OK;
 }
 
 af_status af_autofocus_step(af_ctx* c, const af_complex* iq, const af_loss_params* lp,
@@ -965,10 +1114,7 @@ af_status af_autofocus_step(af_ctx* c, const af_complex* iq, const af_loss_param
   if ((st = check_lp(c, lp)) != AF_OK) return st;
   const size_t n = (size_t)c->nx * c->nz;
   AF_HIP(hipMemcpyAsync(c->d_s.p, s, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream), "copy s");
-  // forward, then the backward on the table the forward built
-  if ((st = run_forward(c, iq, lp, terms, nullptr, true, false)) != AF_OK) return st;
-  if ((st = run_backward(c, iq, c->d_bblk.as<float2>(), false, c->d_grad.as<float>())) != AF_OK)
-    return st;
+  if ((st = run_loss(c, iq, lp, terms, c->d_grad.as<float>())) != AF_OK) return st;
   AF_KERNEL(AF_K_ADAM, af::launch_adam(c, ap, step, s, m, v, c->d_grad.as<float>()), "adam");
   return AF_OK;
 }
@@ -1056,8 +1202,7 @@ af_status af_sweep(af_ctx* c, const af_complex* iq, const af_loss_params* lp, in
   for (int k = 0; k < n; ++k) {
     if (dynamic && (st = move_points(c, speeds[k], "af_sweep")) != AF_OK) return st;
     AF_HIP(af::launch_fill(c, c->d_s.as<float>(), ns, (float)(1.0 / speeds[k])), "uniform slowness");
-    if ((st = run_forward(c, iq, lp, c->d_terms.as<float>(), nullptr, false, false)) != AF_OK)
-      return st;
+    if ((st = run_loss(c, iq, lp, c->d_terms.as<float>(), nullptr)) != AF_OK) return st;
     AF_HIP(hipMemcpyAsync(cmpe_dev + k, c->d_terms.as<float>() + AF_TERM_CMPE, sizeof(float),
                           hipMemcpyDeviceToDevice, c->stream),
            "af_sweep copy");
@@ -1078,8 +1223,12 @@ af_status af_sweep(af_ctx* c, const af_complex* iq, const af_loss_params* lp, in
 af_status af_travel_times(af_ctx* c, float* t_dev) {
   af_status st = ready(c, t_dev);
   if (st != AF_OK) return st;
-  if ((st = run_tables(c, nullptr)) != AF_OK) return st;
-  AF_HIP(af::launch_export_T(c, t_dev), "export T");
+  if ((st = run_prepare(c, nullptr)) != AF_OK) return st;
+  for (int k = 0; k < (int)c->chunks.size(); ++k) {
+    c->select(k);
+    AF_KERNEL(AF_K_TABLE, af::launch_table(c), "table");
+    AF_HIP(af::launch_export_T(c, t_dev), "export T");
+  }
   return AF_OK;
 }
 
@@ -1263,6 +1412,20 @@ af_status af_query(af_ctx* c, int what, long long* out) {
     case AF_Q_NA_MAX: *out = c->na_max; break;
     case AF_Q_NBA_MAX: *out = c->nba_max; break;
     case AF_Q_WIDE_TILES: *out = c->n_wide; break;
+    case AF_Q_CHUNKS: *out = (long long)c->chunks.size(); break;
+    case AF_Q_DEVICE_BYTES: {
+      long long b = 0;
+      for (const af::DBuf* d :
+           {&c->d_elem, &c->d_ptpol, &c->d_ptxy, &c->d_prange, &c->d_tiles, &c->d_tabwork,
+            &c->d_daswork, &c->d_order, &c->d_i2c, &c->d_c2i, &c->d_cnn_part, &c->d_ray_uv,
+            &c->d_ray_l2, &c->d_chan, &c->d_s, &c->d_gdev, &c->d_regg, &c->d_scal, &c->d_tab,
+            &c->d_bblk, &c->d_gT, &c->d_gsb, &c->d_part, &c->d_gpad, &c->d_gpart, &c->d_gsum,
+            &c->d_grad, &c->d_terms, &c->d_maps, &c->d_gtp, &c->d_tbase, &c->d_wide,
+            &c->d_cmpe_wide, &c->d_dyn_base, &c->d_elemf, &c->d_tstat})
+        b += (long long)d->bytes;
+      *out = b;
+      break;
+    }
     default: return fail(c, AF_ERR_ARG, "af_query: unknown item");
   }
   return AF_OK;

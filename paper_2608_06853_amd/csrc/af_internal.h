@@ -129,6 +129,42 @@ struct PathArgs {
   float* gpart;           // [n_wg][padded nodes] per-workgroup partial grids
 };
 
+// The tiles the hot-path kernels of one launch cover: all of them, or one chunk
+// of consecutive tiles in bounded-memory mode (af_set_memory_budget).  Per-tile
+// and per-point arrays are offset to the chunk's first tile, so a kernel sees the
+// chunk as a whole problem of n_tiles tiles and P points; the [n_elem][P] and
+// [nb][nb][P] buffers hold one chunk at a time, with stride P.
+struct View {
+  int t0 = 0, n_tiles = 0;    // first tile, tiles
+  long long p0 = 0, P = 0;    // first internal point, points (n_tiles * TILE)
+  const int4* tiles = nullptr;
+  const int2* prange = nullptr;
+  const float2* ptxy = nullptr;
+  const double4* ptpol = nullptr;
+  const int2* tabwork = nullptr;  // work lists with chunk-local tile indices
+  int n_tab_work = 0;
+  const int2* daswork = nullptr;
+  int n_das_work = 0;
+  const int* order = nullptr;
+  int n_order = 0;
+  const int* wide = nullptr;      // chunk-local index among the chunk's wide tiles
+  int n_wide = 0;
+  const long long* tbase = nullptr;  // chunk-local slab offsets (deterministic mode)
+  float* map_cmpe = nullptr;      // the chunk's per-pixel slots of the three maps
+  float* map_cf = nullptr;
+  float* map_cmcc = nullptr;
+  double* part = nullptr;         // the chunk's sub-tile partial sums
+  float2* gsb = nullptr;          // the chunk's points
+};
+
+// Work lists and scratch needs of one chunk (offsets into the concatenated lists).
+struct Chunk {
+  int t0 = 0, n_tiles = 0;
+  int tab_off = 0, n_tab = 0, das_off = 0, n_das = 0, ord_off = 0, n_ord = 0;
+  int n_wide = 0;
+  long long n_gtp = 0;
+};
+
 }  // namespace af
 
 struct af_ctx {
@@ -167,9 +203,17 @@ struct af_ctx {
   double dyn_cref = 1.54, dyn_fc = 1.0, dyn_cmin = 1.54, dyn_cmax = 1.54, dyn_c = 1.54;
   double dyn_box[4] = {0, 0, 0, 0};         // x_lo, x_hi, z_lo, z_hi of every point at every speed
   double dyn_ang[2] = {0, 0};               // polar angle (x on a line) range of the same
-  af::DBuf d_dyn_base, d_elemf, d_tstat, d_dynflag;
-  std::vector<int> tile_order;              // tiles with work, heaviest first
-  int n_tab_work = 0, n_das_work = 0, n_order = 0;
+  af::DBuf d_dyn_base, d_elemf, d_tstat;
+  // chunks of consecutive tiles (one chunk holding every tile unless a memory
+  // budget is set), their work lists, and the view of the current launch
+  size_t mem_budget = 0;                    // bytes for the chunk-sized buffers; 0: none
+  std::vector<af::Chunk> chunks;
+  long long P_chunk = 0;                    // points of the largest chunk
+  int wide_max = 0;                         // most wide tiles of a chunk
+  long long gtp_max = 0;                    // most slab floats of a chunk
+  af::View v;
+  void select(int k);                       // v := chunk k
+  bool bounded() const { return chunks.size() > 1; }
 
   // lens: the physical lens (d_lens_phys, c_lens, t_ttp_phys) and the beamformer's
   // model of it -- the lens thickness its rays refract through (d_lens: 0 for the
@@ -190,14 +234,15 @@ struct af_ctx {
   af::DBuf d_cnn_part;
   af::DBuf d_ray_uv, d_ray_l2;  // per table entry: ray start (grid coordinates), medium leg
   af::DBuf d_chan;  // receive-channel images, allocated by the coherence calls only
-  af::DBuf d_s, d_gdev, d_regg, d_scal, d_tab, d_bblk, d_g, d_gT, d_gsb, d_part, d_gpad, d_gpart,
-      d_grad, d_terms, d_maps, d_img;
+  // d_tab, d_ray_uv, d_ray_l2, d_bblk, d_gT: one chunk ([.][P_chunk]); d_gsum: one
+  // grid of path-adjoint sums per chunk
+  af::DBuf d_s, d_gdev, d_regg, d_scal, d_tab, d_bblk, d_gT, d_gsb, d_part, d_gpad, d_gpart,
+      d_gsum, d_grad, d_terms, d_maps;
   // Transmit-role sums of dL/dT: for every tile and receive block jb of its range
   // one slab [element e - LO][TILE] of sums over the receive elements of jb; the
   // slabs of a tile follow in jb order from d_tbase[tile].
   af::DBuf d_gtp, d_tbase;
   af::DBuf d_wide, d_cmpe_wide;  // CMPE stage of wide tiles (CmpeArgs::wide, wscr)
-  long long n_gtp = 0;
   bool det = false;  // deterministic mode (af_set_deterministic)
 
   af::Geo geo() const;
@@ -245,7 +290,8 @@ hipError_t launch_das_adj(af_ctx* c, const float2* iq, const float2* gblk, bool 
 hipError_t launch_channel_images(af_ctx* c, const float2* iq, float2* X);
 hipError_t launch_export_rx(af_ctx* c, const float2* X, float2* out);
 hipError_t launch_loc(af_ctx* c, const float2* X, float* loc);
-hipError_t launch_path_adj(af_ctx* c);
+hipError_t launch_path_adj(af_ctx* c, float* out);  // the view's grid sums -> out [nodes]
+hipError_t launch_sum_grids(af_ctx* c, float* parts, int n, float* out);  // parts is overwritten
 // dynamic grid: points at k = c_g / c_ref with patch spacing `spacing` from the lens
 // surface rl, their active element ranges, and per tile the statistics in tstat
 hipError_t launch_sweep_points(af_ctx* c, double k, double spacing, double rl, TileStat* tstat);

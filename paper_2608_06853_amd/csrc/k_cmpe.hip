@@ -254,29 +254,34 @@ __global__ __launch_bounds__(256) void k_cmpe(CmpeArgs A) {
   }
 }
 
-// Internal -> caller order: travel times.
+// Internal -> caller order: travel times of the caller points whose internal
+// point lies in the view [p0, p0 + g.P) (the table holds that view).
 __global__ __launch_bounds__(256) void k_export_T(Geo g, const TabEntry* __restrict__ tab,
                                                   const int* __restrict__ c2i,
                                                   const int2* __restrict__ prange, long long Pc,
-                                                  float* __restrict__ out) {
+                                                  long long p0, float* __restrict__ out) {
   const long long pc = (long long)blockIdx.x * 256 + threadIdx.x;
   const int a = blockIdx.y;
   if (pc >= Pc) return;
   const long long p = c2i[pc];
+  if (p < p0 || p >= p0 + g.P) return;
   const int2 pr = prange[p];
   float v = __int_as_float(0x7fc00000);
   if (a >= pr.x && a <= pr.y) {
-    const TabEntry e = tab[(long long)a * g.P + p];
+    const TabEntry e = tab[(long long)a * g.P + (p - p0)];
     const double u = (double)e.ui + (double)e.uf;
     v = (float)(u / g.fs - 0.5 * g.t_ttp + 0.5 * g.t0);
   }
   out[(long long)a * Pc + pc] = v;
 }
 
-// Internal -> caller order: block images, full image and per-pixel maps.
+// Internal -> caller order: block images, full image and per-pixel maps of the
+// caller points whose internal point lies in the view [p0, p0 + g.P) (the block
+// images hold that view; tiles and maps are the whole arrays).
 __global__ __launch_bounds__(256) void k_export_img(Geo g, const float2* __restrict__ bblk,
                                                     const int4* __restrict__ tiles,
                                                     const int* __restrict__ c2i, long long Pc,
+                                                    long long p0,
                                                     int n_pix, const float* __restrict__ mc,
                                                     const float* __restrict__ mcf,
                                                     const float* __restrict__ mcc,
@@ -286,13 +291,14 @@ __global__ __launch_bounds__(256) void k_export_img(Geo g, const float2* __restr
   const long long pc = (long long)blockIdx.x * 256 + threadIdx.x;
   if (pc >= Pc) return;
   const long long p = c2i[pc];
+  if (p < p0 || p >= p0 + g.P) return;
   const int4 tr = tiles[p / TILE];
   float2 acc = make_float2(0.f, 0.f);
   for (int i = 0; i < g.nblk; ++i)
     for (int j = 0; j < g.nblk; ++j) {
       float2 v = make_float2(0.f, 0.f);
       if (tr.x <= tr.y && i >= tr.z && i <= tr.w && j >= tr.z && j <= tr.w)
-        v = bblk[((long long)i * g.nblk + j) * g.P + p];
+        v = bblk[((long long)i * g.nblk + j) * g.P + (p - p0)];
       acc.x += v.x;
       acc.y += v.y;
       if (blk_out) blk_out[((long long)i * g.nblk + j) * Pc + pc] = v;
@@ -335,11 +341,11 @@ hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g,
                        float2* img) {
   CmpeArgs A{};
   A.g = c->geo();
-  A.tiles = c->d_tiles.as<int4>();
+  A.tiles = c->v.tiles;
   A.bblk = bblk;
   A.gout = gout;
-  A.gsb = c->d_gsb.as<float2>();
-  A.part = c->d_part.as<double>();
+  A.gsb = c->v.gsb;
+  A.part = c->v.part;
   A.map_cmpe = map_cmpe;
   A.map_cf = map_cf;
   A.map_cmcc = map_cmcc;
@@ -347,15 +353,15 @@ hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g,
   A.rho_thresh = rho;
   A.sb_scale = sb_scale;
   A.write_g = write_g;
-  A.wide = c->d_wide.as<int>();
+  A.wide = c->v.wide;
   A.wscr = c->d_cmpe_wide.as<float2>();
   A.wstride = c->wstride;
   const int nba = c->nba_lds;  // widest span of the LDS path
   const size_t lds = sizeof(float2) * (size_t)cmpe_wide_stride(nba, c->pps);
-  const dim3 grid((unsigned)(c->P_int / SUB)), block(CMPE_WAVES * SUB);
+  const dim3 grid((unsigned)(c->v.P / SUB)), block(CMPE_WAVES * SUB);
   hipLaunchKernelGGL(k_cmpe<false>, grid, block, lds, c->stream, A);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || c->n_wide == 0) return e;
+  if (e != hipSuccess || c->v.n_wide == 0) return e;
   hipLaunchKernelGGL(k_cmpe<true>, grid, block, 0, c->stream, A);
   return hipGetLastError();
 }
@@ -364,7 +370,7 @@ hipError_t launch_export_T(af_ctx* c, float* out) {
   const long long Pc = c->P;
   dim3 grid((unsigned)((Pc + 255) / 256), (unsigned)c->N);
   hipLaunchKernelGGL(k_export_T, grid, dim3(256), 0, c->stream, c->geo(), c->d_tab.as<TabEntry>(),
-                     c->d_c2i.as<int>(), c->d_prange.as<int2>(), Pc, out);
+                     c->d_c2i.as<int>(), c->d_prange.as<int2>(), Pc, c->v.p0, out);
   return hipGetLastError();
 }
 
@@ -372,7 +378,8 @@ hipError_t launch_export_images(af_ctx* c, const float2* bblk, float2* blk_out, 
                                 float* maps_out) {
   const long long Pc = c->P;
   hipLaunchKernelGGL(k_export_img, dim3((unsigned)((Pc + 255) / 256)), dim3(256), 0, c->stream,
-                     c->geo(), bblk, c->d_tiles.as<int4>(), c->d_c2i.as<int>(), Pc, c->n_pix,
+                     c->geo(), bblk, c->d_tiles.as<int4>(), c->d_c2i.as<int>(), Pc, c->v.p0,
+                     c->n_pix,
                      c->d_maps.as<float>(), c->d_maps.as<float>() + c->n_tiles * c->ppt,
                      c->d_maps.as<float>() + 2 * (size_t)c->n_tiles * c->ppt, blk_out, img_out,
                      maps_out);

@@ -456,20 +456,20 @@ __global__ __launch_bounds__(256) void k_zero_tx(Geo g, const int4* __restrict__
 
 template <int S>
 hipError_t das_fwd_s(af_ctx* c, const DasArgs& A) {
-  hipLaunchKernelGGL(k_das_fwd<S>, dim3(c->n_das_work), dim3(256), 0, c->stream, A);
+  hipLaunchKernelGGL(k_das_fwd<S>, dim3(c->v.n_das_work), dim3(256), 0, c->stream, A);
   return hipGetLastError();
 }
 
 template <int S>
 hipError_t das_adj_s(af_ctx* c, const DasArgs& A) {
   if (c->det) {
-    hipLaunchKernelGGL((k_das_adj<S, true>), dim3(c->n_das_work), dim3(256), 0, c->stream, A);
+    hipLaunchKernelGGL((k_das_adj<S, true>), dim3(c->v.n_das_work), dim3(256), 0, c->stream, A);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_zero_tx, dim3(c->n_tiles), dim3(256), 0, c->stream, A.g, A.tiles, A.gT2);
+  hipLaunchKernelGGL(k_zero_tx, dim3(c->v.n_tiles), dim3(256), 0, c->stream, A.g, A.tiles, A.gT2);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_das_adj<S, false>), dim3(c->n_das_work), dim3(256), 0, c->stream, A);
+  hipLaunchKernelGGL((k_das_adj<S, false>), dim3(c->v.n_das_work), dim3(256), 0, c->stream, A);
   return hipGetLastError();
 }
 
@@ -478,17 +478,17 @@ DasArgs das_args(af_ctx* c, const float2* iq) {
   A.g = c->geo();
   A.tab = c->d_tab.as<TabEntry>();
   A.iq = iq;
-  A.tiles = c->d_tiles.as<int4>();
-  A.prange = c->d_prange.as<int2>();
-  A.work = c->d_daswork.as<int2>();
-  A.order = c->d_order.as<int>();
+  A.tiles = c->v.tiles;
+  A.prange = c->v.prange;
+  A.work = c->v.daswork;
+  A.order = c->v.order;
   return A;
 }
 
 }  // namespace
 
 hipError_t launch_das_fwd(af_ctx* c, const float2* iq, float2* bblk) {
-  if (c->n_das_work == 0) return hipSuccess;
+  if (c->v.n_das_work == 0) return hipSuccess;
   DasArgs A = das_args(c, iq);
   A.bblk = bblk;
   switch (c->S) {
@@ -503,7 +503,7 @@ hipError_t launch_das_fwd(af_ctx* c, const float2* iq, float2* bblk) {
 
 template <int S>
 hipError_t das_rx_s(af_ctx* c, const DasArgs& A, float2* X) {
-  hipLaunchKernelGGL(k_das_rx<S>, dim3(c->n_das_work), dim3(256), 0, c->stream, A, X);
+  hipLaunchKernelGGL(k_das_rx<S>, dim3(c->v.n_das_work), dim3(256), 0, c->stream, A, X);
   return hipGetLastError();
 }
 
@@ -512,7 +512,7 @@ hipError_t launch_channel_images(af_ctx* c, const float2* iq, float2* X) {
   const unsigned nblk = (unsigned)std::min<long long>((n + 255) / 256, 8192);
   hipLaunchKernelGGL(k_fill_zero2, dim3(std::max(nblk, 1u)), dim3(256), 0, c->stream, X, n);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || c->n_das_work == 0) return e;
+  if (e != hipSuccess || c->v.n_das_work == 0) return e;
   DasArgs A = das_args(c, iq);
   switch (c->S) {
     case 1: return das_rx_s<1>(c, A, X);
@@ -538,15 +538,15 @@ hipError_t launch_loc(af_ctx* c, const float2* X, float* loc) {
 }
 
 hipError_t launch_das_adj(af_ctx* c, const float2* iq, const float2* gblk, bool scaled) {
-  if (c->n_das_work == 0) return hipSuccess;
+  if (c->v.n_das_work == 0) return hipSuccess;
   DasArgs A = das_args(c, iq);
   A.gblk = gblk;
   A.gscal = scaled ? nullptr : c->d_scal.as<double>();
-  A.gsb = c->d_gsb.as<float2>();
+  A.gsb = c->v.gsb;
   A.gT = c->d_gT.as<float>();
-  A.gT2 = c->d_gT.as<float>() + (size_t)c->N * c->P_int;
+  A.gT2 = c->d_gT.as<float>() + (size_t)c->N * c->v.P;
   A.gtp = c->d_gtp.as<float>();
-  A.tbase = c->d_tbase.as<long long>();
+  A.tbase = c->v.tbase;
   switch (c->S) {
     case 1: return das_adj_s<1>(c, A);
     case 2: return das_adj_s<2>(c, A);

@@ -493,42 +493,46 @@ __global__ __launch_bounds__(256) void k_zero(float* __restrict__ x, long long n
 
 }  // namespace
 
-hipError_t launch_path_adj(af_ctx* c) {
+hipError_t launch_sum_grids(af_ctx* c, float* parts, int n, float* out) {
   const int nodes = (c->nx + 3) * (c->nz + 3);
-  if (c->n_order == 0) {
-    hipLaunchKernelGGL(k_zero, dim3((nodes + 255) / 256), dim3(256), 0, c->stream,
-                       c->d_gpad.as<float>(), (long long)nodes);
+  const int n_chunk = (n + PCHUNK - 1) / PCHUNK;
+  hipLaunchKernelGGL(k_path_chunk, dim3((nodes + 255) / 256, n_chunk), dim3(256), 0, c->stream,
+                     parts, n, nodes);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_path_reduce, dim3((nodes + 63) / 64), dim3(256), 0, c->stream, parts, n,
+                     nodes, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_path_adj(af_ctx* c, float* out) {
+  const int nodes = (c->nx + 3) * (c->nz + 3);
+  if (c->v.n_order == 0) {
+    hipLaunchKernelGGL(k_zero, dim3((nodes + 255) / 256), dim3(256), 0, c->stream, out,
+                       (long long)nodes);
     return hipGetLastError();
   }
   PathArgs A{};
   A.g = c->geo();
   A.ray_uv = c->d_ray_uv.as<float2>();
   A.ray_l2 = c->d_ray_l2.as<float>();
-  A.ptxy = c->d_ptxy.as<float2>();
-  A.prange = c->d_prange.as<int2>();
-  A.tiles = c->d_tiles.as<int4>();
-  A.order = c->d_order.as<int>();
+  A.ptxy = c->v.ptxy;
+  A.prange = c->v.prange;
+  A.tiles = c->v.tiles;
+  A.order = c->v.order;
   A.gT = c->d_gT.as<float>();
-  A.gT2 = c->d_gT.as<float>() + (size_t)c->N * c->P_int;
+  A.gT2 = c->d_gT.as<float>() + (size_t)c->N * c->v.P;
   A.gtp = c->d_gtp.as<float>();
-  A.tbase = c->d_tbase.as<long long>();
-
+  A.tbase = c->v.tbase;
   A.gpart = c->d_gpart.as<float>();
   const size_t lds = sizeof(float) * (size_t)nodes * 4;
   if (c->det)
-    hipLaunchKernelGGL(k_path_adj<true>, dim3(c->n_order), dim3(256), lds, c->stream, A);
+    hipLaunchKernelGGL(k_path_adj<true>, dim3(c->v.n_order), dim3(256), lds, c->stream, A);
   else
-    hipLaunchKernelGGL(k_path_adj<false>, dim3(c->n_order), dim3(256), lds, c->stream, A);
+    hipLaunchKernelGGL(k_path_adj<false>, dim3(c->v.n_order), dim3(256), lds, c->stream, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int n_chunk = (c->n_order + PCHUNK - 1) / PCHUNK;
-  hipLaunchKernelGGL(k_path_chunk, dim3((nodes + 255) / 256, n_chunk), dim3(256), 0, c->stream,
-                     c->d_gpart.as<float>(), c->n_order, nodes);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_path_reduce, dim3((nodes + 63) / 64), dim3(256), 0, c->stream,
-                     c->d_gpart.as<float>(), c->n_order, nodes, c->d_gpad.as<float>());
-  return hipGetLastError();
+  return launch_sum_grids(c, c->d_gpart.as<float>(), c->v.n_order, out);
 }
 
 }  // namespace af

@@ -109,22 +109,22 @@ hipError_t launch_table(af_ctx* c) {
   TableArgs A;
   A.g = c->geo();
   A.elem = c->d_elem.as<double4>();
-  A.ptpol = c->d_ptpol.as<double4>();
-  A.ptxy = c->d_ptxy.as<float2>();
-  A.prange = c->d_prange.as<int2>();
-  A.tiles = c->d_tiles.as<int4>();
-  A.work = c->d_tabwork.as<int2>();
+  A.ptpol = c->v.ptpol;
+  A.ptxy = c->v.ptxy;
+  A.prange = c->v.prange;
+  A.tiles = c->v.tiles;
+  A.work = c->v.tabwork;
   A.gdev = c->d_gdev.as<float>();
   A.scal = c->d_scal.as<double>();
   A.tab = c->d_tab.as<TabEntry>();
   A.ray_uv = c->d_ray_uv.as<float2>();
   A.ray_l2 = c->d_ray_l2.as<float>();
-  if (c->n_tab_work == 0) return hipSuccess;
+  if (c->v.n_tab_work == 0) return hipSuccess;
   // the fixed row stride only where its copy fits the LDS of a workgroup
   const bool fixed = c->nx + 3 <= TAB_LDS_W &&
                      sizeof(float) * (size_t)TAB_LDS_W * (c->nz + 3) <= TAB_LDS_BYTES;
   const size_t lds = sizeof(float) * (size_t)(fixed ? TAB_LDS_W : c->nx + 3) * (c->nz + 3);
-  const dim3 grid(c->n_tab_work), block(256);
+  const dim3 grid(c->v.n_tab_work), block(256);
 #define AF_TABLE_LAUNCH(M)                                                        \
   if (fixed)                                                                      \
     hipLaunchKernelGGL((k_table<M, true>), grid, block, lds, c->stream, A);      \
