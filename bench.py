@@ -158,6 +158,43 @@ def measured_issue(cfg_name: str, family: str, units: float):
             "valu_lane_instr_per_unit": round(lane_instr / units, 2) if units > 0 else None}
 
 
+def memory_report():
+    """Device memory the context holds and time per autofocus step (forward, adjoint,
+    Adam) without a memory budget and under budgets (af_set_memory_budget: the
+    gradient pass recomputes each chunk's table and block images), on the
+    clinical and the largest workload.  The caller's channel data are not
+    counted."""
+    import torch
+    import afsynth
+    from paper_2608_06853_amd import _lib, workloads
+    out = {}
+    for name, budgets in (("c2_clinical", (0, 1 << 30, 512 << 20)),
+                          ("c5_largest", (0, 4 << 30, 2 << 30))):
+        cfg = afsynth.config_by_name(name)
+        bf, iq, med = workloads.build(cfg)
+        lp = workloads.loss_params(cfg)
+        ap = _lib.adam_params(lr=cfg.method.lr)
+        rows = []
+        for b in budgets:
+            bf.ctx.set_memory_budget(b)
+            s = torch.full(bf.grid.shape, 1.0 / cfg.img.c_ref, device=bf.device)
+            m, v = torch.zeros_like(s), torch.zeros_like(s)
+            terms = bf.empty_terms()
+            bf.ctx.autofocus_step(iq, lp, ap, 1, s, m, v, terms)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for it in range(2, 7):
+                bf.ctx.autofocus_step(iq, lp, ap, it, s, m, v, terms)
+            torch.cuda.synchronize()
+            rows.append({"budget_bytes": b, "chunks": bf.ctx.query(_lib.Q_CHUNKS),
+                         "device_bytes": bf.ctx.query(_lib.Q_DEVICE_BYTES),
+                         "ms_per_autofocus_step": round((time.perf_counter() - t0) / 5 * 1e3, 3)})
+        out[name] = rows
+        del bf, iq
+        torch.cuda.empty_cache()
+    return out
+
+
 def plain_loop_report():
     """The full plain method (sweep + Adam with CMPE and speckle brightness) on the
     two-layer medium with a cyst: speed errors and image quality before and after."""
@@ -564,7 +601,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_autofocus:
         t0 = time.perf_counter()
-        for key, fn in (("plain_loop", plain_loop_report), ("lens_models", lens_model_report),
+        for key, fn in (("plain_loop", plain_loop_report), ("memory", memory_report),
+                        ("lens_models", lens_model_report),
                         ("linear_array", linear_array_report),
                         ("grid_init", grid_init_report),
                         ("refraction_search", refraction_search_report),
