@@ -5,12 +5,14 @@
 * ``CmpeLoss`` is a ``torch.autograd.Function``: its forward runs the library's
   forward pass (travel times, DAS, CMPE, regularisers) and keeps only the
   gradient with respect to the block images; its backward recomputes the
-  travel-time table and runs the hand-written adjoints;
+  travel-time table and runs the hand-written adjoints (under a memory budget
+  the library's chunked loss-and-gradient call runs in the forward instead);
 * ``sweep`` is the global-speed initialisation with the dynamic CMPE grid and
   ``plain_autofocus`` the plain iterative method (Sections II-C and III-A of the
   paper; the optimiser is Adam instead of the plain descent of Eq. 9).
 
-Every numerical step runs in libaf.so; this module only moves arguments.
+Every step of the method runs in libaf.so; this module sequences the calls and
+holds the tensors they read and write.
 """
 from __future__ import annotations
 
