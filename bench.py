@@ -411,8 +411,10 @@ def s_to_target_report(n_heldout: int = 8):
     import afsynth
     from paper_2608_06853_amd import warmstart
     nets = {k: warmstart.load_network(k) for k in ("plain", "true")}
-    keep = ("target_cmpe", "plain_seconds", "plain_iters", "learned_seconds", "learned_iters",
-            "learned_reached", "learned_start", "speedup", "plain_rmse_mps", "learned_rmse_mps")
+    keep = ("target_cmpe", "plain_seconds", "plain_iters", "plain_best_speed", "learned_seconds",
+            "learned_iters", "learned_reached", "learned_start", "learned_speeds_evaluated",
+            "learned_cmpe_map", "learned_cmpe_local", "speedup", "plain_rmse_mps",
+            "learned_rmse_mps")
     out = {}
     rows = [warmstart.s_to_target(afsynth.configs.C4, nets["plain"], seed=9000 + k)
             for k in range(n_heldout)]

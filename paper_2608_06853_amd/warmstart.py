@@ -95,21 +95,25 @@ def run_learned(bf: af.Beamformer, iq, cfg, net, fm: cnn.FeatureMaker, target: f
                 max_iter: int, lp=None, window: int = 2):
     """Warm start + Adam until CMPE <= target.  Returns a dict of timings and results.
 
-    The network's map is judged by the plain objective: it is used if its loss is
-    not above that of the homogeneous 1540 m/s guess.  Otherwise the network's
-    mean speed narrows the plain adaptive-grid sweep to the 2 * window + 1 lattice
-    speeds around it (10 m/s apart); its best uniform map is used if it passes the
-    same test, and only if that fails does the full 41-speed sweep run."""
+    The starts are judged by the CMPE, as the plain sweep ranks its speeds.  The
+    network's mean speed starts a local search on the sweep's lattice (10 m/s
+    apart): the 2 * window + 1 speeds around it, widened towards a lower end until
+    the best speed lies inside the evaluated range, so that on a unimodal sweep
+    curve it finds the full sweep's speed with a fraction of its evaluations.  The
+    start is the network's map if its CMPE is not above the best of those uniform
+    maps, else that best uniform map, as long as the start is not above the
+    homogeneous 1540 m/s guess; only if neither passes does the full 41-speed
+    sweep run."""
     lp = lp or workloads.loss_params(cfg)
     base = bf.img
     terms = bf.empty_terms()
     c_ref, fc = cfg.img.c_ref, cfg.acq.fc
 
-    def loss_on(c_grid, s):
+    def loss_on(c_grid, s):   # the CMPE term, which the sweep ranks its speeds by
         bf.set_speed(c_grid, c_ref, fc)   # the dynamic grid of c_grid
         bf.set_slowness(s)
         bf.ctx.loss_and_grad(iq, lp, terms, None)
-        return float(terms[_lib.TERM_TOTAL].item())
+        return float(terms[_lib.TERM_CMPE].item())
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -118,17 +122,31 @@ def run_learned(bf: af.Beamformer, iq, cfg, net, fm: cnn.FeatureMaker, target: f
     c_mean = min(max(c_mean, 1.340), 1.740)
     l_hom = loss_on(cfg.img.c_ref, torch.full(bf.grid.shape, 1.0 / cfg.img.c_ref, device=bf.device))
     l_net = loss_on(c_mean, s0)
-    start, s_init, c_grid = "map", s0, c_mean
-    if not l_net <= l_hom:
-        lattice = af.sweep_speeds()
-        k0 = int(np.argmin(np.abs(lattice - c_mean)))
-        local = lattice[max(0, k0 - window):k0 + window + 1]
-        _, vals, best = af.sweep(bf, iq, lp, fc, c_ref, speeds=local)
-        if float(np.min(vals)) <= l_hom:
-            start, s_init, c_grid = "local_sweep", bf.s, best
+    lattice = af.sweep_speeds()
+    k0 = int(np.argmin(np.abs(lattice - c_mean)))
+    lo, hi = max(0, k0 - window), min(len(lattice) - 1, k0 + window)
+    done = {}
+    while True:
+        todo = [k for k in range(lo, hi + 1) if k not in done]
+        if todo:
+            _, vals, _ = af.sweep(bf, iq, lp, fc, c_ref, speeds=lattice[todo])
+            done.update(zip(todo, (float(v) for v in vals)))
+        kb = min(done, key=lambda k: (done[k], k))   # the lowest, the slowest on ties
+        if kb == lo and lo > 0:
+            lo = max(0, lo - window)
+        elif kb == hi and hi < len(lattice) - 1:
+            hi = min(len(lattice) - 1, hi + window)
         else:
-            _, _, c_grid = af.sweep(bf, iq, lp, fc, c_ref)
-            start, s_init = "sweep", bf.s
+            break
+    best, l_loc = float(lattice[kb]), done[kb]
+    if l_net <= min(l_loc, l_hom):
+        start, s_init, c_grid = "map", s0, c_mean
+    elif l_loc <= l_hom:
+        start, c_grid = "local_sweep", best
+        s_init = torch.full(bf.grid.shape, 1.0 / best, device=bf.device)
+    else:
+        _, _, c_grid = af.sweep(bf, iq, lp, fc, c_ref)
+        start, s_init = "sweep", bf.s
     bf.set_speed(c_grid, c_ref, fc)
     bf.set_slowness(s_init)
     torch.cuda.synchronize()
@@ -140,7 +158,8 @@ def run_learned(bf: af.Beamformer, iq, cfg, net, fm: cnn.FeatureMaker, target: f
     t_total = t_init + (hist.times[-1] if hist.times else 0.0)
     bf.set_imaging(base)
     return {"start": start, "fallback": start == "sweep", "loss_net": l_net,
-            "loss_homogeneous": l_hom, "init_s": t_init, "iters": len(cm), "reached": reached,
+            "loss_homogeneous": l_hom, "loss_local": l_loc, "speeds_evaluated": len(done),
+            "init_s": t_init, "iters": len(cm), "reached": reached,
             "seconds": t_total, "final_cmpe": cm[-1] if cm else None, "s": s}
 
 
@@ -149,9 +168,12 @@ def s_to_target(cfg, net, n_iter: int = 200, max_iter: int = 400, seed=None, dev
     bf, iq, med = workloads.build(cfg, seed=seed, device=device)
     fm = cnn.FeatureMaker(cfg, device)
     base = bf.img
-    # untimed first use of both paths' kernels, so neither timing includes loading them
+    # untimed first use of both paths' kernels and calls (the sweep over a few
+    # speeds and its dynamic grid included), so neither timing includes loading them
     bf.ctx.loss_and_grad(iq, workloads.loss_params(cfg), bf.empty_terms(), None)
     cnn.predict_slowness(net, fm, iq, cfg, bf.grid)
+    af.sweep(bf, iq, workloads.loss_params(cfg), cfg.acq.fc, speeds=[1.50, 1.54, 1.58])
+    bf.set_imaging(base)
     torch.cuda.synchronize()
     s_plain, cm, times, t_sweep, best = run_plain(bf, iq, cfg, n_iter)
     target = cm[-1]
@@ -165,7 +187,8 @@ def s_to_target(cfg, net, n_iter: int = 200, max_iter: int = 400, seed=None, dev
            "plain_sweep_seconds": t_sweep, "plain_best_speed": best, "plain_iters": k + 1,
            "learned_seconds": res["seconds"], "learned_iters": res["iters"],
            "learned_reached": res["reached"], "learned_fallback": res["fallback"],
-           "learned_start": res["start"],
+           "learned_start": res["start"], "learned_speeds_evaluated": res["speeds_evaluated"],
+           "learned_cmpe_map": res["loss_net"], "learned_cmpe_local": res["loss_local"],
            "learned_init_seconds": res["init_s"],
            "speedup": t_plain / res["seconds"] if res["reached"] else None,
            "plain_rmse_mps": metrics.speed_errors(s_plain.cpu().numpy(), c_true)["rmse_mps"],
