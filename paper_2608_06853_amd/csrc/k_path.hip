@@ -75,11 +75,17 @@ __device__ inline float reduce_scatter16(float v[16], int lane) {
   return h1;
 }
 
+// Adds v to an LDS grid node with one LDS float atomic (no read-back wait).  On a
+// wavefront's private grid copy the lanes of one call hit distinct nodes and the
+// calls of a wavefront execute in order, so the sums are deterministic; on a copy
+// shared by the workgroup's wavefronts the order of their adds varies.
+__device__ inline void lds_add(float* p, float v) { atomicAdd(p, v); }
+
 // Adds the 16 tap sums of acc (summed over the wavefront) to the wavefront's grid
 // copy at cell c; acc is consumed.
 __device__ inline void flush16(float* grid, int c, float (&acc)[16], int lane, int my_off) {
   const float sum = reduce_scatter16(acc, lane);
-  if ((lane & 3) == 0) grid[c + my_off] += sum;
+  if ((lane & 3) == 0) lds_add(grid + c + my_off, sum);
 }
 
 // Sum over the wavefront of v[r], r = 0..3: every lane returns the sum of
@@ -173,11 +179,11 @@ __device__ inline void scatter_window(float* grid, int cb, int W, const float (&
     }
   }
   const float sum16 = reduce_scatter16(v16, lane);
-  if ((lane & 3) == 0) grid[cb + my_off] += sum16;
+  if ((lane & 3) == 0) lds_add(grid + cb + my_off, sum16);
   const float sum4 = reduce_scatter4(v4);
   // node 4 of row (lane >> 4), or node (lane >> 4) of row 4
   const int off4 = HORIZONTAL ? (lane >> 4) * W + 4 : 4 * W + (lane >> 4);
-  if ((lane & 15) == 0) grid[cb + off4] += sum4;
+  if ((lane & 15) == 0) lds_add(grid + cb + off4, sum4);
 }
 
 // Adds the tap weights of NR ray points per lane (cells in `cell`, idle lanes
@@ -199,7 +205,7 @@ __device__ inline bool scatter_union(float* grid, int c0, int W, const int (&cel
       for (int n = 1; n < NR; ++n) val[i] = fmaf(az[n][i >> 2], wx[n][i & 3], val[i]);
     }
     const float sum = reduce_scatter16(val, lane);
-    if ((lane & 3) == 0) grid[c0 + my_off] += sum;
+    if ((lane & 3) == 0) lds_add(grid + c0 + my_off, sum);
     return true;
   }
   // the other cell, relative to c0: +1, -1, +W or -W for every lane (0 if none)
@@ -252,7 +258,7 @@ __device__ inline void scatter_rounds(float* grid, int c0, int cell, const float
 #pragma unroll
     for (int i = 0; i < 16; ++i) vv[i] = in ? val[i] : 0.f;
     const float sum = reduce_scatter16(vv, lane);
-    if ((lane & 3) == 0) grid[ccur + my_off] += sum;
+    if ((lane & 3) == 0) lds_add(grid + ccur + my_off, sum);
     done = done || in;
     const unsigned long long rest = __ballot(!done);
     if (rest == 0ull) break;
@@ -286,9 +292,11 @@ __device__ inline void scatter_pair(float* grid, const int (&cell)[2], const boo
   scatter_one(grid, cell[1], live[1], lead1, W, az[1], wx[1], lane, my_off);
 }
 
-template <bool DET>
+// SHARED: one grid copy for the workgroup (large grids, where four copies would
+// keep the CU below four workgroups); else one private copy per wavefront.
+template <bool DET, bool SHARED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_path_adj(PathArgs A) {
-  extern __shared__ float sg[];  // [4 wavefronts][nodes]
+  extern __shared__ float sg[];  // [copies][nodes]
   const Geo& g = A.g;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -296,9 +304,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int4 tr = A.tiles[tile];
   const int W = g.W;
   const int nodes = W * (g.nz + 3);
-  for (int i = tid; i < 4 * nodes; i += 256) sg[i] = 0.f;
+  constexpr int COPIES = SHARED ? 1 : 4;
+  for (int i = tid; i < COPIES * nodes; i += 256) sg[i] = 0.f;
   __syncthreads();
-  float* grid = sg + (tid >> 6) * nodes;
+  float* grid = SHARED ? sg : sg + (tid >> 6) * nodes;
 
   const long long p = (long long)tile * TILE + tid;
   const int2 pr = A.prange[p];
@@ -448,7 +457,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   // per-workgroup partial grid (plain stores); summed in fixed order by k_path_reduce
   float* part = A.gpart + (long long)blockIdx.x * nodes;
   for (int n = tid; n < nodes; n += 256)
-    part[n] = (sg[n] + sg[nodes + n]) + (sg[2 * nodes + n] + sg[3 * nodes + n]);
+    part[n] = SHARED ? sg[n] : (sg[n] + sg[nodes + n]) + (sg[2 * nodes + n] + sg[3 * nodes + n]);
 }
 
 // gpad[n] = sum over workgroups of their partial grids, in a fixed order
@@ -525,11 +534,16 @@ hipError_t launch_path_adj(af_ctx* c, float* out) {
   A.gtp = c->d_gtp.as<float>();
   A.tbase = c->v.tbase;
   A.gpart = c->d_gpart.as<float>();
-  const size_t lds = sizeof(float) * (size_t)nodes * 4;
+  // four private copies while four workgroups of them fit the CU's 160 KB of LDS;
+  // beyond that one shared copy (deterministic mode keeps the private copies)
+  const bool shared = !c->det && sizeof(float) * (size_t)nodes * 4 * 4 > 160 * 1024;
+  const size_t lds = sizeof(float) * (size_t)nodes * (shared ? 1 : 4);
   if (c->det)
-    hipLaunchKernelGGL(k_path_adj<true>, dim3(c->v.n_order), dim3(256), lds, c->stream, A);
+    hipLaunchKernelGGL((k_path_adj<true, false>), dim3(c->v.n_order), dim3(256), lds, c->stream, A);
+  else if (shared)
+    hipLaunchKernelGGL((k_path_adj<false, true>), dim3(c->v.n_order), dim3(256), lds, c->stream, A);
   else
-    hipLaunchKernelGGL(k_path_adj<false>, dim3(c->v.n_order), dim3(256), lds, c->stream, A);
+    hipLaunchKernelGGL((k_path_adj<false, false>), dim3(c->v.n_order), dim3(256), lds, c->stream, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_sum_grids(c, c->d_gpart.as<float>(), c->v.n_order, out);
