@@ -292,11 +292,12 @@ __device__ inline void scatter_pair(float* grid, const int (&cell)[2], const boo
   scatter_one(grid, cell[1], live[1], lead1, W, az[1], wx[1], lane, my_off);
 }
 
-// SHARED: one grid copy for the workgroup (large grids, where four copies would
-// keep the CU below four workgroups); else one private copy per wavefront.
-template <bool DET, bool SHARED>
+// COPIES grid copies per workgroup: 4 (one private copy per wavefront), or for
+// large grids, where four copies would keep the CU below four workgroups, 2 (one
+// per pair of wavefronts) or 1 (shared by all four).
+template <bool DET, int COPIES>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_path_adj(PathArgs A) {
-  extern __shared__ float sg[];  // [copies][nodes]
+  extern __shared__ float sg[];  // [COPIES][nodes]
   const Geo& g = A.g;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -304,10 +305,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int4 tr = A.tiles[tile];
   const int W = g.W;
   const int nodes = W * (g.nz + 3);
-  constexpr int COPIES = SHARED ? 1 : 4;
   for (int i = tid; i < COPIES * nodes; i += 256) sg[i] = 0.f;
   __syncthreads();
-  float* grid = SHARED ? sg : sg + (tid >> 6) * nodes;
+  float* grid = sg + ((tid >> 6) * COPIES / 4) * nodes;
 
   const long long p = (long long)tile * TILE + tid;
   const int2 pr = A.prange[p];
@@ -457,7 +457,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   // per-workgroup partial grid (plain stores); summed in fixed order by k_path_reduce
   float* part = A.gpart + (long long)blockIdx.x * nodes;
   for (int n = tid; n < nodes; n += 256)
-    part[n] = SHARED ? sg[n] : (sg[n] + sg[nodes + n]) + (sg[2 * nodes + n] + sg[3 * nodes + n]);
+    part[n] = COPIES == 1   ? sg[n]
+              : COPIES == 2 ? sg[n] + sg[nodes + n]
+                            : (sg[n] + sg[nodes + n]) + (sg[2 * nodes + n] + sg[3 * nodes + n]);
 }
 
 // gpad[n] = sum over workgroups of their partial grids, in a fixed order
@@ -534,16 +536,20 @@ hipError_t launch_path_adj(af_ctx* c, float* out) {
   A.gtp = c->d_gtp.as<float>();
   A.tbase = c->v.tbase;
   A.gpart = c->d_gpart.as<float>();
-  // four private copies while four workgroups of them fit the CU's 160 KB of LDS;
-  // beyond that one shared copy (deterministic mode keeps the private copies)
-  const bool shared = !c->det && sizeof(float) * (size_t)nodes * 4 * 4 > 160 * 1024;
-  const size_t lds = sizeof(float) * (size_t)nodes * (shared ? 1 : 4);
+  // the most copies (4, 2 or 1) of which four workgroups fit the CU's 160 KB of LDS
+  // (deterministic mode keeps four private copies)
+  const size_t per = sizeof(float) * (size_t)nodes * 4;  // one copy in four workgroups
+  const int copies = c->det ? 4 : per * 4 <= 160 * 1024 ? 4 : per * 2 <= 160 * 1024 ? 2 : 1;
+  const size_t lds = sizeof(float) * (size_t)nodes * copies;
+  const dim3 grid(c->v.n_order), block(256);
   if (c->det)
-    hipLaunchKernelGGL((k_path_adj<true, false>), dim3(c->v.n_order), dim3(256), lds, c->stream, A);
-  else if (shared)
-    hipLaunchKernelGGL((k_path_adj<false, true>), dim3(c->v.n_order), dim3(256), lds, c->stream, A);
+    hipLaunchKernelGGL((k_path_adj<true, 4>), grid, block, lds, c->stream, A);
+  else if (copies == 4)
+    hipLaunchKernelGGL((k_path_adj<false, 4>), grid, block, lds, c->stream, A);
+  else if (copies == 2)
+    hipLaunchKernelGGL((k_path_adj<false, 2>), grid, block, lds, c->stream, A);
   else
-    hipLaunchKernelGGL((k_path_adj<false, false>), dim3(c->v.n_order), dim3(256), lds, c->stream, A);
+    hipLaunchKernelGGL((k_path_adj<false, 1>), grid, block, lds, c->stream, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_sum_grids(c, c->d_gpart.as<float>(), c->v.n_order, out);
