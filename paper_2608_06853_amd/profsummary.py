@@ -20,7 +20,7 @@ FAMILIES = {
     "zero_tx": (r"k_zero_tx\(", "k_das.hip"),
     "das_rx": (r"k_das_rx<", "k_das.hip"),
     "loc": (r"k_loc\(", "k_das.hip"),
-    "cmpe": (r"k_cmpe\(", "k_cmpe.hip"),
+    "cmpe": (r"k_cmpe[<(]", "k_cmpe.hip"),
     "gscale": (r"k_gscale\(", "k_misc.hip"),
     "path_adj": (r"k_path_adj[<(]", "k_path.hip"),
     "path_chunk": (r"k_path_chunk\(", "k_path.hip"),
