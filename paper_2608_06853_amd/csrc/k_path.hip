@@ -6,15 +6,17 @@
 // A workgroup takes one tile of points and every active element of it; a
 // wavefront walks the rays from the elements to its 64 points in lock step.  The
 // rays are nearly parallel, so at a given step the lanes usually sit in one grid
-// cell: the 16 tap weights are then summed across the wavefront with a
-// reduce-scatter (17 lane shuffles) and 16 lanes add the sums to the
-// wavefront's private copy of the padded grid with plain LDS read-add-writes
-// (no LDS atomics).  Lanes spread over two neighbouring cells are summed as one
-// window of 4 x 5 or 5 x 4 nodes; lanes spread wider are handled one cell at a
-// time.  The rays of four neighbouring elements are walked together and summed by
-// the same reduce whenever their cells allow it (else by pairs).  The copies are summed into one
-// partial grid per workgroup, and a second kernel adds the partial grids node by
-// node in a fixed order.
+// cell.  Consecutive such steps add the 16 moments c g^b f^a of their ray points
+// (f, g: the fractions in the cell) into registers; when the cell changes, the
+// moments are summed across the wavefront with a reduce-scatter, turned into the
+// 16 tap sums by the Keys coefficients (lane rotations and row exchanges), and 16
+// lanes add them to an LDS copy of the padded grid with LDS float atomics.  Lanes
+// spread over two neighbouring cells are summed as one window of 4 x 5 or 5 x 4
+// nodes; lanes spread wider are handled one cell at a time.  The rays of four
+// neighbouring elements are walked together and summed by the same reduce whenever
+// their cells allow it (else by pairs).  The copies are summed into one partial
+// grid per workgroup, and a second kernel adds the partial grids node by node in a
+// fixed order.
 #include "af_internal.h"
 
 namespace af {
@@ -41,8 +43,12 @@ template <int CTRL>
 __device__ inline float dpp(float x) {
   return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), CTRL, 0xf, 0xf, false));
 }
+template <int CTRL>
+__device__ inline int dppi(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xf, 0xf, false);
+}
 constexpr int DPP_ROR8 = 0x128, DPP_HALF_MIRROR = 0x141, DPP_XOR2 = 0x4e, DPP_XOR1 = 0xb1;
-constexpr int DPP_ROR4 = 0x124, DPP_ROR2 = 0x122, DPP_ROR1 = 0x121;
+constexpr int DPP_ROR12 = 0x12c, DPP_ROR4 = 0x124, DPP_ROR2 = 0x122, DPP_ROR1 = 0x121;
 
 // Sum over the wavefront of v[i], i = 0..15: every lane returns the sum of
 // v[(l >> 2) & 15] (bit 3 of the index is lane bit 5, bit 2 lane bit 4, bit 1
@@ -81,11 +87,72 @@ __device__ inline float reduce_scatter16(float v[16], int lane) {
 // shared by the workgroup's wavefronts the order of their adds varies.
 __device__ inline void lds_add(float* p, float v) { atomicAdd(p, v); }
 
-// Adds the 16 tap sums of acc (summed over the wavefront) to the wavefront's grid
-// copy at cell c; acc is consumed.
-__device__ inline void flush16(float* grid, int c, float (&acc)[16], int lane, int my_off) {
-  const float sum = reduce_scatter16(acc, lane);
-  if ((lane & 3) == 0) lds_add(grid + c + my_off, sum);
+// The value of x in the lane of the same column whose row (lane bits 4-5) differs
+// by 1 (exch16) or by 2 (exch32).
+__device__ inline float exch16(float x) {
+  float a = x, b = x;
+  swap16(a, b);  // a: rows 0, 0, 2, 2 of x; b: rows 1, 1, 3, 3
+  return (threadIdx.x & 16) ? a : b;
+}
+__device__ inline float exch32(float x) {
+  float a = x, b = x;
+  swap32(a, b);  // a: lower half of x twice; b: upper half twice
+  return (threadIdx.x & 32) ? a : b;
+}
+
+// Coefficient of f^pw in the Keys weight of tap t (nodes j0 - 1 .. j0 + 2) at
+// fraction f: the rows of keys_weights written out as polynomials.
+__device__ inline float keys_coef(int t, int pw) {
+  const float t0 = pw == 1 ? -0.5f : pw == 2 ? 1.0f : pw == 3 ? -0.5f : 0.0f;
+  const float t1 = pw == 0 ? 1.0f : pw == 2 ? -2.5f : pw == 3 ? 1.5f : 0.0f;
+  const float t2 = pw == 1 ? 0.5f : pw == 2 ? 2.0f : pw == 3 ? -1.5f : 0.0f;
+  const float t3 = pw == 2 ? -0.5f : pw == 3 ? 0.5f : 0.0f;
+  return t == 0 ? t0 : t == 1 ? t1 : t == 2 ? t2 : t3;
+}
+
+// Per-lane coefficients of the moment flush.  After the reduce-scatter lane l holds
+// the moment of value index (l >> 2) & 15 = 4 b + a (b: power of the z fraction,
+// lane bits 4-5; a: power of the x fraction, lane bits 2-3), and it finishes with
+// the tap (r, c) = (b, a) of its own lane position.  kx[d] is the Keys coefficient
+// of tap c for the power held by the lane the d-th row rotation reads; kz[d] that of
+// tap r for the power held by the lane the d-th row exchange reads.  The sources
+// are found by applying the same moves to the lane's own indices.
+struct MomentCoef {
+  float kx[4], kz[4];
+};
+__device__ inline MomentCoef moment_coef(int lane) {
+  const int tap = (lane >> 2) & 15, c = tap & 3, r = tap >> 2;
+  MomentCoef m;
+  m.kx[0] = keys_coef(c, c);
+  m.kx[1] = keys_coef(c, dppi<DPP_ROR4>(c));
+  m.kx[2] = keys_coef(c, dppi<DPP_ROR8>(c));
+  m.kx[3] = keys_coef(c, dppi<DPP_ROR12>(c));
+  const float rf = (float)r;
+  const float r2 = exch32(rf);
+  m.kz[0] = keys_coef(r, r);
+  m.kz[1] = keys_coef(r, (int)exch16(rf));
+  m.kz[2] = keys_coef(r, (int)r2);
+  m.kz[3] = keys_coef(r, (int)exch16(r2));
+  return m;
+}
+
+// Adds the tap sums of the moments in acc (summed over the wavefront) to the grid
+// copy at cell c: the reduce-scatter leaves each lane one moment; the Keys
+// coefficients are applied along x by rotations inside the row and along z by
+// exchanges between rows.  acc is consumed.
+__device__ inline void flush_moments(float* grid, int c, float (&acc)[16], int lane, int my_off,
+                                     const MomentCoef& K) {
+  const float m = reduce_scatter16(acc, lane);
+  float n = K.kx[0] * m;
+  n = fmaf(K.kx[1], dpp<DPP_ROR4>(m), n);
+  n = fmaf(K.kx[2], dpp<DPP_ROR8>(m), n);
+  n = fmaf(K.kx[3], dpp<DPP_ROR12>(m), n);
+  const float n2 = exch32(n);
+  float w = K.kz[0] * n;
+  w = fmaf(K.kz[1], exch16(n), w);
+  w = fmaf(K.kz[2], n2, w);
+  w = fmaf(K.kz[3], exch16(n2), w);
+  if ((lane & 3) == 0) lds_add(grid + c + my_off, w);
 }
 
 // Sum over the wavefront of v[r], r = 0..3: every lane returns the sum of
@@ -136,6 +203,26 @@ __device__ inline int ray_point(const Ray& r, int k, int nseg, float umax, float
   const int cell = ray_pos(r, k, umax, vmax, W, u, v);
   ray_weights(r, k, nseg, u, v, az, wx);
   return cell;
+}
+
+// Ray point k of one element in moment form: acc[4 b + a] += c_k g^b f^a, with f and
+// g the x and z fractions of the point in its cell and c_k the ray's adjoint weight
+// (halved at both ends of the trapezoid).  Every Keys weight is a cubic in its
+// fraction, so the tap sums of points in one cell are fixed linear combinations of
+// these 16 moments (applied once per cell by flush_moments).
+__device__ inline void ray_moments(const Ray& r, int k, int nseg, float u, float v,
+                                   float (&acc)[16]) {
+  const float f = __builtin_amdgcn_fractf(u), g = __builtin_amdgcn_fractf(v);  // u, v >= 0
+  const float f2 = f * f, f3 = f2 * f;
+  float gb = (k == 0 || k == nseg) ? 0.5f * r.coef : r.coef;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    acc[4 * b] += gb;
+    acc[4 * b + 1] = fmaf(gb, f, acc[4 * b + 1]);
+    acc[4 * b + 2] = fmaf(gb, f2, acc[4 * b + 2]);
+    acc[4 * b + 3] = fmaf(gb, f3, acc[4 * b + 3]);
+    if (b < 3) gb *= g;
+  }
 }
 
 // NR ray points per lane whose cells lie in two neighbouring cells, cb and cb + 1
@@ -318,6 +405,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   // tap (r, c) of value index i = 4 r + c; this lane's reduced tap
   const int my_tap = (lane >> 2) & 15;
   const int my_off = (my_tap >> 2) * W + (my_tap & 3);
+  const MomentCoef kc = moment_coef(lane);
 
   // Elements four at a time: the rays of neighbouring elements to the same points
   // run side by side, so at a step their ray points usually share one cell (or two
@@ -364,7 +452,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       const int lead01 = __ffsll((long long)(lm[0] | lm[1])) - 1;
       const int lead23 = __ffsll((long long)(lm[2] | lm[3])) - 1;
       // Consecutive steps whose ray points all lie in one cell, the same cell, add
-      // their products into acc and share one reduce (flushed when the cell changes
+      // their moments into acc and share one reduce (flushed when the cell changes
       // or a step spreads over more cells).
       // acc is all zeros whenever c_acc is -1, so a step that falls back below holds
       // no pending sums in registers.
@@ -389,21 +477,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
         if (__ballot(!one) == 0ull) {  // the usual case: one cell for the whole wavefront
           if (c0 != c_acc && c_acc >= 0) {
-            flush16(grid, c_acc, acc, lane, my_off);
+            flush_moments(grid, c_acc, acc, lane, my_off, kc);
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[i] = 0.f;
           }
           c_acc = c0;
 #pragma unroll
-          for (int n = 0; n < 4; ++n) {
-            float az[4], wx[4];
-            ray_weights(R[n], k, g.n_seg, u[n], v[n], az, wx);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) acc[i] = fmaf(az[i >> 2], wx[i & 3], acc[i]);
-          }
+          for (int n = 0; n < 4; ++n) ray_moments(R[n], k, g.n_seg, u[n], v[n], acc);
           continue;
         }
-        if (c_acc >= 0) flush16(grid, c_acc, acc, lane, my_off);
+        if (c_acc >= 0) flush_moments(grid, c_acc, acc, lane, my_off, kc);
         c_acc = -1;
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[i] = 0.f;
@@ -423,7 +506,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                        a2, w2, lane, my_off);
         }
       }
-      if (c_acc >= 0) flush16(grid, c_acc, acc, lane, my_off);
+      if (c_acc >= 0) flush_moments(grid, c_acc, acc, lane, my_off, kc);
       continue;
     }
     // some element of the four has no work in this wavefront: pairs and singles
