@@ -57,6 +57,7 @@ struct TableArgs {
   const int2* prange;     // active element range [lo, hi] of each point
   const int4* tiles;      // (LO, HI, bLO, bHI)
   const int2* work;       // (tile, first element of a chunk of TAB_CHUNK)
+  int n_work;             // work items
   const float* gdev;      // padded deviation grid s - s_med
   const double* scal;     // scal[0] = c_med, scal[1] = s_med
   TabEntry* tab;          // [n_elem][P]

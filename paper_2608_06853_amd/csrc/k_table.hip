@@ -17,25 +17,83 @@ namespace {
 constexpr int TAB_LDS_W = 67;
 constexpr size_t TAB_LDS_BYTES = 160 * 1024;  // LDS of one workgroup on gfx950
 
+// Layouts of the slowness deviation in LDS: the padded node grid at its own row
+// stride, the same at the fixed stride TAB_LDS_W (grids with nx + 3 <= TAB_LDS_W:
+// the 16 taps of a path point are then immediate offsets from one address), or the
+// row polynomials of the cells (ROWPOLY).
+enum { GRID_W = 0, GRID_FIXED = 1, ROWPOLY = 2 };
+
+// Row polynomials: along a row of the padded grid, the Keys interpolation inside
+// cell column j0 (nodes j0 - 1 .. j0 + 2, values g0..g3) is the cubic
+// q.x + q.y f + q.z f^2 + q.w f^3 in the fraction f, with the Keys weights'
+// coefficients folded into q.  Stored column-major, [j0][padded row], so the four
+// rows a path point needs are 64 contiguous bytes.
+__device__ __forceinline__ float4 row_poly(float g0, float g1, float g2, float g3) {
+  return make_float4(g1, 0.5f * (g2 - g0), fmaf(-2.5f, g1, g0) + fmaf(2.0f, g2, -0.5f * g3),
+                     1.5f * (g1 - g2) + 0.5f * (g3 - g0));
+}
+
+// path_sum over the row polynomials H ([nx][R] float4, R = nz + 3 padded rows): per
+// point four rows by Horner in the x fraction, then the Keys weights in z.
+__device__ __forceinline__ float path_sum_rowpoly(const float4* H, int R, float u0, float v0,
+                                                  float du, float dv, int nseg, float umax,
+                                                  float vmax) {
+  float acc = 0.f, first = 0.f, last = 0.f;
+  for (int k = 0; k <= nseg; ++k) {
+    const float u = __builtin_amdgcn_fmed3f(fmaf((float)k, du, u0), 0.f, umax);
+    const float v = __builtin_amdgcn_fmed3f(fmaf((float)k, dv, v0), 0.f, vmax);
+    const int j0 = (int)u, i0 = (int)v;
+    const float f = __builtin_amdgcn_fractf(u);  // u, v >= 0: u - j0
+    float wz0, wz1, wz2, wz3;
+    keys_weights(__builtin_amdgcn_fractf(v), wz0, wz1, wz2, wz3);
+    const float4* q = H + j0 * R + i0;
+    float r[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float4 c = q[i];
+      r[i] = fmaf(fmaf(fmaf(c.w, f, c.z), f, c.y), f, c.x);
+    }
+    const float val = wz0 * r[0] + wz1 * r[1] + wz2 * r[2] + wz3 * r[3];
+    acc += val;
+    if (k == 0) first = val;
+    if (k == nseg) last = val;
+  }
+  return acc - 0.5f * (first + last);
+}
+
 // One instantiation per refraction mode (arc or flat lens, root or discrete
-// search), so the default mode keeps its own register allocation; FIXED_W copies
-// the grid at row stride TAB_LDS_W (grids with nx + 3 <= TAB_LDS_W).
-template <int MODE, bool FIXED_W>
-__global__ __launch_bounds__(256) void k_table(TableArgs A) {
+// search), so the default mode keeps its own register allocation, and per layout.
+// A workgroup of ITEMS x 256 threads takes ITEMS consecutive work items (one point
+// per thread) over one LDS copy: two items let a large row-polynomial copy serve
+// twice the wavefronts.
+template <int MODE, int LAYOUT, int ITEMS>
+__global__ __launch_bounds__(256 * ITEMS) __attribute__((amdgpu_waves_per_eu(ITEMS == 1 ? 6 : 4)))
+void k_table(TableArgs A) {
   extern __shared__ float G[];
   const Geo& g = A.g;
-  const int2 w = A.work[blockIdx.x];
-  const int tile = w.x, a0 = w.y;
-  const int4 tr = A.tiles[tile];
-  const int WL = FIXED_W ? TAB_LDS_W : g.W;
-  const int gsz = WL * (g.nz + 3);
-  for (int i = threadIdx.x; i < gsz; i += 256) {
-    const int r = i / WL, c = i - r * WL;
-    G[i] = c < g.W ? A.gdev[r * g.W + c] : 0.f;
+  const int WL = LAYOUT == GRID_FIXED ? TAB_LDS_W : g.W;
+  const int RP = g.nz + 3;
+  if (LAYOUT == ROWPOLY) {
+    float4* H = reinterpret_cast<float4*>(G);
+    for (int i = threadIdx.x; i < g.nx * RP; i += 256 * ITEMS) {
+      const int j0 = i / RP, r = i - j0 * RP;
+      const float* row = A.gdev + r * g.W + j0;
+      H[i] = row_poly(row[0], row[1], row[2], row[3]);
+    }
+  } else {
+    for (int i = threadIdx.x; i < WL * RP; i += 256 * ITEMS) {
+      const int r = i / WL, c = i - r * WL;
+      G[i] = c < g.W ? A.gdev[r * g.W + c] : 0.f;
+    }
   }
   __syncthreads();
+  const int item = blockIdx.x * ITEMS + (int)(threadIdx.x >> 8);
+  if (item >= A.n_work) return;  // the last workgroup's second item (no barrier follows)
+  const int2 w = A.work[item];
+  const int tile = w.x, a0 = w.y;
+  const int4 tr = A.tiles[tile];
 
-  const long long p = (long long)tile * TILE + threadIdx.x;
+  const long long p = (long long)tile * TILE + (threadIdx.x & 255);
   const int2 pr = A.prange[p];
   const double4 pp = A.ptpol[p];
   const float2 pxy = A.ptxy[p];
@@ -69,8 +127,12 @@ __global__ __launch_bounds__(256) void k_table(TableArgs A) {
       float dT = 0.f;
       double uh = 0.0;
       if (ok) {
-        const float acc = path_sum(G, WL, u0, v0, (up - u0) * inv_n, (vp - v0) * inv_n,
-                                   g.n_seg, umax, vmax);
+        const float acc =
+            LAYOUT == ROWPOLY
+                ? path_sum_rowpoly(reinterpret_cast<const float4*>(G), RP, u0, v0,
+                                   (up - u0) * inv_n, (vp - v0) * inv_n, g.n_seg, umax, vmax)
+                : path_sum(G, WL, u0, v0, (up - u0) * inv_n, (vp - v0) * inv_n, g.n_seg, umax,
+                           vmax);
         dT = r.l2 * acc * inv_n;
         uh = (r.t_hom + u_off) * g.fs;
         ok = fabs(uh) < 268435456.0 && fabsf(dT * fsf) < 268435456.f;  // 2^28; false for NaN
@@ -114,22 +176,33 @@ hipError_t launch_table(af_ctx* c) {
   A.prange = c->v.prange;
   A.tiles = c->v.tiles;
   A.work = c->v.tabwork;
+  A.n_work = c->v.n_tab_work;
   A.gdev = c->d_gdev.as<float>();
   A.scal = c->d_scal.as<double>();
   A.tab = c->d_tab.as<TabEntry>();
   A.ray_uv = c->d_ray_uv.as<float2>();
   A.ray_l2 = c->d_ray_l2.as<float>();
   if (c->v.n_tab_work == 0) return hipSuccess;
-  // the fixed row stride only where its copy fits the LDS of a workgroup
+  // The row polynomials where six 256-thread workgroups fit a CU's LDS, or two of
+  // 512 threads; else the padded grid at the fixed row stride where its copy fits
+  // the LDS of a workgroup, else at the grid's own.
+  const size_t poly = sizeof(float4) * (size_t)c->nx * (c->nz + 3);
   const bool fixed = c->nx + 3 <= TAB_LDS_W &&
                      sizeof(float) * (size_t)TAB_LDS_W * (c->nz + 3) <= TAB_LDS_BYTES;
-  const size_t lds = sizeof(float) * (size_t)(fixed ? TAB_LDS_W : c->nx + 3) * (c->nz + 3);
-  const dim3 grid(c->v.n_tab_work), block(256);
-#define AF_TABLE_LAUNCH(M)                                                        \
-  if (fixed)                                                                      \
-    hipLaunchKernelGGL((k_table<M, true>), grid, block, lds, c->stream, A);      \
-  else                                                                            \
-    hipLaunchKernelGGL((k_table<M, false>), grid, block, lds, c->stream, A);
+  const int layout = poly * 2 <= TAB_LDS_BYTES ? ROWPOLY : fixed ? GRID_FIXED : GRID_W;
+  const int items = layout == ROWPOLY && poly * 6 > TAB_LDS_BYTES ? 2 : 1;
+  const size_t lds = layout == ROWPOLY ? poly
+                     : sizeof(float) * (size_t)(fixed ? TAB_LDS_W : c->nx + 3) * (c->nz + 3);
+  const dim3 grid((c->v.n_tab_work + items - 1) / items), block(256 * items);
+#define AF_TABLE_LAUNCH(M)                                                          \
+  if (layout == ROWPOLY && items == 2)                                              \
+    hipLaunchKernelGGL((k_table<M, ROWPOLY, 2>), grid, block, lds, c->stream, A);  \
+  else if (layout == ROWPOLY)                                                       \
+    hipLaunchKernelGGL((k_table<M, ROWPOLY, 1>), grid, block, lds, c->stream, A);  \
+  else if (layout == GRID_FIXED)                                                    \
+    hipLaunchKernelGGL((k_table<M, GRID_FIXED, 1>), grid, block, lds, c->stream, A); \
+  else                                                                              \
+    hipLaunchKernelGGL((k_table<M, GRID_W, 1>), grid, block, lds, c->stream, A);
   switch (refract_mode(A.g.flat != 0, A.g.nsearch, A.g.dlens)) {
     case ARC_ROOT: AF_TABLE_LAUNCH(ARC_ROOT); break;
     case ARC_SEARCH: AF_TABLE_LAUNCH(ARC_SEARCH); break;
