@@ -90,14 +90,13 @@ __device__ inline RayOut trace_lens(double R, double sa, double ca, double rho, 
   float x = fminf(fmaxf(asinf(si1g), lo), hi);
   float lx = 0.f, lz = Rf + (float)(RL - R);
 #pragma unroll
-  for (int it = 0; it < 4; ++it) {
+  // Two safeguarded Newton updates in FP32 with the hardware sine and cosine: the
+  // FP64 step below converges quadratically from there, and T is stationary in the
+  // refraction angle, so the time is exact to FP32 rounding.
+  for (int it = 0; it < 3; ++it) {
     float s, c;
-    if (it < 3) {
-      s = __sinf(x);
-      c = __cosf(x);
-    } else {
-      sincosf(x, &s, &c);
-    }
+    s = __sinf(x);
+    c = __cosf(x);
     const float Q = sqrtf(Rf * Rf * c * c + d2f);
     const float iQ = __builtin_amdgcn_rcpf(Q);
     const float L1 = d2f * __builtin_amdgcn_rcpf(Rf * c + Q);
@@ -118,7 +117,7 @@ __device__ inline RayOut trace_lens(double R, double sa, double ca, double rho, 
     const float dsi2 = dcr * iL2 - cr * vdv * iL2 * iL2 * iL2;
     const float g = si1 * iclf - si2 * icmf;
     const float dg = dsi1 * iclf - dsi2 * icmf;
-    if (it == 3) break;  // (lx, lz) is the lens point at the converged alpha
+    if (it == 2) break;  // (lx, lz) is the lens point at the last alpha
     if (g < 0.f) lo = x; else hi = x;
     const float nw = x - g * __builtin_amdgcn_rcpf(dg);
     x = (nw >= lo && nw <= hi) ? nw : 0.5f * (lo + hi);
