@@ -21,9 +21,12 @@ pytestmark = pytest.mark.gpu
 # curvilinear case with timing offsets, a grid wider than 64 nodes; the
 # conventional model of Eq. 6 (curvilinear and linear) and the model without lens
 # correction, both beamforming data of the physical lens; the configured CMPE
-# threshold 0.9; a tall, narrow grid (4 x 700 nodes) whose fixed-stride copy
-# would not fit in LDS; and a linear array whose deep pixels span up to 24 blocks
-# (more than the CMPE stage stages in LDS: those tiles run it from device memory).
+# threshold 0.9; a tall, narrow grid (4 x 700 nodes: its 45 KB of row polynomials
+# take the table kernel's two-item workgroups); two grids whose row polynomials
+# exceed two copies per CU (over 80 KB), so the table kernel reads the padded grid:
+# 16 x 400 nodes at the fixed row stride, 66 x 80 nodes at its own; and a linear
+# array whose deep pixels span up to 24 blocks (more than the CMPE stage stages in
+# LDS: those tiles run it from device memory).
 CASES = [("micro", 0.0, 0.0, 3, None), ("c1_small", 0.0, 0.0, 3, None),
          ("micro", 0.7, 0.35, 3, None), ("micro", 0.0, 0.0, 1, 2),
          ("micro", 0.0, 0.0, 3, None, 0.01, 0.0), ("micro", 0.0, 0.5, 3, None, 0.01, 0.0),
@@ -39,6 +42,8 @@ CASES = [("micro", 0.0, 0.0, 3, None), ("c1_small", 0.0, 0.0, 3, None),
          ("micro", 0.0, 0.0, 3, None, 0.01, None, 0, None, "bent", 0.9),
          ("c1_small", 0.0, 0.0, 3, None, 0.01, None, 0, None, "bent", 0.9),
          ("micro", 0.0, 0.0, 3, None, 0.01, None, 0, 4, "bent", 0.5, 700),
+         ("micro", 0.0, 0.0, 3, None, 0.01, None, 0, 16, "bent", 0.5, 400),
+         ("micro", 0.0, 0.0, 3, None, 0.01, None, 0, 66, "bent", 0.5, 80),
          ("wide_linear", 0.0, 0.0, 3, None)]
 IDS = ["-".join(str(v) for v in k) for k in CASES]
 
