@@ -1246,8 +1246,8 @@ af_status af_simulate(af_ctx* c, int n_scat, const double* scat_xz, const float*
     if (!(x >= x0 && x <= x1 && z >= z0 && z <= z1))
       return fail(c, AF_ERR_ARG, "af_simulate: grid does not cover every scatterer");
   }
-  if ((size_t)2 * c->Ns * sizeof(float) > 64 * 1024)
-    return fail(c, AF_ERR_ARG, "af_simulate: records longer than 8192 samples");
+  if ((size_t)2 * c->Ns * sizeof(unsigned long long) > 160 * 1024)
+    return fail(c, AF_ERR_ARG, "af_simulate: records longer than 10240 samples");
   AF_HIP(hipSetDevice(c->device), "hipSetDevice");
   af_status st = check_slowness(c, s_true, (size_t)nx * nz, "af_simulate");
   if (st != AF_OK) return st;

@@ -34,13 +34,23 @@ __global__ __launch_bounds__(256) void k_sim_times(Geo g, SimGeo sgeo, const dou
   T[(long long)a * n_scat + k] = r.t_hom + (double)(r.l2 * acc * inv_n);
 }
 
+// The echoes of all scatterers are summed into the record in 64-bit fixed point
+// (units of 2^-32): integer adds commute, so the record is the same on every run
+// whatever order the threads' atomic adds land in (float adds would round
+// differently), and the simulated channel data repeat bit for bit.
+constexpr double SIM_FIX = 4294967296.0;  // 2^32
+
+__device__ inline unsigned long long sim_fixed(float v) {
+  return (unsigned long long)__double2ll_rn((double)v * SIM_FIX);  // |v| < 2^31
+}
+
 __global__ __launch_bounds__(256) void k_sim_synth(Geo g, const double* __restrict__ T, int n_scat,
                                                    const float* __restrict__ amp, double sigma,
                                                    float2* __restrict__ iq) {
-  extern __shared__ float rec[];  // [2 * ns]
+  extern __shared__ unsigned long long rec[];  // [2 * ns], fixed point
   const int t = blockIdx.x / g.n_elem, r = blockIdx.x % g.n_elem;
   const int ns = g.ns;
-  for (int i = threadIdx.x; i < 2 * ns; i += 256) rec[i] = 0.f;
+  for (int i = threadIdx.x; i < 2 * ns; i += 256) rec[i] = 0ull;
   __syncthreads();
   const double half = 6.0 * sigma;
   const float inv2s2 = (float)(0.5 / (sigma * sigma));
@@ -60,13 +70,15 @@ __global__ __launch_bounds__(256) void k_sim_synth(Geo g, const double* __restri
     for (int n = n0; n <= n1; ++n) {
       const float dt = (float)(g.t0 + n / g.fs - tau);
       const float e = __expf(-dt * dt * inv2s2);
-      atomicAdd(&rec[2 * n], e * px);
-      atomicAdd(&rec[2 * n + 1], e * py);
+      atomicAdd(&rec[2 * n], sim_fixed(e * px));
+      atomicAdd(&rec[2 * n + 1], sim_fixed(e * py));
     }
   }
   __syncthreads();
   float2* out = iq + ((long long)t * g.n_elem + r) * ns;
-  for (int i = threadIdx.x; i < ns; i += 256) out[i] = make_float2(rec[2 * i], rec[2 * i + 1]);
+  for (int i = threadIdx.x; i < ns; i += 256)
+    out[i] = make_float2((float)((double)(long long)rec[2 * i] / SIM_FIX),
+                         (float)((double)(long long)rec[2 * i + 1] / SIM_FIX));
 }
 
 }  // namespace
@@ -112,7 +124,7 @@ hipError_t launch_simulate(af_ctx* c, int n_scat, const double* scat_xz, const f
                      d_gd.as<float>(), d_sc.as<double>(), d_T.as<double>());
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const double sigma = std::sqrt(2.0 * std::log(2.0)) / (M_PI * frac_bw * fc);
-  hipLaunchKernelGGL(k_sim_synth, dim3(c->N * c->N), dim3(256), sizeof(float) * 2 * c->Ns,
+  hipLaunchKernelGGL(k_sim_synth, dim3(c->N * c->N), dim3(256), sizeof(unsigned long long) * 2 * c->Ns,
                      c->stream, g, d_T.as<double>(), n_scat, d_amp.as<float>(), sigma, iq);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // temporaries are freed after the stream drains

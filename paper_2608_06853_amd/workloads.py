@@ -66,12 +66,14 @@ def simulate(bf: af.Beamformer, cfg, med, cover) -> torch.Tensor:
     return iq
 
 
-def build(cfg, seed=None, device: int = 0, lens_model: str = "bent"):
+def build(cfg, seed=None, device: int = 0, lens_model: str = "bent",
+          deterministic: bool = False):
     """(Beamformer of ``lens_model`` at a uniform 1/c_ref slowness, channel data,
     medium).  The channel data always come from the bent-ray physics of the lens
-    (the library's simulator uses the physical lens whatever the lens model)."""
+    (the library's simulator uses the physical lens whatever the lens model);
+    ``deterministic`` fixes the gradient's reduction order."""
     acqd, imgd, grid, cover = geometry(cfg, lens_model)
-    bf = af.Beamformer(acqd, imgd, grid, device)
+    bf = af.Beamformer(acqd, imgd, grid, device, deterministic=deterministic)
     med = afsynth.medium_for(cfg, seed)
     iq = simulate(bf, cfg, med, cover)
     bf.set_slowness(torch.full(grid.shape, 1.0 / cfg.img.c_ref, device=bf.device))

@@ -289,3 +289,8 @@ def test_simulator_matches_oracle(name):
     e = G.rel(got, iq_o)
     print("sim rel err", e, flush=True)
     assert e < 2e-3
+    # the echoes are summed in fixed point: a second run gives the same data bit for bit
+    out2 = torch.empty_like(out)
+    bf.ctx.simulate(med.scat_xz, med.scat_amp.astype(np.float32), nx, nz, x0, z0, dx, dz,
+                    torch.from_numpy(s_true).cuda(), 64, acq.fc, acq.frac_bw, out2)
+    assert torch.equal(out, out2)
