@@ -289,7 +289,8 @@ af_status af_travel_times(af_ctx* ctx, float* t_dev);
  * frac_bw truncated at 6 sigma, phase exp(-j 2 pi fd tau).  Uses the geometry,
  * lens and acquisition of af_set_geometry / af_set_lens.  The echoes are summed
  * in 64-bit fixed point (2^-32), so the output repeats bit for bit from run to
- * run; records of up to 10240 samples (AF_ERR_ARG beyond).
+ * run; records of up to 10240 samples, and the sum of |amp| below 2^31
+ * (AF_ERR_ARG otherwise, also for amplitudes that are not finite).
  *   scat_xz [n_scat][2] float64, amp [n_scat] float32 (host);
  *   s_true_dev [nz][nx] float32 (device) on the node grid (x0, z0, dx, dz);
  *   iq_dev [n_elem][n_elem][n_samples] output (device, overwritten). */

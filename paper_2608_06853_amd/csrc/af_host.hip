@@ -1248,6 +1248,12 @@ af_status af_simulate(af_ctx* c, int n_scat, const double* scat_xz, const float*
   }
   if ((size_t)2 * c->Ns * sizeof(unsigned long long) > 160 * 1024)
     return fail(c, AF_ERR_ARG, "af_simulate: records longer than 10240 samples");
+  // the fixed-point record holds sums of magnitude below 2^31; the envelope is at
+  // most 1, so the sum of |amp| bounds every sample
+  double amp_sum = 0.0;
+  for (int k = 0; k < n_scat; ++k) amp_sum += std::fabs((double)amp[k]);
+  if (!(amp_sum < 2147483648.0))
+    return fail(c, AF_ERR_ARG, "af_simulate: amplitudes not finite or their sum not below 2^31");
   AF_HIP(hipSetDevice(c->device), "hipSetDevice");
   af_status st = check_slowness(c, s_true, (size_t)nx * nz, "af_simulate");
   if (st != AF_OK) return st;

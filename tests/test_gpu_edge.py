@@ -204,3 +204,30 @@ def test_non_finite_or_non_positive_slowness_is_reported():
     terms, grad = bf.loss_and_grad(iq_d, lpl, torch.from_numpy(s).cuda())
     f, go = model.loss_and_grad(prob, s.astype(np.float64), lp)
     assert G.rel(grad.cpu().numpy(), go) < 1e-3
+
+
+def test_simulator_amplitudes_out_of_range_are_rejected():
+    """The simulator sums echoes in fixed point with a range of 2^31: amplitudes that
+    are not finite, or whose absolute sum reaches that range, are rejected."""
+    import torch
+    import afsynth
+    from paper_2608_06853_amd import _lib
+    cfg = afsynth.config_by_name("micro")
+    med = afsynth.medium_for(cfg)
+    cfg_, prob, iq, s, lp = G.case("micro")
+    bf = G.beamformer(cfg_, prob)
+    arr, acq = cfg.array, cfg.acq
+    centres = afsynth.pixel_centres(arr, cfg.img)
+    sp = afsynth.patch_spacing(cfg.img, acq)
+    x0, z0, dx, dz, nx, nz = afsynth.sim_box(arr, np.concatenate([centres, med.scat_xz]), sp,
+                                             cfg.sim_spacing)
+    s_true = torch.from_numpy((1.0 / afsynth.speed_on_grid(med, x0, z0, dx, dz, nx, nz))
+                              .astype(np.float32)).cuda()
+    out = torch.empty(iq.size, device="cuda", dtype=torch.complex64)
+    n = len(med.scat_amp)
+    for amp in (np.full(n, np.inf), np.full(n, np.nan), np.full(n, 2.0 ** 32 / n)):
+        print("simulator amplitudes", amp[0], flush=True)
+        with pytest.raises(_lib.AfError) as e:
+            bf.ctx.simulate(med.scat_xz, amp.astype(np.float32), nx, nz, x0, z0, dx, dz, s_true,
+                            64, acq.fc, acq.frac_bw, out)
+        assert e.value.status == _lib.AF_ERR_ARG
