@@ -87,6 +87,10 @@ __device__ inline float reduce_scatter16(float v[16], int lane) {
 // shared by the workgroup's wavefronts the order of their adds varies.
 __device__ inline void lds_add(float* p, float v) { atomicAdd(p, v); }
 
+__device__ inline float readlane_f(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
 // The value of x in the lane of the same column whose row (lane bits 4-5) differs
 // by 1 (exch16) or by 2 (exch32).
 __device__ inline float exch16(float x) {
@@ -209,12 +213,14 @@ __device__ inline int ray_point(const Ray& r, int k, int nseg, float umax, float
 // g the x and z fractions of the point in its cell and c_k the ray's adjoint weight
 // (halved at both ends of the trapezoid).  Every Keys weight is a cubic in its
 // fraction, so the tap sums of points in one cell are fixed linear combinations of
-// these 16 moments (applied once per cell by flush_moments).
-__device__ inline void ray_moments(const Ray& r, int k, int nseg, float u, float v,
+// these 16 moments (applied once per cell by flush_moments).  A ray point with
+// `in` false adds zeros.
+__device__ inline void ray_moments(const Ray& r, int k, int nseg, float u, float v, bool in,
                                    float (&acc)[16]) {
   const float f = __builtin_amdgcn_fractf(u), g = __builtin_amdgcn_fractf(v);  // u, v >= 0
   const float f2 = f * f, f3 = f2 * f;
   float gb = (k == 0 || k == nseg) ? 0.5f * r.coef : r.coef;
+  gb = in ? gb : 0.f;
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     acc[4 * b] += gb;
@@ -449,13 +455,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     for (int n = 0; n < 4; ++n) leads[n] = __ffsll((long long)lm[n]) - 1;
     if (lm[0] != 0ull && lm[1] != 0ull && lm[2] != 0ull && lm[3] != 0ull) {
       const int lead = __ffsll((long long)all) - 1;
-      const int lead01 = __ffsll((long long)(lm[0] | lm[1])) - 1;
-      const int lead23 = __ffsll((long long)(lm[2] | lm[3])) - 1;
-      // Consecutive steps whose ray points all lie in one cell, the same cell, add
-      // their moments into acc and share one reduce (flushed when the cell changes
-      // or a step spreads over more cells).
-      // acc is all zeros whenever c_acc is -1, so a step that falls back below holds
-      // no pending sums in registers.
+      // An idle ray (zero weight) takes the geometry of the lane's first live ray,
+      // or in a lane with none, that of the lead lane's first live ray: every ray
+      // point of a step then lies in a cell that a live ray point of the step
+      // occupies, and the lead lane's ray 0 stands for its first live ray.
+      {
+        float fu = R[3].u0, fv = R[3].v0, fdu = R[3].du, fdv = R[3].dv;
+#pragma unroll
+        for (int n = 2; n >= 0; --n)
+          if (R[n].live) {
+            fu = R[n].u0;
+            fv = R[n].v0;
+            fdu = R[n].du;
+            fdv = R[n].dv;
+          }
+        const float lu = readlane_f(fu, lead), lv = readlane_f(fv, lead);
+        const float ldu = readlane_f(fdu, lead), ldv = readlane_f(fdv, lead);
+        if (!(R[0].live || R[1].live || R[2].live || R[3].live)) {
+          fu = lu;
+          fv = lv;
+          fdu = ldu;
+          fdv = ldv;
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+          if (!R[n].live) {
+            R[n].u0 = fu;
+            R[n].v0 = fv;
+            R[n].du = fdu;
+            R[n].dv = fdv;
+          }
+      }
+      // Moments of ray points in one cell accumulate in acc (pending for cell c_acc)
+      // until a step leaves that cell.  A step whose ray points lie in several cells
+      // takes one round per cell, the pending cell first when the step has points
+      // there: each round adds the moments of its cell's points and is flushed,
+      // except the last, whose cell stays pending.
+      // acc is all zeros whenever c_acc is -1.
       float acc[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[i] = 0.f;
@@ -465,16 +501,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         int cell[4];
 #pragma unroll
         for (int n = 0; n < 4; ++n) cell[n] = ray_pos(R[n], k, umax, vmax, W, u[n], v[n]);
-        // a lane's first live ray point; idle ray points join the leader's cell
-        const int mine = R[0].live ? cell[0] : R[1].live ? cell[1] : R[2].live ? cell[2] : cell[3];
-        const int c0 = __builtin_amdgcn_readlane(mine, lead);
-        int cu[4];
+        const int c0 = __builtin_amdgcn_readlane(cell[0], lead);
         bool one = true;
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          cu[n] = R[n].live ? cell[n] : c0;
-          one = one && cu[n] == c0;
-        }
+        for (int n = 0; n < 4; ++n) one = one && cell[n] == c0;
         if (__ballot(!one) == 0ull) {  // the usual case: one cell for the whole wavefront
           if (c0 != c_acc && c_acc >= 0) {
             flush_moments(grid, c_acc, acc, lane, my_off, kc);
@@ -483,28 +513,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
           }
           c_acc = c0;
 #pragma unroll
-          for (int n = 0; n < 4; ++n) ray_moments(R[n], k, g.n_seg, u[n], v[n], acc);
+          for (int n = 0; n < 4; ++n) ray_moments(R[n], k, g.n_seg, u[n], v[n], true, acc);
           continue;
         }
-        if (c_acc >= 0) flush_moments(grid, c_acc, acc, lane, my_off, kc);
-        c_acc = -1;
+        int cur = c0;
+        if (c_acc >= 0) {
+          bool has = false;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-        float az[4][4], wx[4][4];
+          for (int n = 0; n < 4; ++n) has = has || cell[n] == c_acc;
+          if (__ballot(has) != 0ull) {
+            cur = c_acc;
+          } else {
+            flush_moments(grid, c_acc, acc, lane, my_off, kc);
 #pragma unroll
-        for (int n = 0; n < 4; ++n) ray_weights(R[n], k, g.n_seg, u[n], v[n], az[n], wx[n]);
-        if (scatter_union<4>(grid, c0, W, cu, az, wx, lane, my_off)) continue;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int c2[2] = {cell[2 * h], cell[2 * h + 1]};
-          const bool l2[2] = {R[2 * h].live, R[2 * h + 1].live};
-          const float a2[2][4] = {{az[2 * h][0], az[2 * h][1], az[2 * h][2], az[2 * h][3]},
-                                  {az[2 * h + 1][0], az[2 * h + 1][1], az[2 * h + 1][2], az[2 * h + 1][3]}};
-          const float w2[2][4] = {{wx[2 * h][0], wx[2 * h][1], wx[2 * h][2], wx[2 * h][3]},
-                                  {wx[2 * h + 1][0], wx[2 * h + 1][1], wx[2 * h + 1][2], wx[2 * h + 1][3]}};
-          scatter_pair(grid, c2, l2, h == 0 ? lead01 : lead23, leads[2 * h], leads[2 * h + 1], W,
-                       a2, w2, lane, my_off);
+            for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+          }
         }
+        bool left[4] = {true, true, true, true};
+        while (true) {  // every round takes at least one ray point (of the lane cur came from)
+#pragma unroll
+          for (int n = 0; n < 4; ++n) {
+            const bool in = left[n] && cell[n] == cur;
+            ray_moments(R[n], k, g.n_seg, u[n], v[n], in, acc);
+            left[n] = left[n] && !in;
+          }
+          const unsigned long long rest = __ballot(left[0] || left[1] || left[2] || left[3]);
+          if (rest == 0ull) break;
+          flush_moments(grid, cur, acc, lane, my_off, kc);
+#pragma unroll
+          for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+          const int nxt = left[0] ? cell[0] : left[1] ? cell[1] : left[2] ? cell[2] : cell[3];
+          cur = __builtin_amdgcn_readlane(nxt, __ffsll((long long)rest) - 1);
+        }
+        c_acc = cur;
       }
       if (c_acc >= 0) flush_moments(grid, c_acc, acc, lane, my_off, kc);
       continue;
