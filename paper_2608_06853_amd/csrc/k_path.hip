@@ -6,15 +6,16 @@
 // A workgroup takes one tile of points and every active element of it; a
 // wavefront walks the rays from the elements to its 64 points in lock step.  The
 // rays are nearly parallel, so at a given step the lanes usually sit in one grid
-// cell.  Consecutive such steps add the 16 moments c g^b f^a of their ray points
-// (f, g: the fractions in the cell) into registers; when the cell changes, the
-// moments are summed across the wavefront with a reduce-scatter, turned into the
-// 16 tap sums by the Keys coefficients (lane rotations and row exchanges), and 16
-// lanes add them to an LDS copy of the padded grid with LDS float atomics.  Lanes
-// spread over two neighbouring cells are summed as one window of 4 x 5 or 5 x 4
-// nodes; lanes spread wider are handled one cell at a time.  The rays of four
-// neighbouring elements are walked together and summed by the same reduce whenever
-// their cells allow it (else by pairs).  The copies are summed into one partial
+// cell.  Every Keys weight is a cubic in its fraction, so the tap sums of ray
+// points in one cell are fixed combinations of the 16 moments c g^b f^a (f, g: the
+// fractions in the cell, c: the ray point's adjoint weight).  Ray points add their
+// moments into registers until the wavefront leaves the cell; then the moments are
+// summed across the wavefront with a reduce-scatter, turned into the 16 tap sums
+// by the Keys coefficients (lane rotations and row exchanges), and 16 lanes add
+// them to an LDS copy of the padded grid with LDS float atomics.  A step whose ray
+// points lie in several cells takes one such round per cell.  The rays of four
+// neighbouring elements are walked together (pairs or single elements where the
+// aperture edge leaves fewer with work).  The copies are summed into one partial
 // grid per workgroup, and a second kernel adds the partial grids node by node in a
 // fixed order.
 #include "af_internal.h"
@@ -48,7 +49,7 @@ __device__ inline int dppi(int x) {
   return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xf, 0xf, false);
 }
 constexpr int DPP_ROR8 = 0x128, DPP_HALF_MIRROR = 0x141, DPP_XOR2 = 0x4e, DPP_XOR1 = 0xb1;
-constexpr int DPP_ROR12 = 0x12c, DPP_ROR4 = 0x124, DPP_ROR2 = 0x122, DPP_ROR1 = 0x121;
+constexpr int DPP_ROR12 = 0x12c, DPP_ROR4 = 0x124;
 
 // Sum over the wavefront of v[i], i = 0..15: every lane returns the sum of
 // v[(l >> 2) & 15] (bit 3 of the index is lane bit 5, bit 2 lane bit 4, bit 1
@@ -159,23 +160,6 @@ __device__ inline void flush_moments(float* grid, int c, float (&acc)[16], int l
   if ((lane & 3) == 0) lds_add(grid + c + my_off, w);
 }
 
-// Sum over the wavefront of v[r], r = 0..3: every lane returns the sum of
-// v[l >> 4].  The half-wave swaps leave row r (16 lanes) holding value r summed
-// over four lanes; rotations by 8, 4, 2 and 1 inside the row finish the sum.
-__device__ inline float reduce_scatter4(float v[4]) {
-  swap32(v[0], v[2]);  // lower half: value 0; upper half: value 2
-  v[0] += v[2];
-  swap32(v[1], v[3]);  // lower half: value 1; upper half: value 3
-  v[1] += v[3];
-  swap16(v[0], v[1]);  // rows 0, 2: v[0] of both rows; rows 1, 3: v[1] of both rows
-  float h = v[0] + v[1];
-  h += dpp<DPP_ROR8>(h);
-  h += dpp<DPP_ROR4>(h);
-  h += dpp<DPP_ROR2>(h);
-  h += dpp<DPP_ROR1>(h);
-  return h;
-}
-
 // One element's rays from the wavefront's points: start in grid coordinates, step
 // per segment, and the adjoint weight dL/dT * L2 / N of the lane's ray.
 struct Ray {
@@ -189,24 +173,6 @@ __device__ inline int ray_pos(const Ray& r, int k, float umax, float vmax, int W
   u = __builtin_amdgcn_fmed3f(fmaf((float)k, r.du, r.u0), 0.f, umax);
   v = __builtin_amdgcn_fmed3f(fmaf((float)k, r.dv, r.v0), 0.f, vmax);
   return (int)v * W + (int)u;
-}
-
-// The two weight vectors of ray point k at (u, v) whose outer product az x wx gives
-// the 16 tap weights (trapezoid end weights folded into az).
-__device__ inline void ray_weights(const Ray& r, int k, int nseg, float u, float v, float az[4],
-                                   float wx[4]) {
-  keys_weights(__builtin_amdgcn_fractf(u), wx[0], wx[1], wx[2], wx[3]);  // u, v >= 0: u - j0
-  const float ck = (k == 0 || k == nseg) ? 0.5f * r.coef : r.coef;
-  keys_weights_scaled(__builtin_amdgcn_fractf(v), ck, az[0], az[1], az[2], az[3]);
-}
-
-// Ray point k of every lane: returns its cell and the two weight vectors.
-__device__ inline int ray_point(const Ray& r, int k, int nseg, float umax, float vmax, int W,
-                                float az[4], float wx[4]) {
-  float u, v;
-  const int cell = ray_pos(r, k, umax, vmax, W, u, v);
-  ray_weights(r, k, nseg, u, v, az, wx);
-  return cell;
 }
 
 // Ray point k of one element in moment form: acc[4 b + a] += c_k g^b f^a, with f and
@@ -231,158 +197,114 @@ __device__ inline void ray_moments(const Ray& r, int k, int nseg, float u, float
   }
 }
 
-// NR ray points per lane whose cells lie in two neighbouring cells, cb and cb + 1
-// (horizontal) or cb and cb + W (vertical): every ray point shifts its four weights
-// along that axis into a window of five nodes (by one place if it is in the second
-// cell), so the union of the taps is a 4 x 5 (or 5 x 4) block at cb.  Its first 16
-// nodes are summed by the 16-value reduce-scatter, the last row or column of four by
-// the 4-value one.  (Cells never exceed node nx - 1 or nz - 1, so the window's
-// fifth column or row stays inside the padded grid.)
-template <bool HORIZONTAL, int NR>
-__device__ inline void scatter_window(float* grid, int cb, int W, const float (&a)[NR][4],
-                                      const float (&b)[NR][4], const bool (&shift)[NR], int lane,
-                                      int my_off) {
-  float v16[16], v4[4];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) v16[i] = 0.f;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) v4[q] = 0.f;
-#pragma unroll
-  for (int n = 0; n < NR; ++n) {
-    if (HORIZONTAL) {
-      float bs[5];
-      bs[0] = shift[n] ? 0.f : b[n][0];
-#pragma unroll
-      for (int c = 1; c < 4; ++c) bs[c] = shift[n] ? b[n][c - 1] : b[n][c];
-      bs[4] = shift[n] ? b[n][3] : 0.f;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) v16[i] = fmaf(a[n][i >> 2], bs[i & 3], v16[i]);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) v4[r] = fmaf(a[n][r], bs[4], v4[r]);
-    } else {
-      float as[5];
-      as[0] = shift[n] ? 0.f : a[n][0];
-#pragma unroll
-      for (int r = 1; r < 4; ++r) as[r] = shift[n] ? a[n][r - 1] : a[n][r];
-      as[4] = shift[n] ? a[n][3] : 0.f;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) v16[i] = fmaf(as[i >> 2], b[n][i & 3], v16[i]);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) v4[c] = fmaf(as[4], b[n][c], v4[c]);
-    }
-  }
-  const float sum16 = reduce_scatter16(v16, lane);
-  if ((lane & 3) == 0) lds_add(grid + cb + my_off, sum16);
-  const float sum4 = reduce_scatter4(v4);
-  // node 4 of row (lane >> 4), or node (lane >> 4) of row 4
-  const int off4 = HORIZONTAL ? (lane >> 4) * W + 4 : 4 * W + (lane >> 4);
-  if ((lane & 15) == 0) lds_add(grid + cb + off4, sum4);
-}
-
-// Adds the tap weights of NR ray points per lane (cells in `cell`, idle lanes
-// already moved to c0 with zero weights) when the union of their cells is the one
-// cell c0 or two neighbouring cells; returns false, writing nothing, otherwise.
+// The ray points of NR rays per lane (elements walked together; `all`: the lanes
+// with a live ray), ray point k of every ray at step k.  Moments of ray points in
+// one cell accumulate in acc (pending for cell c_acc) until a step leaves that
+// cell.  A step whose ray points lie in several cells takes one round per cell,
+// the pending cell first when the step has points there: each round adds the
+// moments of its cell's points and is flushed, except the last, whose cell stays
+// pending.
 template <int NR>
-__device__ inline bool scatter_union(float* grid, int c0, int W, const int (&cell)[NR],
-                                     const float (&az)[NR][4], const float (&wx)[NR][4], int lane,
-                                     int my_off) {
-  bool one = true;
+__device__ inline void walk_rays(float* grid, Ray (&R)[NR], unsigned long long all, int nseg,
+                                 float umax, float vmax, int W, int lane, int my_off,
+                                 const MomentCoef& kc) {
+  const int lead = __ffsll((long long)all) - 1;
+  // An idle ray (zero weight) takes the geometry of the lane's first live ray, or
+  // in a lane with none, that of the lead lane's first live ray: every ray point of
+  // a step then lies in a cell that a live ray point of the step occupies, and the
+  // lead lane's ray 0 stands for its first live ray.
+  {
+    // plain value selects (a conditional copy of the fields would become a load
+    // through a selected pointer and put the rays in scratch memory)
+    float fu = R[NR - 1].u0, fv = R[NR - 1].v0, fdu = R[NR - 1].du, fdv = R[NR - 1].dv;
+    bool any = R[NR - 1].live;
 #pragma unroll
-  for (int n = 0; n < NR; ++n) one = one && cell[n] == c0;
-  if (__ballot(!one) == 0ull) {  // the usual case: one cell for the whole wavefront
-    float val[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      val[i] = az[0][i >> 2] * wx[0][i & 3];
-#pragma unroll
-      for (int n = 1; n < NR; ++n) val[i] = fmaf(az[n][i >> 2], wx[n][i & 3], val[i]);
+    for (int n = NR - 2; n >= 0; --n) {
+      const bool l = R[n].live;
+      fu = l ? R[n].u0 : fu;
+      fv = l ? R[n].v0 : fv;
+      fdu = l ? R[n].du : fdu;
+      fdv = l ? R[n].dv : fdv;
+      any = any || l;
     }
-    const float sum = reduce_scatter16(val, lane);
-    if ((lane & 3) == 0) lds_add(grid + c0 + my_off, sum);
-    return true;
+    const float lu = readlane_f(fu, lead), lv = readlane_f(fv, lead);
+    const float ldu = readlane_f(fdu, lead), ldv = readlane_f(fdv, lead);
+    fu = any ? fu : lu;
+    fv = any ? fv : lv;
+    fdu = any ? fdu : ldu;
+    fdv = any ? fdv : ldv;
+#pragma unroll
+    for (int n = 0; n < NR; ++n) {
+      const bool l = R[n].live;
+      R[n].u0 = l ? R[n].u0 : fu;
+      R[n].v0 = l ? R[n].v0 : fv;
+      R[n].du = l ? R[n].du : fdu;
+      R[n].dv = l ? R[n].dv : fdv;
+    }
   }
-  // the other cell, relative to c0: +1, -1, +W or -W for every lane (0 if none)
-  int d = 0;
+  // acc is all zeros whenever c_acc is -1.
+  float acc[16];
 #pragma unroll
-  for (int n = 0; n < NR; ++n) d = cell[n] != c0 ? cell[n] - c0 : d;
-  const int dd = __builtin_amdgcn_readlane(d, __ffsll((long long)__ballot(d != 0)) - 1);
-  bool same = true;
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  int c_acc = -1;  // wavefront-uniform: the cell of the pending sums in acc (-1: none)
+  for (int k = 0; k <= nseg; ++k) {
+    float u[NR], v[NR];
+    int cell[NR];
 #pragma unroll
-  for (int n = 0; n < NR; ++n) same = same && (cell[n] == c0 || cell[n] - c0 == dd);
-  if (__ballot(!same) != 0ull || (dd != 1 && dd != -1 && dd != W && dd != -W)) return false;
-  bool shift[NR];
-  const bool h = dd == 1, hl = dd == -1, v = dd == W;
-  if (h) {
+    for (int n = 0; n < NR; ++n) cell[n] = ray_pos(R[n], k, umax, vmax, W, u[n], v[n]);
+    const int c0 = __builtin_amdgcn_readlane(cell[0], lead);
+    bool one = true;
 #pragma unroll
-    for (int n = 0; n < NR; ++n) shift[n] = cell[n] != c0;
-    scatter_window<true, NR>(grid, c0, W, az, wx, shift, lane, my_off);
-    return true;
+    for (int n = 0; n < NR; ++n) one = one && cell[n] == c0;
+    if (__ballot(!one) == 0ull) {  // the usual case: one cell for the whole wavefront
+      if (c0 != c_acc && c_acc >= 0) {
+        flush_moments(grid, c_acc, acc, lane, my_off, kc);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+      }
+      c_acc = c0;
+#pragma unroll
+      for (int n = 0; n < NR; ++n) ray_moments(R[n], k, nseg, u[n], v[n], true, acc);
+      continue;
+    }
+    int cur = c0;
+    if (c_acc >= 0) {
+      bool has = false;
+#pragma unroll
+      for (int n = 0; n < NR; ++n) has = has || cell[n] == c_acc;
+      if (__ballot(has) != 0ull) {
+        cur = c_acc;
+      } else {
+        flush_moments(grid, c_acc, acc, lane, my_off, kc);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+      }
+    }
+    bool left[NR];
+#pragma unroll
+    for (int n = 0; n < NR; ++n) left[n] = true;
+    while (true) {  // every round takes at least one ray point (of the lane cur came from)
+      bool rem = false;
+#pragma unroll
+      for (int n = 0; n < NR; ++n) {
+        const bool in = left[n] && cell[n] == cur;
+        ray_moments(R[n], k, nseg, u[n], v[n], in, acc);
+        left[n] = left[n] && !in;
+        rem = rem || left[n];
+      }
+      const unsigned long long rest = __ballot(rem);
+      if (rest == 0ull) break;
+      flush_moments(grid, cur, acc, lane, my_off, kc);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+      int nxt = cell[NR - 1];
+#pragma unroll
+      for (int n = NR - 2; n >= 0; --n) nxt = left[n] ? cell[n] : nxt;
+      cur = __builtin_amdgcn_readlane(nxt, __ffsll((long long)rest) - 1);
+    }
+    c_acc = cur;
   }
-  if (hl) {
-#pragma unroll
-    for (int n = 0; n < NR; ++n) shift[n] = cell[n] == c0;
-    scatter_window<true, NR>(grid, c0 - 1, W, az, wx, shift, lane, my_off);
-    return true;
-  }
-  if (v) {
-#pragma unroll
-    for (int n = 0; n < NR; ++n) shift[n] = cell[n] != c0;
-    scatter_window<false, NR>(grid, c0, W, az, wx, shift, lane, my_off);
-    return true;
-  }
-#pragma unroll
-  for (int n = 0; n < NR; ++n) shift[n] = cell[n] == c0;
-  scatter_window<false, NR>(grid, c0 - W, W, az, wx, shift, lane, my_off);
-  return true;
-}
-
-// One ray point per lane spread over more cells: one masked reduce round per
-// distinct cell (idle lanes already moved to c0 with zero weights).
-__device__ inline void scatter_rounds(float* grid, int c0, int cell, const float (&az)[4],
-                                      const float (&wx)[4], int lane, int my_off) {
-  float val[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) val[i] = az[i >> 2] * wx[i & 3];
-  bool done = false;
-  int ccur = c0;
-  while (true) {
-    const bool in = !done && cell == ccur;
-    float vv[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) vv[i] = in ? val[i] : 0.f;
-    const float sum = reduce_scatter16(vv, lane);
-    if ((lane & 3) == 0) lds_add(grid + ccur + my_off, sum);
-    done = done || in;
-    const unsigned long long rest = __ballot(!done);
-    if (rest == 0ull) break;
-    ccur = __builtin_amdgcn_readlane(cell, __ffsll((long long)rest) - 1);
-  }
-}
-
-// One ray point per lane, any spread.
-__device__ inline void scatter_one(float* grid, int cell, bool live, int lead, int W,
-                                   const float (&az)[4], const float (&wx)[4], int lane,
-                                   int my_off) {
-  const int c0 = __builtin_amdgcn_readlane(cell, lead);
-  const int c[1] = {live ? cell : c0};  // idle lanes (zero weights) join the leader's cell
-  const float a1[1][4] = {{az[0], az[1], az[2], az[3]}};
-  const float b1[1][4] = {{wx[0], wx[1], wx[2], wx[3]}};
-  if (!scatter_union<1>(grid, c0, W, c, a1, b1, lane, my_off))
-    scatter_rounds(grid, c0, c[0], az, wx, lane, my_off);
-}
-
-// Ray point k of the rays of two elements (either may be idle in a lane): one
-// reduce when their cells allow it, else each element on its own.
-__device__ inline void scatter_pair(float* grid, const int (&cell)[2], const bool (&live)[2],
-                                    int lead, int lead0, int lead1, int W,
-                                    const float (&az)[2][4], const float (&wx)[2][4], int lane,
-                                    int my_off) {
-  const int c0 = __builtin_amdgcn_readlane(live[0] ? cell[0] : cell[1], lead);
-  const int cu[2] = {live[0] ? cell[0] : c0, live[1] ? cell[1] : c0};
-  if (scatter_union<2>(grid, c0, W, cu, az, wx, lane, my_off)) return;
-  // the two ray points of a lane lie wider apart: each element on its own
-  scatter_one(grid, cell[0], live[0], lead0, W, az[0], wx[0], lane, my_off);
-  scatter_one(grid, cell[1], live[1], lead1, W, az[1], wx[1], lane, my_off);
+  if (c_acc >= 0) flush_moments(grid, c_acc, acc, lane, my_off, kc);
 }
 
 // COPIES grid copies per workgroup: 4 (one private copy per wavefront), or for
@@ -414,9 +336,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const MomentCoef kc = moment_coef(lane);
 
   // Elements four at a time: the rays of neighbouring elements to the same points
-  // run side by side, so at a step their ray points usually share one cell (or two
-  // neighbouring cells) and one reduce covers all four; otherwise the step falls
-  // back to the two pairs, and a pair to its single elements.
+  // run side by side, so at a step their ray points usually share one cell and one
+  // reduce covers all four.  Where some of the four have no work in this wavefront
+  // (the aperture edges), each pair walks on its own, or its one element with work.
   for (int a = tr.x; a <= tr.y; a += 4) {  // wavefront-uniform loop
     Ray R[4];
     unsigned long long lm[4];
@@ -450,104 +372,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
     const unsigned long long all = lm[0] | lm[1] | lm[2] | lm[3];
     if (all == 0ull) continue;
-    int leads[4];
-#pragma unroll
-    for (int n = 0; n < 4; ++n) leads[n] = __ffsll((long long)lm[n]) - 1;
     if (lm[0] != 0ull && lm[1] != 0ull && lm[2] != 0ull && lm[3] != 0ull) {
-      const int lead = __ffsll((long long)all) - 1;
-      // An idle ray (zero weight) takes the geometry of the lane's first live ray,
-      // or in a lane with none, that of the lead lane's first live ray: every ray
-      // point of a step then lies in a cell that a live ray point of the step
-      // occupies, and the lead lane's ray 0 stands for its first live ray.
-      {
-        float fu = R[3].u0, fv = R[3].v0, fdu = R[3].du, fdv = R[3].dv;
-#pragma unroll
-        for (int n = 2; n >= 0; --n)
-          if (R[n].live) {
-            fu = R[n].u0;
-            fv = R[n].v0;
-            fdu = R[n].du;
-            fdv = R[n].dv;
-          }
-        const float lu = readlane_f(fu, lead), lv = readlane_f(fv, lead);
-        const float ldu = readlane_f(fdu, lead), ldv = readlane_f(fdv, lead);
-        if (!(R[0].live || R[1].live || R[2].live || R[3].live)) {
-          fu = lu;
-          fv = lv;
-          fdu = ldu;
-          fdv = ldv;
-        }
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-          if (!R[n].live) {
-            R[n].u0 = fu;
-            R[n].v0 = fv;
-            R[n].du = fdu;
-            R[n].dv = fdv;
-          }
-      }
-      // Moments of ray points in one cell accumulate in acc (pending for cell c_acc)
-      // until a step leaves that cell.  A step whose ray points lie in several cells
-      // takes one round per cell, the pending cell first when the step has points
-      // there: each round adds the moments of its cell's points and is flushed,
-      // except the last, whose cell stays pending.
-      // acc is all zeros whenever c_acc is -1.
-      float acc[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-      int c_acc = -1;  // wavefront-uniform: the cell of the pending sums in acc (-1: none)
-      for (int k = 0; k <= g.n_seg; ++k) {
-        float u[4], v[4];
-        int cell[4];
-#pragma unroll
-        for (int n = 0; n < 4; ++n) cell[n] = ray_pos(R[n], k, umax, vmax, W, u[n], v[n]);
-        const int c0 = __builtin_amdgcn_readlane(cell[0], lead);
-        bool one = true;
-#pragma unroll
-        for (int n = 0; n < 4; ++n) one = one && cell[n] == c0;
-        if (__ballot(!one) == 0ull) {  // the usual case: one cell for the whole wavefront
-          if (c0 != c_acc && c_acc >= 0) {
-            flush_moments(grid, c_acc, acc, lane, my_off, kc);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-          }
-          c_acc = c0;
-#pragma unroll
-          for (int n = 0; n < 4; ++n) ray_moments(R[n], k, g.n_seg, u[n], v[n], true, acc);
-          continue;
-        }
-        int cur = c0;
-        if (c_acc >= 0) {
-          bool has = false;
-#pragma unroll
-          for (int n = 0; n < 4; ++n) has = has || cell[n] == c_acc;
-          if (__ballot(has) != 0ull) {
-            cur = c_acc;
-          } else {
-            flush_moments(grid, c_acc, acc, lane, my_off, kc);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-          }
-        }
-        bool left[4] = {true, true, true, true};
-        while (true) {  // every round takes at least one ray point (of the lane cur came from)
-#pragma unroll
-          for (int n = 0; n < 4; ++n) {
-            const bool in = left[n] && cell[n] == cur;
-            ray_moments(R[n], k, g.n_seg, u[n], v[n], in, acc);
-            left[n] = left[n] && !in;
-          }
-          const unsigned long long rest = __ballot(left[0] || left[1] || left[2] || left[3]);
-          if (rest == 0ull) break;
-          flush_moments(grid, cur, acc, lane, my_off, kc);
-#pragma unroll
-          for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-          const int nxt = left[0] ? cell[0] : left[1] ? cell[1] : left[2] ? cell[2] : cell[3];
-          cur = __builtin_amdgcn_readlane(nxt, __ffsll((long long)rest) - 1);
-        }
-        c_acc = cur;
-      }
-      if (c_acc >= 0) flush_moments(grid, c_acc, acc, lane, my_off, kc);
+      walk_rays<4>(grid, R, all, g.n_seg, umax, vmax, W, lane, my_off, kc);
       continue;
     }
     // some element of the four has no work in this wavefront: pairs and singles
@@ -556,25 +382,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       const unsigned long long m0 = lm[2 * h], m1 = lm[2 * h + 1];
       if ((m0 | m1) == 0ull) continue;
       if (m0 == 0ull || m1 == 0ull) {  // one element with work
-        const Ray& r = m0 != 0ull ? R[2 * h] : R[2 * h + 1];
-        const int lead = __ffsll((long long)(m0 | m1)) - 1;
-        for (int k = 0; k <= g.n_seg; ++k) {
-          float az[4], wx[4];
-          const int cell = ray_point(r, k, g.n_seg, umax, vmax, W, az, wx);
-          scatter_one(grid, cell, r.live, lead, W, az, wx, lane, my_off);
-        }
+        const bool s0 = m0 != 0ull;
+        Ray R1[1];
+        R1[0].u0 = s0 ? R[2 * h].u0 : R[2 * h + 1].u0;
+        R1[0].v0 = s0 ? R[2 * h].v0 : R[2 * h + 1].v0;
+        R1[0].du = s0 ? R[2 * h].du : R[2 * h + 1].du;
+        R1[0].dv = s0 ? R[2 * h].dv : R[2 * h + 1].dv;
+        R1[0].coef = s0 ? R[2 * h].coef : R[2 * h + 1].coef;
+        R1[0].live = s0 ? R[2 * h].live : R[2 * h + 1].live;
+        walk_rays<1>(grid, R1, m0 | m1, g.n_seg, umax, vmax, W, lane, my_off, kc);
         continue;
       }
-      const int lead = __ffsll((long long)(m0 | m1)) - 1;
-      const bool l2[2] = {R[2 * h].live, R[2 * h + 1].live};
-      for (int k = 0; k <= g.n_seg; ++k) {
-        float az[2][4], wx[2][4];
-        int cell[2];
-#pragma unroll
-        for (int n = 0; n < 2; ++n)
-          cell[n] = ray_point(R[2 * h + n], k, g.n_seg, umax, vmax, W, az[n], wx[n]);
-        scatter_pair(grid, cell, l2, lead, leads[2 * h], leads[2 * h + 1], W, az, wx, lane, my_off);
-      }
+      Ray R2[2] = {R[2 * h], R[2 * h + 1]};
+      walk_rays<2>(grid, R2, m0 | m1, g.n_seg, umax, vmax, W, lane, my_off, kc);
     }
   }
   __syncthreads();
