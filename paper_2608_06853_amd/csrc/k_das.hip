@@ -68,10 +68,11 @@ __device__ inline int wave_max(int v) {
 // the first two samples of its channel and is zeroed); without, the caller has
 // shown for the whole wavefront that every sample lies strictly inside the
 // record.  Masked entries carry a zero phasor and contribute nothing either way.
-template <int S, bool CHECK>
+template <int S, bool CHECK, bool SKIP = false>
 __device__ inline void gather(const float2* __restrict__ base, int ns, const TabEntry& et,
                               const Rx (&rx)[S], float2 (&a0)[S], float2 (&a1)[S], float (&fr)[S],
                               bool (&ok)[S]) {
+  const bool t_on = et.er != 0.f || et.ei != 0.f;
 #pragma unroll
   for (int k = 0; k < S; ++k) {
     int kk;
@@ -86,8 +87,18 @@ __device__ inline void gather(const float2* __restrict__ base, int ns, const Tab
       ok[k] = true;
     }
     const float2* q = base + (unsigned)(k * ns + kk);
-    a0[k] = q[0];
-    a1[k] = q[1];
+    if (SKIP) {  // a lane whose sample is apodised out (zero phasor) loads nothing
+      float2 v0 = make_float2(0.f, 0.f), v1 = v0;
+      if (t_on && (rx[k].e.x != 0.f || rx[k].e.y != 0.f)) {
+        v0 = q[0];
+        v1 = q[1];
+      }
+      a0[k] = v0;
+      a1[k] = v1;
+    } else {
+      a0[k] = q[0];
+      a1[k] = q[1];
+    }
   }
 }
 
@@ -132,13 +143,13 @@ __device__ inline bool wave_silent(const TabEntry& et, const Rx (&rx)[S], int ns
   return wave_silent(et, rx_span<S>(rx), ns);
 }
 
-template <int S, bool CHECK>
+template <int S, bool CHECK, bool SKIP>
 __device__ inline void das_fwd_t(const float2* __restrict__ base, int ns, const TabEntry& et,
                                  const Rx (&rx)[S], float2& acc) {
   float2 a0[S], a1[S];
   float fr[S];
   bool ok[S];
-  gather<S, CHECK>(base, ns, et, rx, a0, a1, fr, ok);
+  gather<S, CHECK, SKIP>(base, ns, et, rx, a0, a1, fr, ok);
   float ax = 0.f, ay = 0.f;
 #pragma unroll
   for (int k = 0; k < S; ++k) {
@@ -202,6 +213,12 @@ __global__ __launch_bounds__(256) void k_das_fwd(DasArgs A) {
   const WaveRange wr = wave_range(A.prange, p, tr, jb, S);
   const int tlo = wr.rx_active ? wr.lo : tr.y + 1, thi = wr.rx_active ? wr.hi : tr.x - 1;
   const RxSpan sp = rx_span<S>(rx);
+  // every lane's receive entries all active: then only a masked transmit entry
+  // leaves a lane's samples out (the gathers skip apodised samples only where some are)
+  bool rx_on = true;
+#pragma unroll
+  for (int k = 0; k < S; ++k) rx_on = rx_on && (rx[k].e.x != 0.f || rx[k].e.y != 0.f);
+  const bool rx_full = __ballot(!rx_on) == 0ull;
 
   for (int ib = tr.z; ib <= tr.w; ++ib) {
     float2 acc = make_float2(0.f, 0.f);
@@ -211,8 +228,14 @@ __global__ __launch_bounds__(256) void k_das_fwd(DasArgs A) {
       for (int t = t0; t <= t1; ++t) {
         const TabEntry en = A.tab[(long long)min(t + 1, t1) * P + p];
         const float2* __restrict__ base = A.iq + ((long long)t * N + (long long)jb * S) * ns;
-        if (interior(et, rmin, rmax, ns)) das_fwd_t<S, false>(base, ns, et, rx, acc);
-        else if (!wave_silent(et, sp, ns)) das_fwd_t<S, true>(base, ns, et, rx, acc);
+        if (interior(et, rmin, rmax, ns)) {
+          if (rx_full && __ballot(et.er == 0.f && et.ei == 0.f) == 0ull)
+            das_fwd_t<S, false, false>(base, ns, et, rx, acc);
+          else
+            das_fwd_t<S, false, true>(base, ns, et, rx, acc);
+        } else if (!wave_silent(et, sp, ns)) {
+          das_fwd_t<S, true, true>(base, ns, et, rx, acc);
+        }
         et = en;
       }
     }
