@@ -40,9 +40,11 @@ __device__ inline void swap16(float& a, float& b) {
   a = __uint_as_float(r[0]);
   b = __uint_as_float(r[1]);
 }
+// (every move used here reads a lane that exists, so bound_ctrl changes no result;
+// it lets the compiler fold the move into the instruction that uses it)
 template <int CTRL>
 __device__ inline float dpp(float x) {
-  return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), CTRL, 0xf, 0xf, false));
+  return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), CTRL, 0xf, 0xf, true));
 }
 template <int CTRL>
 __device__ inline int dppi(int x) {
@@ -123,7 +125,7 @@ __device__ inline float keys_coef(int t, int pw) {
 // tap r for the power held by the lane the d-th row exchange reads.  The sources
 // are found by applying the same moves to the lane's own indices.
 struct MomentCoef {
-  float kx[4], kz[4];
+  float kx[4], kz0, kz2, kz1s, kz3s;  // kz1s, kz3s: kz[1], kz[3] of the lane whose row differs by 1
 };
 __device__ inline MomentCoef moment_coef(int lane) {
   const int tap = (lane >> 2) & 15, c = tap & 3, r = tap >> 2;
@@ -134,10 +136,12 @@ __device__ inline MomentCoef moment_coef(int lane) {
   m.kx[3] = keys_coef(c, dppi<DPP_ROR12>(c));
   const float rf = (float)r;
   const float r2 = exch32(rf);
-  m.kz[0] = keys_coef(r, r);
-  m.kz[1] = keys_coef(r, (int)exch16(rf));
-  m.kz[2] = keys_coef(r, (int)r2);
-  m.kz[3] = keys_coef(r, (int)exch16(r2));
+  m.kz0 = keys_coef(r, r);
+  const float kz1 = keys_coef(r, (int)exch16(rf));
+  m.kz2 = keys_coef(r, (int)r2);
+  const float kz3 = keys_coef(r, (int)exch16(r2));
+  m.kz1s = exch16(kz1);
+  m.kz3s = exch16(kz3);
   return m;
 }
 
@@ -152,11 +156,11 @@ __device__ inline void flush_moments(float* grid, int c, float (&acc)[16], int l
   n = fmaf(K.kx[1], dpp<DPP_ROR4>(m), n);
   n = fmaf(K.kx[2], dpp<DPP_ROR8>(m), n);
   n = fmaf(K.kx[3], dpp<DPP_ROR12>(m), n);
+  // along z: w = kz0 n + kz1 n(row ^ 1) + kz2 n(row ^ 2) + kz3 n(row ^ 3); the two
+  // terms from the neighbouring row are formed there and brought over in one exchange
   const float n2 = exch32(n);
-  float w = K.kz[0] * n;
-  w = fmaf(K.kz[1], exch16(n), w);
-  w = fmaf(K.kz[2], n2, w);
-  w = fmaf(K.kz[3], exch16(n2), w);
+  float w = fmaf(K.kz2, n2, K.kz0 * n);
+  w += exch16(fmaf(K.kz3s, n2, K.kz1s * n));
   if ((lane & 3) == 0) lds_add(grid + c + my_off, w);
 }
 
