@@ -19,9 +19,10 @@ constexpr size_t TAB_LDS_BYTES = 160 * 1024;  // LDS of one workgroup on gfx950
 
 // Layouts of the slowness deviation in LDS: the padded node grid at its own row
 // stride, the same at the fixed stride TAB_LDS_W (grids with nx + 3 <= TAB_LDS_W:
-// the 16 taps of a path point are then immediate offsets from one address), or the
-// row polynomials of the cells (ROWPOLY).
-enum { GRID_W = 0, GRID_FIXED = 1, ROWPOLY = 2 };
+// the 16 taps of a path point are then immediate offsets from one address), the
+// row polynomials of the cells (ROWPOLY), or the full bicubic polynomial of every
+// cell (CELLPOLY: four times the row polynomials' bytes, fewer instructions).
+enum { GRID_W = 0, GRID_FIXED = 1, ROWPOLY = 2, CELLPOLY = 3 };
 
 // Row polynomials: along a row of the padded grid, the Keys interpolation inside
 // cell column j0 (nodes j0 - 1 .. j0 + 2, values g0..g3) is the cubic
@@ -61,6 +62,50 @@ __device__ __forceinline__ float path_sum_rowpoly(const float4* H, int R, float 
   return acc - 0.5f * (first + last);
 }
 
+// Cell polynomials: inside cell (j0, i0) the bicubic Keys interpolant is
+// sum over b of g^b P_b(f), P_b(f) = c[b].x + c[b].y f + c[b].z f^2 + c[b].w f^3 (f,
+// g: the x and z fractions).  With q_r the row polynomials of the cell's padded rows
+// i0 .. i0 + 3, c[b] = sum over r of K[r][b] q_r, where K[r][b] is the coefficient
+// of g^b in the Keys weight of row r.  Stored as four float4 per cell, cells
+// column-major ([j0][i0]), so a point reads 64 contiguous bytes.
+__device__ __forceinline__ void cell_poly(const float4 (&q)[4], float4 (&c)[4]) {
+  c[0] = q[1];
+  c[1] = make_float4(0.5f * (q[2].x - q[0].x), 0.5f * (q[2].y - q[0].y),
+                     0.5f * (q[2].z - q[0].z), 0.5f * (q[2].w - q[0].w));
+#define AF_C2(k) (fmaf(-2.5f, q[1].k, q[0].k) + fmaf(2.0f, q[2].k, -0.5f * q[3].k))
+#define AF_C3(k) (1.5f * (q[1].k - q[2].k) + 0.5f * (q[3].k - q[0].k))
+  c[2] = make_float4(AF_C2(x), AF_C2(y), AF_C2(z), AF_C2(w));
+  c[3] = make_float4(AF_C3(x), AF_C3(y), AF_C3(z), AF_C3(w));
+#undef AF_C2
+#undef AF_C3
+}
+
+// path_sum over the cell polynomials C ([nx][nz][4] float4): per point four
+// Horner rows in the x fraction, then Horner in the z fraction.
+__device__ __forceinline__ float path_sum_cellpoly(const float4* C, int nz, float u0, float v0,
+                                                   float du, float dv, int nseg, float umax,
+                                                   float vmax) {
+  float acc = 0.f, first = 0.f, last = 0.f;
+  for (int k = 0; k <= nseg; ++k) {
+    const float u = __builtin_amdgcn_fmed3f(fmaf((float)k, du, u0), 0.f, umax);
+    const float v = __builtin_amdgcn_fmed3f(fmaf((float)k, dv, v0), 0.f, vmax);
+    const int j0 = (int)u, i0 = (int)v;
+    const float f = __builtin_amdgcn_fractf(u), gz = __builtin_amdgcn_fractf(v);  // u, v >= 0
+    const float4* q = C + 4 * (j0 * nz + i0);
+    float r[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const float4 c = q[b];
+      r[b] = fmaf(fmaf(fmaf(c.w, f, c.z), f, c.y), f, c.x);
+    }
+    const float val = fmaf(fmaf(fmaf(r[3], gz, r[2]), gz, r[1]), gz, r[0]);
+    acc += val;
+    if (k == 0) first = val;
+    if (k == nseg) last = val;
+  }
+  return acc - 0.5f * (first + last);
+}
+
 // One instantiation per refraction mode (arc or flat lens, root or discrete
 // search), so the default mode keeps its own register allocation, and per layout.
 // A workgroup of ITEMS x 256 threads takes ITEMS consecutive work items (one point
@@ -73,7 +118,21 @@ void k_table(TableArgs A) {
   const Geo& g = A.g;
   const int WL = LAYOUT == GRID_FIXED ? TAB_LDS_W : g.W;
   const int RP = g.nz + 3;
-  if (LAYOUT == ROWPOLY) {
+  if (LAYOUT == CELLPOLY) {
+    float4* H = reinterpret_cast<float4*>(G);
+    for (int i = threadIdx.x; i < g.nx * g.nz; i += 256 * ITEMS) {
+      const int j0 = i / g.nz, i0 = i - j0 * g.nz;
+      float4 q[4], c[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float* row = A.gdev + (i0 + r) * g.W + j0;
+        q[r] = row_poly(row[0], row[1], row[2], row[3]);
+      }
+      cell_poly(q, c);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) H[4 * i + b] = c[b];
+    }
+  } else if (LAYOUT == ROWPOLY) {
     float4* H = reinterpret_cast<float4*>(G);
     for (int i = threadIdx.x; i < g.nx * RP; i += 256 * ITEMS) {
       const int j0 = i / RP, r = i - j0 * RP;
@@ -128,7 +187,10 @@ void k_table(TableArgs A) {
       double uh = 0.0;
       if (ok) {
         const float acc =
-            LAYOUT == ROWPOLY
+            LAYOUT == CELLPOLY
+                ? path_sum_cellpoly(reinterpret_cast<const float4*>(G), g.nz, u0, v0,
+                                    (up - u0) * inv_n, (vp - v0) * inv_n, g.n_seg, umax, vmax)
+            : LAYOUT == ROWPOLY
                 ? path_sum_rowpoly(reinterpret_cast<const float4*>(G), RP, u0, v0,
                                    (up - u0) * inv_n, (vp - v0) * inv_n, g.n_seg, umax, vmax)
                 : path_sum(G, WL, u0, v0, (up - u0) * inv_n, (vp - v0) * inv_n, g.n_seg, umax,
@@ -183,19 +245,30 @@ hipError_t launch_table(af_ctx* c) {
   A.ray_uv = c->d_ray_uv.as<float2>();
   A.ray_l2 = c->d_ray_l2.as<float>();
   if (c->v.n_tab_work == 0) return hipSuccess;
-  // The row polynomials where six 256-thread workgroups fit a CU's LDS, or two of
-  // 512 threads; else the padded grid at the fixed row stride where its copy fits
-  // the LDS of a workgroup, else at the grid's own.
+  // The cell polynomials, then the row polynomials, where six 256-thread
+  // workgroups fit a CU's LDS, or two of 512 threads; else the padded grid at the
+  // fixed row stride where its copy fits the LDS of a workgroup, else at the grid's
+  // own.
+  const size_t cellp = 4 * sizeof(float4) * (size_t)c->nx * c->nz;
   const size_t poly = sizeof(float4) * (size_t)c->nx * (c->nz + 3);
   const bool fixed = c->nx + 3 <= TAB_LDS_W &&
                      sizeof(float) * (size_t)TAB_LDS_W * (c->nz + 3) <= TAB_LDS_BYTES;
-  const int layout = poly * 2 <= TAB_LDS_BYTES ? ROWPOLY : fixed ? GRID_FIXED : GRID_W;
-  const int items = layout == ROWPOLY && poly * 6 > TAB_LDS_BYTES ? 2 : 1;
-  const size_t lds = layout == ROWPOLY ? poly
-                     : sizeof(float) * (size_t)(fixed ? TAB_LDS_W : c->nx + 3) * (c->nz + 3);
+  const int layout = cellp * 2 <= TAB_LDS_BYTES  ? CELLPOLY
+                     : poly * 2 <= TAB_LDS_BYTES ? ROWPOLY
+                     : fixed                     ? GRID_FIXED
+                                                 : GRID_W;
+  const size_t bytes = layout == CELLPOLY ? cellp : poly;
+  const int items = (layout == CELLPOLY || layout == ROWPOLY) && bytes * 6 > TAB_LDS_BYTES ? 2 : 1;
+  const size_t lds = layout == CELLPOLY || layout == ROWPOLY
+                         ? bytes
+                         : sizeof(float) * (size_t)(fixed ? TAB_LDS_W : c->nx + 3) * (c->nz + 3);
   const dim3 grid((c->v.n_tab_work + items - 1) / items), block(256 * items);
 #define AF_TABLE_LAUNCH(M)                                                          \
-  if (layout == ROWPOLY && items == 2)                                              \
+  if (layout == CELLPOLY && items == 2)                                             \
+    hipLaunchKernelGGL((k_table<M, CELLPOLY, 2>), grid, block, lds, c->stream, A); \
+  else if (layout == CELLPOLY)                                                      \
+    hipLaunchKernelGGL((k_table<M, CELLPOLY, 1>), grid, block, lds, c->stream, A); \
+  else if (layout == ROWPOLY && items == 2)                                         \
     hipLaunchKernelGGL((k_table<M, ROWPOLY, 2>), grid, block, lds, c->stream, A);  \
   else if (layout == ROWPOLY)                                                       \
     hipLaunchKernelGGL((k_table<M, ROWPOLY, 1>), grid, block, lds, c->stream, A);  \
