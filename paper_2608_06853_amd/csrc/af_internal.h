@@ -106,6 +106,9 @@ struct CmpeArgs {
   const int* wide;
   float2* wscr;
   long long wstride;
+  // The LDS path runs in one or two launches by the dynamic LDS a tile needs (in
+  // float2): a launch takes the tiles with need in (need_lo, need_hi].
+  long long need_lo, need_hi;
 };
 
 // Per-tile result of the dynamic-grid point update: active element range, whether

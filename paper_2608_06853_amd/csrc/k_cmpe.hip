@@ -33,6 +33,17 @@ constexpr int CMPE_WAVES = 4;
 // the rows that neighbouring pair entries read start two banks apart.
 constexpr int SS = SUB + 1;
 
+// Dynamic LDS (float2) of a sub-tile whose tile spans blocks bLO..bHI: the (npr +
+// 1)^2 subaperture images at row stride SS, then pps x npr^2 pair entries of one
+// float2 and two floats (the layout below).
+__device__ __host__ inline long long cmpe_lds_need(int bLO, int bHI, int nsub, int pps) {
+  const int pLo = bLO - 1 > 0 ? bLO - 1 : 0;
+  const int pHi = nsub - 2 < bHI - 1 ? nsub - 2 : bHI - 1;
+  const long long npr = pHi - pLo + 1 > 0 ? pHi - pLo + 1 : 0;
+  const long long nS = npr > 0 ? npr + 1 : 0;
+  return nS * nS * SS + 2LL * pps * npr * npr;
+}
+
 // One workgroup of 4 wavefronts per 64-point sub-tile.  Phase 1 forms, for this
 // sub-tile, the full image and block energy per point and every subaperture
 // image S(i, j) = sum of its 2 x 2 block images that a pair of the sub-tile can
@@ -56,6 +67,10 @@ __global__ __launch_bounds__(256) void k_cmpe(CmpeArgs A) {
   const int wix = A.wide[tile];
   if ((wix >= 0) != WIDE) return;  // the other launch owns this sub-tile
   const int M = g.patch2, pps = g.pps;
+  if (!WIDE) {  // the LDS path: the launch whose LDS class holds this tile's need
+    const long long need = tr.x <= tr.y ? cmpe_lds_need(tr.z, tr.w, g.nsub, pps) : 0;
+    if (need <= A.need_lo || need > A.need_hi) return;
+  }
   const long long P = g.P;
   const long long slot0 = tile * (4 * pps) + (long long)w * pps;
 
@@ -357,11 +372,27 @@ hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g,
   A.wscr = c->d_cmpe_wide.as<float2>();
   A.wstride = c->wstride;
   const int nba = c->nba_lds;  // widest span of the LDS path
-  const size_t lds = sizeof(float2) * (size_t)cmpe_wide_stride(nba, c->pps);
+  const long long most = cmpe_wide_stride(nba, c->pps);
   const dim3 grid((unsigned)(c->v.P / SUB)), block(CMPE_WAVES * SUB);
-  hipLaunchKernelGGL(k_cmpe<false>, grid, block, lds, c->stream, A);
+  // Tiles of a narrow span run with an allocation that lets six workgroups share a
+  // CU; the wider ones with the widest span's (one launch when that is small).
+  const long long narrow =
+      ((long long)(160 * 1024 / 6) - (long long)(sizeof(float) * CMPE_WAVES * 3 * SUB +
+                                                 sizeof(double) * CMPE_WAVES * 3)) /
+      (long long)sizeof(float2);
+  const long long cut = most <= narrow ? most : narrow;
+  A.need_lo = -1;
+  A.need_hi = cut;
+  hipLaunchKernelGGL(k_cmpe<false>, grid, block, sizeof(float2) * (size_t)cut, c->stream, A);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || c->v.n_wide == 0) return e;
+  if (e != hipSuccess) return e;
+  if (most > cut) {
+    A.need_lo = cut;
+    A.need_hi = most;
+    hipLaunchKernelGGL(k_cmpe<false>, grid, block, sizeof(float2) * (size_t)most, c->stream, A);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (c->v.n_wide == 0) return hipSuccess;
   hipLaunchKernelGGL(k_cmpe<true>, grid, block, 0, c->stream, A);
   return hipGetLastError();
 }
