@@ -109,10 +109,11 @@ __device__ __forceinline__ float path_sum_cellpoly(const float4* C, int nz, floa
 // One instantiation per refraction mode (arc or flat lens, root or discrete
 // search), so the default mode keeps its own register allocation, and per layout.
 // A workgroup of ITEMS x 256 threads takes ITEMS consecutive work items (one point
-// per thread) over one LDS copy: two items let a large row-polynomial copy serve
-// twice the wavefronts.
+// per thread) over one LDS copy: where only two copies fit a CU, two items per
+// row-polynomial copy (4 waves per SIMD) or three per cell-polynomial copy (6 waves
+// per SIMD, within the kernel's 80 registers) serve more wavefronts.
 template <int MODE, int LAYOUT, int ITEMS>
-__global__ __launch_bounds__(256 * ITEMS) __attribute__((amdgpu_waves_per_eu(ITEMS == 1 ? 6 : 4)))
+__global__ __launch_bounds__(256 * ITEMS) __attribute__((amdgpu_waves_per_eu(ITEMS == 2 ? 4 : 6)))
 void k_table(TableArgs A) {
   extern __shared__ float G[];
   const Geo& g = A.g;
@@ -258,14 +259,17 @@ hipError_t launch_table(af_ctx* c) {
                      : fixed                     ? GRID_FIXED
                                                  : GRID_W;
   const size_t bytes = layout == CELLPOLY ? cellp : poly;
-  const int items = (layout == CELLPOLY || layout == ROWPOLY) && bytes * 6 > TAB_LDS_BYTES ? 2 : 1;
+  // (the cell polynomials at two copies per CU: three items per copy, 6 waves per SIMD)
+  const int items = !((layout == CELLPOLY || layout == ROWPOLY) && bytes * 6 > TAB_LDS_BYTES) ? 1
+                    : layout == CELLPOLY                                                ? 3
+                                                                                        : 2;
   const size_t lds = layout == CELLPOLY || layout == ROWPOLY
                          ? bytes
                          : sizeof(float) * (size_t)(fixed ? TAB_LDS_W : c->nx + 3) * (c->nz + 3);
   const dim3 grid((c->v.n_tab_work + items - 1) / items), block(256 * items);
 #define AF_TABLE_LAUNCH(M)                                                          \
-  if (layout == CELLPOLY && items == 2)                                             \
-    hipLaunchKernelGGL((k_table<M, CELLPOLY, 2>), grid, block, lds, c->stream, A); \
+  if (layout == CELLPOLY && items == 3)                                             \
+    hipLaunchKernelGGL((k_table<M, CELLPOLY, 3>), grid, block, lds, c->stream, A); \
   else if (layout == CELLPOLY)                                                      \
     hipLaunchKernelGGL((k_table<M, CELLPOLY, 1>), grid, block, lds, c->stream, A); \
   else if (layout == ROWPOLY && items == 2)                                         \
