@@ -109,11 +109,10 @@ __device__ __forceinline__ float path_sum_cellpoly(const float4* C, int nz, floa
 // One instantiation per refraction mode (arc or flat lens, root or discrete
 // search), so the default mode keeps its own register allocation, and per layout.
 // A workgroup of ITEMS x 256 threads takes ITEMS consecutive work items (one point
-// per thread) over one LDS copy: where only two copies fit a CU, two items per
-// row-polynomial copy (4 waves per SIMD) or three per cell-polynomial copy (6 waves
-// per SIMD, within the kernel's 80 registers) serve more wavefronts.
+// per thread) over one LDS copy: where only two polynomial copies fit a CU, three
+// items per copy keep 6 waves per SIMD (within the kernel's 80 registers).
 template <int MODE, int LAYOUT, int ITEMS>
-__global__ __launch_bounds__(256 * ITEMS) __attribute__((amdgpu_waves_per_eu(ITEMS == 2 ? 4 : 6)))
+__global__ __launch_bounds__(256 * ITEMS) __attribute__((amdgpu_waves_per_eu(6)))
 void k_table(TableArgs A) {
   extern __shared__ float G[];
   const Geo& g = A.g;
@@ -259,10 +258,8 @@ hipError_t launch_table(af_ctx* c) {
                      : fixed                     ? GRID_FIXED
                                                  : GRID_W;
   const size_t bytes = layout == CELLPOLY ? cellp : poly;
-  // (the cell polynomials at two copies per CU: three items per copy, 6 waves per SIMD)
-  const int items = !((layout == CELLPOLY || layout == ROWPOLY) && bytes * 6 > TAB_LDS_BYTES) ? 1
-                    : layout == CELLPOLY                                                ? 3
-                                                                                        : 2;
+  // (two copies per CU: three items per copy, 6 waves per SIMD)
+  const int items = (layout == CELLPOLY || layout == ROWPOLY) && bytes * 6 > TAB_LDS_BYTES ? 3 : 1;
   const size_t lds = layout == CELLPOLY || layout == ROWPOLY
                          ? bytes
                          : sizeof(float) * (size_t)(fixed ? TAB_LDS_W : c->nx + 3) * (c->nz + 3);
@@ -272,8 +269,8 @@ hipError_t launch_table(af_ctx* c) {
     hipLaunchKernelGGL((k_table<M, CELLPOLY, 3>), grid, block, lds, c->stream, A); \
   else if (layout == CELLPOLY)                                                      \
     hipLaunchKernelGGL((k_table<M, CELLPOLY, 1>), grid, block, lds, c->stream, A); \
-  else if (layout == ROWPOLY && items == 2)                                         \
-    hipLaunchKernelGGL((k_table<M, ROWPOLY, 2>), grid, block, lds, c->stream, A);  \
+  else if (layout == ROWPOLY && items == 3)                                         \
+    hipLaunchKernelGGL((k_table<M, ROWPOLY, 3>), grid, block, lds, c->stream, A);  \
   else if (layout == ROWPOLY)                                                       \
     hipLaunchKernelGGL((k_table<M, ROWPOLY, 1>), grid, block, lds, c->stream, A);  \
   else if (layout == GRID_FIXED)                                                    \
