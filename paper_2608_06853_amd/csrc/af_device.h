@@ -10,7 +10,6 @@ namespace af {
 
 constexpr int TILE = 256;           // points per tile = threads of a DAS workgroup
 constexpr int SUB = 64;             // points per CMPE sub-tile = one wavefront
-constexpr int MAX_NBA = 16;         // active blocks per tile the CMPE kernel supports
 
 // One travel-time table entry: sample position u = ui + uf of (T + t_ttp/2 - t0/2) * fs
 // and the apodised phasor h * exp(j 2 pi fd (T + t_ttp/2)).  A masked entry (h = 0)

@@ -160,21 +160,19 @@ af_status build_work_lists(af_ctx* c) {
     c->na_max = std::max(c->na_max, HI - LO + 1);
     c->nba_max = std::max(c->nba_max, bHI - bLO + 1);
   }
-  // CMPE stage: tiles wider than its LDS staging holds take the device-memory path
-  const int lim = af::cmpe_span_limit(c->pps);
+  // CMPE stage: tiles whose staging does not fit LDS take the device-memory path
   c->wstride = af::cmpe_wide_stride(c->nba_max, c->pps);
-  c->nba_lds = 1;
+  c->need_lds = 1;
   c->n_wide = 0;
   std::vector<char> is_wide(std::max(n_tiles, 1), 0);
   for (int t = 0; t < n_tiles; ++t) {
     const int4 tr = tiles[t];
     if (tr.x > tr.y) continue;
-    const int nb = tr.w - tr.z + 1;
-    if (nb > lim) {
+    if (!af::cmpe_fits_lds(tr.z, tr.w, c->nsub, c->pps)) {
       is_wide[t] = 1;
       ++c->n_wide;
     } else {
-      c->nba_lds = std::max(c->nba_lds, nb);
+      c->need_lds = std::max(c->need_lds, af::cmpe_need(tr.z, tr.w, c->nsub, c->pps));
     }
   }
   auto slab_floats = [&](int t) {
@@ -547,11 +545,10 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
   // Pack the pixels, in k-d order, into sub-tiles of pps and tiles of 4 sub-tiles.
   // A tile is closed early (its remaining slots become padding) when the next
   // pixel would widen its span of active blocks beyond what the CMPE kernel
-  // stages in LDS, or beyond the pixel's own span where that is wider (such a
-  // tile takes the CMPE stage's device-memory path); with compact images this
-  // never happens and the packing follows the k-d units exactly.
+  // stages in LDS, unless the pixel's own span is that wide already (such a tile
+  // takes the CMPE stage's device-memory path); with compact images this never
+  // happens and the packing follows the k-d units exactly.
   // slot[k] = tile * ppt + sub-tile * pps + s.
-  const int span_max = af::cmpe_span_limit(pps);
   std::vector<long long> slot(n_pix);
   int n_tiles = 0;
   {
@@ -579,7 +576,7 @@ af_status af_set_geometry(af_ctx* c, int n_elem, const double* elem_xz, int n_pi
       if (!new_tile && plo <= phi) {
         const int nlo = bhi < blo ? plo : std::min(blo, plo);
         const int nhi = bhi < blo ? phi : std::max(bhi, phi);
-        new_tile = nhi - nlo + 1 > std::max(span_max, phi - plo + 1);
+        new_tile = nhi - nlo > phi - plo && !af::cmpe_fits_lds(nlo, nhi, c->nsub, pps);
       }
       if (!new_tile && sidx == pps) {  // current sub-tile full: next sub-tile or tile
         if (w == 3) new_tile = true;

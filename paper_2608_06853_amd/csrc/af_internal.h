@@ -195,7 +195,7 @@ struct af_ctx {
   std::vector<int> prange_lo, prange_hi;    // per internal point
   std::vector<int> tile_lo, tile_hi;
   int na_max = 0, nba_max = 0;
-  int nba_lds = 0;     // widest span among the tiles on the LDS path of the CMPE stage
+  long long need_lds = 0;  // largest dynamic LDS (float2) of a tile on the CMPE stage's LDS path
   int n_wide = 0;      // tiles on its device-memory path
   long long wstride = 0;
   long long active_pairs = 0, active_samples = 0;
@@ -280,7 +280,10 @@ hipError_t launch_prepare_grid(af_ctx* c, const float* s, int nx, int nz, float*
                                int do_reg, const af_loss_params* lp, float* regg);
 hipError_t launch_table(af_ctx* c);
 hipError_t launch_das_fwd(af_ctx* c, const float2* iq, float2* bblk);
-int cmpe_span_limit(int pps);  // largest tile span in blocks whose CMPE stage fits in LDS
+// Dynamic LDS (float2) of the CMPE stage for a tile spanning blocks bLO..bHI (its
+// pair range clamped at the array's ends), and whether it fits one workgroup's LDS
+long long cmpe_need(int bLO, int bHI, int nsub, int pps);
+bool cmpe_fits_lds(int bLO, int bHI, int nsub, int pps);
 long long cmpe_wide_stride(int nba, int pps);  // float2 per sub-tile of a wide tile
 hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g, float rho,
                        float sb_scale, float* map_cmpe, float* map_cf, float* map_cmcc,

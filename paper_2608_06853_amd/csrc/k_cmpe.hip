@@ -337,18 +337,12 @@ long long cmpe_wide_stride(int nba, int pps) {
   return (long long)(nba + 1) * (nba + 1) * SS + 2LL * pps * nba * nba;
 }
 
-int cmpe_span_limit(int pps) {
-  // dynamic LDS of k_cmpe for a tile spanning n blocks: (n + 1)^2 subaperture
-  // images of SUB points (row stride SS) plus pps * n^2 pair entries; the static
-  // arrays take the rest
+long long cmpe_need(int bLO, int bHI, int nsub, int pps) { return cmpe_lds_need(bLO, bHI, nsub, pps); }
+
+bool cmpe_fits_lds(int bLO, int bHI, int nsub, int pps) {
   const size_t budget = 160 * 1024 - sizeof(float) * CMPE_WAVES * 3 * SUB -
                         sizeof(double) * CMPE_WAVES * 3 - 256;
-  for (int n = MAX_NBA; n >= 1; --n) {
-    const size_t need = sizeof(float2) * (size_t)(n + 1) * (n + 1) * SS +
-                        (sizeof(float2) + 2 * sizeof(float)) * (size_t)pps * n * n;
-    if (need <= budget) return n;
-  }
-  return 0;
+  return sizeof(float2) * (size_t)cmpe_lds_need(bLO, bHI, nsub, pps) <= budget;
 }
 
 hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g, float rho,
@@ -371,8 +365,7 @@ hipError_t launch_cmpe(af_ctx* c, const float2* bblk, float2* gout, int write_g,
   A.wide = c->v.wide;
   A.wscr = c->d_cmpe_wide.as<float2>();
   A.wstride = c->wstride;
-  const int nba = c->nba_lds;  // widest span of the LDS path
-  const long long most = cmpe_wide_stride(nba, c->pps);
+  const long long most = std::max(c->need_lds, 1LL);  // the largest need on the LDS path
   const dim3 grid((unsigned)(c->v.P / SUB)), block(CMPE_WAVES * SUB);
   // Tiles of a narrow span run with an allocation that lets six workgroups share a
   // CU; the wider ones with the widest span's (one launch when that is small).
