@@ -87,9 +87,10 @@ const char* af_last_error(const af_ctx* ctx);
  *   fnum      F of the apodisation |x'| <= (F/2) z' (Eq. 4, literal form).
  *   n_seg     ray segments after the lens (N_segments).
  * Caller order of points: p = q * patch^2 + m for pixel q, patch point m.
- * Tiles whose points span more active blocks than the CMPE stage stages in LDS
- * (15 at 3 x 3 patches) run that stage from device memory the context owns
- * (about 0.7 MB per such tile at 16 blocks), at some cost in speed.
+ * Tiles whose CMPE staging (the subaperture images and pair entries of their
+ * span of active blocks) does not fit LDS run that stage from device memory the
+ * context owns, at some cost in speed; at 3 x 3 patches a span of 16 blocks fits
+ * where it reaches an end of the array, whose pair range is shorter.
  * Errors: AF_ERR_ARG if n_elem < 3, block does not divide n_elem, patch is not
  * 1 or 3, sizes are not positive, the elements are out of order or the active
  * element set of a point is not contiguous; AF_ERR_OOM. */

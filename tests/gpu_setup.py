@@ -39,9 +39,9 @@ C1_SMALL = afsynth.configs.C1.with_(
 
 MICRO = afsynth.configs.MICRO
 
-# A linear array whose deeper pixels see more than 15 of its 24 blocks (48
-# elements in blocks of 2): their tiles run the CMPE stage from device memory,
-# the shallow ones from LDS.  12 x 8 pixels from 4 to 24 mm.
+# A linear array whose deeper pixels see more of its 24 blocks (48 elements in
+# blocks of 2) than the CMPE stage can stage in LDS: their tiles run that stage
+# from device memory, the shallow ones from LDS.  12 x 8 pixels from 4 to 24 mm.
 _ML = afsynth.configs.MICRO_LINEAR
 WIDE_LINEAR = _ML.with_(
     name="wide_linear",
